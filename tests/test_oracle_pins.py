@@ -1,0 +1,367 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test states what it pins and why a plausible mistake in the oracle would
+fail it.  No expected value here comes from the HIP path.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import exact
+
+# ---------------------------------------------------------------- Gauss rule
+
+
+def test_gauss_closed_forms(orc):
+    """Textbook Gauss-Legendre nodes/weights (Abramowitz & Stegun 25.4) for q=1..5."""
+    ref = {
+        1: ([0.0], [2.0]),
+        2: ([-1 / math.sqrt(3), 1 / math.sqrt(3)], [1.0, 1.0]),
+        3: ([-math.sqrt(3 / 5), 0.0, math.sqrt(3 / 5)], [5 / 9, 8 / 9, 5 / 9]),
+    }
+    a = math.sqrt(3 / 7 - 2 / 7 * math.sqrt(6 / 5))
+    b = math.sqrt(3 / 7 + 2 / 7 * math.sqrt(6 / 5))
+    wa = (18 + math.sqrt(30)) / 36
+    wb = (18 - math.sqrt(30)) / 36
+    ref[4] = ([-b, -a, a, b], [wb, wa, wa, wb])
+    c = math.sqrt(5 - 2 * math.sqrt(10 / 7)) / 3
+    d = math.sqrt(5 + 2 * math.sqrt(10 / 7)) / 3
+    wc = (322 + 13 * math.sqrt(70)) / 900
+    wd = (322 - 13 * math.sqrt(70)) / 900
+    ref[5] = ([-d, -c, 0.0, c, d], [wd, wc, 128 / 225, wc, wd])
+    for q, (xr, wr) in ref.items():
+        x, w = orc.gauss_legendre(q)
+        np.testing.assert_allclose(x, xr, rtol=0, atol=4e-16)
+        np.testing.assert_allclose(w, wr, rtol=0, atol=4e-16)
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5, 6, 7, 8, 10, 12])
+def test_gauss_exactness(orc, q):
+    """A q-point Gauss rule integrates x^m exactly on [-1,1] for m <= 2q-1,
+    and not m = 2q (which tells a q-point rule from a (q+1)-point one)."""
+    x, w = orc.gauss_legendre(q)
+    assert np.all(np.diff(x) > 0)
+    for m in range(2 * q):
+        exact_val = 0.0 if m % 2 else 2.0 / (m + 1)
+        assert abs(np.dot(w, x ** m) - exact_val) < 1e-14
+    assert abs(np.dot(w, x ** (2 * q)) - 2.0 / (2 * q + 1)) > 1e-10
+
+
+# ---------------------------------------------------------------- Cox-de Boor
+
+
+def _nonuniform_knots(K, p, seed):
+    rng = np.random.default_rng(seed)
+    inner = np.sort(rng.uniform(0.05, 0.95, K - 1))
+    # keep them distinct and well separated
+    inner = np.unique(np.round(inner, 3))
+    assert len(inner) == K - 1
+    return np.concatenate([[0.0] * (p + 1), inner, [1.0] * (p + 1)])
+
+
+@pytest.mark.parametrize("K,p", [(1, 1), (1, 3), (4, 2), (5, 3), (7, 4), (3, 5)])
+def test_partition_of_unity_and_derivative_sum(orc, K, p):
+    """sum_i B_i(x) = 1 and sum_i B_i'(x) = 0 on [0,1]; B_i >= 0 (eqs. cox1/cox2)."""
+    for t in (W.open_uniform_knots(K, p), _nonuniform_knots(K, p, 7) if K > 1 else None):
+        if t is None:
+            continue
+        for x in np.linspace(0, 1, 37):
+            B, dB = orc.basis_all(t, p, x)
+            assert len(B) == K + p
+            assert abs(B.sum() - 1) < 1e-14
+            assert abs(dB.sum()) < 1e-11 * max(1.0, np.abs(dB).max())
+            assert B.min() >= 0
+
+
+def test_uniform_interior_segments(orc):
+    """Uniform B-splines on an interior span equal the textbook cardinal pieces
+    in local t in [0,1]:  p=2: (1-t)^2/2, (1+2t-2t^2)/2, t^2/2;
+    p=3: (1-t)^3/6, (3t^3-6t^2+4)/6, (-3t^3+3t^2+3t+1)/6, t^3/6."""
+    K = 8
+    for p, pieces in [
+        (2, [lambda t: (1 - t) ** 2 / 2, lambda t: (1 + 2 * t - 2 * t * t) / 2, lambda t: t * t / 2]),
+        (3, [lambda t: (1 - t) ** 3 / 6, lambda t: (3 * t ** 3 - 6 * t ** 2 + 4) / 6,
+             lambda t: (-3 * t ** 3 + 3 * t ** 2 + 3 * t + 1) / 6, lambda t: t ** 3 / 6]),
+    ]:
+        kn = W.open_uniform_knots(K, p)
+        e = 4  # interior element [4/8, 5/8]: functions e..e+p
+        for t in np.linspace(0, 0.999, 11):
+            x = (e + t) / K
+            B, _ = orc.basis_all(kn, p, x)
+            for a in range(p + 1):
+                assert abs(B[e + a] - pieces[a](t)) < 1e-14
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_single_element_is_bernstein(orc, p):
+    """K = 1: the basis is the Bernstein basis C(p,a) x^a (1-x)^(p-a); its
+    derivative is p (b_{a-1,p-1} - b_{a,p-1})."""
+    kn = W.open_uniform_knots(1, p)
+    for x in np.linspace(0, 1, 13):
+        B, dB = orc.basis_all(kn, p, x)
+        for a in range(p + 1):
+            assert abs(B[a] - math.comb(p, a) * x ** a * (1 - x) ** (p - a)) < 1e-14
+            bm = lambda j: math.comb(p - 1, j) * x ** j * (1 - x) ** (p - 1 - j) if 0 <= j <= p - 1 else 0.0
+            assert abs(dB[a] - p * (bm(a - 1) - bm(a))) < 1e-12
+
+
+@pytest.mark.parametrize("K,p", [(4, 3), (5, 2), (3, 4)])
+def test_greville_reproduction(orc, K, p):
+    """sum_i xi*_i B_i(x) = x with Greville abscissae (linear precision)."""
+    for t in (W.open_uniform_knots(K, p), _nonuniform_knots(K, p, 3)):
+        g = np.array([float(v) for v in exact.greville(list(t), p)])
+        for x in np.linspace(0, 1, 29):
+            B, dB = orc.basis_all(t, p, x)
+            assert abs(np.dot(g, B) - x) < 1e-14
+            assert abs(np.dot(g, dB) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("K,p", [(1, 2), (3, 2), (4, 3), (2, 4)])
+def test_basis_vs_exact_rational(orc, K, p):
+    """Floating values and textbook-formula derivatives vs the exact piecewise
+    polynomials of exact.py (derivatives there by polynomial differentiation)."""
+    t = [Fraction(0)] * (p + 1) + [Fraction(k, K) for k in range(1, K)] + [Fraction(1)] * (p + 1)
+    for x in [Fraction(0), Fraction(1, 7), Fraction(1, 3), Fraction(1, 2), Fraction(5, 6), Fraction(1)]:
+        vals, ders = exact.basis_values(t, p, x)
+        B, dB = orc.basis_all(np.array([float(v) for v in t]), p, float(x))
+        np.testing.assert_allclose(B, [float(v) for v in vals], rtol=0, atol=2e-15)
+        np.testing.assert_allclose(dB, [float(v) for v in ders], rtol=0, atol=1e-12 * K * p)
+
+
+# ---------------------------------------------------------------- exact 1D matrices
+
+
+def test_exact_1d_interior_rows_textbook():
+    """Interior rows of the uniform 1D mass (/h) and stiffness (*h) matrices
+    (exact integrals of cardinal B-spline products)."""
+    mass = {2: ["11/20", "13/60", "1/120"],
+            3: ["151/315", "397/1680", "1/42", "1/5040"],
+            4: ["15619/36288", "44117/181440", "913/22680", "251/181440", "1/362880"]}
+    stiff = {2: ["1", "-1/3", "-1/6"],
+             3: ["2/3", "-1/8", "-1/5", "-1/120"],
+             4: ["35/72", "-11/360", "-17/90", "-59/2520", "-1/5040"]}
+    K = 16
+    for p in (2, 3, 4):
+        M, A = exact.matrices_1d(exact.open_uniform_knots(K, p), p)
+        i = K // 2
+        h = Fraction(1, K)
+        assert [M[i][i + o] / h for o in range(p + 1)] == [Fraction(s) for s in mass[p]]
+        assert [A[i][i + o] * h for o in range(p + 1)] == [Fraction(s) for s in stiff[p]]
+
+
+def test_exact_1d_bernstein_mass():
+    """K=1: int b_a b_b = C(p,a)C(p,b) / ((2p+1) C(2p,a+b))."""
+    for p in (1, 2, 3, 4, 5):
+        M, A = exact.matrices_1d(exact.open_uniform_knots(1, p), p)
+        for a in range(p + 1):
+            for b in range(p + 1):
+                ref = Fraction(math.comb(p, a) * math.comb(p, b), (2 * p + 1) * math.comb(2 * p, a + b))
+                assert M[a][b] == ref
+            assert sum(A[a]) == 0
+
+
+def test_golden_1d_K8_p2(orc):
+    """Stored exact 1D matrices of the K=8, p=2 open uniform basis
+    (tests/golden/bspline1d_K8_p2.txt, written by tests/golden/make_golden.py
+    from oracle/exact.py)."""
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "bspline1d_K8_p2.txt")
+    rows = {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        name, i, vals = line.split(":")
+        rows[(name, int(i))] = [Fraction(v) for v in vals.split()]
+    M, A = exact.matrices_1d(exact.open_uniform_knots(8, 2), 2)
+    for i in range(10):
+        assert rows[("1920M", i)] == [1920 * v for v in M[i]]
+        assert rows[("A", i)] == A[i]
+    # printed structure: 1920*M first rows [48,28,4], [28,80,50,2], [4,50,132,52,2]
+    assert rows[("1920M", 0)][:3] == [48, 28, 4]
+    assert rows[("1920M", 1)][:4] == [28, 80, 50, 2]
+    assert rows[("1920M", 2)][:5] == [4, 50, 132, 52, 2]
+    assert sum(sum(r) for k, r in rows.items() if k[0] == "1920M") == 1920
+
+
+# ---------------------------------------------------------------- element matrices
+
+
+def _fkron(a, b, c):
+    return np.kron(np.array(a, dtype=object), np.kron(np.array(b, dtype=object), np.array(c, dtype=object)))
+
+
+def _patch(orc, K, p, knots=None):
+    if knots is None:
+        knots = [W.open_uniform_knots(k, p) for k in K]
+    return orc.Patch(p, K, [p + 1] * 3, knots)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_single_element_kronecker(orc, p):
+    """K = 1 in every direction, kappa = 1: element mass = Bernstein mass cubed
+    (Kronecker, x fastest) times the cell volume; stiffness = sum of three
+    Kronecker products with the exact 1D stiffness."""
+    P = _patch(orc, (1, 1, 1), p)
+    kap = W.kappa_constant(1, P.nq)
+    Me, Ke = orc.element_matrices(P, kap)
+    M1, A1 = exact.matrices_1d(exact.open_uniform_knots(1, p), p)
+    Mr = _fkron(M1, M1, M1).astype(float)
+    Kr = (_fkron(M1, M1, A1) + _fkron(M1, A1, M1) + _fkron(A1, M1, M1)).astype(float)
+    np.testing.assert_allclose(Me[0], Mr, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(Ke[0], Kr, rtol=0, atol=1e-13)
+
+
+def test_element_invariants(orc):
+    """For any positive kappa: element matrices symmetric, K_e 1 = 0 (gradient
+    of a constant), sum of M_e entries = sum_q w_q kappa_q; for kappa=1 that
+    sum is the cell volume."""
+    P = _patch(orc, (3, 2, 4), 3)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=11)
+    Me, Ke = orc.element_matrices(P, kap)
+    xs = [orc.quad_nodes(P, d) for d in range(3)]
+    for e in range(P.nelem):
+        ex, ey, ez = e % 3, (e // 3) % 2, e // 6
+        wq = np.einsum("k,j,i->kji", xs[2][1][ez], xs[1][1][ey], xs[0][1][ex]).reshape(-1)
+        assert np.array_equal(Me[e], Me[e].T) or np.abs(Me[e] - Me[e].T).max() < 1e-17
+        assert np.abs(Ke[e] - Ke[e].T).max() < 1e-14
+        assert np.abs(Ke[e].sum(axis=1)).max() < 1e-13 * np.abs(Ke[e]).max()
+        assert abs(Me[e].sum() - np.dot(wq, kap[e])) < 1e-15
+    ones = W.kappa_constant(P.nelem, P.nq)
+    Me1, _ = orc.element_matrices(P, ones, want_k=False)
+    assert abs(Me1[0].sum() - (1 / 3) * (1 / 2) * (1 / 4)) < 1e-16
+
+
+# ---------------------------------------------------------------- global matrices
+
+
+def _structural_pattern(N, p):
+    """(I,J) present iff |i_d - j_d| <= p for every direction; sorted columns."""
+    Nx, Ny, Nz = N
+    rp = [0]
+    cols = []
+    for k in range(Nz):
+        for j in range(Ny):
+            for i in range(Nx):
+                for kk in range(max(0, k - p), min(Nz, k + p + 1)):
+                    for jj in range(max(0, j - p), min(Ny, j + p + 1)):
+                        for ii in range(max(0, i - p), min(Nx, i + p + 1)):
+                            cols.append(ii + Nx * (jj + Ny * kk))
+                rp.append(len(cols))
+    return np.array(rp, dtype=np.int64), np.array(cols, dtype=np.int32)
+
+
+def _csr_to_dense(rp, col, val, n):
+    A = np.zeros((n, n))
+    for r in range(n):
+        A[r, col[rp[r]:rp[r + 1]]] = val[rp[r]:rp[r + 1]]
+    return A
+
+
+def test_global_w1_kronecker(orc):
+    """8^3 elements, p=2, q=3, kappa=1: the assembled global mass equals
+    M1 (x) M1 (x) M1 of the exact 1D mass matrix; nnz = 85 184 and the pattern
+    is the structural one."""
+    P = _patch(orc, (8, 8, 8), 2)
+    kap = W.kappa_constant(P.nelem, P.nq)
+    rp, col, Mv, Kv = orc.assemble(P, kap)
+    assert rp[-1] == 85184
+    rp_s, col_s = _structural_pattern(P.N, 2)
+    assert np.array_equal(rp, rp_s) and np.array_equal(col, col_s)
+    M1, A1 = exact.matrices_1d(exact.open_uniform_knots(8, 2), 2)
+    Mref = _fkron(M1, M1, M1).astype(float)
+    Kref = (_fkron(M1, M1, A1) + _fkron(M1, A1, M1) + _fkron(A1, M1, M1)).astype(float)
+    Md = _csr_to_dense(rp, col, Mv, P.ndof)
+    Kd = _csr_to_dense(rp, col, Kv, P.ndof)
+    assert np.linalg.norm(Md - Mref) / np.linalg.norm(Mref) < 1e-14
+    assert np.linalg.norm(Kd - Kref) / np.linalg.norm(Kref) < 1e-14
+    assert abs(Mv.sum() - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_global_separable_linear_kappa_exact(orc, p):
+    """Anisotropic mesh K=(3,2,4), non-uniform knots, kappa = (1+x)(2+y)(3+z):
+    (p+1)-point Gauss is exact for these integrands, so the assembled matrices
+    equal the exact Kronecker forms with weighted 1D matrices.  Different
+    weights per axis catch a transposed kappa layout or a swapped axis."""
+    K = (3, 2, 4)
+    knots = [W.open_uniform_knots(K[0], p), _nonuniform_knots(2, p, 5), _nonuniform_knots(4, p, 9)]
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    xs = [orc.quad_nodes(P, d)[0] for d in range(3)]
+    kap = W.kappa_separable(1 + xs[0], 2 + xs[1], 3 + xs[2])
+    rp, col, Mv, Kv = orc.assemble(P, kap)
+    tf = [[Fraction(float(v)) for v in k] for k in knots]
+    Mx, Ax = exact.matrices_1d(tf[0], p, (1, 1))
+    My, Ay = exact.matrices_1d(tf[1], p, (2, 1))
+    Mz, Az = exact.matrices_1d(tf[2], p, (3, 1))
+    Mref = _fkron(Mz, My, Mx).astype(float)
+    Kref = (_fkron(Mz, My, Ax) + _fkron(Mz, Ay, Mx) + _fkron(Az, My, Mx)).astype(float)
+    Md = _csr_to_dense(rp, col, Mv, P.ndof)
+    Kd = _csr_to_dense(rp, col, Kv, P.ndof)
+    assert np.linalg.norm(Md - Mref) / np.linalg.norm(Mref) < 1e-14
+    assert np.linalg.norm(Kd - Kref) / np.linalg.norm(Kref) < 1e-13
+
+
+def test_global_invariants_lognormal(orc):
+    """Any kappa: sum of M = sum_q w_q kappa_q; K 1 = 0; symmetry; rows()
+    equals the assembled rows."""
+    P = _patch(orc, (4, 3, 5), 2)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=4)
+    rp, col, Mv, Kv = orc.assemble(P, kap)
+    xs = [orc.quad_nodes(P, d)[1] for d in range(3)]
+    wq = W.kappa_separable(xs[0], xs[1], xs[2])
+    assert abs(Mv.sum() - (wq * kap).sum()) < 1e-14
+    Kd = _csr_to_dense(rp, col, Kv, P.ndof)
+    Md = _csr_to_dense(rp, col, Mv, P.ndof)
+    assert np.abs(Kd.sum(axis=1)).max() < 1e-13 * np.abs(Kd).sum(axis=1).max()
+    assert np.abs(Kd - Kd.T).max() < 1e-15 and np.abs(Md - Md.T).max() < 1e-17
+    dofs = np.array([0, 7, 33, P.ndof // 2, P.ndof - 1])
+    for d, (c, m, k) in zip(dofs, orc.rows(P, kap, dofs)):
+        assert np.array_equal(c, col[rp[d]:rp[d + 1]])
+        np.testing.assert_allclose(m, Mv[rp[d]:rp[d + 1]], rtol=0, atol=1e-17)
+        np.testing.assert_allclose(k, Kv[rp[d]:rp[d + 1]], rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- adjoint
+
+
+def test_kappa_grad_closed_forms(orc):
+    """dL/dkappa_q = w_q (u_h v_h + grad u_h . grad v_h)(x_q): with u = v = 1
+    it is w_q; with u = v = Greville-x (u_h = x) it is w_q (x^2 + 1); with
+    u = Greville-x, v = 1 it is w_q x (mass part only)."""
+    p = 3
+    K = (4, 3, 5)
+    P = _patch(orc, K, p)
+    xn = [orc.quad_nodes(P, d) for d in range(3)]
+    wq = W.kappa_separable(xn[0][1], xn[1][1], xn[2][1])
+    xq = W.kappa_separable(xn[0][0], np.ones_like(xn[1][0]), np.ones_like(xn[2][0]))
+    ones = np.ones(P.ndof)
+    g = orc.kappa_grad(P, ones, ones)
+    np.testing.assert_allclose(g, wq, rtol=1e-14, atol=0)
+    gx = np.array([float(v) for v in exact.greville(list(W.open_uniform_knots(K[0], p)), p)])
+    ux = np.tile(gx, P.N[1] * P.N[2])
+    g2 = orc.kappa_grad(P, ux, ux)
+    np.testing.assert_allclose(g2, wq * (xq ** 2 + 1), rtol=1e-13, atol=0)
+    g3 = orc.kappa_grad(P, ux, ones)
+    np.testing.assert_allclose(g3, wq * xq, rtol=1e-13, atol=1e-18)
+
+
+def test_kappa_grad_linearity(orc):
+    """L(kappa) = u^T (K + M) v is linear in kappa, so L = sum_q kappa_q g_q
+    exactly (Euler's identity); checked against the assembled CSR."""
+    P = _patch(orc, (3, 4, 2), 2)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=2)
+    u = W.normal_vector(P.ndof, 3)
+    v = W.normal_vector(P.ndof, 4)
+    rp, col, Mv, Kv = orc.assemble(P, kap)
+    Av = np.zeros(P.ndof)
+    for r in range(P.ndof):
+        s = slice(rp[r], rp[r + 1])
+        Av[r] = math.fsum((Mv[s] + Kv[s]) * v[col[s]])
+    L = math.fsum(u * Av)
+    g = orc.kappa_grad(P, u, v)
+    assert abs(math.fsum((g * kap).reshape(-1)) - L) < 1e-12 * abs(L)
