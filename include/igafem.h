@@ -1,0 +1,223 @@
+/*
+ * igafem.h -- C ABI of the MI355X (gfx950) B-spline element-integration library.
+ *
+ * The library integrates 3D tensor-product B-spline basis functions element
+ * by element (Woźniak, Szyszka, Rojas: "A study of efficient concurrent
+ * integration methods of B-Spline basis functions in IGA-FEM", arXiv
+ * 2207.00280) and assembles the global matrices:
+ *
+ *   mass       M_IJ = int kappa phi_I phi_J            (Gram matrix, eq. mass_term / eq. 88)
+ *   stiffness  K_IJ = int kappa grad phi_I . grad phi_J (from the weak form, eq. weak_space)
+ *
+ * with phi_I(x) = N_i(x1) N_j(x2) N_k(x3) (eq. basis_construction), each N a
+ * Cox-de Boor B-spline (eqs. cox1/cox2) on an open knot vector (eq.
+ * knot_vector), integrated by the tensor Gauss rule of eq. (10).  The
+ * coefficient kappa is given at every quadrature point and enters eq. (10)
+ * in the slot of J(x^n), next to the element Jacobian.
+ *
+ * CONVENTIONS (fixed where the paper leaves them open)
+ *   - element e_d = 0..K_d-1 of direction d spans [t_d[e_d+p], t_d[e_d+p+1]]
+ *     and carries the global functions e_d..e_d+p (Remark on element-by-element
+ *     pre-computations); N_d = K_d + p functions per direction;
+ *   - flat element index e = ex + Kx (ey + Ky ez);
+ *   - local function index I = a1 + n (a2 + n a3), n = p+1 (x fastest);
+ *   - global DOF index g = i + Nx (j + Ny k) (x fastest);
+ *   - kappa and dL/dkappa: double [E][qz][qy][qx] (element-major, x fastest);
+ *   - element matrices Me, Ke: double [E][n^3][n^3], row-major (row = test I);
+ *   - CSR: row_ptr int64 [ndof+1], col_idx int32 [nnz], columns ascending.
+ *     The pattern is structural: (I,J) is stored iff |i_d - j_d| <= p in every
+ *     direction, numerically-zero entries included.  Values arrays are double
+ *     [nnz] in that order.
+ *
+ * OWNERSHIP AND STREAMS
+ *   The caller owns every array it passes.  Arguments named *_host are host
+ *   memory; every other array is device memory on the current HIP device
+ *   (e.g. from torch).  The library never frees caller memory.  A plan owns
+ *   its device tables and releases them in igaf_plan_destroy.  Calls that
+ *   take a `stream` (a hipStream_t, NULL = the legacy default stream) are
+ *   asynchronous: argument checks run on the host and return before any
+ *   launch; the kernels are queued on `stream` with no host synchronisation.
+ *   A plan may be used from one host thread at a time.
+ *
+ * ERRORS
+ *   Every igaf_status is IGAF_OK (0) or negative; on error nothing has been
+ *   launched and outputs are untouched, and igaf_last_error() returns a
+ *   thread-local message describing the last failure on this thread.
+ *
+ * PRECISION: FP64 throughout.  Supported hot-kernel shapes: 1 <= p <= 5 with
+ * nquad = p+1 in every direction (other Gauss orders are rejected with
+ * IGAF_EUNSUPPORTED by the integration calls; plan creation accepts 1..16).
+ */
+#ifndef IGAFEM_H
+#define IGAFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t igaf_status;
+#define IGAF_OK            0
+#define IGAF_EINVAL       (-1) /* invalid argument (null pointer, bad size, bad knots) */
+#define IGAF_ENOMEM       (-2) /* device or host allocation failed */
+#define IGAF_EDEVICE      (-3) /* a HIP call or kernel launch failed */
+#define IGAF_EUNSUPPORTED (-4) /* valid input outside what the kernels implement */
+
+#define IGAF_MAX_DEGREE 5
+#define IGAF_MAX_QUAD   16
+
+/* Integration algorithm (selects the algorithm, never the result). */
+#define IGAF_CLASSICAL 0   /* Algorithm 1: every matrix value by a full q^3-point sum */
+#define IGAF_SUMFACT   1   /* Algorithm 2 / eqs. finalsum, bufferC: contractions z, y, x */
+
+/* How CSR values are formed (igaf_plan_set_assembly). */
+#define IGAF_ASM_ROWS    0 /* default: owner-computes rows, on-chip reduction, no atomics */
+#define IGAF_ASM_ATOMIC  1 /* element-by-element scatter-add with FP64 atomics */
+
+typedef struct igaf_plan igaf_plan;
+typedef struct igaf_batch igaf_batch;
+
+/* One patch: the paper's problem statement (Sec. 2.3, 3.1): degree p, the
+ * element grid, the knot vectors and the Gauss order per direction. */
+typedef struct {
+    int32_t degree;          /* p >= 1, the same in all directions */
+    int32_t nelem[3];        /* K_x, K_y, K_z >= 1 (non-empty knot spans per direction) */
+    const double* knots[3];  /* HOST, length nelem[d]+2p+1: p+1 equal first knots, p+1 equal
+                                last knots, strictly increasing interior knots (C^{p-1}) */
+    int32_t nquad[3];        /* Gauss-Legendre points per direction, 1..IGAF_MAX_QUAD */
+} igaf_patch_desc;
+
+/* Library version string (static storage). */
+const char* igaf_version(void);
+
+/* Message for the last non-OK status returned on the calling thread
+ * (static thread-local storage, valid until the next failing call). */
+const char* igaf_last_error(void);
+
+/* ---------------------------------------------------------------- host-only
+ * These touch no GPU. */
+
+/* Check a patch description (knot vector form, sizes, degree, Gauss order).
+ * Returns IGAF_OK or IGAF_EINVAL. */
+igaf_status igaf_desc_check(const igaf_patch_desc* desc);
+
+/* Sizes implied by a description: ndof = prod_d (K_d+p); nelem = prod_d K_d;
+ * nqp = prod_d q_d points per element; elem_dim = (p+1)^3; nnz of the
+ * structural CSR pattern = prod_d (N_d (2p+1) - p (p+1)).  Any output may be
+ * NULL. */
+igaf_status igaf_desc_sizes(const igaf_patch_desc* desc, int64_t* ndof, int64_t* nelem,
+                            int64_t* nqp, int64_t* elem_dim, int64_t* nnz);
+
+/* The structural CSR pattern computed on the host into HOST arrays
+ * row_ptr_host[ndof+1], col_idx_host[nnz]. */
+igaf_status igaf_csr_pattern_host(const igaf_patch_desc* desc, int64_t* row_ptr_host,
+                                  int32_t* col_idx_host);
+
+/* ---------------------------------------------------------------- plans */
+
+/* Validate `desc`, build the Gauss rule and the per-element 1D tables on the
+ * current device (Cox-de Boor values and derivatives at the mapped Gauss
+ * nodes, weights w*h/2 folded in, pair products N_a N_b and N_a' N_b' for the
+ * (p+1)(p+2)/2 unordered pairs of each element and direction).  The knot
+ * arrays are copied; the caller may free them afterwards.  Synchronous
+ * (blocks until the tables are built).  *out receives the plan. */
+igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out);
+
+/* Release a plan and its device memory (NULL is ignored).  The caller must
+ * make sure no queued work still uses the plan. */
+void igaf_plan_destroy(igaf_plan* plan);
+
+/* Sizes of the plan's patch (see igaf_desc_sizes). */
+igaf_status igaf_plan_sizes(const igaf_plan* plan, int64_t* ndof, int64_t* nelem, int64_t* nqp,
+                            int64_t* elem_dim, int64_t* nnz);
+
+/* Mapped Gauss nodes x_host[K_d][q_d] of direction `dir` (0,1,2) and the
+ * weights w_host[K_d][q_d] = w_k h_e/2 (w_host may be NULL), so that a caller
+ * can evaluate kappa at the physical quadrature points (eq. 10). */
+igaf_status igaf_quad_nodes(const igaf_plan* plan, int32_t dir, double* x_host, double* w_host);
+
+/* Choose how CSR values are formed by the calls below (IGAF_ASM_ROWS or
+ * IGAF_ASM_ATOMIC).  Both give the same matrix up to rounding order;
+ * IGAF_ASM_ROWS is deterministic. */
+igaf_status igaf_plan_set_assembly(igaf_plan* plan, int32_t mode);
+
+/* ---------------------------------------------------------------- device calls */
+
+/* Fill the structural CSR pattern into DEVICE arrays row_ptr[ndof+1] and
+ * col_idx[nnz] (eq. mass_term gives the matrix; its pattern follows from the
+ * (p+1)^3-function support of each element, Sec. 3.1 Remark). */
+igaf_status igaf_csr_pattern(const igaf_plan* plan, int64_t* row_ptr, int32_t* col_idx,
+                             void* stream);
+
+/* Element matrices (eq. 88 integrated by eq. 10) for every element:
+ * Me, Ke [E][n^3][n^3]; either may be NULL to skip it (not both).
+ * kappa [E][q^3] is required.  method: IGAF_CLASSICAL (Algorithm 1) or
+ * IGAF_SUMFACT (Algorithm 2). */
+igaf_status igaf_element_matrices(const igaf_plan* plan, int32_t method, const double* kappa,
+                                  double* Me, double* Ke, void* stream);
+
+/* Global CSR values from stored element matrices (A = sum over elements of
+ * A^gamma, Sec. 3.1; "insert local element into global"):  Mval, Kval [nnz]
+ * are OVERWRITTEN.  A NULL output skips it; its input must then be NULL too.
+ * Deterministic (each value is summed by one thread in element order). */
+igaf_status igaf_assemble(const igaf_plan* plan, const double* Me, const double* Ke,
+                          double* Mval, double* Kval, void* stream);
+
+/* The hot path: integrate and assemble in one call.  Any of Me, Ke, Mval,
+ * Kval may be NULL (at least one non-NULL); with Me = Ke = NULL the element
+ * matrices are never materialised (streamed mode).  Mval/Kval are
+ * OVERWRITTEN.  method as in igaf_element_matrices (the CSR values are formed
+ * with the sum-factorised contractions in both cases). */
+igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const double* kappa,
+                                    double* Me, double* Ke, double* Mval, double* Kval,
+                                    void* stream);
+
+/* Adjoint of L(kappa) = alphaM u^T M(kappa) v + alphaK u^T K(kappa) v with
+ * respect to kappa at every quadrature point (L is linear in kappa through
+ * the J(x^n) slot of eq. 10):
+ *   grad[e][q] = scale * w_q (alphaM u_h v_h + alphaK grad u_h . grad v_h)(x_q),
+ * u_h = sum_I u_I phi_I.  u, v: device [ndof]; grad: device [E][q^3],
+ * OVERWRITTEN.  No element matrix is formed or stored. */
+igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double* v,
+                            double alphaM, double alphaK, double scale, double* grad,
+                            void* stream);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent patches (the paper's first concurrency level: parts of
+ * the mesh computed concurrently) integrated and assembled to CSR (streamed
+ * mode, M and K) by ONE persistent kernel launch over a cost-sorted work
+ * list.  Tile shapes per degree come from an autotuner run at creation. */
+
+/* Build per-patch plans, the work list and the launch shape; autotunes on the
+ * current device (synchronous).  descs: HOST array of npatch descriptions. */
+igaf_status igaf_batch_create(const igaf_patch_desc* descs, int32_t npatch, igaf_batch** out);
+
+/* Release a batch (NULL is ignored). */
+void igaf_batch_destroy(igaf_batch* batch);
+
+/* The plan of patch i (owned by the batch; do not destroy). */
+const igaf_plan* igaf_batch_plan(const igaf_batch* batch, int32_t i);
+
+/* One persistent launch: for every patch i, Mval[i], Kval[i] (device [nnz_i])
+ * are OVERWRITTEN with the assembled mass and stiffness values for kappa[i]
+ * (device [E_i][q_i^3]).  kappa, Mval, Kval are HOST arrays of npatch device
+ * pointers; Mval[i] / Kval[i] may be NULL to skip that matrix.  The pointer
+ * tables are copied to the device on `stream` (asynchronously, from a staging
+ * buffer the batch owns), so the call may be captured in a HIP graph. */
+igaf_status igaf_batch_integrate_assemble(igaf_batch* batch, const double* const* kappa,
+                                          double* const* Mval, double* const* Kval,
+                                          void* stream);
+
+/* The comparison path: the same work as npatch separate per-patch launches
+ * of igaf_integrate_assemble (streamed mode) on `stream`. */
+igaf_status igaf_batch_integrate_assemble_separate(igaf_batch* batch,
+                                                   const double* const* kappa,
+                                                   double* const* Mval, double* const* Kval,
+                                                   void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IGAFEM_H */

@@ -1,0 +1,310 @@
+// Element matrices of eq. (88) integrated with the tensor Gauss rule of eq. (10):
+//   M_e[I][J] = sum_q c_q  prod_d w N_{a_d} N_{b_d}
+//   K_e[I][J] = sum_q c_q (N'N'.NN.NN + NN.N'N'.NN + NN.NN.N'N')     (x, y, z factors)
+// with c_q = kappa_q (the weights w h/2 of each direction sit in the tables).
+//
+// Two algorithms, the same result up to rounding order:
+//   classical (Algorithm 1): every distinct matrix value is a full q^3-point sum;
+//   sum factorisation (Algorithm 2, eqs. finalsum / bufferC): contract the
+//     quadrature axes one at a time, z -> y -> x:
+//       D_nn[zp][kx][ky] = sum_kz Wnn_z[zp][kz] c[kx,ky,kz]      (D_dd with Wdd_z)
+//       C_a [yp][zp][kx] = sum_ky Wnn_y[yp][ky] D_nn[zp][kx][ky]
+//       C_bc[yp][zp][kx] = sum_ky Wdd_y[yp][ky] D_nn + Wnn_y[yp][ky] D_dd
+//       M[xp][yp][zp]    = sum_kx Wnn_x[xp][kx] C_a
+//       K[xp][yp][zp]    = sum_kx Wdd_x[xp][kx] C_a + Wnn_x[xp][kx] C_bc
+// Every factor N_a N_b (or N'_a N'_b) is symmetric in (a, b), so only the S^3
+// values over unordered per-direction pairs are computed; the dense n^3 x n^3
+// matrices are their expansion (S = (p+1)(p+2)/2; 1000 of 4096 at p = 3).
+//
+// One 256-thread workgroup per element (grid-stride); the stages live in LDS,
+// separated by barriers (the paper's Foata classes become barrier phases).
+#include "common.h"
+#include "launch.h"
+
+namespace igaf {
+
+constexpr int kElemThreads = 256;
+
+template <int P>
+struct ElemShape {
+    static constexpr int n = P + 1;
+    static constexpr int Q = P + 1;
+    static constexpr int S = n * (n + 1) / 2;
+    static constexpr int n3 = n * n * n;
+    static constexpr int n6 = n3 * n3;
+    static constexpr int Q3 = Q * Q * Q;
+    static constexpr int S3 = S * S * S;
+    // all S^3 values fit in LDS up to p = 4; p = 5 works one test-z index at a time
+    static constexpr bool VFULL = P <= 4;
+    static constexpr int VN = VFULL ? S3 : n * S * S;
+};
+
+// METHOD 0 = classical, 1 = sum factorisation.
+template <int P, int METHOD, bool ATOMIC>
+__global__ __launch_bounds__(kElemThreads) void k_element(PatchDev pd, RowMap rm,
+                                                          const double* __restrict__ kappa,
+                                                          double* __restrict__ Me,
+                                                          double* __restrict__ Ke,
+                                                          double* __restrict__ Mv,
+                                                          double* __restrict__ Kv)
+{
+    using Sh = ElemShape<P>;
+    constexpr int n = Sh::n, Q = Sh::Q, S = Sh::S, n3 = Sh::n3, Q3 = Sh::Q3;
+    constexpr int T = kElemThreads;
+    __shared__ double kap[Q3];
+    __shared__ double tw[3][2][S * Q];                       // [dir][nn, dd][s*Q + k]
+    __shared__ double D[2][METHOD ? S * Q * Q : 1];          // [nn, dd][(zp*Q + kx)*Q + ky]
+    __shared__ double C[2][METHOD ? S * S * Q : 1];          // [a, bc][(yp*S + zp)*Q + kx]
+    __shared__ double V[2][Sh::VN];                          // [M, K]
+
+    const int tid = threadIdx.x;
+    const int Kx = pd.d[0].K, Ky = pd.d[1].K;
+
+    // value (xp, yp, zp) of M and K
+    auto value = [&](int xp, int yp, int zp, double& m, double& k) {
+        m = 0.0;
+        k = 0.0;
+        if (METHOD == 1) {
+#pragma unroll
+            for (int kx = 0; kx < Q; ++kx) {
+                double ca = C[0][(yp * S + zp) * Q + kx];
+                double cb = C[1][(yp * S + zp) * Q + kx];
+                double wn = tw[0][0][xp * Q + kx], wd = tw[0][1][xp * Q + kx];
+                m += wn * ca;
+                k += wd * ca + wn * cb;
+            }
+        } else {
+            for (int kz = 0; kz < Q; ++kz) {
+                double nz = tw[2][0][zp * Q + kz], dz = tw[2][1][zp * Q + kz];
+#pragma unroll
+                for (int ky = 0; ky < Q; ++ky) {
+                    double ny = tw[1][0][yp * Q + ky], dy = tw[1][1][yp * Q + ky];
+#pragma unroll
+                    for (int kx = 0; kx < Q; ++kx) {
+                        double c = kap[kx + Q * (ky + Q * kz)];
+                        double nx = tw[0][0][xp * Q + kx], dx = tw[0][1][xp * Q + kx];
+                        m += c * nx * ny * nz;
+                        k += c * (dx * ny * nz + nx * dy * nz + nx * ny * dz);
+                    }
+                }
+            }
+        }
+    };
+
+    auto emit = [&](int64_t e, int ex, int ey, int ez, int i, double m, double k) {
+        if (Me) Me[e * Sh::n6 + i] = m;
+        if (Ke) Ke[e * Sh::n6 + i] = k;
+        if (ATOMIC) {
+            int I = i / n3, J = i % n3;
+            int a1 = I % n, a2 = (I / n) % n, a3 = I / (n * n);
+            int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
+            int64_t pos = rm.pos(ex + a1, ey + a2, ez + a3, ex + b1, ey + b2, ez + b3);
+            if (Mv) unsafeAtomicAdd(Mv + pos, m);
+            if (Kv) unsafeAtomicAdd(Kv + pos, k);
+        }
+    };
+
+    for (int64_t e = blockIdx.x; e < pd.E; e += gridDim.x) {
+        const int ex = (int)(e % Kx);
+        const int ey = (int)((e / Kx) % Ky);
+        const int ez = (int)(e / ((int64_t)Kx * Ky));
+        for (int i = tid; i < Q3; i += T) kap[i] = kappa[e * Q3 + i];
+        for (int i = tid; i < 6 * S * Q; i += T) {
+            int d = i / (2 * S * Q), r = i % (2 * S * Q);
+            int which = r / (S * Q), j = r % (S * Q);
+            int ed = d == 0 ? ex : (d == 1 ? ey : ez);
+            const double* src = which ? pd.d[d].Wdd : pd.d[d].Wnn;
+            tw[d][which][j] = src[(int64_t)ed * S * Q + j];
+        }
+        __syncthreads();
+        if (METHOD == 1) {
+            for (int i = tid; i < S * Q * Q; i += T) {       // stage z
+                int zp = i / (Q * Q), kx = (i / Q) % Q, ky = i % Q;
+                double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+                for (int kz = 0; kz < Q; ++kz) {
+                    double c = kap[kx + Q * (ky + Q * kz)];
+                    d0 += tw[2][0][zp * Q + kz] * c;
+                    d1 += tw[2][1][zp * Q + kz] * c;
+                }
+                D[0][i] = d0;
+                D[1][i] = d1;
+            }
+            __syncthreads();
+            for (int i = tid; i < S * S * Q; i += T) {       // stage y
+                int yp = i / (S * Q), zp = (i / Q) % S, kx = i % Q;
+                double ca = 0.0, cb = 0.0;
+#pragma unroll
+                for (int ky = 0; ky < Q; ++ky) {
+                    double wn = tw[1][0][yp * Q + ky], wd = tw[1][1][yp * Q + ky];
+                    double d0 = D[0][(zp * Q + kx) * Q + ky], d1 = D[1][(zp * Q + kx) * Q + ky];
+                    ca += wn * d0;
+                    cb += wd * d0 + wn * d1;
+                }
+                C[0][i] = ca;
+                C[1][i] = cb;
+            }
+            __syncthreads();
+        }
+        if (Sh::VFULL) {
+            for (int i = tid; i < Sh::S3; i += T) {          // stage x (or the full sums)
+                int xp = i % S, yp = (i / S) % S, zp = i / (S * S);
+                double m, k;
+                value(xp, yp, zp, m, k);
+                V[0][i] = m;
+                V[1][i] = k;
+            }
+            __syncthreads();
+            for (int i = tid; i < Sh::n6; i += T) {          // expand + store
+                int I = i / n3, J = i % n3;
+                int a1 = I % n, a2 = (I / n) % n, a3 = I / (n * n);
+                int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
+                int v = pair_index(a1, b1) + S * (pair_index(a2, b2) + S * pair_index(a3, b3));
+                emit(e, ex, ey, ez, i, V[0][v], V[1][v]);
+            }
+        } else {
+            for (int a3 = 0; a3 < n; ++a3) {                 // one test-z index at a time
+                for (int i = tid; i < n * S * S; i += T) {
+                    int xp = i % S, yp = (i / S) % S, b3 = i / (S * S);
+                    double m, k;
+                    value(xp, yp, pair_index(a3, b3), m, k);
+                    V[0][i] = m;
+                    V[1][i] = k;
+                }
+                __syncthreads();
+                constexpr int rows = n * n;                  // rows with this a3 are contiguous
+                for (int r = tid; r < rows * n3; r += T) {
+                    int I = a3 * rows + r / n3, J = r % n3;
+                    int a1 = I % n, a2 = (I / n) % n;
+                    int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
+                    int v = pair_index(a1, b1) + S * (pair_index(a2, b2) + S * b3);
+                    emit(e, ex, ey, ez, I * n3 + J, V[0][v], V[1][v]);
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int P, int METHOD, bool ATOMIC>
+static int launch_element_t(const PatchDev& pd, const double* kappa, double* Me, double* Ke,
+                            double* Mv, double* Kv, hipStream_t st)
+{
+    RowMap rm = make_rowmap(pd);
+    int64_t blocks = pd.E < 2048 * 4 ? pd.E : 2048 * 4;
+    hipLaunchKernelGGL((k_element<P, METHOD, ATOMIC>), dim3((unsigned)blocks), dim3(kElemThreads), 0,
+                       st, pd, rm, kappa, Me, Ke, Mv, Kv);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_element(const PatchDev& pd, int method, const double* kappa, double* Me, double* Ke,
+                   double* Mv, double* Kv, hipStream_t st)
+{
+    bool atomic = Mv || Kv;
+#define IGAF_EL(PP)                                                                            \
+    case PP:                                                                                   \
+        if (method == 1)                                                                       \
+            return atomic ? launch_element_t<PP, 1, true>(pd, kappa, Me, Ke, Mv, Kv, st)       \
+                          : launch_element_t<PP, 1, false>(pd, kappa, Me, Ke, Mv, Kv, st);     \
+        return atomic ? launch_element_t<PP, 0, true>(pd, kappa, Me, Ke, Mv, Kv, st)           \
+                      : launch_element_t<PP, 0, false>(pd, kappa, Me, Ke, Mv, Kv, st);
+    switch (pd.p) {
+        IGAF_EL(1)
+        IGAF_EL(2)
+        IGAF_EL(3)
+        IGAF_EL(4)
+        IGAF_EL(5)
+    default:
+        return -4;
+    }
+#undef IGAF_EL
+}
+
+// ---------------------------------------------------------------------------
+// Assembly from stored element matrices (A = sum over elements of A^gamma):
+// one thread per structural entry (I, J) sums, in element order, the
+// contributions of the elements that carry both functions.  Deterministic.
+template <int P>
+__global__ void k_gather(PatchDev pd, RowMap rm, const double* __restrict__ Me,
+                         const double* __restrict__ Ke, double* __restrict__ Mv,
+                         double* __restrict__ Kv)
+{
+    constexpr int n = P + 1, n3 = n * n * n, O = 2 * P + 1, O3 = O * O * O;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= pd.ndof * O3) return;
+    int64_t g = t / O3;
+    int o = (int)(t % O3);
+    int ox = o % O - P, oy = (o / O) % O - P, oz = o / (O * O) - P;
+    const int Nx = pd.d[0].N, Ny = pd.d[1].N, Nz = pd.d[2].N;
+    const int Kx = pd.d[0].K, Ky = pd.d[1].K, Kz = pd.d[2].K;
+    int ix = (int)(g % Nx), iy = (int)((g / Nx) % Ny), iz = (int)(g / ((int64_t)Nx * Ny));
+    int jx = ix + ox, jy = iy + oy, jz = iz + oz;
+    if (jx < 0 || jx >= Nx || jy < 0 || jy >= Ny || jz < 0 || jz >= Nz) return;
+    int lo[3], hi[3];
+    int iv[3] = {ix, iy, iz}, jv[3] = {jx, jy, jz}, Kd[3] = {Kx, Ky, Kz};
+    for (int d = 0; d < 3; ++d) {
+        int mx = iv[d] > jv[d] ? iv[d] : jv[d];
+        int mn = iv[d] < jv[d] ? iv[d] : jv[d];
+        lo[d] = mx - P < 0 ? 0 : mx - P;
+        hi[d] = mn > Kd[d] - 1 ? Kd[d] - 1 : mn;
+    }
+    double m = 0.0, k = 0.0;
+    for (int ez = lo[2]; ez <= hi[2]; ++ez)
+        for (int ey = lo[1]; ey <= hi[1]; ++ey)
+            for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+                int64_t e = ex + (int64_t)Kx * (ey + (int64_t)Ky * ez);
+                int I = (ix - ex) + n * ((iy - ey) + n * (iz - ez));
+                int J = (jx - ex) + n * ((jy - ey) + n * (jz - ez));
+                int64_t idx = e * (int64_t)n3 * n3 + (int64_t)I * n3 + J;
+                if (Me) m += Me[idx];
+                if (Ke) k += Ke[idx];
+            }
+    int64_t pos = rm.pos(ix, iy, iz, jx, jy, jz);
+    if (Mv) Mv[pos] = m;
+    if (Kv) Kv[pos] = k;
+}
+
+int launch_gather(const PatchDev& pd, const double* Me, const double* Ke, double* Mv, double* Kv,
+                  hipStream_t st)
+{
+    RowMap rm = make_rowmap(pd);
+    int O = 2 * pd.p + 1;
+    int64_t total = pd.ndof * O * O * O;
+    int threads = 256;
+    int64_t blocks = (total + threads - 1) / threads;
+    switch (pd.p) {
+#define IGAF_G(PP)                                                                             \
+    case PP:                                                                                   \
+        hipLaunchKernelGGL(k_gather<PP>, dim3((unsigned)blocks), dim3(threads), 0, st, pd, rm, \
+                           Me, Ke, Mv, Kv);                                                    \
+        break;
+        IGAF_G(1)
+        IGAF_G(2)
+        IGAF_G(3)
+        IGAF_G(4)
+        IGAF_G(5)
+#undef IGAF_G
+    default:
+        return -4;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+__global__ void k_fill_zero(double* __restrict__ a, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) a[i] = 0.0;
+}
+
+int launch_fill_zero(double* a, int64_t n, hipStream_t st)
+{
+    if (!a || n <= 0) return 0;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, a, n);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace igaf

@@ -1,0 +1,422 @@
+// C ABI of the library: argument checks, Gauss rule, plan objects (device
+// tables), dispatch of the kernels.  See include/igafem.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/igafem.h"
+#include "batch.h"
+#include "common.h"
+#include "launch.h"
+
+using namespace igaf;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+igaf_status fail(igaf_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+// Gauss-Legendre rule on [-1, 1], nodes ascending: roots of P_q by Newton's
+// method from the asymptotic first guess x ~ (1 - 1/(8q^2) + 1/(8q^3)) cos(pi (4i+3)/(4q+2)),
+// weights 2 / ((1 - x^2) P_q'(x)^2).
+void gauss_rule(int q, double* xi, double* wr)
+{
+    for (int i = 0; i < q; ++i) {
+        double x = (1.0 - 1.0 / (8.0 * q * q) + 1.0 / (8.0 * q * q * q)) *
+                   std::cos(M_PI * (4.0 * i + 3.0) / (4.0 * q + 2.0));
+        double dP = 1.0;
+        for (int it = 0; it < 64; ++it) {
+            double Pm1 = 1.0, Pk = x;     // P_0, P_1
+            for (int k = 1; k < q; ++k) {
+                double Pn = ((2.0 * k + 1.0) * x * Pk - k * Pm1) / (k + 1.0);
+                Pm1 = Pk;
+                Pk = Pn;
+            }
+            if (q == 1) { Pk = x; Pm1 = 1.0; }
+            dP = q * (Pm1 - x * Pk) / (1.0 - x * x);
+            double step = Pk / dP;
+            x -= step;
+            if (std::fabs(step) <= 1e-16 * std::fabs(x) + 1e-300) break;
+        }
+        double Pm1 = 1.0, Pk = x;
+        for (int k = 1; k < q; ++k) {
+            double Pn = ((2.0 * k + 1.0) * x * Pk - k * Pm1) / (k + 1.0);
+            Pm1 = Pk;
+            Pk = Pn;
+        }
+        if (q == 1) { Pk = x; Pm1 = 1.0; }
+        dP = q * (Pm1 - x * Pk) / (1.0 - x * x);
+        xi[q - 1 - i] = x;   // the guesses run from +1 downwards
+        wr[q - 1 - i] = 2.0 / ((1.0 - x * x) * dP * dP);
+    }
+}
+
+igaf_status check_desc(const igaf_patch_desc* d)
+{
+    if (!d) return fail(IGAF_EINVAL, "desc is NULL");
+    int p = d->degree;
+    if (p < 1) return fail(IGAF_EINVAL, "degree %d < 1", p);
+    for (int a = 0; a < 3; ++a) {
+        if (d->nelem[a] < 1) return fail(IGAF_EINVAL, "nelem[%d] = %d < 1", a, d->nelem[a]);
+        if (d->nelem[a] > (1 << 20)) return fail(IGAF_EINVAL, "nelem[%d] = %d too large", a, d->nelem[a]);
+        if (d->nquad[a] < 1 || d->nquad[a] > IGAF_MAX_QUAD)
+            return fail(IGAF_EINVAL, "nquad[%d] = %d outside [1, %d]", a, d->nquad[a], IGAF_MAX_QUAD);
+        const double* t = d->knots[a];
+        if (!t) return fail(IGAF_EINVAL, "knots[%d] is NULL", a);
+        int nk = d->nelem[a] + 2 * p + 1;
+        for (int i = 0; i < nk; ++i)
+            if (!std::isfinite(t[i])) return fail(IGAF_EINVAL, "knots[%d][%d] is not finite", a, i);
+        for (int i = 0; i + 1 < nk; ++i)
+            if (t[i] > t[i + 1]) return fail(IGAF_EINVAL, "knots[%d] decreases at %d", a, i);
+        for (int i = 1; i <= p; ++i) {
+            if (t[i] != t[0]) return fail(IGAF_EINVAL, "knots[%d]: first %d knots not equal (open vector)", a, p + 1);
+            if (t[nk - 1 - i] != t[nk - 1]) return fail(IGAF_EINVAL, "knots[%d]: last %d knots not equal (open vector)", a, p + 1);
+        }
+        for (int i = p; i < nk - p - 1; ++i)
+            if (!(t[i] < t[i + 1]))
+                return fail(IGAF_EINVAL, "knots[%d]: span %d is empty (repeated interior knot)", a, i - p);
+    }
+    // the global sizes must fit the index types (int32 columns, int64 rows)
+    double ndof = 1.0;
+    for (int a = 0; a < 3; ++a) ndof *= (double)(d->nelem[a] + p);
+    if (ndof >= 2147483647.0) return fail(IGAF_EINVAL, "ndof %.0f does not fit int32 column indices", ndof);
+    return IGAF_OK;
+}
+
+int64_t band_total(int N, int p)
+{
+    int64_t T = 0;
+    for (int i = 0; i < N; ++i) T += band_len(i, p, N);
+    return T;
+}
+
+void sizes_of(const igaf_patch_desc* d, int64_t* ndof, int64_t* nelem, int64_t* nqp, int64_t* edim,
+              int64_t* nnz)
+{
+    int p = d->degree;
+    int64_t N = 1, E = 1, Qn = 1, T = 1;
+    for (int a = 0; a < 3; ++a) {
+        N *= d->nelem[a] + p;
+        E *= d->nelem[a];
+        Qn *= d->nquad[a];
+        T *= band_total(d->nelem[a] + p, p);
+    }
+    if (ndof) *ndof = N;
+    if (nelem) *nelem = E;
+    if (nqp) *nqp = Qn;
+    if (edim) *edim = (int64_t)(p + 1) * (p + 1) * (p + 1);
+    if (nnz) *nnz = T;
+}
+
+}  // namespace
+
+struct igaf_plan {
+    int p, n, S;
+    int K[3], q[3], N[3];
+    int64_t E, ndof, nnz, nqp;
+    std::vector<double> xnode[3], wnode[3];   // host copies, [K][q]
+    double* dmem = nullptr;
+    int64_t* dpre = nullptr;
+    PatchDev dev;
+    int device = 0;
+    int asm_mode = IGAF_ASM_ROWS;
+};
+
+namespace igaf {
+const PatchDev& plan_dev(const igaf_plan* p) { return p->dev; }
+int plan_degree(const igaf_plan* p) { return p->p; }
+bool plan_hot_supported(const igaf_plan* p)
+{
+    return p->p >= 1 && p->p <= IGAF_MAX_DEGREE && p->q[0] == p->p + 1 && p->q[1] == p->p + 1 &&
+           p->q[2] == p->p + 1;
+}
+}  // namespace igaf
+
+extern "C" {
+
+const char* igaf_version(void) { return "igafem 0.1 (gfx950, fp64)"; }
+
+const char* igaf_last_error(void) { return g_err; }
+
+igaf_status igaf_desc_check(const igaf_patch_desc* desc) { return check_desc(desc); }
+
+igaf_status igaf_desc_sizes(const igaf_patch_desc* desc, int64_t* ndof, int64_t* nelem,
+                            int64_t* nqp, int64_t* elem_dim, int64_t* nnz)
+{
+    igaf_status st = check_desc(desc);
+    if (st) return st;
+    sizes_of(desc, ndof, nelem, nqp, elem_dim, nnz);
+    return IGAF_OK;
+}
+
+igaf_status igaf_csr_pattern_host(const igaf_patch_desc* desc, int64_t* row_ptr, int32_t* col)
+{
+    igaf_status st = check_desc(desc);
+    if (st) return st;
+    if (!row_ptr || !col) return fail(IGAF_EINVAL, "row_ptr_host / col_idx_host is NULL");
+    int p = desc->degree;
+    int Nx = desc->nelem[0] + p, Ny = desc->nelem[1] + p, Nz = desc->nelem[2] + p;
+    int64_t o = 0, g = 0;
+    for (int iz = 0; iz < Nz; ++iz)
+        for (int iy = 0; iy < Ny; ++iy)
+            for (int ix = 0; ix < Nx; ++ix) {
+                row_ptr[g++] = o;
+                for (int jz = band_lo(iz, p); jz <= band_hi(iz, p, Nz); ++jz)
+                    for (int jy = band_lo(iy, p); jy <= band_hi(iy, p, Ny); ++jy)
+                        for (int jx = band_lo(ix, p); jx <= band_hi(ix, p, Nx); ++jx)
+                            col[o++] = (int32_t)(jx + (int64_t)Nx * (jy + (int64_t)Ny * jz));
+            }
+    row_ptr[g] = o;
+    return IGAF_OK;
+}
+
+igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
+{
+    if (!out) return fail(IGAF_EINVAL, "out is NULL");
+    *out = nullptr;
+    igaf_status st = check_desc(desc);
+    if (st) return st;
+    if (desc->degree > IGAF_MAX_DEGREE)
+        return fail(IGAF_EUNSUPPORTED, "degree %d > %d", desc->degree, IGAF_MAX_DEGREE);
+
+    igaf_plan* P = new (std::nothrow) igaf_plan();
+    if (!P) return fail(IGAF_ENOMEM, "host allocation failed");
+    P->p = desc->degree;
+    P->n = P->p + 1;
+    P->S = P->n * (P->n + 1) / 2;
+    for (int a = 0; a < 3; ++a) {
+        P->K[a] = desc->nelem[a];
+        P->q[a] = desc->nquad[a];
+        P->N[a] = P->K[a] + P->p;
+    }
+    sizes_of(desc, &P->ndof, &P->E, &P->nqp, nullptr, &P->nnz);
+
+    // device layout: per direction [knots | xi | wr | Wnn | Wdd | Nv | dN | wq]
+    int64_t dcount = 0, icount = 0;
+    int64_t off[3][8];
+    for (int a = 0; a < 3; ++a) {
+        int K = P->K[a], Q = P->q[a], nk = K + 2 * P->p + 1;
+        int64_t sz[8] = {nk, Q, Q, (int64_t)K * P->S * Q, (int64_t)K * P->S * Q,
+                         (int64_t)K * P->n * Q, (int64_t)K * P->n * Q, (int64_t)K * Q};
+        for (int j = 0; j < 8; ++j) {
+            off[a][j] = dcount;
+            dcount += (sz[j] + 31) & ~int64_t(31);   // 256-byte aligned pieces
+        }
+        icount += P->N[a] + 1;
+    }
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return fail(IGAF_EDEVICE, "hipGetDevice failed (no GPU?)");
+    }
+    if (hipMalloc(&P->dmem, sizeof(double) * dcount) != hipSuccess) {
+        delete P;
+        return fail(IGAF_ENOMEM, "hipMalloc of %lld doubles failed", (long long)dcount);
+    }
+    if (hipMalloc(&P->dpre, sizeof(int64_t) * icount) != hipSuccess) {
+        (void)hipFree(P->dmem);
+        delete P;
+        return fail(IGAF_ENOMEM, "hipMalloc of prefix tables failed");
+    }
+    int64_t ioff = 0;
+    P->dev.p = P->p;
+    P->dev.E = P->E;
+    P->dev.ndof = P->ndof;
+    P->dev.nnz = P->nnz;
+    igaf_status rc = IGAF_OK;
+    for (int a = 0; a < 3 && rc == IGAF_OK; ++a) {
+        int K = P->K[a], Q = P->q[a], nk = K + 2 * P->p + 1, N = P->N[a];
+        std::vector<double> xi(Q), wr(Q);
+        gauss_rule(Q, xi.data(), wr.data());
+        const double* t = desc->knots[a];
+        P->xnode[a].resize((size_t)K * Q);
+        P->wnode[a].resize((size_t)K * Q);
+        for (int e = 0; e < K; ++e) {
+            double x0 = t[e + P->p], h = t[e + P->p + 1] - x0;
+            for (int k = 0; k < Q; ++k) {
+                P->xnode[a][(size_t)e * Q + k] = x0 + 0.5 * (xi[k] + 1.0) * h;
+                P->wnode[a][(size_t)e * Q + k] = 0.5 * wr[k] * h;
+            }
+        }
+        std::vector<int64_t> pre(N + 1);
+        pre[0] = 0;
+        for (int i = 0; i < N; ++i) pre[i + 1] = pre[i] + band_len(i, P->p, N);
+        P->dev.T[a] = pre[N];
+        double* base = P->dmem;
+        bool ok = hipMemcpy(base + off[a][0], t, sizeof(double) * nk, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(base + off[a][1], xi.data(), sizeof(double) * Q, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(base + off[a][2], wr.data(), sizeof(double) * Q, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(P->dpre + ioff, pre.data(), sizeof(int64_t) * (N + 1), hipMemcpyHostToDevice) == hipSuccess;
+        if (!ok) {
+            rc = fail(IGAF_EDEVICE, "hipMemcpy of tables failed");
+            break;
+        }
+        DirTables& D = P->dev.d[a];
+        D.Wnn = base + off[a][3];
+        D.Wdd = base + off[a][4];
+        D.Nv = base + off[a][5];
+        D.dN = base + off[a][6];
+        D.wq = base + off[a][7];
+        D.pre = P->dpre + ioff;
+        D.K = K;
+        D.N = N;
+        D.Q = Q;
+        ioff += N + 1;
+        if (launch_basis_tables(P->p, base + off[a][0], K, base + off[a][1], base + off[a][2], Q,
+                                base + off[a][3], base + off[a][4], base + off[a][5],
+                                base + off[a][6], base + off[a][7], nullptr) != 0)
+            rc = fail(IGAF_EDEVICE, "basis-table launch failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    if (rc == IGAF_OK && hipStreamSynchronize(nullptr) != hipSuccess)
+        rc = fail(IGAF_EDEVICE, "basis-table kernel failed");
+    if (rc != IGAF_OK) {
+        (void)hipFree(P->dmem);
+        (void)hipFree(P->dpre);
+        delete P;
+        return rc;
+    }
+    *out = P;
+    return IGAF_OK;
+}
+
+void igaf_plan_destroy(igaf_plan* plan)
+{
+    if (!plan) return;
+    (void)hipFree(plan->dmem);
+    (void)hipFree(plan->dpre);
+    delete plan;
+}
+
+igaf_status igaf_plan_sizes(const igaf_plan* plan, int64_t* ndof, int64_t* nelem, int64_t* nqp,
+                            int64_t* elem_dim, int64_t* nnz)
+{
+    if (!plan) return fail(IGAF_EINVAL, "plan is NULL");
+    if (ndof) *ndof = plan->ndof;
+    if (nelem) *nelem = plan->E;
+    if (nqp) *nqp = plan->nqp;
+    if (elem_dim) *elem_dim = (int64_t)plan->n * plan->n * plan->n;
+    if (nnz) *nnz = plan->nnz;
+    return IGAF_OK;
+}
+
+igaf_status igaf_quad_nodes(const igaf_plan* plan, int32_t dir, double* x, double* w)
+{
+    if (!plan) return fail(IGAF_EINVAL, "plan is NULL");
+    if (dir < 0 || dir > 2) return fail(IGAF_EINVAL, "dir %d not in 0..2", dir);
+    if (!x) return fail(IGAF_EINVAL, "x_host is NULL");
+    std::memcpy(x, plan->xnode[dir].data(), sizeof(double) * plan->xnode[dir].size());
+    if (w) std::memcpy(w, plan->wnode[dir].data(), sizeof(double) * plan->wnode[dir].size());
+    return IGAF_OK;
+}
+
+igaf_status igaf_plan_set_assembly(igaf_plan* plan, int32_t mode)
+{
+    if (!plan) return fail(IGAF_EINVAL, "plan is NULL");
+    if (mode != IGAF_ASM_ROWS && mode != IGAF_ASM_ATOMIC)
+        return fail(IGAF_EINVAL, "assembly mode %d unknown", mode);
+    plan->asm_mode = mode;
+    return IGAF_OK;
+}
+
+igaf_status igaf_csr_pattern(const igaf_plan* plan, int64_t* row_ptr, int32_t* col, void* stream)
+{
+    if (!plan) return fail(IGAF_EINVAL, "plan is NULL");
+    if (!row_ptr || !col) return fail(IGAF_EINVAL, "row_ptr / col_idx is NULL");
+    if (launch_csr_pattern(plan->dev, row_ptr, col, (hipStream_t)stream))
+        return fail(IGAF_EDEVICE, "pattern launch failed");
+    return IGAF_OK;
+}
+
+static igaf_status check_hot(const igaf_plan* plan, int method)
+{
+    if (!plan) return fail(IGAF_EINVAL, "plan is NULL");
+    if (method != IGAF_CLASSICAL && method != IGAF_SUMFACT)
+        return fail(IGAF_EINVAL, "method %d unknown", method);
+    if (!plan_hot_supported(plan))
+        return fail(IGAF_EUNSUPPORTED, "kernels implement nquad = degree+1 in every direction "
+                    "(got p=%d, q=%d,%d,%d)", plan->p, plan->q[0], plan->q[1], plan->q[2]);
+    return IGAF_OK;
+}
+
+static igaf_status launched(int rc, const char* what)
+{
+    if (rc == -4) return fail(IGAF_EUNSUPPORTED, "%s: unsupported shape", what);
+    if (rc) return fail(IGAF_EDEVICE, "%s: launch failed: %s", what, hipGetErrorString(hipGetLastError()));
+    return IGAF_OK;
+}
+
+igaf_status igaf_element_matrices(const igaf_plan* plan, int32_t method, const double* kappa,
+                                  double* Me, double* Ke, void* stream)
+{
+    igaf_status st = check_hot(plan, method);
+    if (st) return st;
+    if (!kappa) return fail(IGAF_EINVAL, "kappa is NULL");
+    if (!Me && !Ke) return fail(IGAF_EINVAL, "Me and Ke are both NULL");
+    return launched(launch_element(plan->dev, method, kappa, Me, Ke, nullptr, nullptr,
+                                   (hipStream_t)stream), "element matrices");
+}
+
+igaf_status igaf_assemble(const igaf_plan* plan, const double* Me, const double* Ke, double* Mval,
+                          double* Kval, void* stream)
+{
+    if (!plan) return fail(IGAF_EINVAL, "plan is NULL");
+    if (!Mval && !Kval) return fail(IGAF_EINVAL, "Mval and Kval are both NULL");
+    if ((Mval && !Me) || (Kval && !Ke)) return fail(IGAF_EINVAL, "an output has no input matrices");
+    if (plan->p > IGAF_MAX_DEGREE) return fail(IGAF_EUNSUPPORTED, "degree too large");
+    return launched(launch_gather(plan->dev, Mval ? Me : nullptr, Kval ? Ke : nullptr, Mval, Kval,
+                                  (hipStream_t)stream), "assemble");
+}
+
+igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const double* kappa,
+                                    double* Me, double* Ke, double* Mval, double* Kval,
+                                    void* stream)
+{
+    igaf_status st = check_hot(plan, method);
+    if (st) return st;
+    if (!kappa) return fail(IGAF_EINVAL, "kappa is NULL");
+    if (!Me && !Ke && !Mval && !Kval) return fail(IGAF_EINVAL, "all outputs are NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if ((Mval || Kval) && plan->asm_mode == IGAF_ASM_ATOMIC) {
+        st = launched(launch_fill_zero(Mval, Mval ? plan->nnz : 0, s), "zero");
+        if (!st) st = launched(launch_fill_zero(Kval, Kval ? plan->nnz : 0, s), "zero");
+        if (!st) st = launched(launch_element(plan->dev, method, kappa, Me, Ke, Mval, Kval, s),
+                               "integrate+atomic assembly");
+        return st;
+    }
+    if (Me || Ke) {
+        st = launched(launch_element(plan->dev, method, kappa, Me, Ke, nullptr, nullptr, s),
+                      "element matrices");
+        if (st) return st;
+    }
+    if (Mval || Kval) return launched(launch_rows(plan->dev, kappa, Mval, Kval, s), "row assembly");
+    return IGAF_OK;
+}
+
+igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double* v,
+                            double alphaM, double alphaK, double scale, double* grad, void* stream)
+{
+    igaf_status st = check_hot(plan, IGAF_SUMFACT);
+    if (st) return st;
+    if (!u || !v || !grad) return fail(IGAF_EINVAL, "u, v or grad is NULL");
+    return launched(launch_kappa_grad(plan->dev, u, v, alphaM, alphaK, scale, grad,
+                                      (hipStream_t)stream), "kappa gradient");
+}
+
+}  // extern "C"
+
+namespace igaf {
+igaf_status set_error(igaf_status st, const char* msg) { return fail(st, "%s", msg); }
+}  // namespace igaf

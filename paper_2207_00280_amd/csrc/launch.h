@@ -1,0 +1,38 @@
+// Internal launchers (host side of each kernel file).  All return 0 on
+// success, -3 on a launch failure, -4 for an unsupported shape.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace igaf {
+
+int launch_basis_tables(int p, const double* t, int K, const double* xi, const double* wr, int Q,
+                        double* Wnn, double* Wdd, double* Nv, double* dN, double* wq,
+                        hipStream_t st);
+
+int launch_csr_pattern(const PatchDev& pd, int64_t* row_ptr, int32_t* col, hipStream_t st);
+
+// Element matrices (dense, [E][n^3][n^3]) by sum factorisation or classical
+// quadrature; with Mval/Kval non-null the element values are also
+// scatter-added into the CSR values with FP64 atomics (which must be zeroed
+// first).
+int launch_element(const PatchDev& pd, int method, const double* kappa, double* Me, double* Ke,
+                   double* Mval_atomic, double* Kval_atomic, hipStream_t st);
+
+// CSR values by owner-computes rows (no atomics): overwrites Mval / Kval.
+int launch_rows(const PatchDev& pd, const double* kappa, double* Mval, double* Kval,
+                hipStream_t st);
+
+// CSR values gathered from stored element matrices: overwrites Mval / Kval.
+int launch_gather(const PatchDev& pd, const double* Me, const double* Ke, double* Mval,
+                  double* Kval, hipStream_t st);
+
+int launch_fill_zero(double* a, int64_t n, hipStream_t st);
+
+int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,
+                      double alphaK, double scale, double* grad, hipStream_t st);
+
+}  // namespace igaf

@@ -1,0 +1,123 @@
+// 1D basis tables (Cox-de Boor values and derivatives at the mapped Gauss
+// nodes, Sec. 2.3 eqs. cox1/cox2) and the structural CSR pattern.
+#include "common.h"
+#include "launch.h"
+
+namespace igaf {
+
+// One thread per (element e, Gauss point k) of one direction.  The p+1
+// functions that are non-zero on span s = e+p are built with the local
+// triangular form of the Cox-de Boor recursion (all denominators are knot
+// differences that contain the non-empty span, so none is zero); the
+// derivative uses the standard B-spline derivative formula with the degree
+// p-1 values of the same triangle.
+template <int P>
+__global__ void k_basis_tables(const double* __restrict__ t, int K, const double* __restrict__ xi,
+                               const double* __restrict__ wr, int Q, double* __restrict__ Wnn,
+                               double* __restrict__ Wdd, double* __restrict__ Nv,
+                               double* __restrict__ dN, double* __restrict__ wq)
+{
+    constexpr int n = P + 1;
+    constexpr int S = n * (n + 1) / 2;
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= K * Q) return;
+    int e = gid / Q, k = gid % Q;
+    int s = e + P;
+    double x0 = t[s], x1 = t[s + 1], h = x1 - x0;
+    double x = x0 + 0.5 * (xi[k] + 1.0) * h;
+    double w = 0.5 * wr[k] * h;
+
+    double ndu[n][n];     // upper triangle: values per degree; lower: knot differences
+    double left[n], right[n];
+    ndu[0][0] = 1.0;
+    for (int j = 1; j <= P; ++j) {
+        left[j] = x - t[s + 1 - j];
+        right[j] = t[s + j] - x;
+        double saved = 0.0;
+        for (int r = 0; r < j; ++r) {
+            ndu[j][r] = right[r + 1] + left[j - r];
+            double tmp = ndu[r][j - 1] / ndu[j][r];
+            ndu[r][j] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        ndu[j][j] = saved;
+    }
+    double N[n], D[n];
+    for (int a = 0; a <= P; ++a) {
+        N[a] = ndu[a][P];
+        double lo = 0.0, hi = 0.0;
+        if (a >= 1) lo = ndu[a - 1][P - 1] / (t[s + a] - t[s + a - P]);
+        if (a <= P - 1) hi = ndu[a][P - 1] / (t[s + a + 1] - t[s + a + 1 - P]);
+        D[a] = P * (lo - hi);
+    }
+    for (int a = 0; a <= P; ++a) {
+        Nv[((int64_t)e * n + a) * Q + k] = N[a];
+        dN[((int64_t)e * n + a) * Q + k] = D[a];
+    }
+    wq[(int64_t)e * Q + k] = w;
+    for (int b = 0; b <= P; ++b)
+        for (int a = 0; a <= b; ++a) {
+            int sp = pair_index(a, b);
+            Wnn[((int64_t)e * S + sp) * Q + k] = w * N[a] * N[b];
+            Wdd[((int64_t)e * S + sp) * Q + k] = w * D[a] * D[b];
+        }
+}
+
+int launch_basis_tables(int p, const double* t, int K, const double* xi, const double* wr, int Q,
+                        double* Wnn, double* Wdd, double* Nv, double* dN, double* wq,
+                        hipStream_t st)
+{
+    int threads = 64;
+    int blocks = (K * Q + threads - 1) / threads;
+    switch (p) {
+#define IGAF_CASE(PP)                                                                        \
+    case PP:                                                                                 \
+        hipLaunchKernelGGL(k_basis_tables<PP>, dim3(blocks), dim3(threads), 0, st, t, K, xi, \
+                           wr, Q, Wnn, Wdd, Nv, dN, wq);                                     \
+        break;
+        IGAF_CASE(1)
+        IGAF_CASE(2)
+        IGAF_CASE(3)
+        IGAF_CASE(4)
+        IGAF_CASE(5)
+#undef IGAF_CASE
+    default:
+        return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// One thread per row (DOF): row_ptr from the closed form of RowMap and the
+// ascending column list of the box |j_d - i_d| <= p (clipped to the patch).
+__global__ void k_csr_pattern(RowMap rm, int64_t ndof, int64_t nnz, int64_t* __restrict__ row_ptr,
+                              int32_t* __restrict__ col)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g > ndof) return;
+    if (g == ndof) {
+        row_ptr[ndof] = nnz;
+        return;
+    }
+    int Nx = rm.N[0], Ny = rm.N[1], Nz = rm.N[2], p = rm.p;
+    int ix = (int)(g % Nx);
+    int iy = (int)((g / Nx) % Ny);
+    int iz = (int)(g / ((int64_t)Nx * Ny));
+    int64_t o = rm.row_start(ix, iy, iz);
+    row_ptr[g] = o;
+    for (int jz = band_lo(iz, p); jz <= band_hi(iz, p, Nz); ++jz)
+        for (int jy = band_lo(iy, p); jy <= band_hi(iy, p, Ny); ++jy)
+            for (int jx = band_lo(ix, p); jx <= band_hi(ix, p, Nx); ++jx)
+                col[o++] = (int32_t)(jx + (int64_t)Nx * (jy + (int64_t)Ny * jz));
+}
+
+int launch_csr_pattern(const PatchDev& pd, int64_t* row_ptr, int32_t* col, hipStream_t st)
+{
+    RowMap rm = make_rowmap(pd);
+    int threads = 256;
+    int64_t blocks = (pd.ndof + 1 + threads - 1) / threads;
+    hipLaunchKernelGGL(k_csr_pattern, dim3((unsigned)blocks), dim3(threads), 0, st, rm, pd.ndof,
+                       pd.nnz, row_ptr, col);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace igaf

@@ -1,0 +1,370 @@
+"""Python binding of libigafem.so (the C ABI in include/igafem.h).
+
+Argument marshalling only: every step of the integration runs in the HIP
+kernels of the library; torch provides device memory and streams.  Importing
+this module loads the library and raises if it has not been built; the
+integration calls raise if no GPU is present.  There is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libigafem.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
+CLASSICAL, SUMFACT = 0, 1
+ASM_ROWS, ASM_ATOMIC = 0, 1
+MAX_DEGREE = 5
+
+SYMBOLS = [
+    "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_csr_pattern_host",
+    "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes",
+    "igaf_plan_set_assembly", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
+    "igaf_integrate_assemble", "igaf_kappa_grad", "igaf_batch_create", "igaf_batch_destroy",
+    "igaf_batch_plan", "igaf_batch_integrate_assemble", "igaf_batch_integrate_assemble_separate",
+]
+
+
+class IgafError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("igafem status %d: %s" % (status, msg))
+        self.status = status
+
+
+class PatchDesc(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("nelem", ctypes.c_int32 * 3),
+                ("knots", ctypes.POINTER(ctypes.c_double) * 3), ("nquad", ctypes.c_int32 * 3)]
+
+
+_lib = None
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load libigafem.so (raises if it is missing: build it with
+    ``python -m paper_2207_00280_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libigafem.so not built (run python -m paper_2207_00280_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.igaf_version.restype = ctypes.c_char_p
+    L.igaf_last_error.restype = ctypes.c_char_p
+    st = ctypes.c_int32
+    L.igaf_desc_check.argtypes = [ctypes.POINTER(PatchDesc)]
+    L.igaf_desc_sizes.argtypes = [ctypes.POINTER(PatchDesc)] + [_i64p] * 5
+    L.igaf_csr_pattern_host.argtypes = [ctypes.POINTER(PatchDesc), _i64p, _i32p]
+    L.igaf_plan_create.argtypes = [ctypes.POINTER(PatchDesc), ctypes.POINTER(_vp)]
+    L.igaf_plan_destroy.argtypes = [_vp]
+    L.igaf_plan_destroy.restype = None
+    L.igaf_plan_sizes.argtypes = [_vp] + [_i64p] * 5
+    L.igaf_quad_nodes.argtypes = [_vp, ctypes.c_int32, _dp, _dp]
+    L.igaf_plan_set_assembly.argtypes = [_vp, ctypes.c_int32]
+    L.igaf_csr_pattern.argtypes = [_vp, _vp, _vp, _vp]
+    L.igaf_element_matrices.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
+    L.igaf_assemble.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    L.igaf_integrate_assemble.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.igaf_kappa_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, _vp, _vp]
+    L.igaf_batch_create.argtypes = [ctypes.POINTER(PatchDesc), ctypes.c_int32, ctypes.POINTER(_vp)]
+    L.igaf_batch_destroy.argtypes = [_vp]
+    L.igaf_batch_destroy.restype = None
+    L.igaf_batch_plan.argtypes = [_vp, ctypes.c_int32]
+    L.igaf_batch_plan.restype = _vp
+    ptrs = ctypes.POINTER(_vp)
+    L.igaf_batch_integrate_assemble.argtypes = [_vp, ptrs, ptrs, ptrs, _vp]
+    L.igaf_batch_integrate_assemble_separate.argtypes = [_vp, ptrs, ptrs, ptrs, _vp]
+    for name in SYMBOLS:
+        f = getattr(L, name)
+        if f.restype is ctypes.c_int:   # default restype -> status
+            f.restype = st
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != OK:
+        raise IgafError(status, lib().igaf_last_error().decode())
+
+
+def version():
+    return lib().igaf_version().decode()
+
+
+def make_desc(p, K, knots, q=None):
+    """Build a PatchDesc; keeps the knot arrays alive on the returned object."""
+    if q is None:
+        q = (p + 1,) * 3
+    d = PatchDesc()
+    d.degree = int(p)
+    keep = []
+    for a in range(3):
+        d.nelem[a] = int(K[a])
+        d.nquad[a] = int(q[a])
+        t = np.ascontiguousarray(knots[a], dtype=np.float64)
+        keep.append(t)
+        d.knots[a] = t.ctypes.data_as(_dp)
+    d._keep = keep
+    return d
+
+
+def desc_sizes(desc):
+    v = [ctypes.c_int64() for _ in range(5)]
+    _check(lib().igaf_desc_sizes(ctypes.byref(desc), *[ctypes.byref(x) for x in v]))
+    return dict(zip(["ndof", "nelem", "nqp", "elem_dim", "nnz"], [x.value for x in v]))
+
+
+def desc_check(desc):
+    """Returns (status, message)."""
+    s = lib().igaf_desc_check(ctypes.byref(desc))
+    return s, (lib().igaf_last_error().decode() if s else "")
+
+
+def csr_pattern_host(desc):
+    sz = desc_sizes(desc)
+    rp = np.zeros(sz["ndof"] + 1, dtype=np.int64)
+    col = np.zeros(sz["nnz"], dtype=np.int32)
+    _check(lib().igaf_csr_pattern_host(ctypes.byref(desc), rp.ctypes.data_as(_i64p),
+                                       col.ctypes.data_as(_i32p)))
+    return rp, col
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need_f64_cuda(t, name, numel=None):
+    torch = _torch()
+    if t.dtype != torch.float64:
+        raise TypeError("%s must be float64 (got %s)" % (name, t.dtype))
+    if not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), numel))
+
+
+class Plan:
+    """A patch bound to the current device: tables built at construction."""
+
+    def __init__(self, p, K, knots, q=None):
+        self.desc = make_desc(p, K, knots, q)
+        h = _vp()
+        _check(lib().igaf_plan_create(ctypes.byref(self.desc), ctypes.byref(h)))
+        self._h = h
+        self.p = int(p)
+        self.K = tuple(int(k) for k in K)
+        self.q = tuple(int(x) for x in (q if q is not None else (p + 1,) * 3))
+        v = [ctypes.c_int64() for _ in range(5)]
+        _check(lib().igaf_plan_sizes(h, *[ctypes.byref(x) for x in v]))
+        self.ndof, self.nelem, self.nqp, self.elem_dim, self.nnz = [x.value for x in v]
+
+    @classmethod
+    def _wrap(cls, handle, desc):
+        self = cls.__new__(cls)
+        self.desc = desc
+        self._h = _vp(handle)
+        self._owned = False
+        self.p = desc.degree
+        self.K = tuple(desc.nelem)
+        self.q = tuple(desc.nquad)
+        v = [ctypes.c_int64() for _ in range(5)]
+        _check(lib().igaf_plan_sizes(self._h, *[ctypes.byref(x) for x in v]))
+        self.ndof, self.nelem, self.nqp, self.elem_dim, self.nnz = [x.value for x in v]
+        return self
+
+    def close(self):
+        if getattr(self, "_h", None) and getattr(self, "_owned", True):
+            lib().igaf_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def quad_nodes(self, d):
+        x = np.zeros(self.K[d] * self.q[d])
+        w = np.zeros(self.K[d] * self.q[d])
+        _check(lib().igaf_quad_nodes(self._h, d, x.ctypes.data_as(_dp), w.ctypes.data_as(_dp)))
+        return x.reshape(self.K[d], self.q[d]), w.reshape(self.K[d], self.q[d])
+
+    def set_assembly(self, mode):
+        _check(lib().igaf_plan_set_assembly(self._h, int(mode)))
+
+    def csr_pattern(self, stream=None):
+        torch = _torch()
+        rp = torch.empty(self.ndof + 1, dtype=torch.int64, device="cuda")
+        col = torch.empty(self.nnz, dtype=torch.int32, device="cuda")
+        _check(lib().igaf_csr_pattern(self._h, _ptr(rp), _ptr(col), _stream(stream)))
+        return rp, col
+
+    def _alloc(self, *shape):
+        torch = _torch()
+        return torch.empty(*shape, dtype=torch.float64, device="cuda")
+
+    def element_matrices(self, kappa, method=SUMFACT, want_m=True, want_k=True, Me=None, Ke=None,
+                         stream=None):
+        _need_f64_cuda(kappa, "kappa", self.nelem * self.nqp)
+        n3 = self.elem_dim
+        if want_m and Me is None:
+            Me = self._alloc(self.nelem, n3, n3)
+        if want_k and Ke is None:
+            Ke = self._alloc(self.nelem, n3, n3)
+        Me = Me if want_m else None
+        Ke = Ke if want_k else None
+        for t, nm in ((Me, "Me"), (Ke, "Ke")):
+            if t is not None:
+                _need_f64_cuda(t, nm, self.nelem * n3 * n3)
+        _check(lib().igaf_element_matrices(self._h, int(method), _ptr(kappa), _ptr(Me), _ptr(Ke),
+                                           _stream(stream)))
+        return Me, Ke
+
+    def assemble(self, Me, Ke, Mval=None, Kval=None, stream=None):
+        if Me is not None and Mval is None:
+            Mval = self._alloc(self.nnz)
+        if Ke is not None and Kval is None:
+            Kval = self._alloc(self.nnz)
+        _check(lib().igaf_assemble(self._h, _ptr(Me), _ptr(Ke), _ptr(Mval), _ptr(Kval),
+                                   _stream(stream)))
+        return Mval, Kval
+
+    def integrate_assemble(self, kappa, method=SUMFACT, want_elem=True, want_csr=True, want_m=True,
+                           want_k=True, Me=None, Ke=None, Mval=None, Kval=None, stream=None):
+        _need_f64_cuda(kappa, "kappa", self.nelem * self.nqp)
+        n3 = self.elem_dim
+        if want_elem:
+            if want_m and Me is None:
+                Me = self._alloc(self.nelem, n3, n3)
+            if want_k and Ke is None:
+                Ke = self._alloc(self.nelem, n3, n3)
+        if want_csr:
+            if want_m and Mval is None:
+                Mval = self._alloc(self.nnz)
+            if want_k and Kval is None:
+                Kval = self._alloc(self.nnz)
+        Me = Me if (want_elem and want_m) else None
+        Ke = Ke if (want_elem and want_k) else None
+        Mval = Mval if (want_csr and want_m) else None
+        Kval = Kval if (want_csr and want_k) else None
+        for t, nm, ne in ((Me, "Me", self.nelem * n3 * n3), (Ke, "Ke", self.nelem * n3 * n3),
+                          (Mval, "Mval", self.nnz), (Kval, "Kval", self.nnz)):
+            if t is not None:
+                _need_f64_cuda(t, nm, ne)
+        _check(lib().igaf_integrate_assemble(self._h, int(method), _ptr(kappa), _ptr(Me), _ptr(Ke),
+                                             _ptr(Mval), _ptr(Kval), _stream(stream)))
+        return Me, Ke, Mval, Kval
+
+    def kappa_grad(self, u, v, alphaM=1.0, alphaK=1.0, scale=1.0, grad=None, stream=None):
+        _need_f64_cuda(u, "u", self.ndof)
+        _need_f64_cuda(v, "v", self.ndof)
+        if grad is None:
+            grad = self._alloc(self.nelem, self.nqp)
+        _need_f64_cuda(grad, "grad", self.nelem * self.nqp)
+        _check(lib().igaf_kappa_grad(self._h, _ptr(u), _ptr(v), float(alphaM), float(alphaK),
+                                     float(scale), _ptr(grad), _stream(stream)))
+        return grad
+
+
+def _ptr_array(tensors):
+    arr = (_vp * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = t.data_ptr() if t is not None else None
+    return arr
+
+
+class Batch:
+    """Many independent patches integrated and assembled (CSR, streamed) together."""
+
+    def __init__(self, specs):
+        """specs: list of (p, K, knots[, q])."""
+        self.descs_keep = [make_desc(*s) for s in specs]
+        arr = (PatchDesc * len(specs))()
+        for i, d in enumerate(self.descs_keep):
+            arr[i] = d
+        self._arr = arr
+        h = _vp()
+        _check(lib().igaf_batch_create(arr, len(specs), ctypes.byref(h)))
+        self._h = h
+        self.plans = [Plan._wrap(lib().igaf_batch_plan(h, i), self.descs_keep[i])
+                      for i in range(len(specs))]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().igaf_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def integrate_assemble(self, kappas, Mvals, Kvals, separate=False, stream=None):
+        f = lib().igaf_batch_integrate_assemble_separate if separate else lib().igaf_batch_integrate_assemble
+        _check(f(self._h, _ptr_array(kappas), _ptr_array(Mvals) if Mvals is not None else None,
+                 _ptr_array(Kvals) if Kvals is not None else None, _stream(stream)))
+
+
+def _autograd():
+    torch = _torch()
+
+    class KappaBilinearLoss(torch.autograd.Function):
+        """L(kappa) = alphaM u^T M(kappa) v + alphaK u^T K(kappa) v.
+
+        L is linear in kappa, so L = <kappa, dL/dkappa>; both the value and
+        the gradient come from the adjoint kernel (igaf_kappa_grad), which
+        recomputes basis products instead of storing element matrices."""
+
+        @staticmethod
+        def forward(ctx, kappa, u, v, plan, alphaM=1.0, alphaK=1.0):
+            g = plan.kappa_grad(u, v, alphaM, alphaK, 1.0)
+            ctx.save_for_backward(u, v)
+            ctx.plan, ctx.alphaM, ctx.alphaK = plan, alphaM, alphaK
+            return (g.reshape(-1) * kappa.reshape(-1)).sum()
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            u, v = ctx.saved_tensors
+            # recompute (no element matrices, no stored gradient); grad_out folded into scale
+            g = ctx.plan.kappa_grad(u, v, ctx.alphaM, ctx.alphaK, float(grad_out))
+            return g, None, None, None, None, None
+
+    return KappaBilinearLoss
+
+
+_KBL = None
+
+
+def kappa_bilinear_loss(kappa, u, v, plan, alphaM=1.0, alphaK=1.0):
+    global _KBL
+    if _KBL is None:
+        _KBL = _autograd()
+    return _KBL.apply(kappa, u, v, plan, alphaM, alphaK)

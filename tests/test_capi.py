@@ -1,0 +1,139 @@
+"""C-ABI contract tests that need no GPU: the library loads, exports every
+symbol include/igafem.h declares, and its host-side logic (argument checks,
+sizes, the structural CSR pattern) is right.  Pattern pins come from the
+oracle's brute-force union of element pairs."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2207_00280_amd import igafem as ig
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "igafem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(igaf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    L = ig.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(ig.SYMBOLS) == names
+
+
+def test_version():
+    assert "gfx950" in ig.version()
+
+
+@pytest.mark.parametrize("p,K", [(1, (3, 2, 4)), (2, (8, 8, 8)), (3, (5, 4, 3)), (4, (2, 3, 1)),
+                                 (5, (1, 2, 2))])
+def test_sizes_and_pattern_vs_oracle(orc, p, K):
+    """nnz closed form prod_d (N_d (2p+1) - p (p+1)); the host pattern equals the
+    oracle's brute-force union of element pairs, bit for bit."""
+    knots = [W.open_uniform_knots(k, p) for k in K]
+    d = ig.make_desc(p, K, knots)
+    sz = ig.desc_sizes(d)
+    N = [k + p for k in K]
+    assert sz["ndof"] == N[0] * N[1] * N[2]
+    assert sz["nelem"] == K[0] * K[1] * K[2]
+    assert sz["nqp"] == (p + 1) ** 3
+    assert sz["elem_dim"] == (p + 1) ** 3
+    assert sz["nnz"] == np.prod([n * (2 * p + 1) - p * (p + 1) for n in N])
+    rp, col = ig.csr_pattern_host(d)
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    rp_o, col_o, _, _ = orc.assemble(P, W.kappa_constant(P.nelem, P.nq))
+    assert rp.dtype == np.int64 and col.dtype == np.int32
+    assert np.array_equal(rp, rp_o)
+    assert np.array_equal(col, col_o)
+
+
+def test_headline_sizes():
+    """64^3 elements, p=3: 67^3 DOFs and 95 443 993 structural nonzeros."""
+    d = ig.make_desc(3, (64, 64, 64), [W.open_uniform_knots(64, 3)] * 3)
+    sz = ig.desc_sizes(d)
+    assert sz["ndof"] == 67 ** 3 and sz["nnz"] == 95443993
+
+
+def _bad(p=2, K=(3, 3, 3), knots=None, q=None):
+    if knots is None:
+        knots = [W.open_uniform_knots(k, p) for k in K]
+    return ig.make_desc(p, K, knots, q)
+
+
+@pytest.mark.parametrize("case,frag", [
+    ("p0", "degree"),
+    ("K0", "nelem"),
+    ("q0", "nquad"),
+    ("q17", "nquad"),
+    ("decreasing", "decreases"),
+    ("not_open", "open"),
+    ("repeated_interior", "empty"),
+    ("nan", "finite"),
+])
+def test_desc_errors(case, frag):
+    kn = W.open_uniform_knots(3, 2)
+    if case == "p0":
+        d = _bad(p=0, knots=[W.open_uniform_knots(3, 0)] * 3)
+    elif case == "K0":
+        d = _bad(K=(3, 0, 3), knots=[kn, W.open_uniform_knots(1, 2)[:5], kn])
+    elif case == "q0":
+        d = _bad(q=(3, 0, 3))
+    elif case == "q17":
+        d = _bad(q=(3, 3, 17))
+    elif case == "decreasing":
+        k2 = kn.copy()
+        k2[3], k2[4] = k2[4], k2[3]
+        d = _bad(knots=[kn, k2, kn])
+    elif case == "not_open":
+        k2 = kn.copy()
+        k2[0] = -0.1
+        d = _bad(knots=[kn, kn, k2])
+    elif case == "repeated_interior":
+        k2 = kn.copy()
+        k2[4] = k2[3]
+        d = _bad(knots=[k2, kn, kn])
+    elif case == "nan":
+        k2 = kn.copy()
+        k2[3] = float("nan")
+        d = _bad(knots=[kn, k2, kn])
+    st, msg = ig.desc_check(d)
+    assert st == ig.EINVAL
+    assert frag in msg
+    with pytest.raises(ig.IgafError) as ei:
+        ig.desc_sizes(d)
+    assert ei.value.status == ig.EINVAL
+
+
+def test_null_arguments():
+    L = ig.lib()
+    assert L.igaf_desc_check(None) == ig.EINVAL
+    assert "NULL" in L.igaf_last_error().decode()
+    assert L.igaf_plan_create(None, None) == ig.EINVAL
+    assert L.igaf_plan_sizes(None, None, None, None, None, None) == ig.EINVAL
+    assert L.igaf_element_matrices(None, 1, None, None, None, None) == ig.EINVAL
+    assert L.igaf_integrate_assemble(None, 1, None, None, None, None, None, None) == ig.EINVAL
+    assert L.igaf_kappa_grad(None, None, None, 1.0, 1.0, 1.0, None, None) == ig.EINVAL
+    assert L.igaf_assemble(None, None, None, None, None, None) == ig.EINVAL
+    assert L.igaf_batch_create(None, 0, None) == ig.EINVAL
+    L.igaf_plan_destroy(None)
+    L.igaf_batch_destroy(None)
+
+
+def test_plan_create_rejects_before_device():
+    """Invalid descriptions fail on the host before any device call (so this
+    runs without a GPU)."""
+    import ctypes
+
+    L = ig.lib()
+    h = ctypes.c_void_p()
+    d = _bad(p=0, knots=[W.open_uniform_knots(3, 0)] * 3)
+    assert L.igaf_plan_create(ctypes.byref(d), ctypes.byref(h)) == ig.EINVAL
+    assert h.value is None
