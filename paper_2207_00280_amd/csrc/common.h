@@ -15,6 +15,13 @@
 
 namespace igaf {
 
+// Read-only table pointer in the constant address space: loads at
+// wave-uniform addresses through it become scalar (SMEM) loads even where
+// barriers or LDS traffic would stop the compiler from proving the global
+// memory unclobbered.  Only for tables written before the kernel starts.
+typedef const __attribute__((address_space(4))) double* ctab;
+__host__ __device__ inline ctab as_ctab(const double* p) { return (ctab)(p); }
+
 struct DirTables {
     const double* Wnn;
     const double* Wdd;

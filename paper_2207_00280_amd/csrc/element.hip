@@ -155,12 +155,27 @@ __global__ __launch_bounds__(kElemThreads) void k_element(PatchDev pd, RowMap rm
                 V[1][i] = k;
             }
             __syncthreads();
-            for (int i = tid; i < Sh::n6; i += T) {          // expand + store
-                int I = i / n3, J = i % n3;
-                int a1 = I % n, a2 = (I / n) % n, a3 = I / (n * n);
-                int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
-                int v = pair_index(a1, b1) + S * (pair_index(a2, b2) + S * pair_index(a3, b3));
-                emit(e, ex, ey, ez, i, V[0][v], V[1][v]);
+            if (!ATOMIC && n3 % 2 == 0) {
+                // expand + store two consecutive entries of a row per lane (16-byte stores)
+                for (int i2 = tid; i2 < Sh::n6 / 2; i2 += T) {
+                    const int i = 2 * i2, I = i / n3, J = i % n3;
+                    const int a1 = I % n, a2 = (I / n) % n, a3 = I / (n * n);
+                    const int b2 = (J / n) % n, b3 = J / (n * n), b1 = J % n;
+                    const int vyz = S * (pair_index(a2, b2) + S * pair_index(a3, b3));
+                    const int v0 = pair_index(a1, b1) + vyz, v1 = pair_index(a1, b1 + 1) + vyz;
+                    if (Me)
+                        *reinterpret_cast<double2*>(Me + e * Sh::n6 + i) = make_double2(V[0][v0], V[0][v1]);
+                    if (Ke)
+                        *reinterpret_cast<double2*>(Ke + e * Sh::n6 + i) = make_double2(V[1][v0], V[1][v1]);
+                }
+            } else {
+                for (int i = tid; i < Sh::n6; i += T) {      // expand + store
+                    int I = i / n3, J = i % n3;
+                    int a1 = I % n, a2 = (I / n) % n, a3 = I / (n * n);
+                    int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
+                    int v = pair_index(a1, b1) + S * (pair_index(a2, b2) + S * pair_index(a3, b3));
+                    emit(e, ex, ey, ez, i, V[0][v], V[1][v]);
+                }
             }
         } else {
             for (int a3 = 0; a3 < n; ++a3) {                 // one test-z index at a time

@@ -134,6 +134,9 @@ struct igaf_plan {
     PatchDev dev;
     int device = 0;
     int asm_mode = IGAF_ASM_ROWS;
+    // side stream + events: the CSR kernel runs beside the element kernel
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace igaf {
@@ -282,10 +285,13 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
     }
     if (rc == IGAF_OK && hipStreamSynchronize(nullptr) != hipSuccess)
         rc = fail(IGAF_EDEVICE, "basis-table kernel failed");
+    if (rc == IGAF_OK &&
+        (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
+         hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
+         hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess))
+        rc = fail(IGAF_EDEVICE, "stream/event creation failed");
     if (rc != IGAF_OK) {
-        (void)hipFree(P->dmem);
-        (void)hipFree(P->dpre);
-        delete P;
+        igaf_plan_destroy(P);
         return rc;
     }
     *out = P;
@@ -295,6 +301,10 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
 void igaf_plan_destroy(igaf_plan* plan)
 {
     if (!plan) return;
+    if (plan->side) (void)hipStreamSynchronize(plan->side);
+    if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+    if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
+    if (plan->side) (void)hipStreamDestroy(plan->side);
     (void)hipFree(plan->dmem);
     (void)hipFree(plan->dpre);
     delete plan;
@@ -396,13 +406,25 @@ igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const
                                "integrate+atomic assembly");
         return st;
     }
-    if (Me || Ke) {
-        st = launched(launch_element(plan->dev, method, kappa, Me, Ke, nullptr, nullptr, s),
-                      "element matrices");
-        if (st) return st;
+    if ((Me || Ke) && (Mval || Kval)) {
+        // fork: the CSR rows kernel (compute-heavy) runs on the plan's side
+        // stream beside the element kernel (HBM-store-bound); join before return
+        if (hipEventRecord(plan->ev_fork, s) != hipSuccess ||
+            hipStreamWaitEvent(plan->side, plan->ev_fork, 0) != hipSuccess)
+            return fail(IGAF_EDEVICE, "stream fork failed");
+        st = launched(launch_rows(plan->dev, kappa, Mval, Kval, plan->side), "row assembly");
+        if (hipEventRecord(plan->ev_join, plan->side) != hipSuccess)
+            return fail(IGAF_EDEVICE, "stream join failed");
+        igaf_status st2 = launched(launch_element(plan->dev, method, kappa, Me, Ke, nullptr, nullptr, s),
+                                   "element matrices");
+        if (hipStreamWaitEvent(s, plan->ev_join, 0) != hipSuccess)
+            return fail(IGAF_EDEVICE, "stream join failed");
+        return st ? st : st2;
     }
-    if (Mval || Kval) return launched(launch_rows(plan->dev, kappa, Mval, Kval, s), "row assembly");
-    return IGAF_OK;
+    if (Me || Ke)
+        return launched(launch_element(plan->dev, method, kappa, Me, Ke, nullptr, nullptr, s),
+                        "element matrices");
+    return launched(launch_rows(plan->dev, kappa, Mval, Kval, s), "row assembly");
 }
 
 igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double* v,
