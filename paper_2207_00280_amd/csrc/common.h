@@ -37,6 +37,7 @@ struct PatchDev {
     int p;
     int64_t E, ndof, nnz;
     int64_t T[3];   // number of (i, j) pairs with |i - j| <= p per direction
+    int elem_grid;  // workgroups of the element kernels (grid-stride over elements)
 };
 
 // index of the unordered pair {a, b} among the (p+1)(p+2)/2 pairs

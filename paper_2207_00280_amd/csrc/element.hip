@@ -207,7 +207,7 @@ static int launch_element_t(const PatchDev& pd, const double* kappa, double* Me,
                             double* Mv, double* Kv, hipStream_t st)
 {
     RowMap rm = make_rowmap(pd);
-    int64_t blocks = pd.E < 2048 * 4 ? pd.E : 2048 * 4;
+    int64_t blocks = pd.E < pd.elem_grid ? pd.E : pd.elem_grid;
     hipLaunchKernelGGL((k_element<P, METHOD, ATOMIC>), dim3((unsigned)blocks), dim3(kElemThreads), 0,
                        st, pd, rm, kappa, Me, Ke, Mv, Kv);
     return hipGetLastError() == hipSuccess ? 0 : -3;

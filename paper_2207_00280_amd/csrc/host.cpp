@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -236,6 +237,16 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
     }
     int64_t ioff = 0;
     P->dev.p = P->p;
+    // element kernels: two 256-lane workgroups per CU saturate the HBM store
+    // path and leave LDS for the CSR kernel running beside them
+    int ncu = 256;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess)
+        ncu = 256;
+    P->dev.elem_grid = 2 * ncu;
+    if (const char* g = std::getenv("IGAF_ELEM_GRID")) {   // tuning override
+        int v = std::atoi(g);
+        if (v > 0) P->dev.elem_grid = v;
+    }
     P->dev.E = P->E;
     P->dev.ndof = P->ndof;
     P->dev.nnz = P->nnz;
@@ -407,17 +418,18 @@ igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const
         return st;
     }
     if ((Me || Ke) && (Mval || Kval)) {
-        // fork: the CSR rows kernel (compute-heavy) runs on the plan's side
-        // stream beside the element kernel (HBM-store-bound); join before return
+        // fork: the element kernel (HBM-store-bound) is queued first on the
+        // caller's stream, the CSR rows kernel (latency-bound) on the plan's
+        // side stream, so its workgroups fill the CU slots the element kernel
+        // leaves; the caller's stream then waits for both.
         if (hipEventRecord(plan->ev_fork, s) != hipSuccess ||
             hipStreamWaitEvent(plan->side, plan->ev_fork, 0) != hipSuccess)
             return fail(IGAF_EDEVICE, "stream fork failed");
-        st = launched(launch_rows(plan->dev, kappa, Mval, Kval, plan->side), "row assembly");
-        if (hipEventRecord(plan->ev_join, plan->side) != hipSuccess)
-            return fail(IGAF_EDEVICE, "stream join failed");
         igaf_status st2 = launched(launch_element(plan->dev, method, kappa, Me, Ke, nullptr, nullptr, s),
                                    "element matrices");
-        if (hipStreamWaitEvent(s, plan->ev_join, 0) != hipSuccess)
+        st = launched(launch_rows(plan->dev, kappa, Mval, Kval, plan->side), "row assembly");
+        if (hipEventRecord(plan->ev_join, plan->side) != hipSuccess ||
+            hipStreamWaitEvent(s, plan->ev_join, 0) != hipSuccess)
             return fail(IGAF_EDEVICE, "stream join failed");
         return st ? st : st2;
     }
