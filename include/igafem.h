@@ -190,7 +190,8 @@ igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double
  * list.  Tile shapes per degree come from an autotuner run at creation. */
 
 /* Build per-patch plans, the work list and the launch shape; autotunes on the
- * current device (synchronous).  descs: HOST array of npatch descriptions. */
+ * current device (synchronous; the choice is cached per device and set of
+ * degrees).  descs: HOST array of npatch descriptions. */
 igaf_status igaf_batch_create(const igaf_patch_desc* descs, int32_t npatch, igaf_batch** out);
 
 /* Release a batch (NULL is ignored). */
@@ -199,12 +200,22 @@ void igaf_batch_destroy(igaf_batch* batch);
 /* The plan of patch i (owned by the batch; do not destroy). */
 const igaf_plan* igaf_batch_plan(const igaf_batch* batch, int32_t i);
 
+/* The autotuner's choice and the work list: family (0: every z column
+ * offset of a row in one work item at p <= 3, 1: finer splits), persistent
+ * grid (workgroups of one wavefront), number of work items.  Any output may
+ * be NULL. */
+igaf_status igaf_batch_info(const igaf_batch* batch, int32_t* family, int32_t* grid,
+                            int32_t* nitems);
+
 /* One persistent launch: for every patch i, Mval[i], Kval[i] (device [nnz_i])
  * are OVERWRITTEN with the assembled mass and stiffness values for kappa[i]
  * (device [E_i][q_i^3]).  kappa, Mval, Kval are HOST arrays of npatch device
  * pointers; Mval[i] / Kval[i] may be NULL to skip that matrix.  The pointer
- * tables are copied to the device on `stream` (asynchronously, from a staging
- * buffer the batch owns), so the call may be captured in a HIP graph. */
+ * tables are copied to the device on `stream` from a pinned staging buffer
+ * the batch owns; when they differ from the previous call the host first
+ * waits for `stream`.  The call may be captured in a HIP graph once it has
+ * run eagerly with the same pointers (changing them during capture returns
+ * IGAF_EINVAL).  Overlapping calls on one batch from different streams race. */
 igaf_status igaf_batch_integrate_assemble(igaf_batch* batch, const double* const* kappa,
                                           double* const* Mval, double* const* Kval,
                                           void* stream);

@@ -85,4 +85,13 @@ inline RowMap make_rowmap(const PatchDev& pd)
     return m;
 }
 
+// One patch of a batched launch, as the persistent kernel reads it.
+struct BatchPatch {
+    PatchDev pd;
+    RowMap rm;
+    const double* kappa;
+    double* Mv;
+    double* Kv;
+};
+
 }  // namespace igaf

@@ -26,6 +26,15 @@ int launch_element(const PatchDev& pd, int method, const double* kappa, double* 
 int launch_rows(const PatchDev& pd, const double* kappa, double* Mval, double* Kval,
                 hipStream_t st);
 
+// Batched CSR rows: one persistent launch over a cost-sorted list of
+// (patch, work item) pairs; ctr[2] are device counters that start at zero and
+// are left at zero by the launch.
+int launch_rows_batch(int fam, int grid, const BatchPatch* patches, const int2* items, int nitems,
+                      int* ctr, hipStream_t st);
+int rows_item_count(int p, int fam, int Ny, int Nz);
+int rows_batch_lds_bytes(int fam);
+double rows_item_cost(int p, int fam, int Kx);
+
 // CSR values gathered from stored element matrices: overwrites Mval / Kval.
 int launch_gather(const PatchDev& pd, const double* Me, const double* Ke, double* Mval,
                   double* Kval, hipStream_t st);

@@ -23,7 +23,8 @@ SYMBOLS = [
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes",
     "igaf_plan_set_assembly", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
     "igaf_integrate_assemble", "igaf_kappa_grad", "igaf_batch_create", "igaf_batch_destroy",
-    "igaf_batch_plan", "igaf_batch_integrate_assemble", "igaf_batch_integrate_assemble_separate",
+    "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
+    "igaf_batch_integrate_assemble_separate",
 ]
 
 
@@ -77,6 +78,7 @@ def lib():
     L.igaf_batch_destroy.restype = None
     L.igaf_batch_plan.argtypes = [_vp, ctypes.c_int32]
     L.igaf_batch_plan.restype = _vp
+    L.igaf_batch_info.argtypes = [_vp, _i32p, _i32p, _i32p]
     ptrs = ctypes.POINTER(_vp)
     L.igaf_batch_integrate_assemble.argtypes = [_vp, ptrs, ptrs, ptrs, _vp]
     L.igaf_batch_integrate_assemble_separate.argtypes = [_vp, ptrs, ptrs, ptrs, _vp]
@@ -326,6 +328,11 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def info(self):
+        v = [ctypes.c_int32() for _ in range(3)]
+        _check(lib().igaf_batch_info(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(["family", "grid", "nitems"], [x.value for x in v]))
 
     def integrate_assemble(self, kappas, Mvals, Kvals, separate=False, stream=None):
         f = lib().igaf_batch_integrate_assemble_separate if separate else lib().igaf_batch_integrate_assemble
