@@ -1,15 +1,25 @@
 """Benchmark of the B-spline element-integration hot path on one MI355X.
 
-Workload (the headline): unit cube, 64^3 uniform elements, p=3 (C^2 open
-uniform knots), 4-point Gauss rule per direction, kappa = 1 + 0.5 sin(2 pi x)
+Headline workload: unit cube, 64^3 uniform elements, p=3 (C^2 open uniform
+knots), 4-point Gauss rule per direction, kappa = 1 + 0.5 sin(2 pi x)
 sin(2 pi y) sin(2 pi z) at the quadrature points, FP64.  One step = one
-igaf_integrate_assemble call, sum factorisation, producing the dense element
-matrices M_e and K_e of all 262 144 elements AND the global CSR values of M
-and K (95 443 993 nonzeros each).  Inputs are resident in HBM before timing.
+igaf_integrate_assemble call (sum factorisation) that produces the dense
+element matrices M_e and K_e of all 262 144 elements AND the CSR values of
+the global M and K (95 443 993 nonzeros each).  Inputs are resident in HBM
+before the timed region; inputs are synthetic (seeded).
 
-Prints ONE JSON line (rank 0).  See --help.
+The same run also times, on the same GPU: the element kernel and the CSR
+kernel alone (roofline of the dominant kernel), classical quadrature, the
+atomic assembly, the 128^3 streamed workload (p = 2, 3, 4), the 256-patch
+batched persistent launch against 256 separate launches (eager and
+graph-captured), and the adjoint against the plain forward assembly; and
+the CPU oracle on a bounded sample of the headline workload.
+
+Prints ONE JSON line on stdout.  --mode kernel:<name> runs one kernel only
+(for profiler counter passes).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +36,8 @@ import workloads as W  # noqa: E402
 METRIC = "element matrices/s (mass+stiffness, 64^3 p=3, FP64) + % HBM/FP64 roofline"
 HBM_PEAK = 8.0e12        # bytes/s, MI355X published
 FP64_PEAK = 78.6e12      # flop/s, MI355X published (vector = matrix)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_element_sumfact_64c_p3.json")
+ELEMENT_SRC = os.path.join(ROOT, "paper_2207_00280_amd", "csrc", "element.hip")
 
 
 def log(*a):
@@ -33,8 +45,8 @@ def log(*a):
 
 
 def sumfact_flops(p):
-    """Minimum sum-factorisation flops per element with symmetric pairs:
-    stage z 4 S q^3, stage y 6 S^2 q^2, stage x 6 S^3 q (M and K)."""
+    """Minimum sum-factorisation flops per element (M and K) with symmetric
+    pairs: stage z 4 S q^3, stage y 6 S^2 q^2, stage x 6 S^3 q."""
     n = p + 1
     q = p + 1
     S = n * (n + 1) // 2
@@ -42,8 +54,8 @@ def sumfact_flops(p):
 
 
 def timed(fn, steps, warmup, stream):
-    """Run fn warmup times, then time `steps` calls with HIP events on `stream`;
-    returns the list of per-call milliseconds."""
+    """fn() `warmup` times, then `steps` calls bracketed by HIP events recorded
+    on `stream` (the stream the kernels run on); per-call milliseconds."""
     import torch
 
     for _ in range(warmup):
@@ -58,9 +70,26 @@ def timed(fn, steps, warmup, stream):
     return [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
 
 
+def element_src_hash():
+    return hashlib.sha256(open(ELEMENT_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for_current_kernel():
+    """HBM bytes per launch of the element kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE passes, if they were taken on the
+    current kernel source; else None."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("element_src_sha256_16") != element_src_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
 def cpu_baseline(nsample, chunk=4096):
     """The CPU oracle (classical quadrature, M_e and K_e) on the first
-    `nsample` elements of the same workload, all host threads."""
+    `nsample` elements of the headline workload, all host threads."""
     import oracle
 
     P = oracle.Patch(3, (64, 64, 64), (4, 4, 4), [W.open_uniform_knots(64, 3)] * 3)
@@ -72,8 +101,146 @@ def cpu_baseline(nsample, chunk=4096):
     dt = time.perf_counter() - t0
     return {"value": nsample / dt, "unit": "element matrices/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "first %d of the 262144 elements (classical quadrature, M_e and K_e, "
-                      "no assembly), %.1f s" % (nsample, dt)}
+            "sample": "first %d of the 262144 elements of the headline workload (classical "
+                      "quadrature, M_e and K_e, no assembly), %.1f s" % (nsample, dt)}
+
+
+class Headline:
+    def __init__(self, ig, torch):
+        p, K = 3, (64, 64, 64)
+        self.p = p
+        self.plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
+        xs = [self.plan.quad_nodes(d)[0] for d in range(3)]
+        self.kappa = torch.from_numpy(W.kappa_sine(*xs)).cuda()
+        E, n3, nnz = self.plan.nelem, self.plan.elem_dim, self.plan.nnz
+        self.Me = torch.empty(E, n3, n3, dtype=torch.float64, device="cuda")
+        self.Ke = torch.empty_like(self.Me)
+        self.Mval = torch.empty(nnz, dtype=torch.float64, device="cuda")
+        self.Kval = torch.empty_like(self.Mval)
+        self.ig = ig
+        torch.cuda.synchronize()
+
+    def step(self):
+        self.plan.integrate_assemble(self.kappa, method=self.ig.SUMFACT, Me=self.Me, Ke=self.Ke,
+                                     Mval=self.Mval, Kval=self.Kval)
+
+    def element(self, method=None):
+        self.plan.element_matrices(self.kappa, method=self.ig.SUMFACT if method is None else method,
+                                   Me=self.Me, Ke=self.Ke)
+
+    def csr(self):
+        self.plan.integrate_assemble(self.kappa, want_elem=False, Mval=self.Mval, Kval=self.Kval)
+
+
+def bench_w3(ig, torch, stream, steps):
+    out = {}
+    for p in W.W3["ps"]:
+        K = W.W3["K"]
+        plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
+        kap = torch.from_numpy(W.kappa_lognormal(plan.nelem, plan.nqp, W.W3["seed"])).cuda()
+        Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+        Kv = torch.empty_like(Mv)
+        ms = float(np.mean(timed(lambda: plan.integrate_assemble(kap, want_elem=False, Mval=Mv, Kval=Kv),
+                                 steps, 2, stream)))
+        b = plan.nelem * plan.nqp * 8 + 2 * plan.nnz * 8
+        f = plan.nelem * sumfact_flops(p)
+        troof = max(b / HBM_PEAK, f / FP64_PEAK)
+        out["p%d" % p] = {"ms": ms, "elements_per_s": plan.nelem / (ms * 1e-3), "nnz": plan.nnz,
+                          "bytes": b, "GB/s": b / (ms * 1e-3) / 1e9, "roofline_ms": troof * 1e3,
+                          "frac": troof / (ms * 1e-3)}
+        log("W3 p=%d: %.3f ms (%.1f%% of roofline)" % (p, ms, 100 * troof / (ms * 1e-3)))
+        del kap, Mv, Kv, plan
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_w4(ig, torch, stream, steps):
+    shapes = W.batch_patches(**{k: W.W4[k] for k in ("npatch", "seed", "kmin", "kmax", "ps")})
+    kap_h = W.batch_kappas(shapes, seed=W.W4["seed"])
+    t0 = time.perf_counter()
+    B = ig.Batch([(d["p"], d["K"], [W.open_uniform_knots(k, d["p"]) for k in d["K"]]) for d in shapes])
+    t_create = time.perf_counter() - t0
+    kaps = [torch.from_numpy(k).cuda() for k in kap_h]
+    del kap_h
+    Ms = [torch.empty(pl.nnz, dtype=torch.float64, device="cuda") for pl in B.plans]
+    Ks = [torch.empty(pl.nnz, dtype=torch.float64, device="cuda") for pl in B.plans]
+    E = sum(pl.nelem for pl in B.plans)
+    nnz = sum(pl.nnz for pl in B.plans)
+    b = sum(pl.nelem * pl.nqp * 8 for pl in B.plans) + 2 * nnz * 8
+    f = sum(pl.nelem * sumfact_flops(pl.p) for pl in B.plans)
+    troof = max(b / HBM_PEAK, f / FP64_PEAK)
+    ms_b = float(np.mean(timed(lambda: B.integrate_assemble(kaps, Ms, Ks), steps, 2, stream)))
+    ms_s = float(np.mean(timed(lambda: B.integrate_assemble(kaps, Ms, Ks, separate=True), steps, 2, stream)))
+    # the 256 separate launches captured in one HIP graph and replayed
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B.integrate_assemble(kaps, Ms, Ks, separate=True, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        B.integrate_assemble(kaps, Ms, Ks, separate=True, stream=s)
+    ms_g = float(np.mean(timed(g.replay, steps, 2, torch.cuda.current_stream())))
+    # the persistent launch captured and replayed
+    with torch.cuda.stream(s):
+        B.integrate_assemble(kaps, Ms, Ks, stream=s)
+    torch.cuda.synchronize()
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2, stream=s):
+        B.integrate_assemble(kaps, Ms, Ks, stream=s)
+    ms_g2 = float(np.mean(timed(g2.replay, steps, 2, torch.cuda.current_stream())))
+    info = B.info()
+    out = {"patches": len(shapes), "elements": E, "nnz": nnz, "bytes": b, "flops": f,
+           "roofline_ms": troof * 1e3,
+           "persistent": {"ms": ms_b, "elements_per_s": E / (ms_b * 1e-3), "frac": troof / (ms_b * 1e-3)},
+           "persistent_graph": {"ms": ms_g2, "elements_per_s": E / (ms_g2 * 1e-3)},
+           "separate_eager": {"ms": ms_s, "elements_per_s": E / (ms_s * 1e-3)},
+           "separate_graph": {"ms": ms_g, "elements_per_s": E / (ms_g * 1e-3)},
+           "autotune": info, "create_s": t_create}
+    log("W4: persistent %.2f ms, graph %.2f ms, separate %.2f ms, separate graph %.2f ms (%s)"
+        % (ms_b, ms_g2, ms_s, ms_g, info))
+    del Ms, Ks, kaps, B, g, g2
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_w5(ig, torch, stream, steps):
+    cfg = W.W5
+    p, K = cfg["p"], cfg["K"]
+    plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
+    kap = torch.from_numpy(W.kappa_lognormal(plan.nelem, plan.nqp, cfg["seed_kappa"])).cuda()
+    u = torch.from_numpy(W.normal_vector(plan.ndof, cfg["seed_u"])).cuda()
+    v = torch.from_numpy(W.normal_vector(plan.ndof, cfg["seed_v"])).cuda()
+    g = torch.empty_like(kap)
+    Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+    Kv = torch.empty_like(Mv)
+    ms_a = float(np.mean(timed(lambda: plan.kappa_grad(u, v, grad=g), steps, 2, stream)))
+    ms_f = float(np.mean(timed(lambda: plan.integrate_assemble(kap, want_elem=False, Mval=Mv, Kval=Kv),
+                               steps, 2, stream)))
+    b = plan.nelem * plan.nqp * 8 + 2 * plan.ndof * 8
+    out = {"points": plan.nelem * plan.nqp, "adjoint_ms": ms_a, "forward_csr_ms": ms_f,
+           "adjoint_GB/s": b / (ms_a * 1e-3) / 1e9, "adjoint_frac_hbm": b / (ms_a * 1e-3) / HBM_PEAK,
+           "speedup_vs_forward": ms_f / ms_a}
+    log("W5: adjoint %.3f ms, forward CSR %.3f ms" % (ms_a, ms_f))
+    del kap, u, v, g, Mv, Kv, plan
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_kernel_mode(name, ig, torch, steps):
+    """Run one kernel `steps` times (no timing output) for profiler passes."""
+    if name == "copy":
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(steps):
+            b.copy_(a)
+    else:
+        h = Headline(ig, torch)
+        fn = {"element": h.element, "csr": h.csr, "headline": h.step,
+              "classical": lambda: h.element(ig.CLASSICAL)}[name]
+        for _ in range(steps):
+            fn()
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "kernel:" + name, "steps": steps}), flush=True)
 
 
 def main():
@@ -81,10 +248,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=65536,
+    ap.add_argument("--cpu-sample", type=int, default=262144,
                     help="elements of the CPU-oracle sample (0 = skip)")
-    ap.add_argument("--only-headline", action="store_true",
-                    help="time the headline step only (for profiling)")
+    ap.add_argument("--mode", default="full",
+                    help="full | headline | kernel:{element,csr,classical,headline,copy}")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -98,31 +265,24 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.mode.startswith("kernel:"):
+        run_kernel_mode(args.mode.split(":", 1)[1], ig, torch, args.steps)
+        return
     stream = torch.cuda.current_stream()
-
-    p, K = 3, (64, 64, 64)
-    knots = [W.open_uniform_knots(k, p) for k in K]
-    plan = ig.Plan(p, K, knots)
-    xs = [plan.quad_nodes(d)[0] for d in range(3)]
-    kappa = torch.from_numpy(W.kappa_sine(*xs)).cuda()
+    h = Headline(ig, torch)
+    plan = h.plan
     E, n3, nnz = plan.nelem, plan.elem_dim, plan.nnz
-    Me = torch.empty(E, n3, n3, dtype=torch.float64, device="cuda")
-    Ke = torch.empty_like(Me)
-    Mval = torch.empty(nnz, dtype=torch.float64, device="cuda")
-    Kval = torch.empty_like(Mval)
-    torch.cuda.synchronize()
     log("plan ready: E=%d nnz=%d" % (E, nnz))
 
-    def step():
-        plan.integrate_assemble(kappa, method=ig.SUMFACT, Me=Me, Ke=Ke, Mval=Mval, Kval=Kval)
-
-    ms = timed(step, args.steps, args.warmup, stream)
+    ms = timed(h.step, args.steps, args.warmup, stream)
     ms_step = float(np.mean(ms))
     log("headline: %.3f ms/step (min %.3f)" % (ms_step, min(ms)))
 
     bytes_kappa = E * plan.nqp * 8
     bytes_elem = 2 * E * n3 * n3 * 8
     bytes_csr = 2 * nnz * 8
+    step_bytes = bytes_kappa + bytes_elem + bytes_csr
+    step_flops = E * sumfact_flops(3)
     out = {
         "metric": METRIC,
         "value": E / (ms_step * 1e-3),
@@ -136,50 +296,51 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "unit cube 64^3 elements, p=3, 4-point Gauss, kappa=1+0.5sin sin sin, "
-                               "sum factorization, M_e+K_e dense + CSR M,K (95443993 nnz)",
-                   "elements": E, "degree": p, "nquad": 4, "nnz": nnz, "method": "sumfact",
+        "config": {"workload": "unit cube 64^3 elements, p=3, 4-point Gauss, kappa=1+0.5 sin sin sin; "
+                               "one igaf_integrate_assemble: dense M_e+K_e of all elements and CSR M,K "
+                               "(95443993 nnz each), sum factorization",
+                   "elements": E, "degree": 3, "nquad": 4, "nnz": nnz, "method": "sumfact",
                    "assembly": "rows"},
+        "step_roofline": {"bound": "hbm", "bytes": step_bytes, "flops": step_flops,
+                          "achieved": step_bytes / (ms_step * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                          "unit": "GB/s", "frac": step_bytes / (ms_step * 1e-3) / HBM_PEAK},
     }
-    step_bytes = bytes_kappa + bytes_elem + bytes_csr
-    out["step_roofline"] = {"bound": "hbm", "bytes": step_bytes,
-                            "achieved": step_bytes / (ms_step * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
-                            "unit": "GB/s", "frac": step_bytes / (ms_step * 1e-3) / HBM_PEAK}
-
-    if not args.only_headline:
-        # per-kernel timing of the same work: element kernel, then the CSR kernel
-        ms_el = timed(lambda: plan.element_matrices(kappa, method=ig.SUMFACT, Me=Me, Ke=Ke),
-                      args.steps, args.warmup, stream)
-        ms_csr = timed(lambda: plan.integrate_assemble(kappa, want_elem=False, Mval=Mval, Kval=Kval),
-                       args.steps, args.warmup, stream)
-        t_el = float(np.mean(ms_el)) * 1e-3
-        t_csr = float(np.mean(ms_csr)) * 1e-3
+    if args.mode == "full":
+        # the same work kernel by kernel: the element kernel (dominant) and the CSR kernel
+        ms_el = float(np.mean(timed(h.element, args.steps, args.warmup, stream)))
+        ms_csr = float(np.mean(timed(h.csr, args.steps, args.warmup, stream)))
         alg_el = bytes_kappa + bytes_elem
-        out["roofline"] = {"bound": "hbm", "achieved": alg_el / t_el / 1e9, "peak": HBM_PEAK / 1e9,
-                           "unit": "GB/s", "frac": alg_el / t_el / HBM_PEAK, "traffic": None,
-                           "kernel": "k_element<3,SUMFACT> (dense M_e, K_e store)",
-                           "ms": t_el * 1e3}
-        out["kernels"] = {
-            "element_sumfact": {"ms": t_el * 1e3, "bytes": alg_el, "GB/s": alg_el / t_el / 1e9,
-                                "frac_hbm": alg_el / t_el / HBM_PEAK,
-                                "flops": E * sumfact_flops(p)},
-            "csr_rows": {"ms": t_csr * 1e3, "bytes": bytes_kappa + bytes_csr,
-                         "GB/s": (bytes_kappa + bytes_csr) / t_csr / 1e9,
-                         "frac_hbm": (bytes_kappa + bytes_csr) / t_csr / HBM_PEAK},
-        }
-        ms_cl = timed(lambda: plan.element_matrices(kappa, method=ig.CLASSICAL, Me=Me, Ke=Ke),
-                      max(3, args.steps // 4), 1, stream)
-        t_cl = float(np.mean(ms_cl)) * 1e-3
-        out["kernels"]["element_classical"] = {"ms": t_cl * 1e3, "elements_per_s": E / t_cl}
+        traffic = traffic_for_current_kernel()
+        out["roofline"] = {"bound": "hbm", "achieved": alg_el / (ms_el * 1e-3) / 1e9,
+                           "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                           "frac": alg_el / (ms_el * 1e-3) / HBM_PEAK, "traffic": traffic,
+                           "kernel": "igaf::k_element<3,1,false> (sum factorisation, dense M_e/K_e store)",
+                           "bytes_per_launch": alg_el, "ms": ms_el}
+        ms_cl = float(np.mean(timed(lambda: h.element(ig.CLASSICAL), max(3, args.steps // 4), 1, stream)))
         plan.set_assembly(ig.ASM_ATOMIC)
-        ms_at = timed(lambda: plan.integrate_assemble(kappa, want_elem=False, Mval=Mval, Kval=Kval),
-                      max(3, args.steps // 4), 1, stream)
+        ms_at = float(np.mean(timed(h.csr, max(3, args.steps // 4), 1, stream)))
         plan.set_assembly(ig.ASM_ROWS)
-        out["kernels"]["csr_atomic"] = {"ms": float(np.mean(ms_at))}
+        csr_b = bytes_kappa + bytes_csr
+        out["kernels"] = {
+            "element_sumfact": {"ms": ms_el, "bytes": alg_el, "GB/s": alg_el / (ms_el * 1e-3) / 1e9,
+                                "frac_hbm": alg_el / (ms_el * 1e-3) / HBM_PEAK, "flops": step_flops},
+            "csr_rows": {"ms": ms_csr, "bytes": csr_b, "GB/s": csr_b / (ms_csr * 1e-3) / 1e9,
+                         "frac_hbm": csr_b / (ms_csr * 1e-3) / HBM_PEAK},
+            "element_classical": {"ms": ms_cl, "elements_per_s": E / (ms_cl * 1e-3),
+                                  "flops_8n6q3": E * 8 * 4 ** 6 * 4 ** 3,
+                                  "frac_fp64_8n6q3": E * 8 * 4 ** 6 * 4 ** 3 / (ms_cl * 1e-3) / FP64_PEAK},
+            "csr_atomic": {"ms": ms_at, "GB/s": csr_b / (ms_at * 1e-3) / 1e9},
+        }
         log(json.dumps(out["kernels"]))
-
-    del Me, Ke
-    torch.cuda.empty_cache()
+        del h
+        torch.cuda.empty_cache()
+        steps_x = max(3, args.steps // 4)
+        out["w3_streamed_128c"] = bench_w3(ig, torch, stream, steps_x)
+        out["w4_batched_256"] = bench_w4(ig, torch, stream, steps_x)
+        out["w5_adjoint_96c"] = bench_w5(ig, torch, stream, steps_x)
+    else:
+        del h
+        torch.cuda.empty_cache()
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
         log("cpu baseline: %s" % json.dumps(out["cpu_baseline"]))
