@@ -105,6 +105,20 @@ def cpu_baseline(nsample, chunk=4096):
                       "quadrature, M_e and K_e, no assembly), %.1f s" % (nsample, dt)}
 
 
+def measured_peaks(torch, stream):
+    """Write and copy bandwidth of plain torch kernels on 8 GiB / 4 GiB
+    buffers on this GPU (context for the HBM fractions)."""
+    a = torch.empty(1 << 30, dtype=torch.float64, device="cuda")
+    ms_f = min(timed(lambda: a.fill_(1.0), 5, 1, stream))
+    b = a[: 1 << 29]
+    c = a[1 << 29:]
+    ms_c = min(timed(lambda: c.copy_(b), 5, 1, stream))
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"write_GB/s": 8 * (1 << 30) / (ms_f * 1e-3) / 1e9,
+            "copy_GB/s": 2 * 8 * (1 << 29) / (ms_c * 1e-3) / 1e9}
+
+
 class Headline:
     def __init__(self, ig, torch):
         p, K = 3, (64, 64, 64)
@@ -274,9 +288,16 @@ def main():
     E, n3, nnz = plan.nelem, plan.elem_dim, plan.nnz
     log("plan ready: E=%d nnz=%d" % (E, nnz))
 
-    ms = timed(h.step, args.steps, args.warmup, stream)
+    for _ in range(args.warmup):
+        h.step()
+    plan.set_timing(True)        # HIP events around each kernel of every timed step
+    ms = timed(h.step, args.steps, 0, stream)
     ms_step = float(np.mean(ms))
-    log("headline: %.3f ms/step (min %.3f)" % (ms_step, min(ms)))
+    el_ms, el_n = plan.timing(0)
+    csr_ms, csr_n = plan.timing(1)
+    plan.set_timing(False)
+    log("headline: %.3f ms/step (min %.3f); in-step element kernel %.3f ms, CSR kernel %.3f ms"
+        % (ms_step, min(ms), el_ms, csr_ms))
 
     bytes_kappa = E * plan.nqp * 8
     bytes_elem = 2 * E * n3 * n3 * 8
@@ -305,17 +326,19 @@ def main():
                           "achieved": step_bytes / (ms_step * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
                           "unit": "GB/s", "frac": step_bytes / (ms_step * 1e-3) / HBM_PEAK},
     }
+    # roofline of the dominant kernel (the element-matrix kernel, HBM-store-bound), from
+    # its HIP-event intervals inside the timed steps (it runs beside the CSR kernel)
+    alg_el = bytes_kappa + bytes_elem
+    out["roofline"] = {"bound": "hbm", "achieved": alg_el / (el_ms * 1e-3) / 1e9,
+                       "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                       "frac": alg_el / (el_ms * 1e-3) / HBM_PEAK, "traffic": traffic_for_current_kernel(),
+                       "kernel": "igaf::k_element<3,1,false> (sum factorisation, dense M_e/K_e store)",
+                       "bytes_per_launch": alg_el, "ms": el_ms, "launches": el_n,
+                       "csr_kernel_in_step_ms": csr_ms}
     if args.mode == "full":
-        # the same work kernel by kernel: the element kernel (dominant) and the CSR kernel
+        # the same work kernel by kernel, each alone on the GPU
         ms_el = float(np.mean(timed(h.element, args.steps, args.warmup, stream)))
         ms_csr = float(np.mean(timed(h.csr, args.steps, args.warmup, stream)))
-        alg_el = bytes_kappa + bytes_elem
-        traffic = traffic_for_current_kernel()
-        out["roofline"] = {"bound": "hbm", "achieved": alg_el / (ms_el * 1e-3) / 1e9,
-                           "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                           "frac": alg_el / (ms_el * 1e-3) / HBM_PEAK, "traffic": traffic,
-                           "kernel": "igaf::k_element<3,1,false> (sum factorisation, dense M_e/K_e store)",
-                           "bytes_per_launch": alg_el, "ms": ms_el}
         ms_cl = float(np.mean(timed(lambda: h.element(ig.CLASSICAL), max(3, args.steps // 4), 1, stream)))
         plan.set_assembly(ig.ASM_ATOMIC)
         ms_at = float(np.mean(timed(h.csr, max(3, args.steps // 4), 1, stream)))
@@ -334,6 +357,8 @@ def main():
         log(json.dumps(out["kernels"]))
         del h
         torch.cuda.empty_cache()
+        out["measured_peaks"] = measured_peaks(torch, stream)
+        log("measured peaks: %s" % json.dumps(out["measured_peaks"]))
         steps_x = max(3, args.steps // 4)
         out["w3_streamed_128c"] = bench_w3(ig, torch, stream, steps_x)
         out["w4_batched_256"] = bench_w4(ig, torch, stream, steps_x)

@@ -142,6 +142,18 @@ igaf_status igaf_quad_nodes(const igaf_plan* plan, int32_t dir, double* x_host, 
  * IGAF_ASM_ROWS is deterministic. */
 igaf_status igaf_plan_set_assembly(igaf_plan* plan, int32_t mode);
 
+/* Measurement: with enable != 0, igaf_integrate_assemble records HIP timing
+ * events around each kernel it launches (element kernel on the caller's
+ * stream, CSR kernel on the stream it runs on; nothing is recorded while a
+ * stream is being captured).  Enabling or disabling waits for the device and
+ * clears the log. */
+igaf_status igaf_plan_set_timing(igaf_plan* plan, int32_t enable);
+
+/* Average duration in ms and number of logged launches of `kernel`
+ * (0 = element-matrix kernel, 1 = CSR kernel) since timing was enabled;
+ * waits for the logged events. */
+igaf_status igaf_plan_timing(igaf_plan* plan, int32_t kernel, double* avg_ms, int32_t* count);
+
 /* ---------------------------------------------------------------- device calls */
 
 /* Fill the structural CSR pattern into DEVICE arrays row_ptr[ndof+1] and

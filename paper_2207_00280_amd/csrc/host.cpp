@@ -138,7 +138,35 @@ struct igaf_plan {
     // side stream + events: the CSR kernel runs beside the element kernel
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // opt-in kernel interval log of igaf_integrate_assemble (timing events)
+    bool timing = false;
+    std::vector<hipEvent_t> tev[2];   // [element | csr]: start, end, start, end, ...
 };
+
+namespace {
+void timing_clear(igaf_plan* P)
+{
+    for (auto& v : P->tev) {
+        for (hipEvent_t e : v) (void)hipEventDestroy(e);
+        v.clear();
+    }
+}
+
+// Record one timing event of kernel `k` on stream `s` (skipped under capture).
+void timing_mark(igaf_plan* P, int k, hipStream_t s)
+{
+    if (!P->timing) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    if (hipEventRecord(e, s) != hipSuccess) {
+        (void)hipEventDestroy(e);
+        return;
+    }
+    P->tev[k].push_back(e);
+}
+}  // namespace
 
 namespace igaf {
 const PatchDev& plan_dev(const igaf_plan* p) { return p->dev; }
@@ -312,6 +340,7 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
 void igaf_plan_destroy(igaf_plan* plan)
 {
     if (!plan) return;
+    timing_clear(plan);
     if (plan->side) (void)hipStreamSynchronize(plan->side);
     if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
     if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
@@ -425,18 +454,60 @@ igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const
         if (hipEventRecord(plan->ev_fork, s) != hipSuccess ||
             hipStreamWaitEvent(plan->side, plan->ev_fork, 0) != hipSuccess)
             return fail(IGAF_EDEVICE, "stream fork failed");
+        igaf_plan* mp = const_cast<igaf_plan*>(plan);
+        timing_mark(mp, 0, s);
         igaf_status st2 = launched(launch_element(plan->dev, method, kappa, Me, Ke, nullptr, nullptr, s),
                                    "element matrices");
+        timing_mark(mp, 0, s);
+        timing_mark(mp, 1, plan->side);
         st = launched(launch_rows(plan->dev, kappa, Mval, Kval, plan->side), "row assembly");
+        timing_mark(mp, 1, plan->side);
         if (hipEventRecord(plan->ev_join, plan->side) != hipSuccess ||
             hipStreamWaitEvent(s, plan->ev_join, 0) != hipSuccess)
             return fail(IGAF_EDEVICE, "stream join failed");
         return st ? st : st2;
     }
-    if (Me || Ke)
-        return launched(launch_element(plan->dev, method, kappa, Me, Ke, nullptr, nullptr, s),
-                        "element matrices");
-    return launched(launch_rows(plan->dev, kappa, Mval, Kval, s), "row assembly");
+    igaf_plan* mp = const_cast<igaf_plan*>(plan);
+    if (Me || Ke) {
+        timing_mark(mp, 0, s);
+        st = launched(launch_element(plan->dev, method, kappa, Me, Ke, nullptr, nullptr, s),
+                      "element matrices");
+        timing_mark(mp, 0, s);
+        return st;
+    }
+    timing_mark(mp, 1, s);
+    st = launched(launch_rows(plan->dev, kappa, Mval, Kval, s), "row assembly");
+    timing_mark(mp, 1, s);
+    return st;
+}
+
+igaf_status igaf_plan_set_timing(igaf_plan* plan, int32_t enable)
+{
+    if (!plan) return fail(IGAF_EINVAL, "plan is NULL");
+    if (hipDeviceSynchronize() != hipSuccess) return fail(IGAF_EDEVICE, "device sync failed");
+    timing_clear(plan);
+    plan->timing = enable != 0;
+    return IGAF_OK;
+}
+
+igaf_status igaf_plan_timing(igaf_plan* plan, int32_t kernel, double* avg_ms, int32_t* count)
+{
+    if (!plan) return fail(IGAF_EINVAL, "plan is NULL");
+    if (kernel != 0 && kernel != 1) return fail(IGAF_EINVAL, "kernel %d not 0 or 1", kernel);
+    const auto& v = plan->tev[kernel];
+    double tot = 0.0;
+    int n = 0;
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
+        float ms = 0.f;
+        if (hipEventSynchronize(v[i + 1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, v[i], v[i + 1]) != hipSuccess)
+            return fail(IGAF_EDEVICE, "timing event query failed");
+        tot += ms;
+        ++n;
+    }
+    if (avg_ms) *avg_ms = n ? tot / n : 0.0;
+    if (count) *count = n;
+    return IGAF_OK;
 }
 
 igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double* v,

@@ -21,7 +21,7 @@ MAX_DEGREE = 5
 SYMBOLS = [
     "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_csr_pattern_host",
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes",
-    "igaf_plan_set_assembly", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
+    "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
     "igaf_integrate_assemble", "igaf_kappa_grad", "igaf_batch_create", "igaf_batch_destroy",
     "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
     "igaf_batch_integrate_assemble_separate",
@@ -67,6 +67,8 @@ def lib():
     L.igaf_plan_sizes.argtypes = [_vp] + [_i64p] * 5
     L.igaf_quad_nodes.argtypes = [_vp, ctypes.c_int32, _dp, _dp]
     L.igaf_plan_set_assembly.argtypes = [_vp, ctypes.c_int32]
+    L.igaf_plan_set_timing.argtypes = [_vp, ctypes.c_int32]
+    L.igaf_plan_timing.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _i32p]
     L.igaf_csr_pattern.argtypes = [_vp, _vp, _vp, _vp]
     L.igaf_element_matrices.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
     L.igaf_assemble.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
@@ -220,6 +222,17 @@ class Plan:
 
     def set_assembly(self, mode):
         _check(lib().igaf_plan_set_assembly(self._h, int(mode)))
+
+    def set_timing(self, enable=True):
+        """Log HIP-event intervals of every kernel igaf_integrate_assemble launches."""
+        _check(lib().igaf_plan_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self, kernel):
+        """(average ms, count) of the logged launches; kernel 0 = element, 1 = CSR."""
+        a = ctypes.c_double()
+        n = ctypes.c_int32()
+        _check(lib().igaf_plan_timing(self._h, int(kernel), ctypes.byref(a), ctypes.byref(n)))
+        return a.value, n.value
 
     def csr_pattern(self, stream=None):
         torch = _torch()
