@@ -6,118 +6,145 @@
 // gathered and interpolated to the q^3 points by sum factorisation
 // (contract a1 -> x points, a2 -> y points, a3 -> z points, each with the
 // value and the derivative table), so no element matrix is ever formed.
-// One 64-lane group per element, EPB elements per workgroup.
+//
+// One 64-lane wavefront per element (grid-stride, four independent
+// wavefronts per workgroup, synchronised only within the wavefront):
+//   stage x: lane (a2, a3, kx) gathers u, v along a1 and forms the value and
+//            x-derivative contractions,
+//   stage y: lane (kx, ky, a3) contracts a2 (value, y-derivative, and the
+//            x-derivative carried along),
+//   stage z: lane (kx, ky, kz) = quadrature point contracts a3 and writes
+//            the point's gradient entry (one contiguous q^3 run per element).
 #include "common.h"
 #include "launch.h"
 
 namespace igaf {
 
-template <int P, int EPB>
-__global__ __launch_bounds__(64 * EPB) void k_kappa_grad(PatchDev pd, const double* __restrict__ u,
-                                                        const double* __restrict__ v,
-                                                        double alphaM, double alphaK, double scale,
-                                                        double* __restrict__ grad)
+__device__ inline void adj_wave_sync()
 {
-    constexpr int n = P + 1, Q = P + 1, n3 = n * n * n, Q3 = Q * Q * Q;
-    constexpr int L = 64;
-    __shared__ double tb[EPB][3][3][n * Q];     // [elem][dir][N, dN, w (first Q)][a*Q + k]
-    __shared__ double cf[EPB][2][n3];           // u, v coefficients [a3][a2][a1]
-    __shared__ double X[EPB][2][2][n * n * Q];  // stage x: [u,v][N,dN][(a3*n + a2)*Q + kx]
-    __shared__ double Y[EPB][2][3][n * Q * Q];  // stage y: [u,v][NN, dN y, dN x][(a3*Q + ky)*Q + kx]
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-    const int g = threadIdx.x / L, lane = threadIdx.x % L;
+template <int P>
+__global__ __launch_bounds__(256) void k_kappa_grad(PatchDev pd, const double* __restrict__ u,
+                                                    const double* __restrict__ v, double alphaM,
+                                                    double alphaK, double scale,
+                                                    double* __restrict__ grad)
+{
+    constexpr int n = P + 1, Q = P + 1, Q3 = Q * Q * Q;
+    constexpr int NX = n * n * Q;     // stage-x items (a2, a3, kx)
+    constexpr int NY = n * Q * Q;     // stage-y items (kx, ky, a3)
+    __shared__ double Xs[4][4][NX];   // per wavefront: u0, u1, v0, v1 at [(a3 n + a2) Q + kx]
+    __shared__ double Ys[4][6][NY];   // per wavefront: u00, u01, u10, v00, v01, v10 at [(a3 Q + ky) Q + kx]
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
     const int Kx = pd.d[0].K, Ky = pd.d[1].K;
     const int Nx = pd.d[0].N, Ny = pd.d[1].N;
-    for (int64_t base = (int64_t)blockIdx.x * EPB; base < pd.E; base += (int64_t)gridDim.x * EPB) {
-        const int64_t e = base + g;
-        const bool live = e < pd.E;
-        const int ex = live ? (int)(e % Kx) : 0;
-        const int ey = live ? (int)((e / Kx) % Ky) : 0;
-        const int ez = live ? (int)(e / ((int64_t)Kx * Ky)) : 0;
-        if (live) {
-            for (int i = lane; i < 3 * 3 * n * Q; i += L) {
-                int d = i / (3 * n * Q), r = i % (3 * n * Q), w = r / (n * Q), j = r % (n * Q);
-                int ed = d == 0 ? ex : (d == 1 ? ey : ez);
-                double val;
-                if (w == 0) val = pd.d[d].Nv[(int64_t)ed * n * Q + j];
-                else if (w == 1) val = pd.d[d].dN[(int64_t)ed * n * Q + j];
-                else val = j < Q ? pd.d[d].wq[(int64_t)ed * Q + j] : 0.0;
-                tb[g][d][w][j] = val;
+    const double* __restrict__ Nvx = pd.d[0].Nv;
+    const double* __restrict__ dNx = pd.d[0].dN;
+    const double* __restrict__ Nvy = pd.d[1].Nv;
+    const double* __restrict__ dNy = pd.d[1].dN;
+    const double* __restrict__ Nvz = pd.d[2].Nv;
+    const double* __restrict__ dNz = pd.d[2].dN;
+    double(*X)[NX] = Xs[w];
+    double(*Y)[NY] = Ys[w];
+
+    for (int64_t e = (int64_t)blockIdx.x * 4 + w; e < pd.E; e += (int64_t)gridDim.x * 4) {
+        const int ex = (int)(e % Kx);
+        const int ey = (int)((e / Kx) % Ky);
+        const int ez = (int)(e / ((int64_t)Kx * Ky));
+        // stage x
+        for (int i0 = 0; i0 < NX; i0 += 64) {
+            const bool act = i0 + lane < NX;
+            const int i = act ? i0 + lane : NX - 1;
+            const int a2 = i % n, a3 = (i / n) % n, kx = i / (n * n);
+            const int64_t g0 = ex + (int64_t)Nx * ((ey + a2) + (int64_t)Ny * (ez + a3));
+            double su0 = 0.0, su1 = 0.0, sv0 = 0.0, sv1 = 0.0;
+#pragma unroll
+            for (int a1 = 0; a1 < n; ++a1) {
+                const double uu = u[g0 + a1], vv = v[g0 + a1];
+                const double nx = Nvx[((int64_t)ex * n + a1) * Q + kx];
+                const double dx = dNx[((int64_t)ex * n + a1) * Q + kx];
+                su0 += uu * nx;
+                su1 += uu * dx;
+                sv0 += vv * nx;
+                sv1 += vv * dx;
             }
-            for (int i = lane; i < 2 * n3; i += L) {
-                int w = i / n3, a = i % n3;
-                int a1 = a % n, a2 = (a / n) % n, a3 = a / (n * n);
-                int64_t gi = (ex + a1) + (int64_t)Nx * ((ey + a2) + (int64_t)Ny * (ez + a3));
-                cf[g][w][a] = (w ? v : u)[gi];
+            if (act) {
+                const int j = (a3 * n + a2) * Q + kx;
+                X[0][j] = su0;
+                X[1][j] = su1;
+                X[2][j] = sv0;
+                X[3][j] = sv1;
             }
         }
-        __syncthreads();
-        if (live) {
-            for (int i = lane; i < 2 * 2 * n * n * Q; i += L) {   // stage x
-                int f = i / (2 * n * n * Q), r = i % (2 * n * n * Q), w = r / (n * n * Q);
-                int j = r % (n * n * Q), kx = j % Q, a32 = j / Q;   // a32 = a3*n + a2
-                const double* t = tb[g][0][w];
-                double s = 0.0;
+        adj_wave_sync();
+        // stage y
+        for (int i0 = 0; i0 < NY; i0 += 64) {
+            const bool act = i0 + lane < NY;
+            const int i = act ? i0 + lane : NY - 1;
+            const int kx = i % Q, ky = (i / Q) % Q, a3 = i / (Q * Q);
+            double r[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int a1 = 0; a1 < n; ++a1) s += t[a1 * Q + kx] * cf[g][f][a32 * n + a1];
-                X[g][f][w][j] = s;
+            for (int a2 = 0; a2 < n; ++a2) {
+                const double ny = Nvy[((int64_t)ey * n + a2) * Q + ky];
+                const double dy = dNy[((int64_t)ey * n + a2) * Q + ky];
+                const int j = (a3 * n + a2) * Q + kx;
+                const double u0 = X[0][j], u1 = X[1][j], v0 = X[2][j], v1 = X[3][j];
+                r[0] += ny * u0;
+                r[1] += dy * u0;
+                r[2] += ny * u1;
+                r[3] += ny * v0;
+                r[4] += dy * v0;
+                r[5] += ny * v1;
+            }
+            if (act) {
+#pragma unroll
+                for (int f = 0; f < 6; ++f) Y[f][i] = r[f];
             }
         }
-        __syncthreads();
-        if (live) {
-            for (int i = lane; i < 2 * 3 * n * Q * Q; i += L) {   // stage y
-                int f = i / (3 * n * Q * Q), r = i % (3 * n * Q * Q), w = r / (n * Q * Q);
-                int j = r % (n * Q * Q), kx = j % Q, ky = (j / Q) % Q, a3 = j / (Q * Q);
-                const double* ty = tb[g][1][w == 1 ? 1 : 0];      // w: 0 NN, 1 y-derivative, 2 x-derivative
-                const double* xs = X[g][f][w == 2 ? 1 : 0];
-                double s = 0.0;
+        adj_wave_sync();
+        // stage z + combine: item = quadrature point kx + Q (ky + Q kz)
+        for (int i0 = 0; i0 < Q3; i0 += 64) {
+            const bool act = i0 + lane < Q3;
+            const int i = act ? i0 + lane : Q3 - 1;
+            const int kx = i % Q, ky = (i / Q) % Q, kz = i / (Q * Q);
+            double uh = 0.0, udx = 0.0, udy = 0.0, udz = 0.0;
+            double vh = 0.0, vdx = 0.0, vdy = 0.0, vdz = 0.0;
 #pragma unroll
-                for (int a2 = 0; a2 < n; ++a2) s += ty[a2 * Q + ky] * xs[(a3 * n + a2) * Q + kx];
-                Y[g][f][w][j] = s;
+            for (int a3 = 0; a3 < n; ++a3) {
+                const double nz = Nvz[((int64_t)ez * n + a3) * Q + kz];
+                const double dz = dNz[((int64_t)ez * n + a3) * Q + kz];
+                const int j = (a3 * Q + ky) * Q + kx;
+                uh += nz * Y[0][j];
+                udz += dz * Y[0][j];
+                udy += nz * Y[1][j];
+                udx += nz * Y[2][j];
+                vh += nz * Y[3][j];
+                vdz += dz * Y[3][j];
+                vdy += nz * Y[4][j];
+                vdx += nz * Y[5][j];
             }
+            const double wq = pd.d[0].wq[(int64_t)ex * Q + kx] * pd.d[1].wq[(int64_t)ey * Q + ky] *
+                              pd.d[2].wq[(int64_t)ez * Q + kz];
+            const double r = alphaM * uh * vh + alphaK * (udx * vdx + udy * vdy + udz * vdz);
+            if (act) grad[e * Q3 + i] = scale * wq * r;
         }
-        __syncthreads();
-        if (live) {
-            for (int i = lane; i < Q3; i += L) {                   // stage z + combine
-                int kx = i % Q, ky = (i / Q) % Q, kz = i / (Q * Q);
-                double val[2], gx[2], gy[2], gz[2];
-#pragma unroll
-                for (int f = 0; f < 2; ++f) {
-                    double s0 = 0.0, sz = 0.0, sy = 0.0, sx = 0.0;
-#pragma unroll
-                    for (int a3 = 0; a3 < n; ++a3) {
-                        double nz = tb[g][2][0][a3 * Q + kz], dz = tb[g][2][1][a3 * Q + kz];
-                        int j = (a3 * Q + ky) * Q + kx;
-                        s0 += nz * Y[g][f][0][j];
-                        sz += dz * Y[g][f][0][j];
-                        sy += nz * Y[g][f][1][j];
-                        sx += nz * Y[g][f][2][j];
-                    }
-                    val[f] = s0;
-                    gx[f] = sx;
-                    gy[f] = sy;
-                    gz[f] = sz;
-                }
-                double wq = tb[g][0][2][kx] * tb[g][1][2][ky] * tb[g][2][2][kz];
-                double r = alphaM * val[0] * val[1] + alphaK * (gx[0] * gx[1] + gy[0] * gy[1] + gz[0] * gz[1]);
-                grad[e * Q3 + i] = scale * wq * r;
-            }
-        }
-        __syncthreads();
+        adj_wave_sync();
     }
 }
 
 int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,
                       double alphaK, double scale, double* grad, hipStream_t st)
 {
-    constexpr int EPB = 4;
-    int64_t blocks = (pd.E + EPB - 1) / EPB;
-    if (blocks > 8192) blocks = 8192;
+    int64_t blocks = (pd.E + 3) / 4;
+    if (blocks > 4096) blocks = 4096;
     switch (pd.p) {
-#define IGAF_A(PP)                                                                             \
-    case PP:                                                                                   \
-        hipLaunchKernelGGL((k_kappa_grad<PP, EPB>), dim3((unsigned)blocks), dim3(64 * EPB), 0, \
-                           st, pd, u, v, alphaM, alphaK, scale, grad);                         \
+#define IGAF_A(PP)                                                                         \
+    case PP:                                                                               \
+        hipLaunchKernelGGL((k_kappa_grad<PP>), dim3((unsigned)blocks), dim3(256), 0, st, pd, u, \
+                           v, alphaM, alphaK, scale, grad);                                \
         break;
         IGAF_A(1)
         IGAF_A(2)

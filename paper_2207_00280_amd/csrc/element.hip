@@ -104,19 +104,47 @@ __global__ __launch_bounds__(kElemThreads) void k_element(PatchDev pd, RowMap rm
         }
     };
 
+    // the next element's kappa and tables are fetched into registers while
+    // the current element is computed and stored
+    constexpr int NKP = (Q3 + T - 1) / T, NTW = (6 * S * Q + T - 1) / T;
+    double pk[NKP], pt[NTW];
+    auto fetch = [&](int64_t e) {
+        const int ex = (int)(e % Kx);
+        const int ey = (int)((e / Kx) % Ky);
+        const int ez = (int)(e / ((int64_t)Kx * Ky));
+#pragma unroll
+        for (int r = 0; r < NKP; ++r) {
+            const int i = tid + r * T;
+            pk[r] = i < Q3 ? kappa[e * Q3 + i] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < NTW; ++r) {
+            const int i = tid + r * T;
+            double val = 0.0;
+            if (i < 6 * S * Q) {
+                const int d = i / (2 * S * Q), rr = i % (2 * S * Q);
+                const int which = rr / (S * Q), j = rr % (S * Q);
+                const int ed = d == 0 ? ex : (d == 1 ? ey : ez);
+                const double* src = which ? pd.d[d].Wdd : pd.d[d].Wnn;
+                val = src[(int64_t)ed * S * Q + j];
+            }
+            pt[r] = val;
+        }
+    };
+    if (blockIdx.x < pd.E) fetch(blockIdx.x);
+
     for (int64_t e = blockIdx.x; e < pd.E; e += gridDim.x) {
         const int ex = (int)(e % Kx);
         const int ey = (int)((e / Kx) % Ky);
         const int ez = (int)(e / ((int64_t)Kx * Ky));
-        for (int i = tid; i < Q3; i += T) kap[i] = kappa[e * Q3 + i];
-        for (int i = tid; i < 6 * S * Q; i += T) {
-            int d = i / (2 * S * Q), r = i % (2 * S * Q);
-            int which = r / (S * Q), j = r % (S * Q);
-            int ed = d == 0 ? ex : (d == 1 ? ey : ez);
-            const double* src = which ? pd.d[d].Wdd : pd.d[d].Wnn;
-            tw[d][which][j] = src[(int64_t)ed * S * Q + j];
-        }
+#pragma unroll
+        for (int r = 0; r < NKP; ++r)
+            if (tid + r * T < Q3) kap[tid + r * T] = pk[r];
+#pragma unroll
+        for (int r = 0; r < NTW; ++r)
+            if (tid + r * T < 6 * S * Q) (&tw[0][0][0])[tid + r * T] = pt[r];
         __syncthreads();
+        if (e + gridDim.x < pd.E) fetch(e + gridDim.x);
         if (METHOD == 1) {
             for (int i = tid; i < S * Q * Q; i += T) {       // stage z
                 int zp = i / (Q * Q), kx = (i / Q) % Q, ky = i % Q;

@@ -389,11 +389,13 @@ static int launch_rows_wave_t(const PatchDev& pd, const double* kappa, double* M
 int launch_rows(const PatchDev& pd, const double* kappa, double* Mv, double* Kv, hipStream_t st)
 {
     switch (pd.p) {
+    // launch shapes measured on MI355X: family 0 (no z-offset split); four
+    // wavefronts per workgroup up to p = 3, one above (LDS and VGPR heavy)
     case 1: return launch_rows_wave_t<1, 0, 4>(pd, kappa, Mv, Kv, st);
     case 2: return launch_rows_wave_t<2, 0, 4>(pd, kappa, Mv, Kv, st);
     case 3: return launch_rows_wave_t<3, 0, 4>(pd, kappa, Mv, Kv, st);
-    case 4: return launch_rows_wave_t<4, 1, 2>(pd, kappa, Mv, Kv, st);
-    case 5: return launch_rows_wave_t<5, 1, 2>(pd, kappa, Mv, Kv, st);
+    case 4: return launch_rows_wave_t<4, 0, 1>(pd, kappa, Mv, Kv, st);
+    case 5: return launch_rows_wave_t<5, 0, 1>(pd, kappa, Mv, Kv, st);
     default: return -4;
     }
 }
