@@ -7,8 +7,12 @@
 // (contract a1 -> x points, a2 -> y points, a3 -> z points, each with the
 // value and the derivative table), so no element matrix is ever formed.
 //
-// One 64-lane wavefront per element (grid-stride, four independent
-// wavefronts per workgroup, synchronised only within the wavefront):
+// One 64-lane wavefront per x-run of elements (fixed ey, ez; grid-stride over
+// runs, four independent wavefronts per workgroup, synchronised only within
+// the wavefront).  The run's y and z tables are cached in LDS; each stage-x
+// lane keeps a sliding window of the p+1 coefficients of u and v along x, so
+// one new value per field is loaded per element, one element ahead.  Per
+// element:
 //   stage x: lane (a2, a3, kx) gathers u, v along a1 and forms the value and
 //            x-derivative contractions,
 //   stage y: lane (kx, ky, a3) contracts a2 (value, y-derivative, and the
@@ -36,110 +40,194 @@ __global__ __launch_bounds__(256) void k_kappa_grad(PatchDev pd, const double* _
     constexpr int n = P + 1, Q = P + 1, Q3 = Q * Q * Q;
     constexpr int NX = n * n * Q;     // stage-x items (a2, a3, kx)
     constexpr int NY = n * Q * Q;     // stage-y items (kx, ky, a3)
+    constexpr int NPX = (NX + 63) / 64;
+    constexpr int TS = 4 * n * Q + 2 * Q;
     __shared__ double Xs[4][4][NX];   // per wavefront: u0, u1, v0, v1 at [(a3 n + a2) Q + kx]
     __shared__ double Ys[4][6][NY];   // per wavefront: u00, u01, u10, v00, v01, v10 at [(a3 Q + ky) Q + kx]
+    __shared__ double Ts[4][TS];      // per wavefront: N_y, N'_y, N_z, N'_z [a][k], w_y, w_z [k]
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
-    const int Kx = pd.d[0].K, Ky = pd.d[1].K;
+    const int Kx = pd.d[0].K, Ky = pd.d[1].K, Kz = pd.d[2].K;
     const int Nx = pd.d[0].N, Ny = pd.d[1].N;
     const double* __restrict__ Nvx = pd.d[0].Nv;
     const double* __restrict__ dNx = pd.d[0].dN;
-    const double* __restrict__ Nvy = pd.d[1].Nv;
-    const double* __restrict__ dNy = pd.d[1].dN;
-    const double* __restrict__ Nvz = pd.d[2].Nv;
-    const double* __restrict__ dNz = pd.d[2].dN;
+    const double* __restrict__ wqx = pd.d[0].wq;
     double(*X)[NX] = Xs[w];
     double(*Y)[NY] = Ys[w];
+    double* Tw = Ts[w];
+    constexpr int RUN = 32;                     // elements per run (a chunk of an x row)
+    const int nchunk = (Kx + RUN - 1) / RUN;
+    const int nruns = nchunk * Ky * Kz;
 
-    for (int64_t e = (int64_t)blockIdx.x * 4 + w; e < pd.E; e += (int64_t)gridDim.x * 4) {
-        const int ex = (int)(e % Kx);
-        const int ey = (int)((e / Kx) % Ky);
-        const int ez = (int)(e / ((int64_t)Kx * Ky));
-        // stage x
-        for (int i0 = 0; i0 < NX; i0 += 64) {
-            const bool act = i0 + lane < NX;
-            const int i = act ? i0 + lane : NX - 1;
-            const int a2 = i % n, a3 = (i / n) % n, kx = i / (n * n);
-            const int64_t g0 = ex + (int64_t)Nx * ((ey + a2) + (int64_t)Ny * (ez + a3));
-            double su0 = 0.0, su1 = 0.0, sv0 = 0.0, sv1 = 0.0;
+    // one run of consecutive x elements (fixed ey, ez) per wavefront
+    for (int run = blockIdx.x * 4 + w; run < nruns; run += gridDim.x * 4) {
+        const int ch = run % nchunk, ey = (run / nchunk) % Ky, ez = run / (nchunk * Ky);
+        const int ex0 = ch * RUN, ex1 = min(Kx, ex0 + RUN);
+        for (int i = lane; i < TS; i += 64) {
+            double t;
+            if (i < 4 * n * Q) {
+                const int tab = i / (n * Q), j = i % (n * Q);
+                const int d = tab < 2 ? 1 : 2, ed = tab < 2 ? ey : ez;
+                t = (tab % 2 ? pd.d[d].dN : pd.d[d].Nv)[(int64_t)ed * n * Q + j];
+            } else {
+                const int j = i - 4 * n * Q;
+                t = j < Q ? pd.d[1].wq[(int64_t)ey * Q + j] : pd.d[2].wq[(int64_t)ez * Q + j - Q];
+            }
+            Tw[i] = t;
+        }
+        // sliding windows u[g0 + ex + a1], a1 = 0..p, of every stage-x item
+        double uw[NPX][n], vw[NPX][n];
+        int64_t g0[NPX];
+#pragma unroll
+        for (int ps = 0; ps < NPX; ++ps) {
+            const int i = min(ps * 64 + lane, NX - 1);
+            const int a2 = i % n, a3 = (i / n) % n;
+            g0[ps] = (int64_t)Nx * ((ey + a2) + (int64_t)Ny * (ez + a3));
 #pragma unroll
             for (int a1 = 0; a1 < n; ++a1) {
-                const double uu = u[g0 + a1], vv = v[g0 + a1];
-                const double nx = Nvx[((int64_t)ex * n + a1) * Q + kx];
-                const double dx = dNx[((int64_t)ex * n + a1) * Q + kx];
-                su0 += uu * nx;
-                su1 += uu * dx;
-                sv0 += vv * nx;
-                sv1 += vv * dx;
-            }
-            if (act) {
-                const int j = (a3 * n + a2) * Q + kx;
-                X[0][j] = su0;
-                X[1][j] = su1;
-                X[2][j] = sv0;
-                X[3][j] = sv1;
+                uw[ps][a1] = u[g0[ps] + ex0 + a1];
+                vw[ps][a1] = v[g0[ps] + ex0 + a1];
             }
         }
-        adj_wave_sync();
-        // stage y
-        for (int i0 = 0; i0 < NY; i0 += 64) {
-            const bool act = i0 + lane < NY;
-            const int i = act ? i0 + lane : NY - 1;
-            const int kx = i % Q, ky = (i / Q) % Q, a3 = i / (Q * Q);
-            double r[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        // x tables and x weights of the current element, fetched one element ahead
+        auto fetch_x = [&](int ex, double (&tn)[NPX][n], double (&td)[NPX][n], double& tw) {
 #pragma unroll
-            for (int a2 = 0; a2 < n; ++a2) {
-                const double ny = Nvy[((int64_t)ey * n + a2) * Q + ky];
-                const double dy = dNy[((int64_t)ey * n + a2) * Q + ky];
-                const int j = (a3 * n + a2) * Q + kx;
-                const double u0 = X[0][j], u1 = X[1][j], v0 = X[2][j], v1 = X[3][j];
-                r[0] += ny * u0;
-                r[1] += dy * u0;
-                r[2] += ny * u1;
-                r[3] += ny * v0;
-                r[4] += dy * v0;
-                r[5] += ny * v1;
+            for (int ps = 0; ps < NPX; ++ps) {
+                const int i = min(ps * 64 + lane, NX - 1);
+                const int kx = i / (n * n);
+#pragma unroll
+                for (int a1 = 0; a1 < n; ++a1) {
+                    tn[ps][a1] = Nvx[((int64_t)ex * n + a1) * Q + kx];
+                    td[ps][a1] = dNx[((int64_t)ex * n + a1) * Q + kx];
+                }
             }
-            if (act) {
+            tw = wqx[(int64_t)ex * Q + lane % Q];
+        };
+        double xn[NPX][n], xd[NPX][n], xw;
+        fetch_x(ex0, xn, xd, xw);
+        adj_wave_sync();
+        for (int ex = ex0; ex < ex1; ++ex) {
+            const int64_t e = ex + (int64_t)Kx * (ey + (int64_t)Ky * ez);
+            // next window entries and next x tables, loaded one element ahead
+            double un[NPX], vn[NPX];
 #pragma unroll
-                for (int f = 0; f < 6; ++f) Y[f][i] = r[f];
+            for (int ps = 0; ps < NPX; ++ps) {
+                const int64_t gi = g0[ps] + (ex + 1 < Kx ? ex + n : ex + n - 1);
+                un[ps] = u[gi];
+                vn[ps] = v[gi];
+            }
+            double cn[NPX][n], cd[NPX][n], cw = xw;
+#pragma unroll
+            for (int ps = 0; ps < NPX; ++ps)
+#pragma unroll
+                for (int a1 = 0; a1 < n; ++a1) {
+                    cn[ps][a1] = xn[ps][a1];
+                    cd[ps][a1] = xd[ps][a1];
+                }
+            fetch_x(ex + 1 < Kx ? ex + 1 : ex, xn, xd, xw);
+            // stage x
+#pragma unroll
+            for (int ps = 0; ps < NPX; ++ps) {
+                const bool act = ps * 64 + lane < NX;
+                const int i = act ? ps * 64 + lane : NX - 1;
+                const int a2 = i % n, a3 = (i / n) % n, kx = i / (n * n);
+                double su0 = 0.0, su1 = 0.0, sv0 = 0.0, sv1 = 0.0;
+#pragma unroll
+                for (int a1 = 0; a1 < n; ++a1) {
+                    const double nx = cn[ps][a1];
+                    const double dx = cd[ps][a1];
+                    su0 += uw[ps][a1] * nx;
+                    su1 += uw[ps][a1] * dx;
+                    sv0 += vw[ps][a1] * nx;
+                    sv1 += vw[ps][a1] * dx;
+                }
+                if (act) {
+                    const int j = (a3 * n + a2) * Q + kx;
+                    X[0][j] = su0;
+                    X[1][j] = su1;
+                    X[2][j] = sv0;
+                    X[3][j] = sv1;
+                }
+            }
+            adj_wave_sync();
+            // stage y
+            for (int i0 = 0; i0 < NY; i0 += 64) {
+                const bool act = i0 + lane < NY;
+                const int i = act ? i0 + lane : NY - 1;
+                const int kx = i % Q, ky = (i / Q) % Q, a3 = i / (Q * Q);
+                double r[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int a2 = 0; a2 < n; ++a2) {
+                    const double ny = Tw[0 * n * Q + a2 * Q + ky];
+                    const double dy = Tw[1 * n * Q + a2 * Q + ky];
+                    const int j = (a3 * n + a2) * Q + kx;
+                    const double u0 = X[0][j], u1 = X[1][j], v0 = X[2][j], v1 = X[3][j];
+                    r[0] += ny * u0;
+                    r[1] += dy * u0;
+                    r[2] += ny * u1;
+                    r[3] += ny * v0;
+                    r[4] += dy * v0;
+                    r[5] += ny * v1;
+                }
+                if (act) {
+#pragma unroll
+                    for (int f = 0; f < 6; ++f) Y[f][i] = r[f];
+                }
+            }
+            adj_wave_sync();
+            // x weights of this element by lane kx: broadcast from lanes 0..Q-1
+            double wxk[Q];
+#pragma unroll
+            for (int kx = 0; kx < Q; ++kx) wxk[kx] = __shfl(cw, kx);
+            // stage z + combine: item = quadrature point kx + Q (ky + Q kz)
+            for (int i0 = 0; i0 < Q3; i0 += 64) {
+                const bool act = i0 + lane < Q3;
+                const int i = act ? i0 + lane : Q3 - 1;
+                const int kx = i % Q, ky = (i / Q) % Q, kz = i / (Q * Q);
+                double uh = 0.0, udx = 0.0, udy = 0.0, udz = 0.0;
+                double vh = 0.0, vdx = 0.0, vdy = 0.0, vdz = 0.0;
+#pragma unroll
+                for (int a3 = 0; a3 < n; ++a3) {
+                    const double nz = Tw[2 * n * Q + a3 * Q + kz];
+                    const double dz = Tw[3 * n * Q + a3 * Q + kz];
+                    const int j = (a3 * Q + ky) * Q + kx;
+                    uh += nz * Y[0][j];
+                    udz += dz * Y[0][j];
+                    udy += nz * Y[1][j];
+                    udx += nz * Y[2][j];
+                    vh += nz * Y[3][j];
+                    vdz += dz * Y[3][j];
+                    vdy += nz * Y[4][j];
+                    vdx += nz * Y[5][j];
+                }
+                double wxq = wxk[0];
+#pragma unroll
+                for (int k = 1; k < Q; ++k) wxq = kx == k ? wxk[k] : wxq;
+                const double wq = wxq * Tw[4 * n * Q + ky] * Tw[4 * n * Q + Q + kz];
+                const double r = alphaM * uh * vh + alphaK * (udx * vdx + udy * vdy + udz * vdz);
+                if (act) grad[e * Q3 + i] = scale * wq * r;
+            }
+            adj_wave_sync();
+            // slide the windows by one element
+#pragma unroll
+            for (int ps = 0; ps < NPX; ++ps) {
+#pragma unroll
+                for (int a1 = 0; a1 + 1 < n; ++a1) {
+                    uw[ps][a1] = uw[ps][a1 + 1];
+                    vw[ps][a1] = vw[ps][a1 + 1];
+                }
+                uw[ps][n - 1] = un[ps];
+                vw[ps][n - 1] = vn[ps];
             }
         }
-        adj_wave_sync();
-        // stage z + combine: item = quadrature point kx + Q (ky + Q kz)
-        for (int i0 = 0; i0 < Q3; i0 += 64) {
-            const bool act = i0 + lane < Q3;
-            const int i = act ? i0 + lane : Q3 - 1;
-            const int kx = i % Q, ky = (i / Q) % Q, kz = i / (Q * Q);
-            double uh = 0.0, udx = 0.0, udy = 0.0, udz = 0.0;
-            double vh = 0.0, vdx = 0.0, vdy = 0.0, vdz = 0.0;
-#pragma unroll
-            for (int a3 = 0; a3 < n; ++a3) {
-                const double nz = Nvz[((int64_t)ez * n + a3) * Q + kz];
-                const double dz = dNz[((int64_t)ez * n + a3) * Q + kz];
-                const int j = (a3 * Q + ky) * Q + kx;
-                uh += nz * Y[0][j];
-                udz += dz * Y[0][j];
-                udy += nz * Y[1][j];
-                udx += nz * Y[2][j];
-                vh += nz * Y[3][j];
-                vdz += dz * Y[3][j];
-                vdy += nz * Y[4][j];
-                vdx += nz * Y[5][j];
-            }
-            const double wq = pd.d[0].wq[(int64_t)ex * Q + kx] * pd.d[1].wq[(int64_t)ey * Q + ky] *
-                              pd.d[2].wq[(int64_t)ez * Q + kz];
-            const double r = alphaM * uh * vh + alphaK * (udx * vdx + udy * vdy + udz * vdz);
-            if (act) grad[e * Q3 + i] = scale * wq * r;
-        }
-        adj_wave_sync();
     }
 }
 
 int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,
                       double alphaK, double scale, double* grad, hipStream_t st)
 {
-    int64_t blocks = (pd.E + 3) / 4;
-    if (blocks > 4096) blocks = 4096;
+    const int64_t runs = (int64_t)((pd.d[0].K + 31) / 32) * pd.d[1].K * pd.d[2].K;   // runs of 32 x elements
+    int64_t blocks = (runs + 3) / 4;
+    if (blocks > 8192) blocks = 8192;
     switch (pd.p) {
 #define IGAF_A(PP)                                                                         \
     case PP:                                                                               \
