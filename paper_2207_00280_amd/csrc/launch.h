@@ -26,6 +26,11 @@ int launch_element(const PatchDev& pd, int method, const double* kappa, double* 
 int launch_rows(const PatchDev& pd, const double* kappa, double* Mval, double* Kval,
                 hipStream_t st);
 
+// The same values by tiles of row pencils per workgroup (stage z shared by
+// the pencils of a tile).
+int launch_rows_tile(const PatchDev& pd, const double* kappa, double* Mval, double* Kval,
+                     hipStream_t st);
+
 // Batched CSR rows: one persistent launch over a cost-sorted list of
 // (patch, work item) pairs; ctr[2] are device counters that start at zero and
 // are left at zero by the launch.

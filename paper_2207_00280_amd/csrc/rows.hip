@@ -128,18 +128,15 @@ __device__ __forceinline__ void rows_wave_pencil(const PatchDev& pd, const RowMa
             const int izc = iz < Nz ? iz : Nz - 1;
             const int jza = max(band_lo(izc, P), izc + OZ0 - P);   // first column z of this item
             const int sub = ((jz - jza) * Ly + (jy - band_lo(iy, P))) * Lx + (ix - P - band_lo(ix, P));
+            // ring slots of elements outside [0, Kx) hold zeros
             double ca[P + 1][Q], cb[P + 1][Q];
 #pragma unroll
             for (int e = 0; e <= P; ++e) {
-                const int ex = ix - P + e;
-                const bool ok = ex >= 0 && ex < Kx;
-                const int slot = clampi(ex, Kx - 1) % (P + 1);
+                const int slot = (ix + 1 + e) % (P + 1);   // (ix - P + e) mod (P + 1)
 #pragma unroll
                 for (int kx = 0; kx < Q; ++kx) {
-                    const double a = C[((slot * 2 + 0) * Q + kx) * NC + c];
-                    const double b = C[((slot * 2 + 1) * Q + kx) * NC + c];
-                    ca[e][kx] = ok ? a : 0.0;
-                    cb[e][kx] = ok ? b : 0.0;
+                    ca[e][kx] = C[((slot * 2 + 0) * Q + kx) * NC + c];
+                    cb[e][kx] = C[((slot * 2 + 1) * Q + kx) * NC + c];
                 }
             }
             double* stM = D + (rz * 2 + 0) * (OZC * O * O);
@@ -157,7 +154,8 @@ __device__ __forceinline__ void rows_wave_pencil(const PatchDev& pd, const RowMa
 #pragma unroll
                     for (int kx = 0; kx < Q; ++kx) {
                         m += wn[kx] * ca[e][kx];
-                        k += wd[kx] * ca[e][kx] + wn[kx] * cb[e][kx];
+                        k += wd[kx] * ca[e][kx];
+                        k += wn[kx] * cb[e][kx];
                     }
                 }
                 const int jx = ix + ox - P;
@@ -187,6 +185,12 @@ __device__ __forceinline__ void rows_wave_pencil(const PatchDev& pd, const RowMa
         wave_sync();
     };
 
+    // the C ring starts zeroed: rows ix < P read the slots of elements
+    // ix - P .. -1, which stay zero until elements 1 .. P overwrite them
+    auto zero_slots = [&](int s0, int ns) {
+        for (int i = lane; i < ns * 2 * Q * NC; i += 64) C[s0 * 2 * Q * NC + i] = 0.0;
+    };
+    zero_slots(0, P + 1);
     double czn[PREFETCH ? NP1 : 1][WZ][Q];          // next slice's kappa columns
     if (PREFETCH) {
 #pragma unroll
@@ -270,7 +274,8 @@ __device__ __forceinline__ void rows_wave_pencil(const PatchDev& pd, const RowMa
 #pragma unroll
                     for (int ky = 0; ky < Q; ++ky) {
                         ca += wn[ky] * d0[e * Q + ky];
-                        cb += wd[ky] * d0[e * Q + ky] + wn[ky] * d1[e * Q + ky];
+                        cb += wd[ky] * d0[e * Q + ky];
+                        cb += wn[ky] * d1[e * Q + ky];
                     }
                 }
                 const int c = (oy * RZ + rz) * OZC + ozl;
@@ -283,7 +288,11 @@ __device__ __forceinline__ void rows_wave_pencil(const PatchDev& pd, const RowMa
         wave_sync();
         emit_row(ex);
     }
-    for (int ix = Kx; ix < Nx; ++ix) emit_row(ix);
+    for (int ix = Kx; ix < Nx; ++ix) {
+        zero_slots(ix % (P + 1), 1);   // element ix is past the end
+        wave_sync();
+        emit_row(ix);
+    }
     wave_sync();
 }
 
@@ -352,52 +361,11 @@ __device__ __forceinline__ void rows_item(const PatchDev& pd, const RowMap& rm, 
     }
 }
 
-// Logical block index with XCD-aware order: the hardware hands workgroup b to
-// XCD b % 8, so XCD x receives the contiguous logical range [x*nb8, (x+1)*nb8)
-// and neighbouring pencils (which share kappa and tables) share one L2.
-__device__ inline int xcd_block(int b, int nb8) { return (b % 8) * nb8 + b / 8; }
-
-template <int P, int FAM, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_rows_wave(PatchDev pd, RowMap rm,
-                                                        const double* __restrict__ kappa,
-                                                        double* __restrict__ Mv,
-                                                        double* __restrict__ Kv, int nitems,
-                                                        int nb8)
-{
-    using Sh = CfgShape<P, FAM>;
-    __shared__ double lds[WPB][Sh::WAVE_LDS];
-    // wave index made provably uniform, so that item-derived addresses are scalar
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
-    const int item = xcd_block(blockIdx.x, nb8) * WPB + w;
-    if (item >= nitems) return;
-    rows_item<P, FAM>(pd, rm, kappa, Mv, Kv, item, lds[w], lane);
-}
-
-template <int P, int FAM, int WPB>
-static int launch_rows_wave_t(const PatchDev& pd, const double* kappa, double* Mv, double* Kv,
-                              hipStream_t st)
-{
-    RowMap rm = make_rowmap(pd);
-    int nitems = rows_items<P, FAM>(pd.d[1].N, pd.d[2].N);
-    int nb = (nitems + WPB - 1) / WPB;
-    int nb8 = (nb + 7) / 8;
-    hipLaunchKernelGGL((k_rows_wave<P, FAM, WPB>), dim3(nb8 * 8), dim3(64 * WPB), 0, st, pd, rm,
-                       kappa, Mv, Kv, nitems, nb8);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
-}
 
 int launch_rows(const PatchDev& pd, const double* kappa, double* Mv, double* Kv, hipStream_t st)
 {
-    switch (pd.p) {
-    // launch shapes measured on MI355X: family 0 (no z-offset split); four
-    // wavefronts per workgroup up to p = 3, one above (LDS and VGPR heavy)
-    case 1: return launch_rows_wave_t<1, 0, 4>(pd, kappa, Mv, Kv, st);
-    case 2: return launch_rows_wave_t<2, 0, 4>(pd, kappa, Mv, Kv, st);
-    case 3: return launch_rows_wave_t<3, 0, 4>(pd, kappa, Mv, Kv, st);
-    case 4: return launch_rows_wave_t<4, 0, 1>(pd, kappa, Mv, Kv, st);
-    case 5: return launch_rows_wave_t<5, 0, 1>(pd, kappa, Mv, Kv, st);
-    default: return -4;
-    }
+    // one patch: tiles of pencils per workgroup (stage z shared by a tile)
+    return launch_rows_tile(pd, kappa, Mv, Kv, st);
 }
 
 int rows_item_count(int p, int fam, int Ny, int Nz)

@@ -1,0 +1,446 @@
+// CSR values of the global mass and stiffness matrices by owner-computes rows,
+// one workgroup per tile of row pencils.
+//
+// The global matrix is the sum of the element matrices (Sec. 3.1).  Summing
+// the sum-factorised element contractions over the elements that carry a pair
+// of functions gives, for rows I = (ix,iy,iz) and columns J = I + o - p,
+//   M_IJ = sum_{gx,gy,gz} c[g] Bx(ix,jx)[gx] By(iy,jy)[gy] Bz(iz,jz)[gz]
+// where g runs over the Gauss points of the elements in the common support and
+// B(i,j)[g] = w N_i N_j is the pair table of the element holding g (the tables
+// the element kernels use).  The stiffness has the three derivative
+// placements.  The contraction runs z -> y -> x as in Algorithm 2, but over
+// global point sets, so every CSR value is summed in one thread and written
+// once, without atomics.
+//
+// A workgroup owns the row pencils (iy, iz), iy in [iy0, iy0+TY), iz in
+// [iz0, iz0+TZ), for the rows ix of one x segment.  It sweeps the x elements
+// in order; for element ex:
+//   stage z  (one wavefront group per z row iz, shared by the TY pencils):
+//            D[iz][t][oz][ey][ky][kx] = sum_{ez,kz} Wz[t] kappa   for the
+//            TY+p y elements of the tile's window (t: N N or N'N' pair table)
+//   stage y  (one wavefront group per y row iy):
+//            C[pen][0|1][kx][oy][oz] = sum_{ey,ky} Wy D  (the three products
+//            of Algorithm 2's y stage folded into two: NN.NN and N'N.NN+NN.N'N')
+//   stage x  (one thread per (pencil, oy, oz)): the thread keeps C of the last
+//            p+1 x elements in registers (a ring), and row ix = ex is then
+//            complete: its values for every ox are summed and staged in LDS
+//            at their place in the CSR row,
+//   stores   the staged rows go out as contiguous segments.
+// Stages z and y use wave-uniform tables (scalar loads); stage x's tables
+// depend on ix only.  o* in [0, 2p] are column offsets j = i + o - p.
+#include "common.h"
+#include "launch.h"
+
+namespace igaf {
+
+namespace {
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// smallest y >= x with y = r (mod 16): LDS strides that spread the lanes of a
+// wavefront over the 64-bit banks
+constexpr int pad16(int x, int r) { return x + (((r - x) % 16) + 16) % 16; }
+
+__device__ inline int opaque_zero_t()
+{
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    return z;
+}
+
+__device__ inline int clampi_t(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
+
+// Number of structural entries in the rows before row i of one direction,
+// sum_{i' < i} (min(N-1, i'+p) - max(0, i'-p) + 1), in closed form (the same
+// prefix the plan tabulates): no memory round trip on the store path.
+__device__ inline int64_t band_prefix(int i, int p, int N)
+{
+    auto tri = [](int64_t m) { return m > 0 ? m * (m + 1) / 2 : (int64_t)0; };
+    const int64_t ii = i;
+    return ii * (p + 1) + ii * (ii - 1) / 2 - tri(ii - 1 - p) - tri(ii + p - N);
+}
+
+}  // namespace
+
+template <int P_, int TY_, int TZ_, int WPE_, bool PREF_>
+struct Tile {
+    static constexpr int P = P_, TY = TY_, TZ = TZ_;
+    static constexpr int WPE = WPE_;                    // wavefronts per SIMD aimed at
+    static constexpr bool PREF = PREF_;                 // kappa of the next element in registers
+    static constexpr int Q = P + 1, O = 2 * P + 1, S = (P + 1) * (P + 2) / 2;
+    static constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
+    static constexpr int NLY = TY + P;                  // y elements in the window
+    static constexpr int NPEN = TY * TZ;                // pencils per tile
+    static constexpr int NZI = NLY * Q2, WZI = (NZI + 63) / 64;     // stage z, per z row
+    static constexpr int NYI = TZ * O * Q, WYI = (NYI + 63) / 64;   // stage y, per y row
+    static constexpr int NXI = NPEN * O * O, WX = (NXI + 63) / 64;  // stage x
+    static constexpr int NW = cmax(cmax(TZ * WZI, TY * WYI), WX);
+    static constexpr int NT = 64 * NW;
+    // D[zr][t][oz][ly][ky][kx]
+    static constexpr int DOZ = pad16(NZI, Q);
+    static constexpr int DT = O * DOZ;
+    static constexpr int DZR = pad16(2 * DT, Q * O);
+    static constexpr int DSZ = TZ * DZR;
+    // C[pen][t][kx][oy][oz]
+    static constexpr int CKX = O * O;
+    static constexpr int CT = Q * CKX;
+    static constexpr int CPEN = pad16(2 * CT, O * O);
+    static constexpr int CSZ = NPEN * CPEN;
+    // staged rows [pen][t][row position | junk slot], over the D region (dead
+    // after stage y); columns outside the patch are written to the junk slot
+    static constexpr int SROW = O * O * O + 1;
+    static constexpr int SSZ = NPEN * 2 * SROW;
+    static constexpr int R0 = cmax(DSZ, SSZ);
+    static constexpr int LDS = R0 + CSZ;                // doubles
+    static constexpr int SIT = (O * O * O + NT - 1) / NT;   // store passes per row
+    static_assert(NW <= 16, "workgroup too large");
+};
+
+// Tile shapes per degree (measured on MI355X): TY pencils share stage z; TZ
+// rows fill the lanes of stage y; the register budget (WPE wavefronts per
+// SIMD) and the LDS size let two to four workgroups share a CU.
+template <int P> struct TileCfg;
+template <> struct TileCfg<1> { using T = Tile<1, 4, 4, 4, true>; };
+template <> struct TileCfg<2> { using T = Tile<2, 4, 2, 4, true>; };
+template <> struct TileCfg<3> { using T = Tile<3, 2, 2, 4, false>; };
+template <> struct TileCfg<4> { using T = Tile<4, 3, 1, 2, true>; };
+template <> struct TileCfg<5> { using T = Tile<5, 2, 1, 2, false>; };
+
+// Logical workgroup index with XCD-aware order: the hardware hands workgroup
+// b to XCD b % 8, so XCD x receives the contiguous logical range
+// [x*nb8, (x+1)*nb8): neighbouring tiles (which share kappa) share one L2.
+__device__ inline int xcd_tile(int b, int nb8) { return (b % 8) * nb8 + b / 8; }
+
+template <class T>
+__global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE))) void k_rows_tile(PatchDev pd, RowMap rm,
+                                                     const double* __restrict__ kappa,
+                                                     double* __restrict__ Mv,
+                                                     double* __restrict__ Kv, int nty, int ntz,
+                                                     int nseg, int seglen, int nb8)
+{
+    constexpr int P = T::P, Q = T::Q, O = T::O, S = T::S, Q2 = T::Q2, Q3 = T::Q3;
+    __shared__ double lds[T::LDS];
+    double* const D = lds;
+    double* const STG = lds;
+    double* const C = lds + T::R0;
+
+    const int tid = threadIdx.x;
+    // wave index made provably uniform, so that wave-derived addresses are scalar
+    const int w = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
+    const int ntile = nty * ntz;
+    const int b = xcd_tile(blockIdx.x, nb8);
+    if (b >= ntile * nseg) return;   // whole workgroup
+    const int seg = b / ntile, tile = b % ntile;
+    const int iy0 = (tile % nty) * T::TY, iz0 = (tile / nty) * T::TZ;
+    const int Kx = pd.d[0].K, Ky = pd.d[1].K, Kz = pd.d[2].K;
+    const int Nx = pd.d[0].N, Ny = pd.d[1].N, Nz = pd.d[2].N;
+    const int X0 = seg * seglen, X1 = min(Nx, X0 + seglen);   // rows emitted
+    const int xs = max(0, X0 - P);                             // first element swept
+    const ctab Wnx = as_ctab(pd.d[0].Wnn), Wdx = as_ctab(pd.d[0].Wdd);
+    const ctab Wny = as_ctab(pd.d[1].Wnn), Wdy = as_ctab(pd.d[1].Wdd);
+    const ctab Wnz = as_ctab(pd.d[2].Wnn), Wdz = as_ctab(pd.d[2].Wdd);
+
+    // stage-x thread: pencil pen = yr*TZ + zr, row combo (oy, oz)
+    const int xi = w * 64 + lane;
+    const bool xact = xi < T::NXI;
+    const int xit = xact ? xi : T::NXI - 1;
+    const int xoz = xit % O, xoy = (xit / O) % O, xpen = xit / (O * O);
+    const int xiy = iy0 + xpen / T::TZ, xiz = iz0 + xpen % T::TZ;
+    const int xjy = xiy + xoy - P, xjz = xiz + xoz - P;
+    const bool xrow = xact && xiy < Ny && xiz < Nz && xjy >= 0 && xjy < Ny && xjz >= 0 && xjz < Nz;
+    const int xLy = band_len(min(xiy, Ny - 1), P, Ny);
+    // row position of column (jx = band_lo(ix), xjy, xjz) without the Lx factor
+    const int xsub = xrow ? (xjz - band_lo(xiz, P)) * xLy + (xjy - band_lo(xiy, P)) : 0;
+
+    // stage-z thread: z row zr, point (kx, ky) of y element ly of the window
+    const int zr = w / T::WZI;
+    const int zitem = (w % T::WZI) * 64 + lane;
+    const int zit = zitem < T::NZI ? zitem : T::NZI - 1;
+    const int zoff = zit % Q + Q * ((zit / Q) % Q);
+    const int zkey = clampi_t(iy0 - P + zit / Q2, Ky - 1);   // y elements outside are never read
+    double kpf[T::PREF ? P + 1 : 1][Q];
+    auto prefetch = [&](int ex) {
+        const double* kcol = kappa + ((int64_t)ex + (int64_t)Kx * zkey) * Q3 + zoff;
+#pragma unroll
+        for (int e = 0; e <= P; ++e) {
+            const int ezc = clampi_t(iz0 + zr - P + e, Kz - 1);
+            const double* kp = kcol + (int64_t)Kx * Ky * Q3 * ezc;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) kpf[T::PREF ? e : 0][k] = kp[Q2 * k];
+        }
+    };
+    if constexpr (T::PREF) {
+        if (w < T::TZ * T::WZI && xs < Kx) prefetch(xs);
+    }
+
+    // lane l < NPEN of every wavefront: row start of pencil l without its x
+    // part, and Ly*Lz (0 for pencils outside the patch)
+    int64_t pbase = 0;
+    int plen = 0;
+    {
+        const int pl = lane < T::NPEN ? lane : 0;
+        const int iy = iy0 + pl / T::TZ, iz = iz0 + pl % T::TZ;
+        if (lane < T::NPEN && iy < Ny && iz < Nz) {
+            const int Ly = band_len(iy, P, Ny), Lz = band_len(iz, P, Nz);
+            plen = Ly * Lz;
+            pbase = band_prefix(iz, P, Nz) * rm.T[1] * rm.T[0] + Lz * band_prefix(iy, P, Ny) * rm.T[0];
+        }
+    }
+
+    // ring of C for elements ex-P .. ex (zero outside [0, Kx)): [e][kx][NN | mixed]
+    double ring[P + 1][Q][2];
+#pragma unroll
+    for (int e = 0; e <= P; ++e)
+#pragma unroll
+        for (int k = 0; k < Q; ++k) ring[e][k][0] = ring[e][k][1] = 0.0;
+
+    // each pencil's staged row ix as one contiguous segment; all LDS reads of
+    // a pencil are issued before its stores
+    auto store_row = [&](int ix) {
+        const int Lx = band_len(ix, P, Nx);
+        const int64_t px = band_prefix(ix, P, Nx);
+#pragma unroll 1
+        for (int pen = 0; pen < T::NPEN; ++pen) {
+            const int Lyz = __builtin_amdgcn_readlane(plen, pen);
+            if (Lyz == 0) continue;   // pencil outside the patch
+            const int L = Lx * Lyz;
+            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)pbase, pen);
+            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(pbase >> 32), pen);
+            const int64_t rs = (int64_t)(((uint64_t)hi << 32) | lo) + (int64_t)Lyz * px;
+            const double* st = STG + pen * 2 * T::SROW;
+            double vm[T::SIT], vk[T::SIT];
+#pragma unroll
+            for (int j = 0; j < T::SIT; ++j) {
+                const int i = min(tid + j * T::NT, T::SROW - 1);
+                vm[j] = st[i];
+                vk[j] = st[T::SROW + i];
+            }
+#pragma unroll
+            for (int j = 0; j < T::SIT; ++j) {
+                const int i = tid + j * T::NT;
+                if (i < L) {
+                    if (Mv) Mv[rs + i] = vm[j];
+                    if (Kv) Kv[rs + i] = vk[j];
+                }
+            }
+        }
+    };
+
+    for (int ix = xs; ix < X1; ++ix) {
+        const bool elem = ix < Kx;    // element ex = ix exists
+        const bool emit = ix >= X0;   // row ix belongs to this segment
+        const int z0 = opaque_zero_t();
+        if (elem) {
+            // ---- stage z
+            if (w < T::TZ * T::WZI) {
+                const int item = zitem;
+                const bool act = item < T::NZI;
+                const int iz = iz0 + zr + z0;   // opaque: table bases are recomputed per element
+                const double* kcol = kappa + ((int64_t)ix + (int64_t)Kx * zkey) * Q3 + zoff;
+                double d0[O], d1[O];
+#pragma unroll
+                for (int o = 0; o < O; ++o) d0[o] = d1[o] = 0.0;
+                const ctab wnz = Wnz + z0, wdz = Wdz + z0;
+#pragma unroll
+                for (int e = 0; e <= P; ++e) {
+                    const int ez = iz - P + e;
+                    if (ez < 0 || ez >= Kz) continue;   // wave-uniform
+                    double kz[Q];
+                    if constexpr (T::PREF) {
+#pragma unroll
+                        for (int k = 0; k < Q; ++k) kz[k] = kpf[e][k];
+                    } else {
+                        const double* kp = kcol + (int64_t)Kx * Ky * Q3 * ez;
+#pragma unroll
+                        for (int k = 0; k < Q; ++k) kz[k] = kp[Q2 * k];
+                    }
+                    const ctab wnE = wnz + (int64_t)ez * (S * Q), wdE = wdz + (int64_t)ez * (S * Q);
+#pragma unroll
+                    for (int bb = 0; bb <= P; ++bb) {
+                        const int sp = pair_index(P - e, bb);
+                        const ctab wn = wnE + sp * Q, wd = wdE + sp * Q;   // constant offsets
+#pragma unroll
+                        for (int k = 0; k < Q; ++k) {
+                            d0[e + bb] += wn[k] * kz[k];
+                            d1[e + bb] += wd[k] * kz[k];
+                        }
+                    }
+                    // one z element's loads in flight at a time: keeps the
+                    // register budget of two workgroups per CU
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if constexpr (T::PREF) {
+                    if (ix + 1 < Kx) prefetch(ix + 1);
+                }
+                if (act) {
+                    double* dp = D + zr * T::DZR + item;
+#pragma unroll
+                    for (int o = 0; o < O; ++o) {
+                        dp[o * T::DOZ] = d0[o];
+                        dp[T::DT + o * T::DOZ] = d1[o];
+                    }
+                }
+            }
+            __syncthreads();
+            // ---- stage y
+            if (w < T::TY * T::WYI) {
+                const int yr = w / T::WYI;
+                const int iy = iy0 + yr + z0;
+                if (iy < Ny) {
+                    const int item = (w % T::WYI) * 64 + lane;
+                    const bool act = item < T::NYI;
+                    const int it = act ? item : T::NYI - 1;
+                    const int kx = it % Q, oz = (it / Q) % O, zr = it / (Q * O);
+                    double ca[O], cb[O];
+#pragma unroll
+                    for (int o = 0; o < O; ++o) ca[o] = cb[o] = 0.0;
+                    const ctab wny = Wny + z0, wdy = Wdy + z0;
+#pragma unroll
+                    for (int e = 0; e <= P; ++e) {
+                        const int ey = iy - P + e;
+                        if (ey < 0 || ey >= Ky) continue;   // wave-uniform
+                        const double* dp = D + zr * T::DZR + oz * T::DOZ + (yr + e) * Q2 + kx;
+                        double a[Q], c[Q];
+#pragma unroll
+                        for (int k = 0; k < Q; ++k) {
+                            a[k] = dp[k * Q];
+                            c[k] = dp[T::DT + k * Q];
+                        }
+                        const ctab wnE = wny + (int64_t)ey * (S * Q), wdE = wdy + (int64_t)ey * (S * Q);
+#pragma unroll
+                        for (int bb = 0; bb <= P; ++bb) {
+                            const int sp = pair_index(P - e, bb);
+                            const ctab wn = wnE + sp * Q, wd = wdE + sp * Q;
+#pragma unroll
+                            for (int k = 0; k < Q; ++k) {
+                                ca[e + bb] += wn[k] * a[k];
+                                cb[e + bb] += wd[k] * a[k];
+                                cb[e + bb] += wn[k] * c[k];
+                            }
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    if (act) {
+                        double* cp = C + (yr * T::TZ + zr) * T::CPEN + kx * T::CKX + oz;
+#pragma unroll
+                        for (int o = 0; o < O; ++o) {
+                            cp[o * O] = ca[o];
+                            cp[T::CT + o * O] = cb[o];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // ---- stage x
+        if (w < T::WX) {
+#pragma unroll
+            for (int e = 0; e < P; ++e)
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    ring[e][k][0] = ring[e + 1][k][0];
+                    ring[e][k][1] = ring[e + 1][k][1];
+                }
+            if (elem) {
+                const double* cp = C + xpen * T::CPEN + xoy * O + xoz;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    ring[P][k][0] = cp[k * T::CKX];
+                    ring[P][k][1] = cp[T::CT + k * T::CKX];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < Q; ++k) ring[P][k][0] = ring[P][k][1] = 0.0;
+            }
+        }
+        if (emit) {
+            if (w < T::WX) {
+                const int Lx = band_len(ix, P, Nx);
+                const int sub = xsub * Lx + (ix - P - band_lo(ix, P));   // + ox
+                double* stM = STG + xpen * 2 * T::SROW;
+                double m[O], k[O];
+#pragma unroll
+                for (int o = 0; o < O; ++o) m[o] = k[o] = 0.0;
+#pragma unroll
+                for (int e = 0; e <= P; ++e) {
+                    const int exc = clampi_t(ix - P + e, Kx - 1);   // ring holds zeros outside
+                    const ctab wnE = Wnx + (int64_t)exc * (S * Q), wdE = Wdx + (int64_t)exc * (S * Q);
+#pragma unroll
+                    for (int bb = 0; bb <= P; ++bb) {
+                        const int sp = pair_index(P - e, bb);
+                        const ctab wn = wnE + sp * Q, wd = wdE + sp * Q;
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) {
+                            m[e + bb] += wn[q] * ring[e][q][0];
+                            k[e + bb] += wd[q] * ring[e][q][0];
+                            k[e + bb] += wn[q] * ring[e][q][1];
+                        }
+                    }
+                }
+                // branch-free stores (a branch per column would pull the
+                // column's arithmetic, and all its table loads, apart)
+#pragma unroll
+                for (int ox = 0; ox < O; ++ox) {
+                    const int jx = ix + ox - P;
+                    const int pos = xrow && jx >= 0 && jx < Nx ? sub + ox : T::SROW - 1;
+                    stM[pos] = m[ox];
+                    stM[T::SROW + pos] = k[ox];
+                }
+            }
+            __syncthreads();
+            store_row(ix);
+            __syncthreads();   // the next stage z rewrites the staged rows
+        }
+    }
+}
+
+template <class T>
+static int launch_rows_tile_t(const PatchDev& pd, const double* kappa, double* Mv, double* Kv,
+                              hipStream_t st)
+{
+    RowMap rm = make_rowmap(pd);
+    const int Nx = pd.d[0].N, Ny = pd.d[1].N, Nz = pd.d[2].N;
+    const int nty = (Ny + T::TY - 1) / T::TY, ntz = (Nz + T::TZ - 1) / T::TZ;
+    const int ntile = nty * ntz;
+    // x segments: enough workgroups to keep every slot busy to the end, each
+    // segment paying p warm-up elements (stages z and y only)
+    static int slots = 0;
+    if (!slots) {
+        int dev = 0, ncu = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rows_tile<T>, T::NT, 0) != hipSuccess)
+            return -3;
+        slots = ncu * (per > 0 ? per : 1);
+    }
+    int nseg = 1;
+    double best = 1e300;
+    for (int s = 1; s <= 16 && (Nx + s - 1) / s >= 2 * T::P + 2; ++s) {
+        const int64_t items = (int64_t)ntile * s;
+        const double rounds = (double)((items + slots - 1) / slots);
+        const double cost = rounds * ((Nx + s - 1) / s + 0.5 * T::P);
+        if (cost < best - 1e-9) {
+            best = cost;
+            nseg = s;
+        }
+    }
+    const int seglen = (Nx + nseg - 1) / nseg;
+    const int nb = ntile * nseg, nb8 = (nb + 7) / 8;
+    hipLaunchKernelGGL(k_rows_tile<T>, dim3(nb8 * 8), dim3(T::NT), 0, st, pd, rm, kappa, Mv, Kv,
+                       nty, ntz, nseg, seglen, nb8);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_rows_tile(const PatchDev& pd, const double* kappa, double* Mv, double* Kv,
+                     hipStream_t st)
+{
+    switch (pd.p) {
+    case 1: return launch_rows_tile_t<TileCfg<1>::T>(pd, kappa, Mv, Kv, st);
+    case 2: return launch_rows_tile_t<TileCfg<2>::T>(pd, kappa, Mv, Kv, st);
+    case 3: return launch_rows_tile_t<TileCfg<3>::T>(pd, kappa, Mv, Kv, st);
+    case 4: return launch_rows_tile_t<TileCfg<4>::T>(pd, kappa, Mv, Kv, st);
+    case 5: return launch_rows_tile_t<TileCfg<5>::T>(pd, kappa, Mv, Kv, st);
+    default: return -4;
+    }
+}
+
+}  // namespace igaf
