@@ -11,7 +11,7 @@ before the timed region; inputs are synthetic (seeded).
 The same run also times, on the same GPU: the element kernel and the CSR
 kernel alone (roofline of the dominant kernel), classical quadrature, the
 atomic assembly, the 128^3 streamed workload (p = 2, 3, 4), the 256-patch
-batched persistent launch against 256 separate launches (eager and
+batched single launch against 256 separate launches (eager and
 graph-captured), and the adjoint against the plain forward assembly; and
 the CPU oracle on a bounded sample of the headline workload.
 
@@ -194,7 +194,7 @@ def bench_w4(ig, torch, stream, steps):
     with torch.cuda.graph(g, stream=s):
         B.integrate_assemble(kaps, Ms, Ks, separate=True, stream=s)
     ms_g = float(np.mean(timed(g.replay, steps, 2, torch.cuda.current_stream())))
-    # the persistent launch captured and replayed
+    # the batched launch captured and replayed
     with torch.cuda.stream(s):
         B.integrate_assemble(kaps, Ms, Ks, stream=s)
     torch.cuda.synchronize()
@@ -205,12 +205,12 @@ def bench_w4(ig, torch, stream, steps):
     info = B.info()
     out = {"patches": len(shapes), "elements": E, "nnz": nnz, "bytes": b, "flops": f,
            "roofline_ms": troof * 1e3,
-           "persistent": {"ms": ms_b, "elements_per_s": E / (ms_b * 1e-3), "frac": troof / (ms_b * 1e-3)},
-           "persistent_graph": {"ms": ms_g2, "elements_per_s": E / (ms_g2 * 1e-3)},
+           "batched": {"ms": ms_b, "elements_per_s": E / (ms_b * 1e-3), "frac": troof / (ms_b * 1e-3)},
+           "batched_graph": {"ms": ms_g2, "elements_per_s": E / (ms_g2 * 1e-3)},
            "separate_eager": {"ms": ms_s, "elements_per_s": E / (ms_s * 1e-3)},
            "separate_graph": {"ms": ms_g, "elements_per_s": E / (ms_g * 1e-3)},
-           "autotune": info, "create_s": t_create}
-    log("W4: persistent %.2f ms, graph %.2f ms, separate %.2f ms, separate graph %.2f ms (%s)"
+           "launch": info, "create_s": t_create}
+    log("W4: batched %.2f ms, graph %.2f ms, separate %.2f ms, separate graph %.2f ms (%s)"
         % (ms_b, ms_g2, ms_s, ms_g, info))
     del Ms, Ks, kaps, B, g, g2
     torch.cuda.empty_cache()

@@ -198,12 +198,11 @@ igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double
 /* ---------------------------------------------------------------- batches
  * Many independent patches (the paper's first concurrency level: parts of
  * the mesh computed concurrently) integrated and assembled to CSR (streamed
- * mode, M and K) by ONE persistent kernel launch over a cost-sorted work
- * list.  Tile shapes per degree come from an autotuner run at creation. */
+ * mode, M and K) by ONE kernel launch over one work list: one workgroup per
+ * (patch, tile of row pencils) item, items sorted longest first. */
 
-/* Build per-patch plans, the work list and the launch shape; autotunes on the
- * current device (synchronous; the choice is cached per device and set of
- * degrees).  descs: HOST array of npatch descriptions. */
+/* Build per-patch plans, the device patch table and the work list
+ * (synchronous).  descs: HOST array of npatch descriptions. */
 igaf_status igaf_batch_create(const igaf_patch_desc* descs, int32_t npatch, igaf_batch** out);
 
 /* Release a batch (NULL is ignored). */
@@ -212,14 +211,14 @@ void igaf_batch_destroy(igaf_batch* batch);
 /* The plan of patch i (owned by the batch; do not destroy). */
 const igaf_plan* igaf_batch_plan(const igaf_batch* batch, int32_t i);
 
-/* The autotuner's choice and the work list: family (0: every z column
- * offset of a row in one work item at p <= 3, 1: finer splits), persistent
- * grid (workgroups of one wavefront), number of work items.  Any output may
- * be NULL. */
+/* The launch shape: family (kind of work item; 0 = a tile of row pencils,
+ * the only kind), grid (workgroups of 256 threads launched, the item count
+ * rounded up to whole XCD chunks), number of work items.  Any output may be
+ * NULL. */
 igaf_status igaf_batch_info(const igaf_batch* batch, int32_t* family, int32_t* grid,
                             int32_t* nitems);
 
-/* One persistent launch: for every patch i, Mval[i], Kval[i] (device [nnz_i])
+/* One launch: for every patch i, Mval[i], Kval[i] (device [nnz_i])
  * are OVERWRITTEN with the assembled mass and stiffness values for kappa[i]
  * (device [E_i][q_i^3]).  kappa, Mval, Kval are HOST arrays of npatch device
  * pointers; Mval[i] / Kval[i] may be NULL to skip that matrix.  The pointer

@@ -1,15 +1,12 @@
 // Batched integration + assembly of many independent patches (the paper's
 // first concurrency level: parts of the mesh computed concurrently) in ONE
-// persistent launch.  Host side: per-patch plans, the cost-sorted work list,
-// the device patch table, and the autotuner that picks the work-item family
-// (how finely the z column offsets of a row are split) and the persistent
-// grid size by timing candidates on one representative patch per degree.
+// launch.  Host side: per-patch plans, the device patch table and the work
+// list of (patch, tile) items, sorted longest first so that the hardware's
+// in-order workgroup dispatch balances the launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
-#include <map>
-#include <mutex>
 #include <new>
 #include <vector>
 
@@ -20,19 +17,9 @@ using namespace igaf;
 
 namespace {
 
-struct Tuned {
-    int fam = 0;
-    int grid = 0;
-};
-
-std::mutex g_tune_mu;
-std::map<std::pair<int, unsigned>, Tuned> g_tune_cache;   // (device, degree mask) -> choice
-
-struct WorkList {
-    std::vector<int2> items;
-};
-
-WorkList build_items(const std::vector<igaf_plan*>& plans, int fam)
+// Every tile of every patch, longest first; stable, so that the tiles of one
+// patch stay in order (neighbouring tiles share kappa and tables in cache).
+std::vector<int2> build_items(const std::vector<igaf_plan*>& plans)
 {
     struct C {
         double cost;
@@ -41,17 +28,16 @@ WorkList build_items(const std::vector<igaf_plan*>& plans, int fam)
     std::vector<C> all;
     for (size_t i = 0; i < plans.size(); ++i) {
         const PatchDev& pd = plan_dev(plans[i]);
-        int n = rows_item_count(pd.p, fam, pd.d[1].N, pd.d[2].N);
-        double c = rows_item_cost(pd.p, fam, pd.d[0].K);
+        int n = 0;
+        double c = 0.0;
+        if (rows_tile_info(pd.p, pd.d[1].N, pd.d[2].N, pd.d[0].K, &n, &c) != 0) continue;
         for (int k = 0; k < n; ++k) all.push_back({c, make_int2((int)i, k)});
     }
-    // longest first; stable so that items of one patch stay in order (their
-    // neighbouring pencils share kappa and tables in cache)
     std::stable_sort(all.begin(), all.end(), [](const C& a, const C& b) { return a.cost > b.cost; });
-    WorkList w;
-    w.items.reserve(all.size());
-    for (auto& c : all) w.items.push_back(c.it);
-    return w;
+    std::vector<int2> items;
+    items.reserve(all.size());
+    for (auto& c : all) items.push_back(c.it);
+    return items;
 }
 
 }  // namespace
@@ -59,12 +45,10 @@ WorkList build_items(const std::vector<igaf_plan*>& plans, int fam)
 struct igaf_batch {
     std::vector<igaf_plan*> plans;
     int device = 0;
-    int fam = 0, grid = 0;
     int nitems = 0;
     BatchPatch* d_patches = nullptr;
     BatchPatch* h_patches = nullptr;   // pinned staging of the device table
     int2* d_items = nullptr;
-    int* d_ctr = nullptr;
     bool uploaded = false;
 };
 
@@ -74,7 +58,6 @@ static void batch_free(igaf_batch* B)
     if (B->d_patches) (void)hipFree(B->d_patches);
     if (B->h_patches) (void)hipHostFree(B->h_patches);
     if (B->d_items) (void)hipFree(B->d_items);
-    if (B->d_ctr) (void)hipFree(B->d_ctr);
     for (auto* p : B->plans) igaf_plan_destroy(p);
     delete B;
 }
@@ -86,115 +69,6 @@ static BatchPatch make_patch(const igaf_plan* p)
     b.pd = plan_dev(p);
     b.rm = make_rowmap(b.pd);
     return b;
-}
-
-// Install the items of `plans` for family `fam` into the device list `d_items`
-// (reallocated as needed); returns the number of items or -1.
-static int install_items(const std::vector<igaf_plan*>& plans, int fam, int2** d_items)
-{
-    WorkList w = build_items(plans, fam);
-    if (*d_items) (void)hipFree(*d_items);
-    *d_items = nullptr;
-    if (hipMalloc(d_items, sizeof(int2) * std::max<size_t>(1, w.items.size())) != hipSuccess) return -1;
-    if (hipMemcpy(*d_items, w.items.data(), sizeof(int2) * w.items.size(), hipMemcpyHostToDevice) !=
-        hipSuccess)
-        return -1;
-    return (int)w.items.size();
-}
-
-// Time the candidates on one representative (largest) patch per degree.
-static igaf_status autotune(igaf_batch* B, Tuned* out)
-{
-    unsigned mask = 0;
-    std::map<int, igaf_plan*> rep;
-    for (auto* p : B->plans) {
-        const PatchDev& pd = plan_dev(p);
-        mask |= 1u << pd.p;
-        auto it = rep.find(pd.p);
-        if (it == rep.end() || plan_dev(it->second).E < pd.E) rep[pd.p] = p;
-    }
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_cache.find({B->device, mask});
-        if (it != g_tune_cache.end()) {
-            *out = it->second;
-            return IGAF_OK;
-        }
-    }
-    int ncu = 256;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, B->device) != hipSuccess)
-        ncu = 256;
-    std::vector<igaf_plan*> mini;
-    for (auto& kv : rep) mini.push_back(kv.second);
-    // scratch inputs / outputs for the representative patches
-    std::vector<BatchPatch> hp;
-    std::vector<void*> bufs;
-    bool ok = true;
-    for (auto* p : mini) {
-        BatchPatch b = make_patch(p);
-        const PatchDev& pd = b.pd;
-        int64_t nq = (int64_t)pd.d[0].Q * pd.d[1].Q * pd.d[2].Q;
-        double *k = nullptr, *m = nullptr, *kk = nullptr;
-        ok = ok && hipMalloc(&k, sizeof(double) * pd.E * nq) == hipSuccess;
-        ok = ok && hipMalloc(&m, sizeof(double) * pd.nnz) == hipSuccess;
-        ok = ok && hipMalloc(&kk, sizeof(double) * pd.nnz) == hipSuccess;
-        bufs.push_back(k);
-        bufs.push_back(m);
-        bufs.push_back(kk);
-        if (!ok) break;
-        ok = launch_fill_zero(k, pd.E * nq, nullptr) == 0;   // any finite coefficient times the same
-        b.kappa = k;
-        b.Mv = m;
-        b.Kv = kk;
-        hp.push_back(b);
-    }
-    BatchPatch* dp = nullptr;
-    int2* di = nullptr;
-    int* ctr = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    ok = ok && hipMalloc(&dp, sizeof(BatchPatch) * hp.size()) == hipSuccess &&
-         hipMemcpy(dp, hp.data(), sizeof(BatchPatch) * hp.size(), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMalloc(&ctr, 2 * sizeof(int)) == hipSuccess && hipMemset(ctr, 0, 2 * sizeof(int)) == hipSuccess &&
-         hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
-    Tuned best;
-    float best_ms = 1e30f;
-    for (int fam = 0; ok && fam < 2; ++fam) {
-        int n = install_items(mini, fam, &di);
-        if (n < 0) {
-            ok = false;
-            break;
-        }
-        for (int wpc : {1, 2, 3, 4, 6, 8}) {
-            int grid = wpc * ncu;
-            float ms = 1e30f;
-            for (int rep = 0; rep < 3 && ok; ++rep) {
-                ok = hipEventRecord(e0, nullptr) == hipSuccess &&
-                     launch_rows_batch(fam, grid, dp, di, n, ctr, nullptr) == 0 &&
-                     hipEventRecord(e1, nullptr) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
-                float t = 0.f;
-                if (ok && hipEventElapsedTime(&t, e0, e1) == hipSuccess && rep > 0) ms = std::min(ms, t);
-            }
-            if (ok && ms < best_ms) {
-                best_ms = ms;
-                best.fam = fam;
-                best.grid = grid;
-            }
-        }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (dp) (void)hipFree(dp);
-    if (di) (void)hipFree(di);
-    if (ctr) (void)hipFree(ctr);
-    for (void* b : bufs)
-        if (b) (void)hipFree(b);
-    if (!ok || best.grid == 0) return set_error(IGAF_EDEVICE, "batch autotuning failed");
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[{B->device, mask}] = best;
-    }
-    *out = best;
-    return IGAF_OK;
 }
 
 extern "C" {
@@ -223,20 +97,14 @@ igaf_status igaf_batch_create(const igaf_patch_desc* descs, int32_t npatch, igaf
         batch_free(B);
         return set_error(IGAF_EDEVICE, "hipGetDevice failed");
     }
-    Tuned t;
-    igaf_status st = autotune(B, &t);
-    if (st) {
-        batch_free(B);
-        return st;
-    }
-    B->fam = t.fam;
-    B->grid = t.grid;
-    B->nitems = install_items(B->plans, B->fam, &B->d_items);
-    bool ok = B->nitems >= 0 &&
+    std::vector<int2> items = build_items(B->plans);
+    B->nitems = (int)items.size();
+    bool ok = hipMalloc(&B->d_items, sizeof(int2) * std::max<size_t>(1, items.size())) == hipSuccess &&
+              hipMemcpy(B->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice) ==
+                  hipSuccess &&
               hipMalloc(&B->d_patches, sizeof(BatchPatch) * npatch) == hipSuccess &&
               hipHostMalloc(&B->h_patches, sizeof(BatchPatch) * npatch, hipHostMallocDefault) == hipSuccess &&
-              hipMalloc(&B->d_ctr, 2 * sizeof(int)) == hipSuccess &&
-              hipMemset(B->d_ctr, 0, 2 * sizeof(int)) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+              hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         batch_free(B);
         return set_error(IGAF_ENOMEM, "batch device allocation failed");
@@ -262,8 +130,8 @@ const igaf_plan* igaf_batch_plan(const igaf_batch* B, int32_t i)
 igaf_status igaf_batch_info(const igaf_batch* B, int32_t* family, int32_t* grid, int32_t* nitems)
 {
     if (!B) return set_error(IGAF_EINVAL, "batch is NULL");
-    if (family) *family = B->fam;
-    if (grid) *grid = B->grid;
+    if (family) *family = 0;   // work items are tiles of row pencils
+    if (grid) *grid = rows_batch_grid(B->nitems);
     if (nitems) *nitems = B->nitems;
     return IGAF_OK;
 }
@@ -300,7 +168,7 @@ igaf_status igaf_batch_integrate_assemble(igaf_batch* B, const double* const* ka
     if (hipMemcpyAsync(B->d_patches, B->h_patches, sizeof(BatchPatch) * n, hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return set_error(IGAF_EDEVICE, "patch table upload failed");
-    if (launch_rows_batch(B->fam, B->grid, B->d_patches, B->d_items, B->nitems, B->d_ctr, s))
+    if (launch_rows_batch(B->d_patches, B->d_items, B->nitems, s))
         return set_error(IGAF_EDEVICE, "batched launch failed");
     return IGAF_OK;
 }

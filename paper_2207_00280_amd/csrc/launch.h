@@ -22,23 +22,17 @@ int launch_csr_pattern(const PatchDev& pd, int64_t* row_ptr, int32_t* col, hipSt
 int launch_element(const PatchDev& pd, int method, const double* kappa, double* Me, double* Ke,
                    double* Mval_atomic, double* Kval_atomic, hipStream_t st);
 
-// CSR values by owner-computes rows (no atomics): overwrites Mval / Kval.
+// CSR values by owner-computes rows (no atomics), one workgroup per tile of
+// row pencils: overwrites Mval / Kval.
 int launch_rows(const PatchDev& pd, const double* kappa, double* Mval, double* Kval,
                 hipStream_t st);
 
-// The same values by tiles of row pencils per workgroup (stage z shared by
-// the pencils of a tile).
-int launch_rows_tile(const PatchDev& pd, const double* kappa, double* Mval, double* Kval,
-                     hipStream_t st);
-
-// Batched CSR rows: one persistent launch over a cost-sorted list of
-// (patch, work item) pairs; ctr[2] are device counters that start at zero and
-// are left at zero by the launch.
-int launch_rows_batch(int fam, int grid, const BatchPatch* patches, const int2* items, int nitems,
-                      int* ctr, hipStream_t st);
-int rows_item_count(int p, int fam, int Ny, int Nz);
-int rows_batch_lds_bytes(int fam);
-double rows_item_cost(int p, int fam, int Kx);
+// Batched CSR rows: one workgroup per (patch, tile) item of `items`, which
+// the host sorts longest first; rows_batch_grid is the launch's workgroup
+// count, rows_tile_info the tiles of a patch and the relative cost of one.
+int launch_rows_batch(const BatchPatch* patches, const int2* items, int nitems, hipStream_t st);
+int rows_batch_grid(int nitems);
+int rows_tile_info(int p, int Ny, int Nz, int Kx, int* ntile, double* cost);
 
 // CSR values gathered from stored element matrices: overwrites Mval / Kval.
 int launch_gather(const PatchDev& pd, const double* Me, const double* Ke, double* Mval,

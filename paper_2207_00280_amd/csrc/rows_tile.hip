@@ -110,15 +110,15 @@ template <> struct TileCfg<5> { using T = Tile<5, 2, 1, 2, false>; };
 // [x*nb8, (x+1)*nb8): neighbouring tiles (which share kappa) share one L2.
 __device__ inline int xcd_tile(int b, int nb8) { return (b % 8) * nb8 + b / 8; }
 
+// One tile (pencils iy0.., iz0..) over the rows [seg*seglen, (seg+1)*seglen)
+// of a patch, by one workgroup of T::NT threads with T::LDS doubles of LDS.
 template <class T>
-__global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE))) void k_rows_tile(PatchDev pd, RowMap rm,
-                                                     const double* __restrict__ kappa,
-                                                     double* __restrict__ Mv,
-                                                     double* __restrict__ Kv, int nty, int ntz,
-                                                     int nseg, int seglen, int nb8)
+__device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
+                                         const double* __restrict__ kappa,
+                                         double* __restrict__ Mv, double* __restrict__ Kv,
+                                         int tile, int seg, int nty, int seglen, double* lds)
 {
     constexpr int P = T::P, Q = T::Q, O = T::O, S = T::S, Q2 = T::Q2, Q3 = T::Q3;
-    __shared__ double lds[T::LDS];
     double* const D = lds;
     double* const STG = lds;
     double* const C = lds + T::R0;
@@ -126,10 +126,6 @@ __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE)))
     const int tid = threadIdx.x;
     // wave index made provably uniform, so that wave-derived addresses are scalar
     const int w = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
-    const int ntile = nty * ntz;
-    const int b = xcd_tile(blockIdx.x, nb8);
-    if (b >= ntile * nseg) return;   // whole workgroup
-    const int seg = b / ntile, tile = b % ntile;
     const int iy0 = (tile % nty) * T::TY, iz0 = (tile / nty) * T::TZ;
     const int Kx = pd.d[0].K, Ky = pd.d[1].K, Kz = pd.d[2].K;
     const int Nx = pd.d[0].N, Ny = pd.d[1].N, Nz = pd.d[2].N;
@@ -394,6 +390,18 @@ __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE)))
 }
 
 template <class T>
+__global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE))) void k_rows_tile(
+    PatchDev pd, RowMap rm, const double* __restrict__ kappa, double* __restrict__ Mv,
+    double* __restrict__ Kv, int nty, int ntz, int nseg, int seglen, int nb8)
+{
+    __shared__ double lds[T::LDS];
+    const int ntile = nty * ntz;
+    const int b = xcd_tile(blockIdx.x, nb8);
+    if (b >= ntile * nseg) return;   // whole workgroup
+    tile_run<T>(pd, rm, kappa, Mv, Kv, b % ntile, b / ntile, nty, seglen, lds);
+}
+
+template <class T>
 static int launch_rows_tile_t(const PatchDev& pd, const double* kappa, double* Mv, double* Kv,
                               hipStream_t st)
 {
@@ -430,8 +438,7 @@ static int launch_rows_tile_t(const PatchDev& pd, const double* kappa, double* M
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_rows_tile(const PatchDev& pd, const double* kappa, double* Mv, double* Kv,
-                     hipStream_t st)
+int launch_rows(const PatchDev& pd, const double* kappa, double* Mv, double* Kv, hipStream_t st)
 {
     switch (pd.p) {
     case 1: return launch_rows_tile_t<TileCfg<1>::T>(pd, kappa, Mv, Kv, st);
@@ -439,6 +446,122 @@ int launch_rows_tile(const PatchDev& pd, const double* kappa, double* Mv, double
     case 3: return launch_rows_tile_t<TileCfg<3>::T>(pd, kappa, Mv, Kv, st);
     case 4: return launch_rows_tile_t<TileCfg<4>::T>(pd, kappa, Mv, Kv, st);
     case 5: return launch_rows_tile_t<TileCfg<5>::T>(pd, kappa, Mv, Kv, st);
+    default: return -4;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched launch: one workgroup per work item (patch, tile) of a list sorted
+// longest first; every degree's tile is one workgroup of 256 threads, so one
+// kernel runs any of them.  Each tile sweeps all rows of its pencils.
+
+template <int P> using TileOf = typename TileCfg<P>::T;
+static_assert(TileOf<1>::NT == 256 && TileOf<2>::NT == 256 && TileOf<3>::NT == 256 &&
+                  TileOf<4>::NT == 256 && TileOf<5>::NT == 256,
+              "the batched kernel runs every degree's tile with 256 threads");
+constexpr int kBatchLds = cmax(cmax(cmax(TileOf<1>::LDS, TileOf<2>::LDS), cmax(TileOf<3>::LDS, TileOf<4>::LDS)),
+                               TileOf<5>::LDS);
+constexpr int kBatchChunk = 16;   // consecutive work items handed to one XCD
+
+template <class Tp>
+__device__ inline Tp uniform_ptr(Tp p)
+{
+    uint64_t v = reinterpret_cast<uint64_t>(p);
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<Tp>(((uint64_t)hi << 32) | lo);
+}
+
+__device__ inline int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// the patch record in scalar registers
+__device__ inline void uniform_patch(const BatchPatch& src, PatchDev& pd, RowMap& rm,
+                                     const double*& kappa, double*& Mv, double*& Kv)
+{
+    pd = src.pd;
+    rm = src.rm;
+    for (int d = 0; d < 3; ++d) {
+        pd.d[d].Wnn = uniform_ptr(pd.d[d].Wnn);
+        pd.d[d].Wdd = uniform_ptr(pd.d[d].Wdd);
+        pd.d[d].K = uniform_int(pd.d[d].K);
+        pd.d[d].N = uniform_int(pd.d[d].N);
+        rm.T[d] = ((int64_t)uniform_int((int)(rm.T[d] >> 32)) << 32) | (uint32_t)uniform_int((int)rm.T[d]);
+    }
+    pd.p = uniform_int(pd.p);
+    kappa = uniform_ptr(src.kappa);
+    Mv = uniform_ptr(src.Mv);
+    Kv = uniform_ptr(src.Kv);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rows_tile_batch(const BatchPatch* __restrict__ patches,
+                                                         const int2* __restrict__ items, int nitems)
+{
+    __shared__ double lds[kBatchLds];
+    // XCD x (which receives workgroups b = x mod 8) takes the item chunks
+    // x, x+8, x+16, ...: neighbouring tiles share its L2, and the list stays
+    // longest-first on every XCD
+    const int x = blockIdx.x % 8, j = blockIdx.x / 8;
+    const int b = ((j / kBatchChunk) * 8 + x) * kBatchChunk + j % kBatchChunk;
+    if (b >= nitems) return;
+    const int2 it = items[b];
+    const int pid = uniform_int(it.x), tile = uniform_int(it.y);
+    PatchDev pd;
+    RowMap rm;
+    const double* kappa;
+    double *Mv, *Kv;
+    uniform_patch(patches[pid], pd, rm, kappa, Mv, Kv);
+    const int Ny = pd.d[1].N;
+    switch (pd.p) {
+#define IGAF_TB(PP)                                                                                 \
+    case PP:                                                                                        \
+        tile_run<TileOf<PP>>(pd, rm, kappa, Mv, Kv, tile, 0, (Ny + TileOf<PP>::TY - 1) / TileOf<PP>::TY, \
+                             1 << 30, lds);                                                         \
+        break;
+        IGAF_TB(1)
+        IGAF_TB(2)
+        IGAF_TB(3)
+        IGAF_TB(4)
+        IGAF_TB(5)
+#undef IGAF_TB
+    default:
+        break;
+    }
+}
+
+int launch_rows_batch(const BatchPatch* patches, const int2* items, int nitems, hipStream_t st)
+{
+    if (nitems <= 0) return 0;
+    const int grid = (nitems + 8 * kBatchChunk - 1) / (8 * kBatchChunk) * (8 * kBatchChunk);
+    hipLaunchKernelGGL(k_rows_tile_batch, dim3(grid), dim3(256), 0, st, patches, items, nitems);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int rows_batch_grid(int nitems)
+{
+    return nitems <= 0 ? 0 : (nitems + 8 * kBatchChunk - 1) / (8 * kBatchChunk) * (8 * kBatchChunk);
+}
+
+// Tiles of a degree-p patch and the relative cost of one (a whole x sweep):
+// fused-multiply-add issue slots of its wavefronts per x element, times the
+// elements swept.  Used to sort the batch longest first.
+template <class T>
+static void tile_info_t(int Ny, int Nz, int Kx, int* ntile, double* cost)
+{
+    *ntile = ((Ny + T::TY - 1) / T::TY) * ((Nz + T::TZ - 1) / T::TZ);
+    constexpr double terms = (double)(T::P + 1) * (T::P + 1) * T::Q;
+    const double per_elem = T::TZ * T::WZI * 2.0 * terms + T::TY * T::WYI * 3.0 * terms + T::WX * 3.0 * terms;
+    *cost = per_elem * (Kx + T::P);
+}
+
+int rows_tile_info(int p, int Ny, int Nz, int Kx, int* ntile, double* cost)
+{
+    switch (p) {
+    case 1: tile_info_t<TileOf<1>>(Ny, Nz, Kx, ntile, cost); return 0;
+    case 2: tile_info_t<TileOf<2>>(Ny, Nz, Kx, ntile, cost); return 0;
+    case 3: tile_info_t<TileOf<3>>(Ny, Nz, Kx, ntile, cost); return 0;
+    case 4: tile_info_t<TileOf<4>>(Ny, Nz, Kx, ntile, cost); return 0;
+    case 5: tile_info_t<TileOf<5>>(Ny, Nz, Kx, ntile, cost); return 0;
     default: return -4;
     }
 }

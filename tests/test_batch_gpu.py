@@ -1,4 +1,4 @@
-"""Batched persistent launch (igaf_batch_integrate_assemble): many independent
+"""Batched launch (igaf_batch_integrate_assemble): many independent
 patches of uneven sizes and degrees in one launch.
 
 Checked against the oracle (small patches, every CSR value), against the
@@ -57,7 +57,7 @@ def test_batch_small_vs_oracle(orc, ig):
         assert relfro(to_host(Ms[i]), Mo) <= 1e-12, i
         assert relfro(to_host(Ks[i]), Ko) <= 1e-12, i
     info = B.info()
-    assert info["family"] in (0, 1) and info["grid"] > 0 and info["nitems"] > 0
+    assert info["family"] == 0 and info["grid"] >= info["nitems"] > 0
     # mass only
     Ms2 = [torch.zeros_like(m) for m in Ms]
     B.integrate_assemble(kaps, Ms2, None)
@@ -67,7 +67,7 @@ def test_batch_small_vs_oracle(orc, ig):
 
 
 def test_batch_graph_replay(ig):
-    """The persistent launch captured in a HIP graph: three replays, with
+    """The batched launch captured in a HIP graph: three replays, with
     eager work between them, each equal to the eager result."""
     import torch
 
@@ -98,7 +98,7 @@ def test_batch_graph_replay(ig):
 
 def test_w4_batch_fullscale(orc, ig):
     """256 patches (seed 1): K_d ~ U{8..48}, p ~ U{2..5}, log-normal kappa.
-    The persistent launch equals the 256 per-patch launches value for value
+    The batched launch equals the 256 per-patch launches value for value
     (same arithmetic per value; relative Frobenius <= 1e-12 per patch), and
     complete rows of 4 patches equal the oracle's."""
     import torch
