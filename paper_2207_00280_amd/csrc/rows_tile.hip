@@ -26,6 +26,12 @@
 //            complete: its values for every ox are summed and staged in LDS
 //            at their place in the CSR row,
 //   stores   the staged rows go out as contiguous segments.
+// Two schedules run these stages.  Sequential: every wavefront takes part in
+// each stage in turn, four workgroup barriers per element.  Pipelined: stage-z/y
+// wavefronts compute element ex (kappa of ex+1 already in their registers)
+// while stage-x wavefronts finish and store row ex-1, with C double-buffered
+// and two barriers per element; the two roles run separate loops, so the
+// register ring and the kappa prefetch never share a wavefront's registers.
 // Stages z and y use wave-uniform tables (scalar loads); stage x's tables
 // depend on ix only.  o* in [0, 2p] are column offsets j = i + o - p.
 #include "common.h"
@@ -61,11 +67,12 @@ __device__ inline int64_t band_prefix(int i, int p, int N)
 
 }  // namespace
 
-template <int P_, int TY_, int TZ_, int WPE_, bool PREF_>
+template <int P_, int TY_, int TZ_, int WPE_, bool PREF_, bool PIPE_>
 struct Tile {
     static constexpr int P = P_, TY = TY_, TZ = TZ_;
     static constexpr int WPE = WPE_;                    // wavefronts per SIMD aimed at
-    static constexpr bool PREF = PREF_;                 // kappa of the next element in registers
+    static constexpr bool PREF = PREF_;                 // sequential: kappa of the next element in registers
+    static constexpr bool PIPE = PIPE_;                 // pipelined schedule
     static constexpr int Q = P + 1, O = 2 * P + 1, S = (P + 1) * (P + 2) / 2;
     static constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
     static constexpr int NLY = TY + P;                  // y elements in the window
@@ -73,8 +80,11 @@ struct Tile {
     static constexpr int NZI = NLY * Q2, WZI = (NZI + 63) / 64;     // stage z, per z row
     static constexpr int NYI = TZ * O * Q, WYI = (NYI + 63) / 64;   // stage y, per y row
     static constexpr int NXI = NPEN * O * O, WX = (NXI + 63) / 64;  // stage x
-    static constexpr int NW = cmax(cmax(TZ * WZI, TY * WYI), WX);
+    static constexpr int NWZ = TZ * WZI, NWY = TY * WYI, NWZY = cmax(NWZ, NWY);
+    static constexpr int NW = PIPE ? NWZY + WX : cmax(NWZY, WX);
     static constexpr int NT = 64 * NW;
+    static constexpr int XW0 = PIPE ? NWZY : 0;         // first stage-x wavefront
+    static constexpr int NTS = PIPE ? 64 * WX : NT;     // threads that store rows
     // D[zr][t][oz][ly][ky][kx]
     static constexpr int DOZ = pad16(NZI, Q);
     static constexpr int DT = O * DOZ;
@@ -85,13 +95,16 @@ struct Tile {
     static constexpr int CT = Q * CKX;
     static constexpr int CPEN = pad16(2 * CT, O * O);
     static constexpr int CSZ = NPEN * CPEN;
-    // staged rows [pen][t][row position | junk slot], over the D region (dead
-    // after stage y); columns outside the patch are written to the junk slot
+    // staged rows [pen][t][row position | junk slot]; columns outside the
+    // patch are written to the junk slot
     static constexpr int SROW = O * O * O + 1;
     static constexpr int SSZ = NPEN * 2 * SROW;
-    static constexpr int R0 = cmax(DSZ, SSZ);
-    static constexpr int LDS = R0 + CSZ;                // doubles
-    static constexpr int SIT = (O * O * O + NT - 1) / NT;   // store passes per row
+    static constexpr int SIT = (O * O * O + NTS - 1) / NTS;   // store passes per row
+    // LDS (doubles).  Sequential: [D | staged rows] [C]; the rows reuse D,
+    // dead after stage y.  Pipelined: [D] [C0] [C1] [staged rows].
+    static constexpr int OFF_C = PIPE ? DSZ : cmax(DSZ, SSZ);
+    static constexpr int OFF_S = PIPE ? DSZ + 2 * CSZ : 0;
+    static constexpr int LDS = PIPE ? DSZ + 2 * CSZ + SSZ : cmax(DSZ, SSZ) + CSZ;
     static_assert(NW <= 16, "workgroup too large");
 };
 
@@ -99,16 +112,306 @@ struct Tile {
 // rows fill the lanes of stage y; the register budget (WPE wavefronts per
 // SIMD) and the LDS size let two to four workgroups share a CU.
 template <int P> struct TileCfg;
-template <> struct TileCfg<1> { using T = Tile<1, 4, 4, 4, true>; };
-template <> struct TileCfg<2> { using T = Tile<2, 4, 2, 4, true>; };
-template <> struct TileCfg<3> { using T = Tile<3, 2, 2, 4, false>; };
-template <> struct TileCfg<4> { using T = Tile<4, 3, 1, 2, true>; };
-template <> struct TileCfg<5> { using T = Tile<5, 2, 1, 2, false>; };
+template <> struct TileCfg<1> { using T = Tile<1, 4, 4, 4, true, false>; };
+template <> struct TileCfg<2> { using T = Tile<2, 4, 2, 4, true, true>; };
+template <> struct TileCfg<3> { using T = Tile<3, 2, 2, 4, false, true>; };
+template <> struct TileCfg<4> { using T = Tile<4, 3, 1, 2, true, false>; };
+template <> struct TileCfg<5> { using T = Tile<5, 2, 1, 2, false, false>; };
 
-// Logical workgroup index with XCD-aware order: the hardware hands workgroup
-// b to XCD b % 8, so XCD x receives the contiguous logical range
-// [x*nb8, (x+1)*nb8): neighbouring tiles (which share kappa) share one L2.
-__device__ inline int xcd_tile(int b, int nb8) { return (b % 8) * nb8 + b / 8; }
+// The batched kernel runs every degree's tile with the same 256 threads: the
+// sequential schedule.
+template <int P> struct BatchCfg;
+template <> struct BatchCfg<1> { using T = Tile<1, 4, 4, 2, true, false>; };
+template <> struct BatchCfg<2> { using T = Tile<2, 4, 2, 2, true, false>; };
+template <> struct BatchCfg<3> { using T = Tile<3, 2, 2, 2, false, false>; };
+template <> struct BatchCfg<4> { using T = Tile<4, 3, 1, 2, true, false>; };
+template <> struct BatchCfg<5> { using T = Tile<5, 2, 1, 2, false, false>; };
+
+// Per-workgroup constants of one tile.
+struct TileCtx {
+    const double* kappa;
+    double* Mv;
+    double* Kv;
+    ctab Wnx, Wdx, Wny, Wdy, Wnz, Wdz;
+    int64_t T0, T1;   // structural entries of one direction's 1D pattern
+    int Kx, Ky, Kz, Nx, Ny, Nz;
+    int iy0, iz0;
+};
+
+// ---- stage z: thread of wavefront w (< NWZ) holds item (kx, ky, ly) of z row zr
+template <class T>
+struct ZThread {
+    int zr, item, off, key;
+    __device__ ZThread(const TileCtx& c, int w, int lane)
+    {
+        zr = w / T::WZI;
+        item = (w % T::WZI) * 64 + lane;
+        const int it = item < T::NZI ? item : T::NZI - 1;
+        off = it % T::Q + T::Q * ((it / T::Q) % T::Q);
+        key = clampi_t(c.iy0 - T::P + it / T::Q2, c.Ky - 1);   // y elements outside are never read
+    }
+};
+
+// kappa of the thread's z window for element ex: kw[e][kz], e = 0..P
+template <class T>
+__device__ __forceinline__ void z_load(const TileCtx& c, const ZThread<T>& zt, int ex,
+                                       double (&kw)[T::P + 1][T::Q])
+{
+    constexpr int P = T::P, Q = T::Q, Q2 = T::Q2, Q3 = T::Q3;
+    const double* kcol = c.kappa + ((int64_t)ex + (int64_t)c.Kx * zt.key) * Q3 + zt.off;
+#pragma unroll
+    for (int e = 0; e <= P; ++e) {
+        const int ezc = clampi_t(c.iz0 + zt.zr - P + e, c.Kz - 1);
+        const double* kp = kcol + (int64_t)c.Kx * c.Ky * Q3 * ezc;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) kw[e][k] = kp[Q2 * k];
+    }
+}
+
+// D for element ex.  FROM_REGS: kappa from kw; otherwise loaded here, one z
+// element at a time (keeps the register budget of the sequential schedule).
+template <class T, bool FROM_REGS>
+__device__ __forceinline__ void z_stage(const TileCtx& c, const ZThread<T>& zt, int ex,
+                                        const double (&kw)[T::P + 1][T::Q], double* D, int z0)
+{
+    constexpr int P = T::P, Q = T::Q, O = T::O, S = T::S, Q2 = T::Q2, Q3 = T::Q3;
+    const int iz = c.iz0 + zt.zr + z0;   // opaque: table bases are recomputed per element
+    const double* kcol = c.kappa + ((int64_t)ex + (int64_t)c.Kx * zt.key) * Q3 + zt.off;
+    double d0[O], d1[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o) d0[o] = d1[o] = 0.0;
+    const ctab wnz = c.Wnz + z0, wdz = c.Wdz + z0;
+#pragma unroll
+    for (int e = 0; e <= P; ++e) {
+        const int ez = iz - P + e;
+        if (ez < 0 || ez >= c.Kz) continue;   // wave-uniform
+        double kz[Q];
+        if constexpr (FROM_REGS) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) kz[k] = kw[e][k];
+        } else {
+            const double* kp = kcol + (int64_t)c.Kx * c.Ky * Q3 * ez;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) kz[k] = kp[Q2 * k];
+        }
+        const ctab wnE = wnz + (int64_t)ez * (S * Q), wdE = wdz + (int64_t)ez * (S * Q);
+#pragma unroll
+        for (int bb = 0; bb <= P; ++bb) {
+            const int sp = pair_index(P - e, bb);
+            const ctab wn = wnE + sp * Q, wd = wdE + sp * Q;   // constant offsets
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                d0[e + bb] += wn[k] * kz[k];
+                d1[e + bb] += wd[k] * kz[k];
+            }
+        }
+        if constexpr (!FROM_REGS) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (zt.item < T::NZI) {
+        double* dp = D + zt.zr * T::DZR + zt.item;
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+            dp[o * T::DOZ] = d0[o];
+            dp[T::DT + o * T::DOZ] = d1[o];
+        }
+    }
+}
+
+// ---- stage y for wavefront w (< NWY): C of the y row w / WYI
+template <class T>
+__device__ __forceinline__ void y_stage(const TileCtx& c, int w, int lane, const double* D, double* C,
+                                        int z0)
+{
+    constexpr int P = T::P, Q = T::Q, O = T::O, S = T::S, Q2 = T::Q2;
+    const int yr = w / T::WYI;
+    const int iy = c.iy0 + yr + z0;
+    if (iy >= c.Ny) return;   // wave-uniform
+    const int item = (w % T::WYI) * 64 + lane;
+    const bool act = item < T::NYI;
+    const int it = act ? item : T::NYI - 1;
+    const int kx = it % Q, oz = (it / Q) % O, zr = it / (Q * O);
+    double ca[O], cb[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o) ca[o] = cb[o] = 0.0;
+    const ctab wny = c.Wny + z0, wdy = c.Wdy + z0;
+#pragma unroll
+    for (int e = 0; e <= P; ++e) {
+        const int ey = iy - P + e;
+        if (ey < 0 || ey >= c.Ky) continue;   // wave-uniform
+        const double* dp = D + zr * T::DZR + oz * T::DOZ + (yr + e) * Q2 + kx;
+        double a[Q], b[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            a[k] = dp[k * Q];
+            b[k] = dp[T::DT + k * Q];
+        }
+        const ctab wnE = wny + (int64_t)ey * (S * Q), wdE = wdy + (int64_t)ey * (S * Q);
+#pragma unroll
+        for (int bb = 0; bb <= P; ++bb) {
+            const int sp = pair_index(P - e, bb);
+            const ctab wn = wnE + sp * Q, wd = wdE + sp * Q;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                ca[e + bb] += wn[k] * a[k];
+                cb[e + bb] += wd[k] * a[k];
+                cb[e + bb] += wn[k] * b[k];
+            }
+        }
+        // sequential schedule: one y element's reads in flight at a time, for
+        // the register budget (the pipelined stage-y wavefronts hold no ring)
+        if constexpr (!T::PIPE) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (act) {
+        double* cp = C + (yr * T::TZ + zr) * T::CPEN + kx * T::CKX + oz;
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+            cp[o * O] = ca[o];
+            cp[T::CT + o * O] = cb[o];
+        }
+    }
+}
+
+// ---- stage x: thread xi = (stage-x wavefront)*64 + lane owns combo (pen, oy, oz)
+template <class T>
+struct XThread {
+    int pen, oy, oz, sub;
+    bool row;
+    __device__ XThread(const TileCtx& c, int xi)
+    {
+        constexpr int P = T::P, O = T::O;
+        const bool act = xi < T::NXI;
+        const int it = act ? xi : T::NXI - 1;
+        oz = it % O;
+        oy = (it / O) % O;
+        pen = it / (O * O);
+        const int iy = c.iy0 + pen / T::TZ, iz = c.iz0 + pen % T::TZ;
+        const int jy = iy + oy - P, jz = iz + oz - P;
+        row = act && iy < c.Ny && iz < c.Nz && jy >= 0 && jy < c.Ny && jz >= 0 && jz < c.Nz;
+        const int Ly = band_len(min(iy, c.Ny - 1), P, c.Ny);
+        // row position of column (jx = band_lo(ix), jy, jz) without the Lx factor
+        sub = row ? (jz - band_lo(iz, P)) * Ly + (jy - band_lo(iy, P)) : 0;
+    }
+};
+
+// ring: C of elements ex-P .. ex (zero outside [0, Kx)) as [e][kx][NN | mixed];
+// shift in the next element's C (null: an element past the end)
+template <class T>
+__device__ __forceinline__ void x_shift(const XThread<T>& xt, double (&ring)[T::P + 1][T::Q][2],
+                                        const double* C)
+{
+    constexpr int P = T::P, Q = T::Q, O = T::O;
+#pragma unroll
+    for (int e = 0; e < P; ++e)
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            ring[e][k][0] = ring[e + 1][k][0];
+            ring[e][k][1] = ring[e + 1][k][1];
+        }
+    if (C) {
+        const double* cp = C + xt.pen * T::CPEN + xt.oy * O + xt.oz;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            ring[P][k][0] = cp[k * T::CKX];
+            ring[P][k][1] = cp[T::CT + k * T::CKX];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) ring[P][k][0] = ring[P][k][1] = 0.0;
+    }
+}
+
+// row ix: every ox of the thread's (oy, oz), staged at its row position
+template <class T>
+__device__ __forceinline__ void x_row(const TileCtx& c, const XThread<T>& xt,
+                                      const double (&ring)[T::P + 1][T::Q][2], int ix, double* STG)
+{
+    constexpr int P = T::P, Q = T::Q, O = T::O, S = T::S;
+    const int Lx = band_len(ix, P, c.Nx);
+    const int sub = xt.sub * Lx + (ix - P - band_lo(ix, P));   // + ox
+    double* stM = STG + xt.pen * 2 * T::SROW;
+    double m[O], k[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o) m[o] = k[o] = 0.0;
+#pragma unroll
+    for (int e = 0; e <= P; ++e) {
+        const int exc = clampi_t(ix - P + e, c.Kx - 1);   // the ring holds zeros outside
+        const ctab wnE = c.Wnx + (int64_t)exc * (S * Q), wdE = c.Wdx + (int64_t)exc * (S * Q);
+#pragma unroll
+        for (int bb = 0; bb <= P; ++bb) {
+            const int sp = pair_index(P - e, bb);
+            const ctab wn = wnE + sp * Q, wd = wdE + sp * Q;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                m[e + bb] += wn[q] * ring[e][q][0];
+                k[e + bb] += wd[q] * ring[e][q][0];
+                k[e + bb] += wn[q] * ring[e][q][1];
+            }
+        }
+    }
+    // branch-free stores (a branch per column would pull the column's
+    // arithmetic, and all its table loads, apart)
+#pragma unroll
+    for (int ox = 0; ox < O; ++ox) {
+        const int jx = ix + ox - P;
+        const int pos = xt.row && jx >= 0 && jx < c.Nx ? sub + ox : T::SROW - 1;
+        stM[pos] = m[ox];
+        stM[T::SROW + pos] = k[ox];
+    }
+}
+
+// Row-start parts of pencil `lane` (lanes < NPEN): the row start without its
+// x part, and Ly*Lz (0 for pencils outside the patch).
+template <class T>
+__device__ __forceinline__ void pencil_rows(const TileCtx& c, int lane, int64_t& pbase, int& plen)
+{
+    constexpr int P = T::P;
+    pbase = 0;
+    plen = 0;
+    const int pl = lane < T::NPEN ? lane : 0;
+    const int iy = c.iy0 + pl / T::TZ, iz = c.iz0 + pl % T::TZ;
+    if (lane < T::NPEN && iy < c.Ny && iz < c.Nz) {
+        const int Ly = band_len(iy, P, c.Ny), Lz = band_len(iz, P, c.Nz);
+        plen = Ly * Lz;
+        pbase = band_prefix(iz, P, c.Nz) * c.T1 * c.T0 + Lz * band_prefix(iy, P, c.Ny) * c.T0;
+    }
+}
+
+// Each pencil's staged row ix as one contiguous segment, by the NTS storing
+// threads (ts = 0..NTS-1); all LDS reads of a pencil are issued before its
+// stores.
+template <class T>
+__device__ __forceinline__ void store_row(const TileCtx& c, const double* STG, int ix, int ts,
+                                          int64_t pbase, int plen)
+{
+    constexpr int P = T::P;
+    const int Lx = band_len(ix, P, c.Nx);
+    const int64_t px = band_prefix(ix, P, c.Nx);
+#pragma unroll 1
+    for (int pen = 0; pen < T::NPEN; ++pen) {
+        const int Lyz = __builtin_amdgcn_readlane(plen, pen);
+        if (Lyz == 0) continue;   // pencil outside the patch
+        const int L = Lx * Lyz;
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)pbase, pen);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(pbase >> 32), pen);
+        const int64_t rs = (int64_t)(((uint64_t)hi << 32) | lo) + (int64_t)Lyz * px;
+        const double* st = STG + pen * 2 * T::SROW;
+        double vm[T::SIT], vk[T::SIT];
+#pragma unroll
+        for (int j = 0; j < T::SIT; ++j) {
+            const int i = min(ts + j * T::NTS, T::SROW - 1);
+            vm[j] = st[i];
+            vk[j] = st[T::SROW + i];
+        }
+#pragma unroll
+        for (int j = 0; j < T::SIT; ++j) {
+            const int i = ts + j * T::NTS;
+            if (i < L) {
+                if (c.Mv) c.Mv[rs + i] = vm[j];
+                if (c.Kv) c.Kv[rs + i] = vk[j];
+            }
+        }
+    }
+}
 
 // One tile (pencils iy0.., iz0..) over the rows [seg*seglen, (seg+1)*seglen)
 // of a patch, by one workgroup of T::NT threads with T::LDS doubles of LDS.
@@ -118,276 +421,126 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
                                          double* __restrict__ Mv, double* __restrict__ Kv,
                                          int tile, int seg, int nty, int seglen, double* lds)
 {
-    constexpr int P = T::P, Q = T::Q, O = T::O, S = T::S, Q2 = T::Q2, Q3 = T::Q3;
-    double* const D = lds;
-    double* const STG = lds;
-    double* const C = lds + T::R0;
+    constexpr int P = T::P, Q = T::Q;
+    TileCtx c;
+    c.kappa = kappa;
+    c.Mv = Mv;
+    c.Kv = Kv;
+    c.Wnx = as_ctab(pd.d[0].Wnn);
+    c.Wdx = as_ctab(pd.d[0].Wdd);
+    c.Wny = as_ctab(pd.d[1].Wnn);
+    c.Wdy = as_ctab(pd.d[1].Wdd);
+    c.Wnz = as_ctab(pd.d[2].Wnn);
+    c.Wdz = as_ctab(pd.d[2].Wdd);
+    c.T0 = rm.T[0];
+    c.T1 = rm.T[1];
+    c.Kx = pd.d[0].K;
+    c.Ky = pd.d[1].K;
+    c.Kz = pd.d[2].K;
+    c.Nx = pd.d[0].N;
+    c.Ny = pd.d[1].N;
+    c.Nz = pd.d[2].N;
+    c.iy0 = (tile % nty) * T::TY;
+    c.iz0 = (tile / nty) * T::TZ;
+    const int X0 = seg * seglen, X1 = min(c.Nx, X0 + seglen);   // rows emitted
+    const int xs = max(0, X0 - P);                               // first element swept
 
     const int tid = threadIdx.x;
     // wave index made provably uniform, so that wave-derived addresses are scalar
     const int w = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
-    const int iy0 = (tile % nty) * T::TY, iz0 = (tile / nty) * T::TZ;
-    const int Kx = pd.d[0].K, Ky = pd.d[1].K, Kz = pd.d[2].K;
-    const int Nx = pd.d[0].N, Ny = pd.d[1].N, Nz = pd.d[2].N;
-    const int X0 = seg * seglen, X1 = min(Nx, X0 + seglen);   // rows emitted
-    const int xs = max(0, X0 - P);                             // first element swept
-    const ctab Wnx = as_ctab(pd.d[0].Wnn), Wdx = as_ctab(pd.d[0].Wdd);
-    const ctab Wny = as_ctab(pd.d[1].Wnn), Wdy = as_ctab(pd.d[1].Wdd);
-    const ctab Wnz = as_ctab(pd.d[2].Wnn), Wdz = as_ctab(pd.d[2].Wdd);
+    double* const D = lds;
+    double* const C0 = lds + T::OFF_C;
+    double* const STG = lds + T::OFF_S;
 
-    // stage-x thread: pencil pen = yr*TZ + zr, row combo (oy, oz)
-    const int xi = w * 64 + lane;
-    const bool xact = xi < T::NXI;
-    const int xit = xact ? xi : T::NXI - 1;
-    const int xoz = xit % O, xoy = (xit / O) % O, xpen = xit / (O * O);
-    const int xiy = iy0 + xpen / T::TZ, xiz = iz0 + xpen % T::TZ;
-    const int xjy = xiy + xoy - P, xjz = xiz + xoz - P;
-    const bool xrow = xact && xiy < Ny && xiz < Nz && xjy >= 0 && xjy < Ny && xjz >= 0 && xjz < Nz;
-    const int xLy = band_len(min(xiy, Ny - 1), P, Ny);
-    // row position of column (jx = band_lo(ix), xjy, xjz) without the Lx factor
-    const int xsub = xrow ? (xjz - band_lo(xiz, P)) * xLy + (xjy - band_lo(xiy, P)) : 0;
-
-    // stage-z thread: z row zr, point (kx, ky) of y element ly of the window
-    const int zr = w / T::WZI;
-    const int zitem = (w % T::WZI) * 64 + lane;
-    const int zit = zitem < T::NZI ? zitem : T::NZI - 1;
-    const int zoff = zit % Q + Q * ((zit / Q) % Q);
-    const int zkey = clampi_t(iy0 - P + zit / Q2, Ky - 1);   // y elements outside are never read
-    double kpf[T::PREF ? P + 1 : 1][Q];
-    auto prefetch = [&](int ex) {
-        const double* kcol = kappa + ((int64_t)ex + (int64_t)Kx * zkey) * Q3 + zoff;
-#pragma unroll
-        for (int e = 0; e <= P; ++e) {
-            const int ezc = clampi_t(iz0 + zr - P + e, Kz - 1);
-            const double* kp = kcol + (int64_t)Kx * Ky * Q3 * ezc;
-#pragma unroll
-            for (int k = 0; k < Q; ++k) kpf[T::PREF ? e : 0][k] = kp[Q2 * k];
+    if constexpr (!T::PIPE) {
+        const ZThread<T> zt(c, w, lane);
+        double kw[P + 1][Q];
+        if constexpr (T::PREF) {
+            if (w < T::NWZ && xs < c.Kx) z_load<T>(c, zt, xs, kw);
         }
-    };
-    if constexpr (T::PREF) {
-        if (w < T::TZ * T::WZI && xs < Kx) prefetch(xs);
-    }
+        const XThread<T> xt(c, w * 64 + lane);
+        int64_t pbase;
+        int plen;
+        pencil_rows<T>(c, lane, pbase, plen);
+        double ring[P + 1][Q][2];
+#pragma unroll
+        for (int e = 0; e <= P; ++e)
+#pragma unroll
+            for (int k = 0; k < Q; ++k) ring[e][k][0] = ring[e][k][1] = 0.0;
 
-    // lane l < NPEN of every wavefront: row start of pencil l without its x
-    // part, and Ly*Lz (0 for pencils outside the patch)
-    int64_t pbase = 0;
-    int plen = 0;
-    {
-        const int pl = lane < T::NPEN ? lane : 0;
-        const int iy = iy0 + pl / T::TZ, iz = iz0 + pl % T::TZ;
-        if (lane < T::NPEN && iy < Ny && iz < Nz) {
-            const int Ly = band_len(iy, P, Ny), Lz = band_len(iz, P, Nz);
-            plen = Ly * Lz;
-            pbase = band_prefix(iz, P, Nz) * rm.T[1] * rm.T[0] + Lz * band_prefix(iy, P, Ny) * rm.T[0];
-        }
-    }
-
-    // ring of C for elements ex-P .. ex (zero outside [0, Kx)): [e][kx][NN | mixed]
-    double ring[P + 1][Q][2];
-#pragma unroll
-    for (int e = 0; e <= P; ++e)
-#pragma unroll
-        for (int k = 0; k < Q; ++k) ring[e][k][0] = ring[e][k][1] = 0.0;
-
-    // each pencil's staged row ix as one contiguous segment; all LDS reads of
-    // a pencil are issued before its stores
-    auto store_row = [&](int ix) {
-        const int Lx = band_len(ix, P, Nx);
-        const int64_t px = band_prefix(ix, P, Nx);
-#pragma unroll 1
-        for (int pen = 0; pen < T::NPEN; ++pen) {
-            const int Lyz = __builtin_amdgcn_readlane(plen, pen);
-            if (Lyz == 0) continue;   // pencil outside the patch
-            const int L = Lx * Lyz;
-            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)pbase, pen);
-            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(pbase >> 32), pen);
-            const int64_t rs = (int64_t)(((uint64_t)hi << 32) | lo) + (int64_t)Lyz * px;
-            const double* st = STG + pen * 2 * T::SROW;
-            double vm[T::SIT], vk[T::SIT];
-#pragma unroll
-            for (int j = 0; j < T::SIT; ++j) {
-                const int i = min(tid + j * T::NT, T::SROW - 1);
-                vm[j] = st[i];
-                vk[j] = st[T::SROW + i];
-            }
-#pragma unroll
-            for (int j = 0; j < T::SIT; ++j) {
-                const int i = tid + j * T::NT;
-                if (i < L) {
-                    if (Mv) Mv[rs + i] = vm[j];
-                    if (Kv) Kv[rs + i] = vk[j];
-                }
-            }
-        }
-    };
-
-    for (int ix = xs; ix < X1; ++ix) {
-        const bool elem = ix < Kx;    // element ex = ix exists
-        const bool emit = ix >= X0;   // row ix belongs to this segment
-        const int z0 = opaque_zero_t();
-        if (elem) {
-            // ---- stage z
-            if (w < T::TZ * T::WZI) {
-                const int item = zitem;
-                const bool act = item < T::NZI;
-                const int iz = iz0 + zr + z0;   // opaque: table bases are recomputed per element
-                const double* kcol = kappa + ((int64_t)ix + (int64_t)Kx * zkey) * Q3 + zoff;
-                double d0[O], d1[O];
-#pragma unroll
-                for (int o = 0; o < O; ++o) d0[o] = d1[o] = 0.0;
-                const ctab wnz = Wnz + z0, wdz = Wdz + z0;
-#pragma unroll
-                for (int e = 0; e <= P; ++e) {
-                    const int ez = iz - P + e;
-                    if (ez < 0 || ez >= Kz) continue;   // wave-uniform
-                    double kz[Q];
-                    if constexpr (T::PREF) {
-#pragma unroll
-                        for (int k = 0; k < Q; ++k) kz[k] = kpf[e][k];
-                    } else {
-                        const double* kp = kcol + (int64_t)Kx * Ky * Q3 * ez;
-#pragma unroll
-                        for (int k = 0; k < Q; ++k) kz[k] = kp[Q2 * k];
-                    }
-                    const ctab wnE = wnz + (int64_t)ez * (S * Q), wdE = wdz + (int64_t)ez * (S * Q);
-#pragma unroll
-                    for (int bb = 0; bb <= P; ++bb) {
-                        const int sp = pair_index(P - e, bb);
-                        const ctab wn = wnE + sp * Q, wd = wdE + sp * Q;   // constant offsets
-#pragma unroll
-                        for (int k = 0; k < Q; ++k) {
-                            d0[e + bb] += wn[k] * kz[k];
-                            d1[e + bb] += wd[k] * kz[k];
-                        }
-                    }
-                    // one z element's loads in flight at a time: keeps the
-                    // register budget of two workgroups per CU
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                if constexpr (T::PREF) {
-                    if (ix + 1 < Kx) prefetch(ix + 1);
-                }
-                if (act) {
-                    double* dp = D + zr * T::DZR + item;
-#pragma unroll
-                    for (int o = 0; o < O; ++o) {
-                        dp[o * T::DOZ] = d0[o];
-                        dp[T::DT + o * T::DOZ] = d1[o];
-                    }
-                }
-            }
-            __syncthreads();
-            // ---- stage y
-            if (w < T::TY * T::WYI) {
-                const int yr = w / T::WYI;
-                const int iy = iy0 + yr + z0;
-                if (iy < Ny) {
-                    const int item = (w % T::WYI) * 64 + lane;
-                    const bool act = item < T::NYI;
-                    const int it = act ? item : T::NYI - 1;
-                    const int kx = it % Q, oz = (it / Q) % O, zr = it / (Q * O);
-                    double ca[O], cb[O];
-#pragma unroll
-                    for (int o = 0; o < O; ++o) ca[o] = cb[o] = 0.0;
-                    const ctab wny = Wny + z0, wdy = Wdy + z0;
-#pragma unroll
-                    for (int e = 0; e <= P; ++e) {
-                        const int ey = iy - P + e;
-                        if (ey < 0 || ey >= Ky) continue;   // wave-uniform
-                        const double* dp = D + zr * T::DZR + oz * T::DOZ + (yr + e) * Q2 + kx;
-                        double a[Q], c[Q];
-#pragma unroll
-                        for (int k = 0; k < Q; ++k) {
-                            a[k] = dp[k * Q];
-                            c[k] = dp[T::DT + k * Q];
-                        }
-                        const ctab wnE = wny + (int64_t)ey * (S * Q), wdE = wdy + (int64_t)ey * (S * Q);
-#pragma unroll
-                        for (int bb = 0; bb <= P; ++bb) {
-                            const int sp = pair_index(P - e, bb);
-                            const ctab wn = wnE + sp * Q, wd = wdE + sp * Q;
-#pragma unroll
-                            for (int k = 0; k < Q; ++k) {
-                                ca[e + bb] += wn[k] * a[k];
-                                cb[e + bb] += wd[k] * a[k];
-                                cb[e + bb] += wn[k] * c[k];
-                            }
-                        }
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                    if (act) {
-                        double* cp = C + (yr * T::TZ + zr) * T::CPEN + kx * T::CKX + oz;
-#pragma unroll
-                        for (int o = 0; o < O; ++o) {
-                            cp[o * O] = ca[o];
-                            cp[T::CT + o * O] = cb[o];
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        // ---- stage x
-        if (w < T::WX) {
-#pragma unroll
-            for (int e = 0; e < P; ++e)
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    ring[e][k][0] = ring[e + 1][k][0];
-                    ring[e][k][1] = ring[e + 1][k][1];
-                }
+        for (int ix = xs; ix < X1; ++ix) {
+            const bool elem = ix < c.Kx;   // element ex = ix exists
+            const bool emit = ix >= X0;    // row ix belongs to this segment
+            const int z0 = opaque_zero_t();
             if (elem) {
-                const double* cp = C + xpen * T::CPEN + xoy * O + xoz;
-#pragma unroll
-                for (int k = 0; k < Q; ++k) {
-                    ring[P][k][0] = cp[k * T::CKX];
-                    ring[P][k][1] = cp[T::CT + k * T::CKX];
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < Q; ++k) ring[P][k][0] = ring[P][k][1] = 0.0;
-            }
-        }
-        if (emit) {
-            if (w < T::WX) {
-                const int Lx = band_len(ix, P, Nx);
-                const int sub = xsub * Lx + (ix - P - band_lo(ix, P));   // + ox
-                double* stM = STG + xpen * 2 * T::SROW;
-                double m[O], k[O];
-#pragma unroll
-                for (int o = 0; o < O; ++o) m[o] = k[o] = 0.0;
-#pragma unroll
-                for (int e = 0; e <= P; ++e) {
-                    const int exc = clampi_t(ix - P + e, Kx - 1);   // ring holds zeros outside
-                    const ctab wnE = Wnx + (int64_t)exc * (S * Q), wdE = Wdx + (int64_t)exc * (S * Q);
-#pragma unroll
-                    for (int bb = 0; bb <= P; ++bb) {
-                        const int sp = pair_index(P - e, bb);
-                        const ctab wn = wnE + sp * Q, wd = wdE + sp * Q;
-#pragma unroll
-                        for (int q = 0; q < Q; ++q) {
-                            m[e + bb] += wn[q] * ring[e][q][0];
-                            k[e + bb] += wd[q] * ring[e][q][0];
-                            k[e + bb] += wn[q] * ring[e][q][1];
-                        }
+                if (w < T::NWZ) {
+                    z_stage<T, T::PREF>(c, zt, ix, kw, D, z0);
+                    if constexpr (T::PREF) {
+                        if (ix + 1 < c.Kx) z_load<T>(c, zt, ix + 1, kw);
                     }
                 }
-                // branch-free stores (a branch per column would pull the
-                // column's arithmetic, and all its table loads, apart)
-#pragma unroll
-                for (int ox = 0; ox < O; ++ox) {
-                    const int jx = ix + ox - P;
-                    const int pos = xrow && jx >= 0 && jx < Nx ? sub + ox : T::SROW - 1;
-                    stM[pos] = m[ox];
-                    stM[T::SROW + pos] = k[ox];
-                }
+                __syncthreads();
+                if (w < T::NWY) y_stage<T>(c, w, lane, D, C0, z0);
+                __syncthreads();
             }
-            __syncthreads();
-            store_row(ix);
-            __syncthreads();   // the next stage z rewrites the staged rows
+            if (w < T::WX) x_shift<T>(xt, ring, elem ? C0 : nullptr);
+            if (emit) {
+                if (w < T::WX) x_row<T>(c, xt, ring, ix, STG);
+                __syncthreads();
+                store_row<T>(c, STG, ix, tid, pbase, plen);
+                __syncthreads();   // the next stage z rewrites the staged rows
+            }
+        }
+    } else {
+        // pipelined: iteration t computes element t on the stage-z/y
+        // wavefronts and finishes row t-1 on the stage-x wavefronts; both
+        // roles pass the same two barriers per iteration
+        const int xe = min(c.Kx, X1);   // elements swept: [xs, xe)
+        if (w < T::NWZY) {
+            const ZThread<T> zt(c, w, lane);
+            double kw[P + 1][Q];
+            if (w < T::NWZ && xs < xe) z_load<T>(c, zt, xs, kw);
+            for (int t = xs; t <= X1; ++t) {
+                const bool el = t < xe;
+                const int z0 = opaque_zero_t();
+                if (el && w < T::NWZ) {
+                    z_stage<T, true>(c, zt, t, kw, D, z0);
+                    if (t + 1 < xe) z_load<T>(c, zt, t + 1, kw);
+                }
+                __syncthreads();
+                if (el && w < T::NWY) y_stage<T>(c, w, lane, D, C0 + (t & 1) * T::CSZ, z0);
+                __syncthreads();
+            }
+        } else {
+            const int wx = w - T::XW0;
+            const XThread<T> xt(c, wx * 64 + lane);
+            int64_t pbase;
+            int plen;
+            pencil_rows<T>(c, lane, pbase, plen);
+            double ring[P + 1][Q][2];
+#pragma unroll
+            for (int e = 0; e <= P; ++e)
+#pragma unroll
+                for (int k = 0; k < Q; ++k) ring[e][k][0] = ring[e][k][1] = 0.0;
+            for (int t = xs; t <= X1; ++t) {
+                const int r = t - 1;   // row finished in this iteration
+                const bool live = r >= xs, emit = r >= X0;
+                if (live) {
+                    x_shift<T>(xt, ring, r < xe ? C0 + (r & 1) * T::CSZ : nullptr);
+                    if (emit) x_row<T>(c, xt, ring, r, STG);
+                }
+                __syncthreads();
+                if (emit) store_row<T>(c, STG, r, wx * 64 + lane, pbase, plen);
+                __syncthreads();
+            }
         }
     }
 }
+
+// Logical workgroup index with XCD-aware order: the hardware hands workgroup
+// b to XCD b % 8, so XCD x receives the contiguous logical range
+// [x*nb8, (x+1)*nb8): neighbouring tiles (which share kappa) share one L2.
+__device__ inline int xcd_tile(int b, int nb8) { return (b % 8) * nb8 + b / 8; }
 
 template <class T>
 __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE))) void k_rows_tile(
@@ -450,13 +603,12 @@ int launch_rows(const PatchDev& pd, const double* kappa, double* Mv, double* Kv,
     }
 }
 
-
 // ---------------------------------------------------------------------------
 // Batched launch: one workgroup per work item (patch, tile) of a list sorted
 // longest first; every degree's tile is one workgroup of 256 threads, so one
 // kernel runs any of them.  Each tile sweeps all rows of its pencils.
 
-template <int P> using TileOf = typename TileCfg<P>::T;
+template <int P> using TileOf = typename BatchCfg<P>::T;
 static_assert(TileOf<1>::NT == 256 && TileOf<2>::NT == 256 && TileOf<3>::NT == 256 &&
                   TileOf<4>::NT == 256 && TileOf<5>::NT == 256,
               "the batched kernel runs every degree's tile with 256 threads");
@@ -494,8 +646,8 @@ __device__ inline void uniform_patch(const BatchPatch& src, PatchDev& pd, RowMap
     Kv = uniform_ptr(src.Kv);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rows_tile_batch(const BatchPatch* __restrict__ patches,
-                                                         const int2* __restrict__ items, int nitems)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rows_tile_batch(
+    const BatchPatch* __restrict__ patches, const int2* __restrict__ items, int nitems)
 {
     __shared__ double lds[kBatchLds];
     // XCD x (which receives workgroups b = x mod 8) takes the item chunks
@@ -532,8 +684,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 int launch_rows_batch(const BatchPatch* patches, const int2* items, int nitems, hipStream_t st)
 {
     if (nitems <= 0) return 0;
-    const int grid = (nitems + 8 * kBatchChunk - 1) / (8 * kBatchChunk) * (8 * kBatchChunk);
-    hipLaunchKernelGGL(k_rows_tile_batch, dim3(grid), dim3(256), 0, st, patches, items, nitems);
+    hipLaunchKernelGGL(k_rows_tile_batch, dim3(rows_batch_grid(nitems)), dim3(256), 0, st, patches,
+                       items, nitems);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -550,7 +702,7 @@ static void tile_info_t(int Ny, int Nz, int Kx, int* ntile, double* cost)
 {
     *ntile = ((Ny + T::TY - 1) / T::TY) * ((Nz + T::TZ - 1) / T::TZ);
     constexpr double terms = (double)(T::P + 1) * (T::P + 1) * T::Q;
-    const double per_elem = T::TZ * T::WZI * 2.0 * terms + T::TY * T::WYI * 3.0 * terms + T::WX * 3.0 * terms;
+    const double per_elem = T::NWZ * 2.0 * terms + T::NWY * 3.0 * terms + T::WX * 3.0 * terms;
     *cost = per_elem * (Kx + T::P);
 }
 
