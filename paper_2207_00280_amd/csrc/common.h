@@ -85,7 +85,7 @@ inline RowMap make_rowmap(const PatchDev& pd)
     return m;
 }
 
-// One patch of a batched launch, as the persistent kernel reads it.
+// One patch of a batched launch, as the batched kernel reads it.
 struct BatchPatch {
     PatchDev pd;
     RowMap rm;
