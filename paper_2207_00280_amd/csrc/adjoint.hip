@@ -9,20 +9,42 @@
 //
 // One 64-lane wavefront per x-run of elements (fixed ey, ez; grid-stride over
 // runs, four independent wavefronts per workgroup, synchronised only within
-// the wavefront).  The run's y and z tables are cached in LDS; each stage-x
-// lane keeps a sliding window of the p+1 coefficients of u and v along x, so
-// one new value per field is loaded per element, one element ahead.  Per
-// element:
-//   stage x: lane (a2, a3, kx) gathers u, v along a1 and forms the value and
-//            x-derivative contractions,
-//   stage y: lane (kx, ky, a3) contracts a2 (value, y-derivative, and the
-//            x-derivative carried along),
-//   stage z: lane (kx, ky, kz) = quadrature point contracts a3 and writes
-//            the point's gradient entry (one contiguous q^3 run per element).
+// the wavefront).  The run's y and z tables are wave-uniform (scalar loads).
+// Elements go in groups of G = 64 / n^2, and each field (u, then v) passes
+// through three stages per group:
+//   stage x: lane (kx, a2, a3), one element at a time, contracts a1 from a
+//            sliding window of the p+1 coefficients along x (one new value
+//            per element): value and x-derivative, into LDS;
+//   stage y: lane (g, kx, a3) contracts a2 for every ky: value, y-derivative
+//            and the x-derivative carried along;
+//   stage z: lane (g, kx, ky) contracts a3 for every kz: value and the three
+//            derivatives at the quadrature points; the u results wait in
+//            registers, the v pass combines them and writes the point's
+//            gradient entry.
+// Each LDS value is written once and read once; stage y's output reuses the
+// buffer of stage x's.
 #include "common.h"
 #include "launch.h"
 
 namespace igaf {
+
+namespace {
+
+constexpr int amax(int a, int b) { return a > b ? a : b; }
+constexpr int amin(int a, int b) { return a < b ? a : b; }
+// smallest y >= x with y = r (mod 16): LDS strides that spread lanes over banks
+constexpr int apad16(int x, int r) { return x + (((r - x) % 16) + 16) % 16; }
+
+// A zero the compiler cannot see through: adding it to the run's table
+// pointers in every stage keeps their scalar loads inside the stage
+// (scalar-cache hits) instead of hoisting 4 n q values per run into scalar
+// registers and spilling them.
+__device__ inline int adj_opaque_zero()
+{
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    return z;
+}
 
 __device__ inline void adj_wave_sync()
 {
@@ -31,192 +53,193 @@ __device__ inline void adj_wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+}  // namespace
+
 template <int P>
-__global__ __launch_bounds__(256) void k_kappa_grad(PatchDev pd, const double* __restrict__ u,
+struct AdjShape {
+    static constexpr int n = P + 1, Q = P + 1, Q2 = Q * Q, Q3 = Q2 * Q;
+    static constexpr int G = amax(1, amin(64 / (n * n), 8));   // elements per group
+    static constexpr int NXI = n * n * Q, NXP = (NXI + 63) / 64;  // stage-x items per element
+    static constexpr int NYI = G * Q * n;                         // stage-y items per group
+    static constexpr int NZI = G * Q2;                            // stage-z items per group
+    static_assert(NYI <= 64 && NZI <= 64, "one pass per group in stages y and z");
+    // X[g][f2][a3][a2][kx] and Y[g][f3][a3][ky][kx] share one buffer
+    static constexpr int XA3 = apad16(n * Q, Q), XF = n * XA3, XG = 2 * XF;
+    static constexpr int YA3 = apad16(Q2, Q), YF = n * YA3, YG = 3 * YF;
+    static constexpr int WS = amax(G * XG, G * YG);               // doubles per wavefront
+    static constexpr int RUN = 32;                                // elements per x-run
+};
+
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 : 2))) void k_kappa_grad(
+    PatchDev pd, const double* __restrict__ u,
                                                     const double* __restrict__ v, double alphaM,
                                                     double alphaK, double scale,
                                                     double* __restrict__ grad)
 {
-    constexpr int n = P + 1, Q = P + 1, Q3 = Q * Q * Q;
-    constexpr int NX = n * n * Q;     // stage-x items (a2, a3, kx)
-    constexpr int NY = n * Q * Q;     // stage-y items (kx, ky, a3)
-    constexpr int NPX = (NX + 63) / 64;
-    constexpr int TS = 4 * n * Q + 2 * Q;
-    __shared__ double Xs[4][4][NX];   // per wavefront: u0, u1, v0, v1 at [(a3 n + a2) Q + kx]
-    __shared__ double Ys[4][6][NY];   // per wavefront: u00, u01, u10, v00, v01, v10 at [(a3 Q + ky) Q + kx]
-    __shared__ double Ts[4][TS];      // per wavefront: N_y, N'_y, N_z, N'_z [a][k], w_y, w_z [k]
+    using A = AdjShape<P>;
+    constexpr int n = A::n, Q = A::Q, Q2 = A::Q2, Q3 = A::Q3, G = A::G, NXP = A::NXP;
+    __shared__ double lds[4][A::WS];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+    double* const B = lds[w];
     const int Kx = pd.d[0].K, Ky = pd.d[1].K, Kz = pd.d[2].K;
     const int Nx = pd.d[0].N, Ny = pd.d[1].N;
     const double* __restrict__ Nvx = pd.d[0].Nv;
     const double* __restrict__ dNx = pd.d[0].dN;
     const double* __restrict__ wqx = pd.d[0].wq;
-    double(*X)[NX] = Xs[w];
-    double(*Y)[NY] = Ys[w];
-    double* Tw = Ts[w];
-    constexpr int RUN = 32;                     // elements per run (a chunk of an x row)
-    const int nchunk = (Kx + RUN - 1) / RUN;
+    const int nchunk = (Kx + A::RUN - 1) / A::RUN;
     const int nruns = nchunk * Ky * Kz;
 
-    // one run of consecutive x elements (fixed ey, ez) per wavefront
+    // fixed lane roles
+    int xkx[NXP], xa2[NXP], xa3[NXP];   // stage x: item i = kx + Q (a2 + n a3)
+#pragma unroll
+    for (int ps = 0; ps < NXP; ++ps) {
+        const int i = min(ps * 64 + lane, A::NXI - 1);
+        xkx[ps] = i % Q;
+        xa2[ps] = (i / Q) % n;
+        xa3[ps] = i / (n * Q);
+    }
+    const bool yact = lane < A::NYI;      // stage y: lane = kx + Q (a3 + n g)
+    const int yl = yact ? lane : A::NYI - 1;
+    const int ykx = yl % Q, ya3 = (yl / Q) % n, yg = yl / (Q * n);
+    const bool zact = lane < A::NZI;      // stage z: lane = kx + Q (ky + Q g)
+    const int zl = zact ? lane : A::NZI - 1;
+    const int zkx = zl % Q, zky = (zl / Q) % Q, zg = zl / Q2;
+
     for (int run = blockIdx.x * 4 + w; run < nruns; run += gridDim.x * 4) {
         const int ch = run % nchunk, ey = (run / nchunk) % Ky, ez = run / (nchunk * Ky);
-        const int ex0 = ch * RUN, ex1 = min(Kx, ex0 + RUN);
-        for (int i = lane; i < TS; i += 64) {
-            double t;
-            if (i < 4 * n * Q) {
-                const int tab = i / (n * Q), j = i % (n * Q);
-                const int d = tab < 2 ? 1 : 2, ed = tab < 2 ? ey : ez;
-                t = (tab % 2 ? pd.d[d].dN : pd.d[d].Nv)[(int64_t)ed * n * Q + j];
-            } else {
-                const int j = i - 4 * n * Q;
-                t = j < Q ? pd.d[1].wq[(int64_t)ey * Q + j] : pd.d[2].wq[(int64_t)ez * Q + j - Q];
-            }
-            Tw[i] = t;
-        }
-        // sliding windows u[g0 + ex + a1], a1 = 0..p, of every stage-x item
-        double uw[NPX][n], vw[NPX][n];
-        int64_t g0[NPX];
+        const int ex0 = ch * A::RUN, ex1 = min(Kx, ex0 + A::RUN);
+        // the run's y and z tables: wave-uniform
+        const ctab Ny0 = as_ctab(pd.d[1].Nv) + (int64_t)ey * n * Q;
+        const ctab Dy0 = as_ctab(pd.d[1].dN) + (int64_t)ey * n * Q;
+        const ctab Nz0 = as_ctab(pd.d[2].Nv) + (int64_t)ez * n * Q;
+        const ctab Dz0 = as_ctab(pd.d[2].dN) + (int64_t)ez * n * Q;
+        const ctab wz0 = as_ctab(pd.d[2].wq) + (int64_t)ez * Q;
+        const double wyl = pd.d[1].wq[(int64_t)ey * Q + zky];   // this lane's y weight
+        // sliding windows of u and v along x at (a2, a3) of every stage-x item
+        double uw[NXP][n], vw[NXP][n];
+        int64_t g0[NXP];
 #pragma unroll
-        for (int ps = 0; ps < NPX; ++ps) {
-            const int i = min(ps * 64 + lane, NX - 1);
-            const int a2 = i % n, a3 = (i / n) % n;
-            g0[ps] = (int64_t)Nx * ((ey + a2) + (int64_t)Ny * (ez + a3));
+        for (int ps = 0; ps < NXP; ++ps) {
+            g0[ps] = (int64_t)Nx * ((ey + xa2[ps]) + (int64_t)Ny * (ez + xa3[ps]));
 #pragma unroll
             for (int a1 = 0; a1 < n; ++a1) {
                 uw[ps][a1] = u[g0[ps] + ex0 + a1];
                 vw[ps][a1] = v[g0[ps] + ex0 + a1];
             }
         }
-        // x tables and x weights of the current element, fetched one element ahead
-        auto fetch_x = [&](int ex, double (&tn)[NPX][n], double (&td)[NPX][n], double& tw) {
+        for (int exg = ex0; exg < ex1; exg += G) {
+            const int ng = min(G, ex1 - exg);   // elements in this group
+
+            double ur[4][Q];                    // u, du/dx, du/dy, du/dz at this lane's points
+            // field f = 0: u, f = 1: v
 #pragma unroll
-            for (int ps = 0; ps < NPX; ++ps) {
-                const int i = min(ps * 64 + lane, NX - 1);
-                const int kx = i / (n * n);
+            for (int f = 0; f < 2; ++f) {
+                const int z0 = adj_opaque_zero();
+                const ctab Ny_ = Ny0 + z0, Dy_ = Dy0 + z0;
+                // ---- stage x, one element of the group at a time (unrolled,
+                // so that the loads of later elements are issued early)
 #pragma unroll
-                for (int a1 = 0; a1 < n; ++a1) {
-                    tn[ps][a1] = Nvx[((int64_t)ex * n + a1) * Q + kx];
-                    td[ps][a1] = dNx[((int64_t)ex * n + a1) * Q + kx];
+                for (int g = 0; g < G; ++g) {
+                    if (g >= ng) break;   // wave-uniform
+                    const int ex = exg + g;
+#pragma unroll
+                    for (int ps = 0; ps < NXP; ++ps) {
+                        const bool act = ps * 64 + lane < A::NXI;
+                        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                        for (int a1 = 0; a1 < n; ++a1) {
+                            const double c = f == 0 ? uw[ps][a1] : vw[ps][a1];
+                            const int64_t t = ((int64_t)ex * n + a1) * Q + xkx[ps];
+                            s0 += c * Nvx[t];
+                            s1 += c * dNx[t];
+                        }
+                        if (act) {
+                            double* xp = B + g * A::XG + xa3[ps] * A::XA3 + xa2[ps] * Q + xkx[ps];
+                            xp[0] = s0;
+                            xp[A::XF] = s1;
+                        }
+                        // slide this field's window by one element
+                        const int64_t gi = g0[ps] + min(ex + n, Nx - 1);
+#pragma unroll
+                        for (int a1 = 0; a1 + 1 < n; ++a1) {
+                            if (f == 0) uw[ps][a1] = uw[ps][a1 + 1];
+                            else vw[ps][a1] = vw[ps][a1 + 1];
+                        }
+                        if (f == 0) uw[ps][n - 1] = u[gi];
+                        else vw[ps][n - 1] = v[gi];
+                    }
                 }
-            }
-            tw = wqx[(int64_t)ex * Q + lane % Q];
-        };
-        double xn[NPX][n], xd[NPX][n], xw;
-        fetch_x(ex0, xn, xd, xw);
-        adj_wave_sync();
-        for (int ex = ex0; ex < ex1; ++ex) {
-            const int64_t e = ex + (int64_t)Kx * (ey + (int64_t)Ky * ez);
-            // next window entries and next x tables, loaded one element ahead
-            double un[NPX], vn[NPX];
+                adj_wave_sync();
+                // ---- stage y: lane (g, kx, a3), every ky
+                {
+                    double x0[n], x1[n];
+                    const double* xp = B + yg * A::XG + ya3 * A::XA3 + ykx;
 #pragma unroll
-            for (int ps = 0; ps < NPX; ++ps) {
-                const int64_t gi = g0[ps] + (ex + 1 < Kx ? ex + n : ex + n - 1);
-                un[ps] = u[gi];
-                vn[ps] = v[gi];
-            }
-            double cn[NPX][n], cd[NPX][n], cw = xw;
+                    for (int a2 = 0; a2 < n; ++a2) {
+                        x0[a2] = xp[a2 * Q];
+                        x1[a2] = xp[A::XF + a2 * Q];
+                    }
+                    adj_wave_sync();   // every read of X before the writes of Y over it
+                    double* yp = B + yg * A::YG + ya3 * A::YA3 + ykx;
 #pragma unroll
-            for (int ps = 0; ps < NPX; ++ps)
+                    for (int ky = 0; ky < Q; ++ky) {
+                        double o0 = 0.0, o1 = 0.0, o2 = 0.0;
 #pragma unroll
-                for (int a1 = 0; a1 < n; ++a1) {
-                    cn[ps][a1] = xn[ps][a1];
-                    cd[ps][a1] = xd[ps][a1];
+                        for (int a2 = 0; a2 < n; ++a2) {
+                            const double ny = Ny_[a2 * Q + ky], dy = Dy_[a2 * Q + ky];
+                            o0 += ny * x0[a2];
+                            o1 += dy * x0[a2];
+                            o2 += ny * x1[a2];
+                        }
+                        if (yact && yg < ng) {
+                            yp[ky * Q] = o0;
+                            yp[A::YF + ky * Q] = o1;
+                            yp[2 * A::YF + ky * Q] = o2;
+                        }
+                    }
                 }
-            fetch_x(ex + 1 < Kx ? ex + 1 : ex, xn, xd, xw);
-            // stage x
+                adj_wave_sync();
+                // ---- stage z: lane (g, kx, ky), every kz
+                {
+                    const int z1 = adj_opaque_zero();
+                    const ctab Nz_ = Nz0 + z1, Dz_ = Dz0 + z1, wz_ = wz0 + z1;
+                    double y0[n], y1[n], y2[n];
+                    const double* yp = B + zg * A::YG + zky * Q + zkx;
 #pragma unroll
-            for (int ps = 0; ps < NPX; ++ps) {
-                const bool act = ps * 64 + lane < NX;
-                const int i = act ? ps * 64 + lane : NX - 1;
-                const int a2 = i % n, a3 = (i / n) % n, kx = i / (n * n);
-                double su0 = 0.0, su1 = 0.0, sv0 = 0.0, sv1 = 0.0;
+                    for (int a3 = 0; a3 < n; ++a3) {
+                        y0[a3] = yp[a3 * A::YA3];
+                        y1[a3] = yp[A::YF + a3 * A::YA3];
+                        y2[a3] = yp[2 * A::YF + a3 * A::YA3];
+                    }
+                    adj_wave_sync();   // every read of Y before the next stage x writes
+                    const int exz = exg + min(zg, ng - 1);
+                    const double wxl = wqx[(int64_t)exz * Q + zkx];
+                    const int64_t e = exz + (int64_t)Kx * (ey + (int64_t)Ky * ez);
 #pragma unroll
-                for (int a1 = 0; a1 < n; ++a1) {
-                    const double nx = cn[ps][a1];
-                    const double dx = cd[ps][a1];
-                    su0 += uw[ps][a1] * nx;
-                    su1 += uw[ps][a1] * dx;
-                    sv0 += vw[ps][a1] * nx;
-                    sv1 += vw[ps][a1] * dx;
+                    for (int kz = 0; kz < Q; ++kz) {
+                        double h = 0.0, dz = 0.0, dy = 0.0, dx = 0.0;
+#pragma unroll
+                        for (int a3 = 0; a3 < n; ++a3) {
+                            const double nz = Nz_[a3 * Q + kz], dzt = Dz_[a3 * Q + kz];
+                            h += nz * y0[a3];
+                            dz += dzt * y0[a3];
+                            dy += nz * y1[a3];
+                            dx += nz * y2[a3];
+                        }
+                        if (f == 0) {
+                            ur[0][kz] = h;
+                            ur[1][kz] = dx;
+                            ur[2][kz] = dy;
+                            ur[3][kz] = dz;
+                        } else {
+                            const double r = alphaM * ur[0][kz] * h +
+                                             alphaK * (ur[1][kz] * dx + ur[2][kz] * dy + ur[3][kz] * dz);
+                            if (zact && zg < ng)
+                                grad[e * Q3 + kz * Q2 + zky * Q + zkx] = scale * (wxl * wyl * wz_[kz]) * r;
+                        }
+                    }
                 }
-                if (act) {
-                    const int j = (a3 * n + a2) * Q + kx;
-                    X[0][j] = su0;
-                    X[1][j] = su1;
-                    X[2][j] = sv0;
-                    X[3][j] = sv1;
-                }
-            }
-            adj_wave_sync();
-            // stage y
-            for (int i0 = 0; i0 < NY; i0 += 64) {
-                const bool act = i0 + lane < NY;
-                const int i = act ? i0 + lane : NY - 1;
-                const int kx = i % Q, ky = (i / Q) % Q, a3 = i / (Q * Q);
-                double r[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int a2 = 0; a2 < n; ++a2) {
-                    const double ny = Tw[0 * n * Q + a2 * Q + ky];
-                    const double dy = Tw[1 * n * Q + a2 * Q + ky];
-                    const int j = (a3 * n + a2) * Q + kx;
-                    const double u0 = X[0][j], u1 = X[1][j], v0 = X[2][j], v1 = X[3][j];
-                    r[0] += ny * u0;
-                    r[1] += dy * u0;
-                    r[2] += ny * u1;
-                    r[3] += ny * v0;
-                    r[4] += dy * v0;
-                    r[5] += ny * v1;
-                }
-                if (act) {
-#pragma unroll
-                    for (int f = 0; f < 6; ++f) Y[f][i] = r[f];
-                }
-            }
-            adj_wave_sync();
-            // x weights of this element by lane kx: broadcast from lanes 0..Q-1
-            double wxk[Q];
-#pragma unroll
-            for (int kx = 0; kx < Q; ++kx) wxk[kx] = __shfl(cw, kx);
-            // stage z + combine: item = quadrature point kx + Q (ky + Q kz)
-            for (int i0 = 0; i0 < Q3; i0 += 64) {
-                const bool act = i0 + lane < Q3;
-                const int i = act ? i0 + lane : Q3 - 1;
-                const int kx = i % Q, ky = (i / Q) % Q, kz = i / (Q * Q);
-                double uh = 0.0, udx = 0.0, udy = 0.0, udz = 0.0;
-                double vh = 0.0, vdx = 0.0, vdy = 0.0, vdz = 0.0;
-#pragma unroll
-                for (int a3 = 0; a3 < n; ++a3) {
-                    const double nz = Tw[2 * n * Q + a3 * Q + kz];
-                    const double dz = Tw[3 * n * Q + a3 * Q + kz];
-                    const int j = (a3 * Q + ky) * Q + kx;
-                    uh += nz * Y[0][j];
-                    udz += dz * Y[0][j];
-                    udy += nz * Y[1][j];
-                    udx += nz * Y[2][j];
-                    vh += nz * Y[3][j];
-                    vdz += dz * Y[3][j];
-                    vdy += nz * Y[4][j];
-                    vdx += nz * Y[5][j];
-                }
-                double wxq = wxk[0];
-#pragma unroll
-                for (int k = 1; k < Q; ++k) wxq = kx == k ? wxk[k] : wxq;
-                const double wq = wxq * Tw[4 * n * Q + ky] * Tw[4 * n * Q + Q + kz];
-                const double r = alphaM * uh * vh + alphaK * (udx * vdx + udy * vdy + udz * vdz);
-                if (act) grad[e * Q3 + i] = scale * wq * r;
-            }
-            adj_wave_sync();
-            // slide the windows by one element
-#pragma unroll
-            for (int ps = 0; ps < NPX; ++ps) {
-#pragma unroll
-                for (int a1 = 0; a1 + 1 < n; ++a1) {
-                    uw[ps][a1] = uw[ps][a1 + 1];
-                    vw[ps][a1] = vw[ps][a1 + 1];
-                }
-                uw[ps][n - 1] = un[ps];
-                vw[ps][n - 1] = vn[ps];
             }
         }
     }
