@@ -195,6 +195,20 @@ igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double
                             double alphaM, double alphaK, double scale, double* grad,
                             void* stream);
 
+/* Matrix-free operator apply, the step after assembly that an explicit time
+ * step takes (the forward Euler step of Sec. 2.2, in the matrix form of
+ * Sec. 2.4, needs M u and K u):
+ *   y = alphaM M(kappa) u + alphaK K(kappa) u
+ * computed element by element by sum factorisation (interpolate u and
+ * grad u to the quadrature points, weight by kappa w, contract back against
+ * the test functions; the element sum of Sec. 3.1), with no element or
+ * global matrix formed.  kappa: device [E][q^3]; u, y: device [ndof]; y is
+ * OVERWRITTEN and must not overlap u.  The element results are added into y
+ * with FP64 atomics, so the summation order, and the last bits of y, may
+ * differ between calls.  Needs nquad = degree + 1 in every direction. */
+igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double* u,
+                       double alphaM, double alphaK, double* y, void* stream);
+
 /* ---------------------------------------------------------------- batches
  * Many independent patches (the paper's first concurrency level: parts of
  * the mesh computed concurrently) integrated and assembled to CSR (streamed

@@ -520,6 +520,19 @@ igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double
                                       (hipStream_t)stream), "kappa gradient");
 }
 
+igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double* u,
+                       double alphaM, double alphaK, double* y, void* stream)
+{
+    igaf_status st = check_hot(plan, IGAF_SUMFACT);
+    if (st) return st;
+    if (!kappa || !u || !y) return fail(IGAF_EINVAL, "kappa, u or y is NULL");
+    if (u == y) return fail(IGAF_EINVAL, "y must not overlap u");
+    hipStream_t s = (hipStream_t)stream;
+    st = launched(launch_fill_zero(y, plan->ndof, s), "zero");
+    if (st) return st;
+    return launched(launch_apply(plan->dev, kappa, u, alphaM, alphaK, y, s), "operator apply");
+}
+
 }  // extern "C"
 
 namespace igaf {

@@ -40,6 +40,10 @@ int launch_gather(const PatchDev& pd, const double* Me, const double* Ke, double
 
 int launch_fill_zero(double* a, int64_t n, hipStream_t st);
 
+// y += alphaM M(kappa) u + alphaK K(kappa) u by FP64 atomics (y zeroed by the caller).
+int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM,
+                 double alphaK, double* y, hipStream_t st);
+
 int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,
                       double alphaK, double scale, double* grad, hipStream_t st);
 

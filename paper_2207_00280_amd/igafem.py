@@ -22,7 +22,7 @@ SYMBOLS = [
     "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_csr_pattern_host",
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes",
     "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
-    "igaf_integrate_assemble", "igaf_kappa_grad", "igaf_batch_create", "igaf_batch_destroy",
+    "igaf_integrate_assemble", "igaf_kappa_grad", "igaf_apply", "igaf_batch_create", "igaf_batch_destroy",
     "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
     "igaf_batch_integrate_assemble_separate",
 ]
@@ -75,6 +75,7 @@ def lib():
     L.igaf_integrate_assemble.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
     L.igaf_kappa_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, _vp, _vp]
+    L.igaf_apply.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]
     L.igaf_batch_create.argtypes = [ctypes.POINTER(PatchDesc), ctypes.c_int32, ctypes.POINTER(_vp)]
     L.igaf_batch_destroy.argtypes = [_vp]
     L.igaf_batch_destroy.restype = None
@@ -296,6 +297,17 @@ class Plan:
         _check(lib().igaf_integrate_assemble(self._h, int(method), _ptr(kappa), _ptr(Me), _ptr(Ke),
                                              _ptr(Mval), _ptr(Kval), _stream(stream)))
         return Me, Ke, Mval, Kval
+
+    def apply(self, kappa, u, alphaM=1.0, alphaK=1.0, y=None, stream=None):
+        """y = alphaM M(kappa) u + alphaK K(kappa) u, matrix-free (igaf_apply)."""
+        _need_f64_cuda(kappa, "kappa", self.nelem * self.nqp)
+        _need_f64_cuda(u, "u", self.ndof)
+        if y is None:
+            y = self._alloc(self.ndof)
+        _need_f64_cuda(y, "y", self.ndof)
+        _check(lib().igaf_apply(self._h, _ptr(kappa), _ptr(u), float(alphaM), float(alphaK),
+                                _ptr(y), _stream(stream)))
+        return y
 
     def kappa_grad(self, u, v, alphaM=1.0, alphaK=1.0, scale=1.0, grad=None, stream=None):
         _need_f64_cuda(u, "u", self.ndof)

@@ -1,0 +1,130 @@
+"""Matrix-free operator apply (igaf_apply) parity.
+
+y = alphaM M(kappa) u + alphaK K(kappa) u without forming any matrix.  The
+oracle's assembled matrices (the plain definition: the sum of the element
+matrices of Algorithm 1) give y = A u entry by entry on small patches; at
+full size the oracle's complete rows give sampled entries one by one, and
+closed forms pin K 1 = 0 and 1^T M 1 = sum_q w_q kappa_q.  The element
+results are added with atomics, so y is compared within rounding, not
+bitwise.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import nonuniform_knots, relfro, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def ig():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2207_00280_amd import igafem
+
+    return igafem
+
+
+def _csr(rp, col, val, n):
+    import scipy.sparse as sp
+
+    return sp.csr_matrix((val, col, rp), shape=(n, n))
+
+
+@pytest.mark.parametrize("p,K,uniform", [(1, (5, 3, 4), True), (2, (4, 5, 3), False),
+                                         (3, (6, 4, 5), True), (3, (5, 3, 4), False),
+                                         (4, (3, 4, 3), True), (5, (2, 3, 2), False)])
+def test_apply_vs_oracle_small(orc, ig, p, K, uniform):
+    """Every entry of y vs A u with A = alphaM M + alphaK K assembled by the
+    oracle, for mass only, stiffness only and a mix."""
+    knots = [W.open_uniform_knots(k, p) if uniform else nonuniform_knots(k, p, 31 * p + d)
+             for d, k in enumerate(K)]
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    plan = ig.Plan(p, K, knots)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=11 + p)
+    u = W.normal_vector(P.ndof, 12 + p)
+    rp, col, Mo, Ko = orc.assemble(P, kap)
+    M, Kk = _csr(rp, col, Mo, P.ndof), _csr(rp, col, Ko, P.ndof)
+    kd, ud = to_dev(kap), to_dev(u)
+    for aM, aK in [(1.0, 0.0), (0.0, 1.0), (0.7, -1.3)]:
+        y = to_host(plan.apply(kd, ud, aM, aK))
+        ref = aM * (M @ u) + aK * (Kk @ u)
+        assert relfro(y, ref) <= 1e-12, (aM, aK)
+
+
+def test_apply_closed_forms(orc, ig):
+    """K 1 = 0 (row sums of the stiffness vanish) and 1^T M 1 = sum_q w_q kappa_q
+    (partition of unity), weights from the oracle's quadrature rule."""
+    p, K = 3, (7, 5, 6)
+    knots = [nonuniform_knots(k, p, 90 + d) for d, k in enumerate(K)]
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    plan = ig.Plan(p, K, knots)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=5)
+    xn = [orc.quad_nodes(P, d) for d in range(3)]
+    wq = W.kappa_separable(xn[0][1], xn[1][1], xn[2][1])
+    ones = to_dev(np.ones(P.ndof))
+    kd = to_dev(kap)
+    m1 = to_host(plan.apply(kd, ones, 1.0, 0.0))
+    k1 = to_host(plan.apply(kd, ones, 0.0, 1.0))
+    assert abs(math.fsum(m1.tolist()) - math.fsum((wq * kap).reshape(-1).tolist())) <= 1e-13 * np.sum(wq * kap)
+    rp, col, _, Ko = orc.assemble(P, kap)
+    rowabs = _csr(rp, col, np.abs(Ko), P.ndof) @ np.ones(P.ndof)
+    assert np.max(np.abs(k1)) <= 64 * EPS * np.max(rowabs)
+
+
+def test_apply_fullscale(orc, ig):
+    """96^3 elements, p=3, log-normal kappa (seed 2), u, v ~ N(0,1) (seeds 3, 4):
+    (1) 256 seeded DOFs (corners included): y_I vs the oracle's complete row I
+        times u, within 1e-12 of the row's absolute sum;
+    (2) K 1 = 0 within 64 eps times the largest sampled absolute row sum;
+    (3) u^T (M + K) v = <kappa, dL/dkappa> (the bilinear form is linear in
+        kappa; the gradient from igaf_kappa_grad), relative 1e-12."""
+    cfg = W.W5
+    p, K = cfg["p"], cfg["K"]
+    knots = [W.open_uniform_knots(k, p) for k in K]
+    plan = ig.Plan(p, K, knots)
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    kap = W.kappa_lognormal(plan.nelem, plan.nqp, seed=cfg["seed_kappa"])
+    u = W.normal_vector(plan.ndof, cfg["seed_u"])
+    v = W.normal_vector(plan.ndof, cfg["seed_v"])
+    kd, ud, vd = to_dev(kap), to_dev(u), to_dev(v)
+    y = to_host(plan.apply(kd, ud, 1.0, 1.0))
+    rng = np.random.default_rng(6)
+    corners = [0, P.N[0] - 1, P.ndof - 1, P.ndof - P.N[0]]
+    dofs = np.concatenate([corners, rng.choice(plan.ndof, 252, replace=False)])
+    worst = 0.0
+    rowabs_k = 0.0
+    for d, (c, m, k) in zip(dofs, orc.rows(P, kap, dofs)):
+        terms = (m + k) * u[c]
+        ref = math.fsum(terms.tolist())
+        worst = max(worst, abs(y[d] - ref) / np.sum(np.abs(terms)))
+        rowabs_k = max(rowabs_k, float(np.sum(np.abs(k))))
+    assert worst <= 1e-12
+    k1 = to_host(plan.apply(kd, to_dev(np.ones(plan.ndof)), 0.0, 1.0))
+    assert np.max(np.abs(k1)) <= 64 * EPS * rowabs_k
+    yv = to_host(plan.apply(kd, vd, 1.0, 1.0))
+    L = math.fsum((u * yv).tolist())
+    g = to_host(plan.kappa_grad(ud, vd))
+    Lg = math.fsum((g.reshape(-1) * kap.reshape(-1)).tolist())
+    assert abs(L - Lg) <= 1e-12 * abs(L)
+
+
+def test_apply_errors(ig):
+    """NULL, aliased and wrongly sized arguments are refused before any launch."""
+    import torch
+
+    p, K = 2, (3, 3, 3)
+    plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
+    kd = to_dev(np.ones((plan.nelem, plan.nqp)))
+    u = to_dev(np.ones(plan.ndof))
+    L = ig.lib()
+    assert L.igaf_apply(plan._h, None, u.data_ptr(), 1.0, 1.0, u.data_ptr(), None) == ig.EINVAL
+    assert L.igaf_apply(plan._h, kd.data_ptr(), u.data_ptr(), 1.0, 1.0, u.data_ptr(), None) == ig.EINVAL
+    with pytest.raises(ValueError):
+        plan.apply(kd, torch.ones(plan.ndof + 1, dtype=torch.float64, device="cuda"))
