@@ -12,8 +12,9 @@ The same run also times, on the same GPU: the element kernel and the CSR
 kernel alone (roofline of the dominant kernel), classical quadrature, the
 atomic assembly, the 128^3 streamed workload (p = 2, 3, 4), the 256-patch
 batched single launch against 256 separate launches (eager and
-graph-captured), and the adjoint against the plain forward assembly; and
-the CPU oracle on a bounded sample of the headline workload.
+graph-captured), the adjoint and the matrix-free operator apply against the
+plain forward assembly; and the CPU oracle on a bounded sample of the
+headline workload.
 
 Prints ONE JSON line on stdout.  --mode kernel:<name> runs one kernel only
 (for profiler counter passes).
@@ -217,7 +218,19 @@ def bench_w4(ig, torch, stream, steps):
     return out
 
 
+def interp_fmas(p):
+    """Fused multiply-adds per element of one field interpolated to the q^3
+    points by sum factorisation with values and first derivatives, q = n =
+    p+1: stage x 2n^4, stage y 3n^4, stage z 4n^4 (the transposed contraction
+    of a weighted field back to the test functions costs the same)."""
+    n = p + 1
+    return 9 * n ** 4
+
+
 def bench_w5(ig, torch, stream, steps):
+    """W5 mesh: the adjoint dL/dkappa, and the matrix-free operator apply
+    y = (M + K) u, each against the plain forward CSR assembly of the mesh;
+    both are FP64-bound (about 10 kflop per element at p = 3)."""
     cfg = W.W5
     p, K = cfg["p"], cfg["K"]
     plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
@@ -225,17 +238,32 @@ def bench_w5(ig, torch, stream, steps):
     u = torch.from_numpy(W.normal_vector(plan.ndof, cfg["seed_u"])).cuda()
     v = torch.from_numpy(W.normal_vector(plan.ndof, cfg["seed_v"])).cuda()
     g = torch.empty_like(kap)
+    y = torch.empty_like(u)
     Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
     Kv = torch.empty_like(Mv)
     ms_a = float(np.mean(timed(lambda: plan.kappa_grad(u, v, grad=g), steps, 2, stream)))
+    ms_y = float(np.mean(timed(lambda: plan.apply(kap, u, 1.0, 1.0, y=y), steps, 2, stream)))
     ms_f = float(np.mean(timed(lambda: plan.integrate_assemble(kap, want_elem=False, Mval=Mv, Kval=Kv),
                                steps, 2, stream)))
-    b = plan.nelem * plan.nqp * 8 + 2 * plan.ndof * 8
-    out = {"points": plan.nelem * plan.nqp, "adjoint_ms": ms_a, "forward_csr_ms": ms_f,
-           "adjoint_GB/s": b / (ms_a * 1e-3) / 1e9, "adjoint_frac_hbm": b / (ms_a * 1e-3) / HBM_PEAK,
-           "speedup_vs_forward": ms_f / ms_a}
-    log("W5: adjoint %.3f ms, forward CSR %.3f ms" % (ms_a, ms_f))
-    del kap, u, v, g, Mv, Kv, plan
+    q3, n3 = plan.nqp, (p + 1) ** 3
+    # adjoint: two fields interpolated, combined at every point (6 FMA);
+    # apply: one field interpolated and one contracted back, weighted at every point
+    f_a = plan.nelem * 2.0 * (2 * interp_fmas(p) + 6 * q3)
+    f_y = plan.nelem * 2.0 * (2 * interp_fmas(p) + 4 * q3)
+    b_a = plan.nelem * q3 * 8 + 2 * plan.ndof * 8
+    b_y = plan.nelem * q3 * 8 + 3 * plan.ndof * 8
+    roof_a = max(b_a / HBM_PEAK, f_a / FP64_PEAK)
+    roof_y = max(b_y / HBM_PEAK, f_y / FP64_PEAK)
+    out = {"points": plan.nelem * plan.nqp, "forward_csr_ms": ms_f,
+           "adjoint": {"ms": ms_a, "bytes": b_a, "flops": f_a, "roofline_ms": roof_a * 1e3,
+                       "frac": roof_a / (ms_a * 1e-3), "bound": "fp64" if f_a / FP64_PEAK > b_a / HBM_PEAK else "hbm",
+                       "speedup_vs_forward": ms_f / ms_a},
+           "apply": {"ms": ms_y, "bytes": b_y, "flops": f_y, "roofline_ms": roof_y * 1e3,
+                     "frac": roof_y / (ms_y * 1e-3), "bound": "fp64" if f_y / FP64_PEAK > b_y / HBM_PEAK else "hbm",
+                     "speedup_vs_forward": ms_f / ms_y}}
+    log("W5: adjoint %.3f ms (%.0f%% of roofline), apply (M+K)u %.3f ms (%.0f%%), forward CSR %.3f ms"
+        % (ms_a, 100 * out["adjoint"]["frac"], ms_y, 100 * out["apply"]["frac"], ms_f))
+    del kap, u, v, g, y, Mv, Kv, plan
     torch.cuda.empty_cache()
     return out
 
@@ -362,7 +390,7 @@ def main():
         steps_x = max(3, args.steps // 4)
         out["w3_streamed_128c"] = bench_w3(ig, torch, stream, steps_x)
         out["w4_batched_256"] = bench_w4(ig, torch, stream, steps_x)
-        out["w5_adjoint_96c"] = bench_w5(ig, torch, stream, steps_x)
+        out["w5_adjoint_apply_96c"] = bench_w5(ig, torch, stream, steps_x)
     else:
         del h
         torch.cuda.empty_cache()

@@ -20,8 +20,10 @@
 //              weighted there by kappa w (alphaM, alphaK folded in), then
 //              contracted back over kz (transposed stage z);
 //   stage y^T: lane (g, kx, a3), every a2;
-//   stage x^T: lane (a1, a2, a3), one element at a time, every kx, and the
-//              atomic add into y.
+//   stage x^T: lane (a1, a2, a3), one element at a time, every kx.  At
+//              p <= 3 (one pass) the lanes of one DOF row along x pass their
+//              partial sums down as the run advances, so each DOF takes one
+//              atomic add per run instead of one per element (p+1 fewer).
 #include "common.h"
 #include "launch.h"
 
@@ -114,6 +116,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
         const ctab Dz0 = as_ctab(pd.d[2].dN) + (int64_t)ez * n * Q;
         const ctab wz0 = as_ctab(pd.d[2].wq) + (int64_t)ez * Q;
         const double wyl = pd.d[1].wq[(int64_t)ey * Q + zky];   // this lane's y weight
+        // stage x^T with one pass (p <= 3): lane (a1, a2, a3) holds the partial
+        // sum of DOF (ex + a1, ey + a2, ez + a3) over the run's elements so far
+        double racc = 0.0;
         // sliding window of u along x at (a2, a3) of every stage-x item
         double uw[NXP][n];
         int64_t g0[NXP];
@@ -286,13 +291,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                         acc += Nvx[t] * rp[kx];
                         acc += dNx[t] * rp[A::XF + kx];
                     }
-                    if (act) {
-                        const int64_t I = (ex + ta1[ps]) + (int64_t)Nx * ((ey + ta2[ps]) + (int64_t)Ny * (ez + ta3[ps]));
+                    const int64_t I = (ex + ta1[ps]) + (int64_t)Nx * ((ey + ta2[ps]) + (int64_t)Ny * (ez + ta3[ps]));
+                    if constexpr (NXP == 1) {
+                        // DOF ex (a1 = 0) has all its contributions of the run
+                        // now (later elements touch DOFs beyond ex): add it to y,
+                        // then move every partial sum down one lane, so that lane
+                        // a1 holds DOF ex + 1 + a1 for the next element
+                        racc += acc;
+                        if (act && ta1[0] == 0) atomicAdd(&y[I], racc);
+                        const double nxt = __shfl(racc, lane + 1);
+                        racc = ta1[0] + 1 < n ? nxt : 0.0;
+                    } else if (act) {
                         atomicAdd(&y[I], acc);
                     }
                 }
             }
             ap_wave_sync();   // every read of R before the next group's stage x writes
+        }
+        if constexpr (NXP == 1) {
+            // DOFs ex1 .. ex1 + p - 1 also take contributions from the next run
+            const bool act = lane < A::NXI;
+            const int64_t I = (ex1 - 1 + ta1[0] + 1) + (int64_t)Nx * ((ey + ta2[0]) + (int64_t)Ny * (ez + ta3[0]));
+            if (act && ta1[0] + 1 < n) atomicAdd(&y[I], racc);
+            racc = 0.0;
         }
     }
 }
