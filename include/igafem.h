@@ -41,8 +41,9 @@
  *
  * ERRORS
  *   Every igaf_status is IGAF_OK (0) or negative; on error nothing has been
- *   launched and outputs are untouched, and igaf_last_error() returns a
- *   thread-local message describing the last failure on this thread.
+ *   launched and outputs are untouched (except IGAF_ENOCONV, whose outputs
+ *   hold the last iterate), and igaf_last_error() returns a thread-local
+ *   message describing the last failure on this thread.
  *
  * PRECISION: FP64 throughout.  Supported hot-kernel shapes: 1 <= p <= 5 with
  * nquad = p+1 in every direction (other Gauss orders are rejected with
@@ -63,6 +64,7 @@ typedef int32_t igaf_status;
 #define IGAF_ENOMEM       (-2) /* device or host allocation failed */
 #define IGAF_EDEVICE      (-3) /* a HIP call or kernel launch failed */
 #define IGAF_EUNSUPPORTED (-4) /* valid input outside what the kernels implement */
+#define IGAF_ENOCONV      (-5) /* an iteration stopped at its limit before its tolerance */
 
 #define IGAF_MAX_DEGREE 5
 #define IGAF_MAX_QUAD   16
@@ -208,6 +210,24 @@ igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double
  * differ between calls.  Needs nquad = degree + 1 in every direction. */
 igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double* u,
                        double alphaM, double alphaK, double* y, void* stream);
+
+/* One forward Euler step of the heat problem (Sec. 2.2, eq. Euler; the
+ * matrix form of Sec. 2.4) with the coefficient kappa in both integrals:
+ *   M(kappa) mu_next = M(kappa) mu - dt K(kappa) mu.
+ * The right-hand side is one igaf_apply; the mass system (symmetric positive
+ * definite) is solved by conjugate gradients started from mu, each iteration
+ * one matrix-free mass apply, until ||r|| <= tol ||b|| or after maxit
+ * iterations (then IGAF_ENOCONV, mu_next holding the last iterate).
+ * kappa: device [E][q^3]; mu, mu_next: device [ndof] (may be the same
+ * array); work: device scratch of igaf_euler_workspace(plan) doubles,
+ * overwritten.  iters, relres: HOST outputs (iterations taken, final
+ * ||r|| / ||b||), either may be NULL.  Synchronous: it waits on `stream` for
+ * the residual of every iteration and returns when the step is done.
+ * Needs nquad = degree + 1 in every direction. */
+int64_t igaf_euler_workspace(const igaf_plan* plan);
+igaf_status igaf_euler_step(const igaf_plan* plan, const double* kappa, const double* mu, double dt,
+                            double tol, int32_t maxit, double* mu_next, double* work,
+                            int32_t* iters, double* relres, void* stream);
 
 /* ---------------------------------------------------------------- batches
  * Many independent patches (the paper's first concurrency level: parts of

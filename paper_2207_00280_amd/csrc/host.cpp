@@ -533,6 +533,31 @@ igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double*
     return launched(launch_apply(plan->dev, kappa, u, alphaM, alphaK, y, s), "operator apply");
 }
 
+int64_t igaf_euler_workspace(const igaf_plan* plan)
+{
+    return plan ? euler_workspace_doubles(plan->ndof) : 0;
+}
+
+igaf_status igaf_euler_step(const igaf_plan* plan, const double* kappa, const double* mu, double dt,
+                            double tol, int32_t maxit, double* mu_next, double* work,
+                            int32_t* iters, double* relres, void* stream)
+{
+    igaf_status st = check_hot(plan, IGAF_SUMFACT);
+    if (st) return st;
+    if (!kappa || !mu || !mu_next || !work) return fail(IGAF_EINVAL, "kappa, mu, mu_next or work is NULL");
+    if (!(tol >= 0.0) || maxit < 0) return fail(IGAF_EINVAL, "tol < 0 or maxit < 0");
+    int it = 0;
+    double rr = 0.0;
+    int rc = run_euler_step(plan->dev, plan->ndof, kappa, mu, dt, tol, maxit, mu_next, work, &it, &rr,
+                            (hipStream_t)stream);
+    if (iters) *iters = it;
+    if (relres) *relres = rr;
+    if (rc < 0) return fail(IGAF_EDEVICE, "Euler step: %s", hipGetErrorString(hipGetLastError()));
+    if (rc > 0) return fail(IGAF_ENOCONV, "Euler step: CG stopped at %d iterations, relative residual %.3e",
+                            it, rr);
+    return IGAF_OK;
+}
+
 }  // extern "C"
 
 namespace igaf {

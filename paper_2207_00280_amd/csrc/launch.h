@@ -44,6 +44,13 @@ int launch_fill_zero(double* a, int64_t n, hipStream_t st);
 int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM,
                  double alphaK, double* y, hipStream_t st);
 
+// Forward Euler step: b = M mu - dt K mu, then CG on M x = b from x = mu.
+// Returns 0 (converged), 1 (maxit reached) or -3.
+int64_t euler_workspace_doubles(int64_t ndof);
+int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const double* mu, double dt,
+                   double tol, int maxit, double* x, double* work, int* iters, double* relres,
+                   hipStream_t st);
+
 int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,
                       double alphaK, double scale, double* grad, hipStream_t st);
 

@@ -13,7 +13,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libigafem.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENOCONV = 0, -1, -2, -3, -4, -5
 CLASSICAL, SUMFACT = 0, 1
 ASM_ROWS, ASM_ATOMIC = 0, 1
 MAX_DEGREE = 5
@@ -22,7 +22,8 @@ SYMBOLS = [
     "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_csr_pattern_host",
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes",
     "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
-    "igaf_integrate_assemble", "igaf_kappa_grad", "igaf_apply", "igaf_batch_create", "igaf_batch_destroy",
+    "igaf_integrate_assemble", "igaf_kappa_grad", "igaf_apply", "igaf_euler_workspace", "igaf_euler_step",
+    "igaf_batch_create", "igaf_batch_destroy",
     "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
     "igaf_batch_integrate_assemble_separate",
 ]
@@ -76,6 +77,10 @@ def lib():
     L.igaf_kappa_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, _vp, _vp]
     L.igaf_apply.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]
+    L.igaf_euler_workspace.argtypes = [_vp]
+    L.igaf_euler_workspace.restype = ctypes.c_int64
+    L.igaf_euler_step.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _vp,
+                                  _vp, _i32p, ctypes.POINTER(ctypes.c_double), _vp]
     L.igaf_batch_create.argtypes = [ctypes.POINTER(PatchDesc), ctypes.c_int32, ctypes.POINTER(_vp)]
     L.igaf_batch_destroy.argtypes = [_vp]
     L.igaf_batch_destroy.restype = None
@@ -308,6 +313,27 @@ class Plan:
         _check(lib().igaf_apply(self._h, _ptr(kappa), _ptr(u), float(alphaM), float(alphaK),
                                 _ptr(y), _stream(stream)))
         return y
+
+    def euler_step(self, kappa, mu, dt, tol=1e-12, maxit=1000, out=None, work=None, stream=None):
+        """One forward Euler step M(kappa) mu_next = M(kappa) mu - dt K(kappa) mu
+        (igaf_euler_step, conjugate gradients on M).  Returns
+        (mu_next, iterations, relative residual); raises IgafError with status
+        ENOCONV if maxit is reached first."""
+        _need_f64_cuda(kappa, "kappa", self.nelem * self.nqp)
+        _need_f64_cuda(mu, "mu", self.ndof)
+        if out is None:
+            out = self._alloc(self.ndof)
+        _need_f64_cuda(out, "out", self.ndof)
+        nw = int(lib().igaf_euler_workspace(self._h))
+        if work is None:
+            work = self._alloc(nw)
+        _need_f64_cuda(work, "work", nw)
+        it = ctypes.c_int32(0)
+        rr = ctypes.c_double(0.0)
+        _check(lib().igaf_euler_step(self._h, _ptr(kappa), _ptr(mu), float(dt), float(tol), int(maxit),
+                                     _ptr(out), _ptr(work), ctypes.byref(it), ctypes.byref(rr),
+                                     _stream(stream)))
+        return out, it.value, rr.value
 
     def kappa_grad(self, u, v, alphaM=1.0, alphaK=1.0, scale=1.0, grad=None, stream=None):
         _need_f64_cuda(u, "u", self.ndof)

@@ -1,0 +1,89 @@
+"""One forward Euler step (igaf_euler_step): M(kappa) mu_next = M(kappa) mu -
+dt K(kappa) mu, right-hand side by the matrix-free apply, mass system by
+conjugate gradients.
+
+Checked against a direct solve with the oracle's assembled matrices (the
+error bound of a linear solve: relative error <= cond(M) x relative
+residual), against the conservation law of the heat problem with the
+Neumann boundary of Sec. 2.1 (1^T K = 0, so 1^T M mu is kept up to the CG
+residual), and for its edge cases.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import nonuniform_knots, relfro, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ig():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2207_00280_amd import igafem
+
+    return igafem
+
+
+@pytest.mark.parametrize("p,K,uniform", [(1, (6, 5, 4), False), (2, (5, 4, 4), True),
+                                         (3, (5, 4, 3), False), (4, (3, 3, 2), True)])
+def test_euler_vs_direct_solve(orc, ig, p, K, uniform):
+    """mu_next vs scipy's direct solve of M x = (M - dt K) mu with the oracle's
+    matrices, within cond_2(M) times the CG's relative residual (+ rounding)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+
+    knots = [W.open_uniform_knots(k, p) if uniform else nonuniform_knots(k, p, 7 * p + d)
+             for d, k in enumerate(K)]
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    plan = ig.Plan(p, K, knots)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=21 + p)
+    mu = W.normal_vector(P.ndof, 22 + p)
+    rp, col, Mo, Ko = orc.assemble(P, kap)
+    M = sp.csr_matrix((Mo, col, rp), shape=(P.ndof, P.ndof))
+    Kk = sp.csr_matrix((Ko, col, rp), shape=(P.ndof, P.ndof))
+    dt = 0.1 / max(K) ** 2
+    ref = spla.spsolve(M.tocsc(), M @ mu - dt * (Kk @ mu))
+    out, iters, relres = plan.euler_step(to_dev(kap), to_dev(mu), dt, tol=1e-13, maxit=5000)
+    assert relres <= 1e-13 and iters > 0
+    cond = np.linalg.cond(M.toarray())
+    assert relfro(to_host(out), ref) <= cond * relres + 1e-13, (cond, relres)
+
+
+def test_euler_conservation_and_edge_cases(ig):
+    """48^3 elements, p=3, log-normal kappa: 1^T M mu_next = 1^T M mu up to
+    |1^T r| <= sqrt(ndof) ||r||; in place equals out of place; a zero state
+    stays zero; maxit reached raises ENOCONV."""
+    import torch
+
+    p, K = 3, (48, 48, 48)
+    knots = [W.open_uniform_knots(k, p) for k in K]
+    plan = ig.Plan(p, K, knots)
+    kap = to_dev(W.kappa_lognormal(plan.nelem, plan.nqp, seed=31))
+    mu = to_dev(W.normal_vector(plan.ndof, 32))
+    dt = 0.1 / 48 ** 2
+    tol = 1e-12
+    out, iters, relres = plan.euler_step(kap, mu, dt, tol=tol, maxit=5000)
+    assert relres <= tol
+    m0 = to_host(plan.apply(kap, mu, 1.0, 0.0))
+    m1 = to_host(plan.apply(kap, out, 1.0, 0.0))
+    b = to_host(plan.apply(kap, mu, 1.0, -dt))
+    s0, s1 = math.fsum(m0.tolist()), math.fsum(m1.tolist())
+    bound = math.sqrt(plan.ndof) * relres * np.linalg.norm(b) + 1e-14 * math.fsum(np.abs(m0).tolist())
+    assert abs(s1 - s0) <= bound, (s1 - s0, bound)
+    # in place: mu_next over mu
+    mu2 = mu.clone()
+    _, it2, rr2 = plan.euler_step(kap, mu2, dt, tol=tol, maxit=5000, out=mu2)
+    assert rr2 <= tol
+    assert relfro(to_host(mu2), to_host(out)) <= 1e-11
+    # zero state
+    z, itz, rz = plan.euler_step(kap, torch.zeros_like(mu), dt)
+    assert itz == 0 and float(torch.count_nonzero(z)) == 0
+    # iteration limit
+    with pytest.raises(ig.IgafError) as ei:
+        plan.euler_step(kap, mu, dt, tol=1e-30, maxit=2)
+    assert ei.value.status == ig.ENOCONV
