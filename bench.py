@@ -12,9 +12,9 @@ The same run also times, on the same GPU: the element kernel and the CSR
 kernel alone (roofline of the dominant kernel), classical quadrature, the
 atomic assembly, the 128^3 streamed workload (p = 2, 3, 4), the 256-patch
 batched single launch against 256 separate launches (eager and
-graph-captured), the adjoint and the matrix-free operator apply against the
-plain forward assembly; and the CPU oracle on a bounded sample of the
-headline workload.
+graph-captured), the adjoint, the matrix-free operator apply and one forward
+Euler step (conjugate gradients on M) against the plain forward assembly;
+and the CPU oracle on a bounded sample of the headline workload.
 
 Prints ONE JSON line on stdout.  --mode kernel:<name> runs one kernel only
 (for profiler counter passes).
@@ -261,8 +261,22 @@ def bench_w5(ig, torch, stream, steps):
            "apply": {"ms": ms_y, "bytes": b_y, "flops": f_y, "roofline_ms": roof_y * 1e3,
                      "frac": roof_y / (ms_y * 1e-3), "bound": "fp64" if f_y / FP64_PEAK > b_y / HBM_PEAK else "hbm",
                      "speedup_vs_forward": ms_f / ms_y}}
-    log("W5: adjoint %.3f ms (%.0f%% of roofline), apply (M+K)u %.3f ms (%.0f%%), forward CSR %.3f ms"
-        % (ms_a, 100 * out["adjoint"]["frac"], ms_y, 100 * out["apply"]["frac"], ms_f))
+    # one forward Euler step M mu_next = (M - dt K) mu: right-hand side by the
+    # apply, conjugate gradients on M to a relative residual of 1e-10
+    dt = 0.1 / max(K) ** 2
+    mu_next = torch.empty_like(u)
+    plan.euler_step(kap, u, dt, tol=1e-10, maxit=20000, out=mu_next)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, iters, relres = plan.euler_step(kap, u, dt, tol=1e-10, maxit=20000, out=mu_next)
+    torch.cuda.synchronize()
+    ms_e = (time.perf_counter() - t0) * 1e3
+    out["euler_step"] = {"ms": ms_e, "cg_iterations": iters, "relres": relres, "dt": dt,
+                         "ms_per_iteration": ms_e / max(1, iters)}
+    del mu_next
+    log("W5: adjoint %.3f ms (%.0f%% of roofline), apply (M+K)u %.3f ms (%.0f%%), forward CSR %.3f ms, "
+        "Euler step %.1f ms (%d CG iterations)"
+        % (ms_a, 100 * out["adjoint"]["frac"], ms_y, 100 * out["apply"]["frac"], ms_f, ms_e, iters))
     del kap, u, v, g, y, Mv, Kv, plan
     torch.cuda.empty_cache()
     return out
