@@ -84,9 +84,14 @@ typedef struct igaf_batch igaf_batch;
  * element grid, the knot vectors and the Gauss order per direction. */
 typedef struct {
     int32_t degree;          /* p >= 1, the same in all directions */
-    int32_t nelem[3];        /* K_x, K_y, K_z >= 1 (non-empty knot spans per direction) */
-    const double* knots[3];  /* HOST, length nelem[d]+2p+1: p+1 equal first knots, p+1 equal
-                                last knots, strictly increasing interior knots (C^{p-1}) */
+    int32_t nelem[3];        /* K_x, K_y, K_z >= 1: knot spans between the end knots */
+    const double* knots[3];  /* HOST, length nelem[d]+2p+1, nondecreasing: p+1 equal first
+                                knots, p+1 equal last knots; an interior knot may repeat up to
+                                p+1 times (continuity C^{p-m} at multiplicity m).  Element e_d
+                                is the span [t[e_d+p], t[e_d+p+1]]; a span of zero length is
+                                still an element (it keeps its kappa entries and its place in
+                                every layout) but has zero Gauss weights and contributes
+                                nothing. */
     int32_t nquad[3];        /* Gauss-Legendre points per direction, 1..IGAF_MAX_QUAD */
 } igaf_patch_desc;
 

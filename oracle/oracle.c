@@ -8,8 +8,11 @@
  *
  * What it follows (paper: "A study of efficient concurrent integration
  * methods of B-Spline basis functions in IGA-FEM", arXiv 2207.00280):
- *   - open knot vector, Sec. 2.3 eq. (knot_vector): p+1 repeated end knots,
- *     simple interior knots; read as K+2p+1 knots indexed 0..K+2p;
+ *   - open knot vector, Sec. 2.3 eq. (knot_vector): p+1 repeated end knots;
+ *     read as K+2p+1 knots indexed 0..K+2p.  Interior knots may repeat up
+ *     to p+1 times (the "more general B-spline basis functions" the paper
+ *     says the method extends to, Sec. 2.3): the recursion below is the
+ *     literal definition and needs no change for them;
  *   - Cox-de Boor recursion, Sec. 2.3 eqs. (cox1)/(cox2), with 0/0 := 0,
  *     evaluated for ALL K+p functions of a direction (no local shortcut);
  *   - derivatives by the textbook B-spline derivative formula (the paper
@@ -26,7 +29,10 @@
  *     ascending, numerically-zero entries kept.
  *
  * Conventions fixed where the paper is silent: element e_d = 0..K_d-1 spans
- * [t[e_d+p], t[e_d+p+1]] and carries global functions e_d..e_d+p; local index
+ * [t[e_d+p], t[e_d+p+1]] and carries global functions e_d..e_d+p (a span of
+ * zero length is still an element: its Gauss weights w*h/2 are zero, so it
+ * adds nothing to any integral, but it keeps its place in every layout and
+ * in the structural pattern); local index
  * I = a1 + n(a2 + n a3) (x fastest); global DOF g = i + Nx(j + Ny k);
  * kappa / gradient layout [E][qz][qy][qx], e = ex + Kx(ey + Ky ez).
  *
@@ -172,7 +178,8 @@ static orc_patch make_patch(int p, const int* K, const int* q, const double* tx,
 
 /* Returns 0 if the patch is acceptable: p >= 1, K_d >= 1, 1 <= q_d <= 32,
  * each knot vector of length K_d+2p+1, nondecreasing, open (first p+1 and
- * last p+1 knots equal) with strictly increasing interior knots. */
+ * last p+1 knots equal), and no basis function identically zero: the
+ * support [t_i, t_{i+p+1}] of every function is a non-empty interval. */
 int orc_validate(int p, const int* K, const int* q, const double* tx, const double* ty,
                  const double* tz)
 {
@@ -186,8 +193,8 @@ int orc_validate(int p, const int* K, const int* q, const double* tx, const doub
             if (!(t[i] <= t[i + 1])) return -1;
         for (int i = 1; i <= p; ++i)
             if (t[i] != t[0] || t[nk - 1 - i] != t[nk - 1]) return -1;
-        for (int i = p; i < nk - p - 1; ++i)
-            if (!(t[i] < t[i + 1])) return -1;
+        for (int i = 0; i + p + 1 < nk; ++i)
+            if (!(t[i] < t[i + p + 1])) return -1;
     }
     return 0;
 }

@@ -87,9 +87,14 @@ igaf_status check_desc(const igaf_patch_desc* d)
             if (t[i] != t[0]) return fail(IGAF_EINVAL, "knots[%d]: first %d knots not equal (open vector)", a, p + 1);
             if (t[nk - 1 - i] != t[nk - 1]) return fail(IGAF_EINVAL, "knots[%d]: last %d knots not equal (open vector)", a, p + 1);
         }
-        for (int i = p; i < nk - p - 1; ++i)
-            if (!(t[i] < t[i + 1]))
-                return fail(IGAF_EINVAL, "knots[%d]: span %d is empty (repeated interior knot)", a, i - p);
+        // interior knots may repeat (reduced continuity, C^{p-m} at a knot of
+        // multiplicity m) as long as no basis function vanishes identically:
+        // the support [t_i, t_{i+p+1}] of every function must be non-empty
+        for (int i = 0; i + p + 1 < nk; ++i)
+            if (!(t[i] < t[i + p + 1]))
+                return fail(IGAF_EINVAL,
+                            "knots[%d]: basis function %d has an empty support (a knot repeated more than "
+                            "p+1 times)", a, i);
     }
     // the global sizes must fit the index types (int32 columns, int64 rows)
     double ndof = 1.0;

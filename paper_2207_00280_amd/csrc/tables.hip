@@ -7,10 +7,12 @@ namespace igaf {
 
 // One thread per (element e, Gauss point k) of one direction.  The p+1
 // functions that are non-zero on span s = e+p are built with the local
-// triangular form of the Cox-de Boor recursion (all denominators are knot
-// differences that contain the non-empty span, so none is zero); the
-// derivative uses the standard B-spline derivative formula with the degree
-// p-1 values of the same triangle.
+// triangular form of the Cox-de Boor recursion (every denominator is a knot
+// difference that contains the span, so none is zero while the span is not
+// empty); the derivative uses the standard B-spline derivative formula with
+// the degree p-1 values of the same triangle.  A span of zero length (a
+// repeated interior knot) has zero Gauss weights: all of its tables are zero,
+// so the element adds nothing anywhere.
 template <int P>
 __global__ void k_basis_tables(const double* __restrict__ t, int K, const double* __restrict__ xi,
                                const double* __restrict__ wr, int Q, double* __restrict__ Wnn,
@@ -27,6 +29,18 @@ __global__ void k_basis_tables(const double* __restrict__ t, int K, const double
     double x = x0 + 0.5 * (xi[k] + 1.0) * h;
     double w = 0.5 * wr[k] * h;
 
+    if (!(h > 0.0)) {
+        for (int a = 0; a <= P; ++a) {
+            Nv[((int64_t)e * n + a) * Q + k] = 0.0;
+            dN[((int64_t)e * n + a) * Q + k] = 0.0;
+        }
+        wq[(int64_t)e * Q + k] = 0.0;
+        for (int sp = 0; sp < S; ++sp) {
+            Wnn[((int64_t)e * S + sp) * Q + k] = 0.0;
+            Wdd[((int64_t)e * S + sp) * Q + k] = 0.0;
+        }
+        return;
+    }
     double ndu[n][n];     // upper triangle: values per degree; lower: knot differences
     double left[n], right[n];
     ndu[0][0] = 1.0;

@@ -75,7 +75,7 @@ def _bad(p=2, K=(3, 3, 3), knots=None, q=None):
     ("q17", "nquad"),
     ("decreasing", "decreases"),
     ("not_open", "open"),
-    ("repeated_interior", "empty"),
+    ("knot_repeated_p_plus_2", "empty support"),
     ("nan", "finite"),
 ])
 def test_desc_errors(case, frag):
@@ -96,9 +96,9 @@ def test_desc_errors(case, frag):
         k2 = kn.copy()
         k2[0] = -0.1
         d = _bad(knots=[kn, kn, k2])
-    elif case == "repeated_interior":
+    elif case == "knot_repeated_p_plus_2":
         k2 = kn.copy()
-        k2[4] = k2[3]
+        k2[3] = k2[0]          # p+2 equal first knots: function 0 vanishes identically
         d = _bad(knots=[k2, kn, kn])
     elif case == "nan":
         k2 = kn.copy()
@@ -110,6 +110,26 @@ def test_desc_errors(case, frag):
     with pytest.raises(ig.IgafError) as ei:
         ig.desc_sizes(d)
     assert ei.value.status == ig.EINVAL
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_repeated_interior_knots_accepted(orc, p):
+    """Interior multiplicity up to p+1 (down to C^-1) is valid input: the
+    sizes follow K = len - 2p - 1 spans (empty ones included), and the host
+    CSR pattern equals the oracle's union of element pairs."""
+    knots = [W.repeated_knots([0.3, 0.7], [p, p + 1], p), W.repeated_knots([0.5], [2], p),
+             W.open_uniform_knots(2, p)]
+    K = tuple(len(t) - 2 * p - 1 for t in knots)
+    d = ig.make_desc(p, K, knots)
+    assert ig.desc_check(d)[0] == ig.OK
+    sz = ig.desc_sizes(d)
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    assert sz["ndof"] == P.ndof and sz["nelem"] == P.nelem
+    kap = np.ones((P.nelem, P.nq))
+    rp_o, col_o, _, _ = orc.assemble(P, kap)
+    rp, col = ig.csr_pattern_host(d)
+    assert sz["nnz"] == len(col_o)
+    assert np.array_equal(rp, rp_o) and np.array_equal(col, col_o)
 
 
 def test_null_arguments():

@@ -365,3 +365,127 @@ def test_kappa_grad_linearity(orc):
     L = math.fsum(u * Av)
     g = orc.kappa_grad(P, u, v)
     assert abs(math.fsum((g * kap).reshape(-1)) - L) < 1e-12 * abs(L)
+
+
+# ---------------------------------------------------------------- reduced continuity
+# Repeated interior knots (the "more general B-spline basis functions" of
+# Sec. 2.3): a knot of multiplicity m leaves the basis C^{p-m} there; a span
+# of zero length is an element with zero Gauss weights.
+
+
+def _bern_mass(p, a, b):
+    """int_0^1 b_{a,p} b_{b,p} (Bernstein), 0 outside 0..p."""
+    if not (0 <= a <= p and 0 <= b <= p):
+        return Fraction(0)
+    return Fraction(math.comb(p, a) * math.comb(p, b), (2 * p + 1) * math.comb(2 * p, a + b))
+
+
+def _bern_blocks(p, breaks, mult):
+    """1D mass and stiffness of a knot vector whose every interior breakpoint
+    has multiplicity `mult` in {p, p+1}: the basis on each non-empty span is
+    the Bernstein basis of that span, so the matrices are the Bernstein element
+    matrices (mass h B, stiffness (p^2/h) D) placed at the span's functions,
+    overlapping by one function for C^0 and not at all for C^-1."""
+    pts = [Fraction(0)] + [Fraction(b) for b in breaks] + [Fraction(1)]
+    nspan = len(pts) - 1
+    step = p if mult == p else p + 1
+    N = step * nspan + (1 if mult == p else 0)
+    M = [[Fraction(0)] * N for _ in range(N)]
+    A = [[Fraction(0)] * N for _ in range(N)]
+    for s in range(nspan):
+        h = pts[s + 1] - pts[s]
+        o = s * step
+        for a in range(p + 1):
+            for b in range(p + 1):
+                M[o + a][o + b] += h * _bern_mass(p, a, b)
+                d = (_bern_mass(p - 1, a - 1, b - 1) - _bern_mass(p - 1, a - 1, b)
+                     - _bern_mass(p - 1, a, b - 1) + _bern_mass(p - 1, a, b))
+                A[o + a][o + b] += p * p * d / h
+    return M, A
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("extra", [0, 1])
+def test_exact_1d_broken_knots_are_bernstein_blocks(p, extra):
+    """C^0 knots (multiplicity p) and C^-1 knots (multiplicity p+1): the exact
+    piecewise-polynomial 1D matrices of exact.py equal the assembled Bernstein
+    element matrices (closed forms), entry by entry as rationals."""
+    breaks = [Fraction(1, 3), Fraction(1, 2)]
+    t = ([Fraction(0)] * (p + 1) + [b for b in breaks for _ in range(p + extra)]
+         + [Fraction(1)] * (p + 1))
+    M, A = exact.matrices_1d(t, p)
+    Mr, Ar = _bern_blocks(p, breaks, p + extra)
+    assert len(M) == len(Mr) == len(t) - p - 1
+    assert M == Mr and A == Ar
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_repeated_knots_basis(orc, p):
+    """Knots with every multiplicity 1..p+1: partition of unity, non-negativity,
+    Greville reproduction (linear precision holds for any knot vector) and the
+    exact piecewise polynomials of exact.py at seeded points."""
+    fixed = W.repeated_knots([0.125, 0.25, 0.5, 0.75][:p + 1], list(range(1, p + 2)), p)
+    seeded, _ = W.random_repeated_knots(5, p, seed=40 + p)
+    rng = np.random.default_rng(7)
+    for t, x in [(t, x) for t in (fixed, seeded) for x in np.concatenate([rng.uniform(0, 1, 25), [0.0, 1.0]])]:
+        tf = [Fraction(float(v)) for v in t]
+        g = np.array([float(v) for v in exact.greville(tf, p)])
+        B, dB = orc.basis_all(t, p, x)
+        assert abs(B.sum() - 1) < 1e-14 and B.min() >= 0
+        assert abs(np.dot(g, B) - x) < 1e-14
+        vals, ders = exact.basis_values(tf, p, Fraction(float(x)))
+        np.testing.assert_allclose(B, [float(v) for v in vals], rtol=0, atol=2e-15)
+        scale = max(1.0, max(abs(float(v)) for v in ders))
+        np.testing.assert_allclose(dB, [float(v) for v in ders], rtol=0, atol=1e-13 * scale)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_global_repeated_knots_exact(orc, p):
+    """A C^0 breakpoint (x), seeded multiplicities 1..p+1 (y) and a C^-1
+    breakpoint (z), kappa = (1+x)(2+y)(3+z): the assembled matrices equal the
+    exact Kronecker forms; the elements on zero-length spans are exactly zero;
+    the pattern is the structural one."""
+    tx = W.repeated_knots([0.25, 0.6], [p, 1], p)
+    ty, _ = W.random_repeated_knots(3, p, seed=60 + p)
+    tz = W.repeated_knots([0.5], [p + 1], p)
+    knots = [tx, ty, tz]
+    K = tuple(len(t) - 2 * p - 1 for t in knots)
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    assert orc.validate(P)
+    xs = [orc.quad_nodes(P, d)[0] for d in range(3)]
+    kap = W.kappa_separable(1 + xs[0], 2 + xs[1], 3 + xs[2])
+    rp, col, Mv, Kv = orc.assemble(P, kap)
+    rp_s, col_s = _structural_pattern(P.N, p)
+    assert np.array_equal(rp, rp_s) and np.array_equal(col, col_s)
+    tf = [[Fraction(float(v)) for v in k] for k in knots]
+    Mx, Ax = exact.matrices_1d(tf[0], p, (1, 1))
+    My, Ay = exact.matrices_1d(tf[1], p, (2, 1))
+    Mz, Az = exact.matrices_1d(tf[2], p, (3, 1))
+    Mref = _fkron(Mz, My, Mx).astype(float)
+    Kref = (_fkron(Mz, My, Ax) + _fkron(Mz, Ay, Mx) + _fkron(Az, My, Mx)).astype(float)
+    Md = _csr_to_dense(rp, col, Mv, P.ndof)
+    Kd = _csr_to_dense(rp, col, Kv, P.ndof)
+    assert np.linalg.norm(Md - Mref) / np.linalg.norm(Mref) < 1e-14
+    assert np.linalg.norm(Kd - Kref) / np.linalg.norm(Kref) < 1e-13
+    Me, Ke = orc.element_matrices(P, kap)
+    h = [np.diff(t)[p:p + k] for t, k in zip(knots, K)]
+    for e in range(P.nelem):
+        ex, ey, ez = e % K[0], (e // K[0]) % K[1], e // (K[0] * K[1])
+        if h[0][ex] == 0 or h[1][ey] == 0 or h[2][ez] == 0:
+            assert not Me[e].any() and not Ke[e].any()
+        else:
+            assert Me[e].any()
+    assert min(min(x) for x in h) == 0.0    # the case has empty spans
+
+
+def test_validate_repeated_knots(orc):
+    """Multiplicity up to p+1 is accepted; p+2 (an identically zero function)
+    is refused, at an end as well as inside."""
+    p = 2
+    ok = W.repeated_knots([0.5], [p + 1], p)
+    bad = W.repeated_knots([0.5], [p + 2], p)
+    bad_end = np.concatenate([[0.0] * (p + 2), [0.5], [1.0] * (p + 1)])
+    for t, want in ((ok, True), (bad, False), (bad_end, False)):
+        k = len(t) - 2 * p - 1
+        P = orc.Patch(p, (k, 1, 1), [3] * 3, [t, W.open_uniform_knots(1, p), W.open_uniform_knots(1, p)])
+        assert orc.validate(P) == want

@@ -29,6 +29,29 @@ def open_uniform_knots(K, p, lo=0.0, hi=1.0):
     return np.array([lo] * (p + 1) + inner + [hi] * (p + 1), dtype=np.float64)
 
 
+def repeated_knots(breaks, mults, p, lo=0.0, hi=1.0):
+    """Open knot vector with interior breakpoints `breaks` (increasing, inside
+    (lo, hi)), breakpoint i repeated mults[i] times (1 <= mults[i] <= p+1):
+    the basis is C^{p - mults[i]} there.  K = len - 2p - 1 spans, the empty
+    ones included."""
+    inner = [b for b, m in zip(breaks, mults) for _ in range(int(m))]
+    return np.array([lo] * (p + 1) + list(inner) + [hi] * (p + 1), dtype=np.float64)
+
+
+def random_repeated_knots(nbreak, p, seed, max_mult=None):
+    """Seeded breakpoints (uniform, kept apart) with multiplicities drawn
+    uniformly from 1..max_mult (default p+1).  Returns (knots, K)."""
+    rng = np.random.default_rng(seed)
+    max_mult = p + 1 if max_mult is None else max_mult
+    while True:
+        breaks = np.sort(rng.uniform(0.03, 0.97, nbreak))
+        if nbreak == 0 or np.min(np.diff(np.concatenate([[0.0], breaks, [1.0]]))) > 0.2 / (nbreak + 1):
+            break
+    mults = rng.integers(1, max_mult + 1, nbreak)
+    t = repeated_knots(breaks, mults, p)
+    return t, len(t) - 2 * p - 1
+
+
 def kappa_layout(fx, fy, fz):
     """Evaluate a separable-looking field given per-direction node values.
 
