@@ -45,6 +45,10 @@ def lib():
         L.orc_element_matrices.argtypes = patch + [dp, ctypes.c_int64, ctypes.c_int64, dp, dp]
         L.orc_assemble.argtypes = patch + [dp, i64p, i32p, dp, dp, i64p]
         L.orc_rows.argtypes = patch + [dp, i64p, ctypes.c_int64, i32p, dp, dp, i32p, ctypes.c_int64]
+        L.orc_element_matrices_geo.argtypes = patch + [dp, dp, ctypes.c_int64, ctypes.c_int64, dp, dp]
+        L.orc_assemble_geo.argtypes = patch + [dp, dp, i64p, i32p, dp, dp, i64p]
+        L.orc_rows_geo.argtypes = patch + [dp, dp, i64p, ctypes.c_int64, i32p, dp, dp, i32p,
+                                           ctypes.c_int64]
         L.orc_kappa_grad.argtypes = patch + [dp, dp, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, dp]
         L.orc_num_threads.restype = ctypes.c_int
@@ -129,46 +133,66 @@ def quad_nodes(P, d):
     return x.reshape(P.K[d], P.q[d]), w.reshape(P.K[d], P.q[d])
 
 
-def element_matrices(P, kappa, e0=0, e1=None, want_m=True, want_k=True):
+def _geo_arg(P, G):
+    if G is None:
+        return None
+    G = _f64(G).reshape(-1)
+    assert G.size == P.nelem * 6 * P.nq
+    return G
+
+
+def element_matrices(P, kappa, e0=0, e1=None, want_m=True, want_k=True, G=None):
     """Classical (Algorithm 1) element matrices for elements [e0, e1):
-    arrays [e1-e0, n^3, n^3] (None where not wanted)."""
+    arrays [e1-e0, n^3, n^3] (None where not wanted).  With G (mapped
+    geometry, [E][6][q^3], components xx yy zz xy xz yz) kappa is the mass
+    coefficient cm = kappa det J and G the stiffness tensor kappa det J J^-1 J^-T."""
     if e1 is None:
         e1 = P.nelem
     kappa = _f64(kappa).reshape(-1)
     assert kappa.size == P.nelem * P.nq
+    G = _geo_arg(P, G)
     n3 = P.n ** 3
     Me = np.zeros((e1 - e0, n3, n3)) if want_m else None
     Ke = np.zeros((e1 - e0, n3, n3)) if want_k else None
-    rc = lib().orc_element_matrices(*P.args(), _dp(kappa), e0, e1, _dp(Me), _dp(Ke))
+    if G is not None:
+        rc = lib().orc_element_matrices_geo(*P.args(), _dp(kappa), _dp(G), e0, e1, _dp(Me), _dp(Ke))
+    else:
+        rc = lib().orc_element_matrices(*P.args(), _dp(kappa), e0, e1, _dp(Me), _dp(Ke))
     if rc != 0:
         raise ValueError("invalid patch or range")
     return Me, Ke
 
 
-def assemble(P, kappa):
-    """Global CSR (row_ptr int64, col int32, Mval, Kval) by brute-force union."""
+def assemble(P, kappa, G=None):
+    """Global CSR (row_ptr int64, col int32, Mval, Kval) by brute-force union
+    (with G: mapped geometry, as in element_matrices)."""
     kappa = _f64(kappa).reshape(-1)
     assert kappa.size == P.nelem * P.nq
+    G = _geo_arg(P, G)
     L = lib()
+    if G is not None:
+        call = lambda *a: L.orc_assemble_geo(*P.args(), _dp(kappa), _dp(G), *a)
+    else:
+        call = lambda *a: L.orc_assemble(*P.args(), _dp(kappa), *a)
     row_ptr = np.zeros(P.ndof + 1, dtype=np.int64)
     nnz = ctypes.c_int64(0)
     i64p = ctypes.POINTER(ctypes.c_int64)
     i32p = ctypes.POINTER(ctypes.c_int32)
-    rc = L.orc_assemble(*P.args(), _dp(kappa), row_ptr.ctypes.data_as(i64p), None, None, None,
-                        ctypes.byref(nnz))
+    rc = call(row_ptr.ctypes.data_as(i64p), None, None, None, ctypes.byref(nnz))
     if rc != 0:
         raise ValueError("invalid patch")
     col = np.zeros(nnz.value, dtype=np.int32)
     Mv = np.zeros(nnz.value)
     Kv = np.zeros(nnz.value)
-    L.orc_assemble(*P.args(), _dp(kappa), row_ptr.ctypes.data_as(i64p), col.ctypes.data_as(i32p),
-                   _dp(Mv), _dp(Kv), ctypes.byref(nnz))
+    call(row_ptr.ctypes.data_as(i64p), col.ctypes.data_as(i32p), _dp(Mv), _dp(Kv), ctypes.byref(nnz))
     return row_ptr, col, Mv, Kv
 
 
-def rows(P, kappa, dofs):
-    """Complete global rows for the given DOFs: list of (cols, mvals, kvals)."""
+def rows(P, kappa, dofs, G=None):
+    """Complete global rows for the given DOFs: list of (cols, mvals, kvals)
+    (with G: mapped geometry, as in element_matrices)."""
     kappa = _f64(kappa).reshape(-1)
+    G = _geo_arg(P, G)
     dofs = np.ascontiguousarray(dofs, dtype=np.int64)
     stride = (2 * P.p + 1) ** 3
     cols = np.zeros((len(dofs), stride), dtype=np.int32)
@@ -177,8 +201,13 @@ def rows(P, kappa, dofs):
     ln = np.zeros(len(dofs), dtype=np.int32)
     i64p = ctypes.POINTER(ctypes.c_int64)
     i32p = ctypes.POINTER(ctypes.c_int32)
-    rc = lib().orc_rows(*P.args(), _dp(kappa), dofs.ctypes.data_as(i64p), len(dofs),
-                        cols.ctypes.data_as(i32p), _dp(mv), _dp(kv), ln.ctypes.data_as(i32p), stride)
+    if G is not None:
+        rc = lib().orc_rows_geo(*P.args(), _dp(kappa), _dp(G), dofs.ctypes.data_as(i64p), len(dofs),
+                                cols.ctypes.data_as(i32p), _dp(mv), _dp(kv), ln.ctypes.data_as(i32p),
+                                stride)
+    else:
+        rc = lib().orc_rows(*P.args(), _dp(kappa), dofs.ctypes.data_as(i64p), len(dofs),
+                            cols.ctypes.data_as(i32p), _dp(mv), _dp(kv), ln.ctypes.data_as(i32p), stride)
     if rc != 0:
         raise ValueError("invalid patch")
     return [(cols[r, :ln[r]].copy(), mv[r, :ln[r]].copy(), kv[r, :ln[r]].copy()) for r in range(len(dofs))]

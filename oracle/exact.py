@@ -122,6 +122,25 @@ def matrices_1d(t, p, weight=(Fraction(1),)):
     return M, A
 
 
+def mixed_1d(t, p, weight=(Fraction(1),)):
+    """Exact 1D B[i][j] = int w N_i' N_j (derivative on the first index only),
+    the factor a cross term d/dx_c d/dx_d (c != d) of a mapped-geometry
+    stiffness leaves in each of its two directions."""
+    spans, B = basis_on_spans(t, p)
+    w = [Fraction(c) for c in weight]
+    n = len(B)
+    out = [[Fraction(0)] * n for _ in range(n)]
+    for s, (lo, hi) in enumerate(spans):
+        for i in range(n):
+            if not B[i][s]:
+                continue
+            dbi = pderiv(B[i][s])
+            for j in range(n):
+                if B[j][s]:
+                    out[i][j] += pint(pmul(w, pmul(dbi, B[j][s])), lo, hi)
+    return out
+
+
 def basis_values(t, p, x):
     """Exact values and derivatives of all basis functions at x (x inside
     [t_0, t_end]; the right end uses the last non-empty span)."""

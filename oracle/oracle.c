@@ -287,27 +287,114 @@ static void classical_element(const orc_patch* P, int ex, int ey, int ez, const 
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* Classical integration on a mapped geometry.  With x = F(xi) and      */
+/* J = dF/dxi at a point, eq. (10)'s J(x^n) slot becomes, for the mass, */
+/* the scalar cm = kappa det J and, for the stiffness, the symmetric   */
+/* 3x3 tensor G = kappa det J J^-1 J^-T, since grad_x phi =            */
+/* J^-T grad_xi phi (chain rule).  The stiffness integrand is then     */
+/* grad_xi phi_I^T G grad_xi phi_J, every term of the 3x3 product kept. */
+/* cm: the element's q^3 values [qz][qy][qx]; G: its 6 q^3 blocks in   */
+/* the order xx, yy, zz, xy, xz, yz.                                    */
+/* ------------------------------------------------------------------ */
+static void classical_element_geo(const orc_patch* P, int ex, int ey, int ez, const double* cm,
+                                  const double* G, double* Me, double* Ke)
+{
+    int p = P->p, n = p + 1, n3 = n * n * n;
+    int qx = P->q[0], qy = P->q[1], qz = P->q[2];
+    int nq = qx * qy * qz;
+    elem1d X, Y, Z;
+    element_1d(P, 0, ex, &X);
+    element_1d(P, 1, ey, &Y);
+    element_1d(P, 2, ez, &Z);
+    for (int i1 = 0; i1 < n; ++i1)              /* test x  */
+    for (int j1 = 0; j1 < n; ++j1)              /* trial x */
+    for (int i2 = 0; i2 < n; ++i2)              /* test y  */
+    for (int j2 = 0; j2 < n; ++j2)              /* trial y */
+    for (int i3 = 0; i3 < n; ++i3)              /* test z  */
+    for (int j3 = 0; j3 < n; ++j3) {            /* trial z */
+        double m = 0.0, k = 0.0;
+        for (int k1 = 0; k1 < qx; ++k1)
+        for (int k2 = 0; k2 < qy; ++k2)
+        for (int k3 = 0; k3 < qz; ++k3) {
+            int kk = k1 + qx * (k2 + qy * k3);
+            double w = X.w[k1] * Y.w[k2] * Z.w[k3];
+            double fi = X.N[i1][k1] * Y.N[i2][k2] * Z.N[i3][k3];
+            double fj = X.N[j1][k1] * Y.N[j2][k2] * Z.N[j3][k3];
+            double gi[3] = {X.dN[i1][k1] * Y.N[i2][k2] * Z.N[i3][k3],
+                            X.N[i1][k1] * Y.dN[i2][k2] * Z.N[i3][k3],
+                            X.N[i1][k1] * Y.N[i2][k2] * Z.dN[i3][k3]};
+            double gj[3] = {X.dN[j1][k1] * Y.N[j2][k2] * Z.N[j3][k3],
+                            X.N[j1][k1] * Y.dN[j2][k2] * Z.N[j3][k3],
+                            X.N[j1][k1] * Y.N[j2][k2] * Z.dN[j3][k3]};
+            double Gm[3][3];
+            Gm[0][0] = G[0 * nq + kk];
+            Gm[1][1] = G[1 * nq + kk];
+            Gm[2][2] = G[2 * nq + kk];
+            Gm[0][1] = Gm[1][0] = G[3 * nq + kk];
+            Gm[0][2] = Gm[2][0] = G[4 * nq + kk];
+            Gm[1][2] = Gm[2][1] = G[5 * nq + kk];
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) s += gi[a] * Gm[a][b] * gj[b];
+            m += w * cm[kk] * fi * fj;
+            k += w * s;
+        }
+        int I = i1 + n * (i2 + n * i3);
+        int J = j1 + n * (j2 + n * j3);
+        if (Me) Me[(size_t)I * n3 + J] = m;
+        if (Ke) Ke[(size_t)I * n3 + J] = k;
+    }
+}
+
+/* One element by either integrand: G == NULL is the identity geometry with
+ * kappa in the J(x^n) slot; otherwise (cm, G) as above. */
+static void element_any(const orc_patch* P, int64_t e, const double* c, const double* G,
+                        double* Me, double* Ke)
+{
+    int ex = (int)(e % P->K[0]);
+    int ey = (int)((e / P->K[0]) % P->K[1]);
+    int ez = (int)(e / ((int64_t)P->K[0] * P->K[1]));
+    int64_t nq = (int64_t)P->q[0] * P->q[1] * P->q[2];
+    if (G)
+        classical_element_geo(P, ex, ey, ez, c + e * nq, G + e * 6 * nq, Me, Ke);
+    else
+        classical_element(P, ex, ey, ez, c + e * nq, Me, Ke);
+}
+
 /* Element matrices for elements [e0, e1) (flat index e = ex + Kx(ey + Ky ez)).
  * kappa is the FULL [E][q^3] array; Me/Ke receive (e1-e0) matrices. */
+static int element_matrices_any(int p, const int* K, const int* q, const double* tx,
+                                const double* ty, const double* tz, const double* c,
+                                const double* G, int64_t e0, int64_t e1, double* Me, double* Ke)
+{
+    if (orc_validate(p, K, q, tx, ty, tz) || !c) return -1;
+    orc_patch P = make_patch(p, K, q, tx, ty, tz);
+    int64_t n3 = (int64_t)(p + 1) * (p + 1) * (p + 1);
+    int64_t E = (int64_t)K[0] * K[1] * K[2];
+    if (e0 < 0 || e1 > E || e0 > e1) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t e = e0; e < e1; ++e)
+        element_any(&P, e, c, G, Me ? Me + (e - e0) * n3 * n3 : NULL,
+                    Ke ? Ke + (e - e0) * n3 * n3 : NULL);
+    return 0;
+}
+
 int orc_element_matrices(int p, const int* K, const int* q, const double* tx, const double* ty,
                          const double* tz, const double* kappa, int64_t e0, int64_t e1,
                          double* Me, double* Ke)
 {
-    if (orc_validate(p, K, q, tx, ty, tz)) return -1;
-    orc_patch P = make_patch(p, K, q, tx, ty, tz);
-    int64_t n3 = (int64_t)(p + 1) * (p + 1) * (p + 1);
-    int64_t nq = (int64_t)q[0] * q[1] * q[2];
-    int64_t E = (int64_t)K[0] * K[1] * K[2];
-    if (e0 < 0 || e1 > E || e0 > e1) return -1;
-#pragma omp parallel for schedule(dynamic, 4)
-    for (int64_t e = e0; e < e1; ++e) {
-        int ex = (int)(e % K[0]);
-        int ey = (int)((e / K[0]) % K[1]);
-        int ez = (int)(e / ((int64_t)K[0] * K[1]));
-        classical_element(&P, ex, ey, ez, kappa + e * nq, Me ? Me + (e - e0) * n3 * n3 : NULL,
-                          Ke ? Ke + (e - e0) * n3 * n3 : NULL);
-    }
-    return 0;
+    return element_matrices_any(p, K, q, tx, ty, tz, kappa, NULL, e0, e1, Me, Ke);
+}
+
+/* The same on a mapped geometry: cm [E][q^3], G [E][6][q^3] (see
+ * classical_element_geo). */
+int orc_element_matrices_geo(int p, const int* K, const int* q, const double* tx,
+                             const double* ty, const double* tz, const double* cm,
+                             const double* G, int64_t e0, int64_t e1, double* Me, double* Ke)
+{
+    if (!G) return -1;
+    return element_matrices_any(p, K, q, tx, ty, tz, cm, G, e0, e1, Me, Ke);
 }
 
 /* ------------------------------------------------------------------ */
@@ -360,9 +447,9 @@ static int64_t ndof_of(const orc_patch* P)
  * function only returns nnz through *nnz_out (and fills row_ptr[ndof+1]);
  * with buffers it fills col[nnz], Mval[nnz], Kval[nnz] (Mval/Kval nullable).
  * kappa: [E][q^3]. */
-int orc_assemble(int p, const int* K, const int* q, const double* tx, const double* ty,
-                 const double* tz, const double* kappa, int64_t* row_ptr, int32_t* col,
-                 double* Mval, double* Kval, int64_t* nnz_out)
+static int assemble_any(int p, const int* K, const int* q, const double* tx, const double* ty,
+                        const double* tz, const double* kappa, const double* G, int64_t* row_ptr,
+                        int32_t* col, double* Mval, double* Kval, int64_t* nnz_out)
 {
     if (orc_validate(p, K, q, tx, ty, tz) || !kappa) return -1;
     orc_patch P = make_patch(p, K, q, tx, ty, tz);
@@ -370,7 +457,6 @@ int orc_assemble(int p, const int* K, const int* q, const double* tx, const doub
     int64_t E = (int64_t)K[0] * K[1] * K[2];
     int64_t N = ndof_of(&P);
     int Nx = K[0] + p, Ny = K[1] + p;
-    int64_t nq = (int64_t)q[0] * q[1] * q[2];
     orc_row* rows = (orc_row*)calloc((size_t)N, sizeof(orc_row));
     double* Me = (double*)malloc(sizeof(double) * (size_t)n3 * n3);
     double* Ke = (double*)malloc(sizeof(double) * (size_t)n3 * n3);
@@ -378,7 +464,7 @@ int orc_assemble(int p, const int* K, const int* q, const double* tx, const doub
         int ex = (int)(e % K[0]);
         int ey = (int)((e / K[0]) % K[1]);
         int ez = (int)(e / ((int64_t)K[0] * K[1]));
-        classical_element(&P, ex, ey, ez, kappa + e * nq, Me, Ke);
+        element_any(&P, e, kappa, G, Me, Ke);
         for (int I = 0; I < n3; ++I) {
             int a1 = I % n, a2 = (I / n) % n, a3 = I / (n * n);
             int64_t gI = (ex + a1) + (int64_t)Nx * ((ey + a2) + (int64_t)Ny * (ez + a3));
@@ -417,20 +503,36 @@ int orc_assemble(int p, const int* K, const int* q, const double* tx, const doub
     return 0;
 }
 
+int orc_assemble(int p, const int* K, const int* q, const double* tx, const double* ty,
+                 const double* tz, const double* kappa, int64_t* row_ptr, int32_t* col,
+                 double* Mval, double* Kval, int64_t* nnz_out)
+{
+    return assemble_any(p, K, q, tx, ty, tz, kappa, NULL, row_ptr, col, Mval, Kval, nnz_out);
+}
+
+/* The same on a mapped geometry: cm [E][q^3], G [E][6][q^3]. */
+int orc_assemble_geo(int p, const int* K, const int* q, const double* tx, const double* ty,
+                     const double* tz, const double* cm, const double* G, int64_t* row_ptr,
+                     int32_t* col, double* Mval, double* Kval, int64_t* nnz_out)
+{
+    if (!G) return -1;
+    return assemble_any(p, K, q, tx, ty, tz, cm, G, row_ptr, col, Mval, Kval, nnz_out);
+}
+
 /* Complete rows of the global matrices for selected DOFs, without building
  * the whole matrix: each row is the sum, over the elements that carry the
  * DOF (Remark "element-by-element pre-computations"), of that element's
  * matrix row.  Output per selected row: up to (2p+1)^3 entries, written at
  * out_col/out_m/out_k + r*stride, with out_len[r] entries (columns sorted). */
-int orc_rows(int p, const int* K, const int* q, const double* tx, const double* ty,
-             const double* tz, const double* kappa, const int64_t* dofs, int64_t ndofs,
-             int32_t* out_col, double* out_m, double* out_k, int32_t* out_len, int64_t stride)
+static int rows_any(int p, const int* K, const int* q, const double* tx, const double* ty,
+                    const double* tz, const double* kappa, const double* G, const int64_t* dofs,
+                    int64_t ndofs, int32_t* out_col, double* out_m, double* out_k,
+                    int32_t* out_len, int64_t stride)
 {
-    if (orc_validate(p, K, q, tx, ty, tz)) return -1;
+    if (orc_validate(p, K, q, tx, ty, tz) || !kappa) return -1;
     orc_patch P = make_patch(p, K, q, tx, ty, tz);
     int n = p + 1, n3 = n * n * n;
     int Nd[3] = {K[0] + p, K[1] + p, K[2] + p};
-    int64_t nq = (int64_t)q[0] * q[1] * q[2];
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t r = 0; r < ndofs; ++r) {
         int64_t g = dofs[r];
@@ -444,7 +546,7 @@ int orc_rows(int p, const int* K, const int* q, const double* tx, const double* 
             int a1 = i[0] - ex, a2 = i[1] - ey, a3 = i[2] - ez;
             if (a1 < 0 || a1 > p || a2 < 0 || a2 > p || a3 < 0 || a3 > p) continue;
             int64_t e = ex + (int64_t)K[0] * (ey + (int64_t)K[1] * ez);
-            classical_element(&P, ex, ey, ez, kappa + e * nq, Me, Ke);
+            element_any(&P, e, kappa, G, Me, Ke);
             int I = a1 + n * (a2 + n * a3);
             for (int J = 0; J < n3; ++J) {
                 int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
@@ -465,6 +567,24 @@ int orc_rows(int p, const int* K, const int* q, const double* tx, const double* 
         free(Ke);
     }
     return 0;
+}
+
+int orc_rows(int p, const int* K, const int* q, const double* tx, const double* ty,
+             const double* tz, const double* kappa, const int64_t* dofs, int64_t ndofs,
+             int32_t* out_col, double* out_m, double* out_k, int32_t* out_len, int64_t stride)
+{
+    return rows_any(p, K, q, tx, ty, tz, kappa, NULL, dofs, ndofs, out_col, out_m, out_k, out_len,
+                    stride);
+}
+
+/* The same on a mapped geometry: cm [E][q^3], G [E][6][q^3]. */
+int orc_rows_geo(int p, const int* K, const int* q, const double* tx, const double* ty,
+                 const double* tz, const double* cm, const double* G, const int64_t* dofs,
+                 int64_t ndofs, int32_t* out_col, double* out_m, double* out_k, int32_t* out_len,
+                 int64_t stride)
+{
+    if (!G) return -1;
+    return rows_any(p, K, q, tx, ty, tz, cm, G, dofs, ndofs, out_col, out_m, out_k, out_len, stride);
 }
 
 /* ------------------------------------------------------------------ */

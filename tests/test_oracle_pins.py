@@ -489,3 +489,149 @@ def test_validate_repeated_knots(orc):
         k = len(t) - 2 * p - 1
         P = orc.Patch(p, (k, 1, 1), [3] * 3, [t, W.open_uniform_knots(1, p), W.open_uniform_knots(1, p)])
         assert orc.validate(P) == want
+
+
+# ---------------------------------------------------------------- mapped geometry
+# x = F(xi): mass coefficient cm = kappa det J, stiffness tensor
+# G = kappa det J J^-1 J^-T per point (workloads.mapped_geometry builds them).
+
+
+def test_exact_mixed_1d_integration_by_parts():
+    """int N_i' N_j + int N_i N_j' = [N_i N_j] at the ends, which on an open
+    knot vector is e_last e_last^T - e_0 e_0^T; exact rationals."""
+    for p, K in [(1, 3), (2, 4), (3, 2), (4, 3)]:
+        for t in (exact.open_uniform_knots(K, p),
+                  [Fraction(0)] * (p + 1) + [Fraction(1, 3)] * p + [Fraction(1)] * (p + 1)):
+            B = exact.mixed_1d(t, p)
+            n = len(B)
+            for i in range(n):
+                for j in range(n):
+                    want = (1 if i == j == n - 1 else 0) - (1 if i == j == 0 else 0)
+                    assert B[i][j] + B[j][i] == want
+
+
+def _greville_dofs(knots, p):
+    g = [np.array([float(v) for v in exact.greville([Fraction(float(x)) for x in t], p)]) for t in knots]
+    N = [len(v) for v in g]
+    i = np.arange(N[0] * N[1] * N[2])
+    return np.stack([g[0][i % N[0]], g[1][(i // N[0]) % N[1]], g[2][i // (N[0] * N[1])]], axis=1)
+
+
+def _points(orc, P):
+    """Parametric node coordinates per direction and the per-point weight
+    product, both in kappa layout [E][q^3]."""
+    xs = [orc.quad_nodes(P, d) for d in range(3)]
+    one = [np.ones_like(x[0]) for x in xs]
+    X = W.kappa_separable(xs[0][0], one[1], one[2])
+    Y = W.kappa_separable(one[0], xs[1][0], one[2])
+    Z = W.kappa_separable(one[0], one[1], xs[2][0])
+    wq = W.kappa_separable(xs[0][1], xs[1][1], xs[2][1])
+    return xs, np.stack([X, Y, Z], axis=-1), wq
+
+
+def test_geometry_scaling_equals_scaled_knots(orc):
+    """F(xi) = diag(s) xi: integrating on the parameter cube with (cm, G) equals
+    the identity-geometry oracle on knot vectors scaled to [0, s_d] (the same
+    points, the same kappa values): element matrices and CSR values."""
+    p, K, s = 2, (3, 2, 4), (2.0, 0.5, 3.0)
+    knots = [_nonuniform_knots(k, p, 30 + d) for d, k in enumerate(K)]
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    xs, _, _ = _points(orc, P)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=8)
+    cm, G = W.mapped_geometry(xs[0][0], xs[1][0], xs[2][0], kap, A=np.diag(s))
+    Ps = orc.Patch(p, K, [p + 1] * 3, [k * sd for k, sd in zip(knots, s)])
+    Me, Ke = orc.element_matrices(P, cm, G=G)
+    Me_s, Ke_s = orc.element_matrices(Ps, kap)
+    assert np.linalg.norm(Me - Me_s) <= 1e-14 * np.linalg.norm(Me_s)
+    assert np.linalg.norm(Ke - Ke_s) <= 1e-13 * np.linalg.norm(Ke_s)
+    _, _, Mv, Kv = orc.assemble(P, cm, G=G)
+    _, _, Mv_s, Kv_s = orc.assemble(Ps, kap)
+    assert np.linalg.norm(Mv - Mv_s) <= 1e-14 * np.linalg.norm(Mv_s)
+    assert np.linalg.norm(Kv - Kv_s) <= 1e-13 * np.linalg.norm(Kv_s)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_geometry_affine_kronecker(orc, p):
+    """A general (non-symmetric) affine map and kappa = 1: the assembled
+    stiffness equals sum_{c,d} G_cd T_cd with the exact 1D factors,
+    T_cc = (A1 in direction c, M1 elsewhere) and, for c != d, B1 = int N' N in
+    direction c, its transpose in direction d (x fastest Kronecker order);
+    the mass equals det(A) M1 (x) M1 (x) M1."""
+    K = (3, 2, 3)
+    A = np.array([[1.5, 0.4, -0.2], [0.1, 0.8, 0.3], [-0.3, 0.2, 1.2]])
+    knots = [W.open_uniform_knots(K[0], p), _nonuniform_knots(2, p, 3), _nonuniform_knots(3, p, 4)]
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    xs, _, _ = _points(orc, P)
+    cm, G = W.mapped_geometry(xs[0][0], xs[1][0], xs[2][0], W.kappa_constant(P.nelem, P.nq), A=A)
+    rp, col, Mv, Kv = orc.assemble(P, cm, G=G)
+    tf = [[Fraction(float(v)) for v in k] for k in knots]
+    M1, A1, B1 = [], [], []
+    for d in range(3):
+        m, a = exact.matrices_1d(tf[d], p)
+        M1.append(np.array(m, dtype=object))
+        A1.append(np.array(a, dtype=object))
+        B1.append(np.array(exact.mixed_1d(tf[d], p), dtype=object))
+    Ai = np.linalg.inv(A)
+    Gc = np.linalg.det(A) * Ai @ Ai.T
+
+    def factor(d, c, e):
+        """1D factor of direction d in the term d/dx_c (test) d/dx_e (trial)."""
+        if d == c and d == e:
+            return A1[d]
+        if d == c:
+            return B1[d]
+        if d == e:
+            return B1[d].T
+        return M1[d]
+
+    Kref = np.zeros((P.ndof, P.ndof))
+    for c in range(3):
+        for e in range(3):
+            Kref += Gc[c, e] * _fkron(factor(2, c, e), factor(1, c, e), factor(0, c, e)).astype(float)
+    Mref = np.linalg.det(A) * _fkron(M1[2], M1[1], M1[0]).astype(float)
+    Kd = _csr_to_dense(rp, col, Kv, P.ndof)
+    Md = _csr_to_dense(rp, col, Mv, P.ndof)
+    assert np.linalg.norm(Kd - Kref) <= 1e-13 * np.linalg.norm(Kref)
+    assert np.linalg.norm(Md - Mref) <= 1e-14 * np.linalg.norm(Mref)
+
+
+def test_geometry_linear_patch_tests(orc):
+    """(a) Affine map, log-normal kappa: physical linear functions are in the
+    space (u_I = c.(A xi*_I + b) + d at the Greville points), so
+    u^T K v = (c1.c2) sum_q w_q cm_q and u^T M v = sum_q w_q cm_q u(x_q) v(x_q)
+    exactly (the quadrature sees the exact integrand).  (b) A curved map
+    (amp = 0.1): parametric linear functions u = c.xi* give
+    u^T K v = sum_q w_q c1^T G_q c2.  Both: K 1 = 0 and symmetry."""
+    p, K = 3, (3, 4, 2)
+    knots = [_nonuniform_knots(k, p, 50 + d) for d, k in enumerate(K)]
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    xs, XI, wq = _points(orc, P)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=12)
+    gr = _greville_dofs(knots, p)
+    c1, c2 = np.array([0.7, -1.2, 0.4]), np.array([-0.3, 0.9, 1.6])
+    A = np.array([[1.2, -0.3, 0.25], [0.15, 0.9, -0.2], [0.05, 0.4, 1.1]])
+    b = np.array([0.3, -0.1, 0.2])
+    # (a) affine
+    cm, G = W.mapped_geometry(xs[0][0], xs[1][0], xs[2][0], kap, A=A, b=b)
+    rp, col, Mv, Kv = orc.assemble(P, cm, G=G)
+    Kd = _csr_to_dense(rp, col, Kv, P.ndof)
+    Md = _csr_to_dense(rp, col, Mv, P.ndof)
+    xg = gr @ A.T + b
+    u, v = xg @ c1 + 0.5, xg @ c2 - 0.25
+    vol = math.fsum((wq * cm).ravel().tolist())
+    assert abs(u @ Kd @ v - np.dot(c1, c2) * vol) <= 1e-12 * abs(np.dot(c1, c2) * vol)
+    xq = XI @ A.T + b
+    mref = math.fsum((wq * cm * (xq @ c1 + 0.5) * (xq @ c2 - 0.25)).ravel().tolist())
+    assert abs(u @ Md @ v - mref) <= 1e-12 * math.fsum(np.abs(wq * cm).ravel().tolist())
+    # (b) curved
+    cm2, G2 = W.mapped_geometry(xs[0][0], xs[1][0], xs[2][0], kap, amp=0.1)
+    rp, col, Mv2, Kv2 = orc.assemble(P, cm2, G=G2)
+    Kd2 = _csr_to_dense(rp, col, Kv2, P.ndof)
+    Gq = np.zeros(G2.shape[:1] + G2.shape[2:] + (3, 3))
+    for c, (r, t) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        Gq[..., r, t] = Gq[..., t, r] = G2[:, c, :]
+    kref = math.fsum((wq * np.einsum("a,...ab,b->...", c1, Gq, c2)).ravel().tolist())
+    assert abs((gr @ c1) @ Kd2 @ (gr @ c2) - kref) <= 1e-12 * abs(kref)
+    for Kk in (Kd, Kd2):
+        assert np.abs(Kk.sum(axis=1)).max() <= 1e-13 * np.abs(Kk).sum(axis=1).max()
+        assert np.abs(Kk - Kk.T).max() <= 1e-14 * np.abs(Kk).max()

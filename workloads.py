@@ -13,6 +13,8 @@ Workloads (unit cube, open uniform knots, Gauss rule with q = p+1):
   W4  256 patches (seed 1): K_d ~ U{8..48}, p ~ U{2..5}, kappa log-normal(0, 0.5)
   W5  96^3 elements,  p=3, kappa log-normal (seed 2), u, v ~ N(0,1) (seeds 3, 4),
       100 finite-difference points (seed 5)
+  W6  64^3 elements,  p=3, mapped geometry (mapped_geometry, amp 0.1, A = I),
+      kappa as W2
 """
 import numpy as np
 
@@ -21,6 +23,7 @@ W2 = dict(name="W2", K=(64, 64, 64), p=3)
 W3 = dict(name="W3", K=(128, 128, 128), ps=(2, 3, 4), seed=0)
 W4 = dict(name="W4", npatch=256, seed=1, kmin=8, kmax=48, ps=(2, 3, 4, 5))
 W5 = dict(name="W5", K=(96, 96, 96), p=3, seed_kappa=2, seed_u=3, seed_v=4, seed_pts=5, npts=100)
+W6 = dict(name="W6", K=(64, 64, 64), p=3, amp=0.1)
 
 
 def open_uniform_knots(K, p, lo=0.0, hi=1.0):
@@ -80,6 +83,52 @@ def kappa_separable(fx, fy, fz):
     """kappa = fx(x) fy(y) fz(z) from per-direction node values [K_d, q_d]."""
     return kappa_layout(np.asarray(fx, dtype=np.float64), np.asarray(fy, dtype=np.float64),
                         np.asarray(fz, dtype=np.float64))
+
+
+def mapped_geometry(xn, yn, zn, kappa, A=None, b=None, amp=0.0):
+    """Per-point coefficients of a mapped geometry x = F(xi) of the unit cube,
+
+        F(xi) = A xi + b + amp (sin(pi y) sin(pi z), sin(pi z) sin(pi x), sin(pi x) sin(pi y)),
+
+    at the parametric nodes xn, yn, zn ([K_d, q_d] per direction).  This is the
+    caller's side of the geometry (the pull-back of the physical integrals to
+    the parameter cube); the integration itself takes the result as input:
+
+        cm = kappa det J                 [E][q^3]      (mass)
+        G  = kappa det J J^-1 J^-T       [E][6][q^3]   (stiffness; xx yy zz xy xz yz)
+
+    with J = dF/dxi.  A defaults to the identity; det J must stay positive
+    (|amp| pi small against A)."""
+    A = np.eye(3) if A is None else np.asarray(A, dtype=np.float64)
+    one = [np.ones_like(np.asarray(v, dtype=np.float64)) for v in (xn, yn, zn)]
+    X = kappa_layout(np.asarray(xn, dtype=np.float64), one[1], one[2])
+    Y = kappa_layout(one[0], np.asarray(yn, dtype=np.float64), one[2])
+    Z = kappa_layout(one[0], one[1], np.asarray(zn, dtype=np.float64))
+    sx, cx = np.sin(np.pi * X), np.cos(np.pi * X)
+    sy, cy = np.sin(np.pi * Y), np.cos(np.pi * Y)
+    sz, cz = np.sin(np.pi * Z), np.cos(np.pi * Z)
+    a = amp * np.pi
+    zero = np.zeros_like(X)
+    # J[r][c] = d F_r / d xi_c
+    J = [[A[0, 0] + zero, A[0, 1] + a * cy * sz, A[0, 2] + a * sy * cz],
+         [A[1, 0] + a * cx * sz, A[1, 1] + zero, A[1, 2] + a * sx * cz],
+         [A[2, 0] + a * cx * sy, A[2, 1] + a * sx * cy, A[2, 2] + zero]]
+    # adjugate: J^-1 = adj / det
+    adj = [[J[1][1] * J[2][2] - J[1][2] * J[2][1], J[0][2] * J[2][1] - J[0][1] * J[2][2],
+            J[0][1] * J[1][2] - J[0][2] * J[1][1]],
+           [J[1][2] * J[2][0] - J[1][0] * J[2][2], J[0][0] * J[2][2] - J[0][2] * J[2][0],
+            J[0][2] * J[1][0] - J[0][0] * J[1][2]],
+           [J[1][0] * J[2][1] - J[1][1] * J[2][0], J[0][1] * J[2][0] - J[0][0] * J[2][1],
+            J[0][0] * J[1][1] - J[0][1] * J[1][0]]]
+    det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0]
+    if np.min(det) <= 0:
+        raise ValueError("geometry map folds over (det J <= 0)")
+    kappa = np.asarray(kappa, dtype=np.float64)
+    f = kappa / det             # kappa det J (adj/det)(adj/det)^T = kappa/det adj adj^T
+    G = np.empty((X.shape[0], 6, X.shape[1]))
+    for c, (r, t) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        G[:, c, :] = f * (adj[r][0] * adj[t][0] + adj[r][1] * adj[t][1] + adj[r][2] * adj[t][2])
+    return kappa * det, G
 
 
 def kappa_lognormal(nelem, nq, seed, sigma=0.5):
