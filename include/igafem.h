@@ -192,6 +192,29 @@ igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const
                                     double* Me, double* Ke, double* Mval, double* Kval,
                                     void* stream);
 
+/* Mapped geometry: the integrals of eq. (10) on x = F(xi), pulled back to
+ * the parameter cube.  The per-point factor J(x^n) of eq. (10) becomes, for
+ * the mass, cm = kappa det J and, for the stiffness, the symmetric tensor
+ * G = kappa det J J^-1 J^-T (J = dF/dxi), which the caller evaluates at the
+ * quadrature points (igaf_quad_nodes gives them):
+ *   M_e[I][J] = sum_q w_q cm_q phi_I phi_J
+ *   K_e[I][J] = sum_q w_q grad_xi phi_I^T G_q grad_xi phi_J
+ * cm   DEVICE [E][q^3] (required when Me or Mval is requested)
+ * G    DEVICE [E][6][q^3]: per element six [qz][qy][qx] blocks, the
+ *      components xx, yy, zz, xy, xz, yz (required when Ke or Kval is)
+ * Me, Ke   DEVICE [E][n^3][n^3] or NULL;  Mval, Kval DEVICE [nnz] or NULL,
+ *      OVERWRITTEN with the assembled CSR values (structural pattern of
+ *      igaf_csr_pattern), added with FP64 atomics: the last bits may vary
+ *      from call to call.  At least one output.
+ * Sum factorisation (Algorithm 2) with ordered per-direction pairs (the
+ * cross terms of G are not symmetric in a pair); nquad = degree+1 in every
+ * direction, else IGAF_EUNSUPPORTED.  cm = kappa, G = kappa I (the identity
+ * geometry) gives the matrices of igaf_integrate_assemble.  Asynchronous on
+ * `stream`. */
+igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm, const double* G,
+                                        double* Me, double* Ke, double* Mval, double* Kval,
+                                        void* stream);
+
 /* Adjoint of L(kappa) = alphaM u^T M(kappa) v + alphaK u^T K(kappa) v with
  * respect to kappa at every quadrature point (L is linear in kappa through
  * the J(x^n) slot of eq. 10):

@@ -1,0 +1,239 @@
+// Element matrices on a mapped geometry x = F(xi) of the parameter cube.
+//
+// Eq. (10) integrates with a per-point factor J(x^n); on a mapped geometry
+// the pull-back to the parameter cube gives, per quadrature point,
+//   mass:       cm = kappa det J                    (a scalar, as before)
+//   stiffness:  G  = kappa det J J^-1 J^-T          (a symmetric 3x3 tensor)
+// since grad_x phi = J^-T grad_xi phi.  The caller evaluates both at the
+// points (its geometry is its own); this file integrates
+//   M_e[I][J] = sum_q cm_q phi_I phi_J
+//   K_e[I][J] = sum_q sum_{c,d} G_cd,q d_c phi_I d_d phi_J
+// by sum factorisation (Algorithm 2 order, z -> y -> x).  A diagonal term
+// G_cc keeps the symmetric per-direction factors N_aN_b and N'_aN'_b of the
+// identity geometry; a cross term G_cd (c != d) puts N'_a N_b in direction c
+// and N_a N'_b in direction d, which are not symmetric in (a, b), so every
+// direction works with ordered pairs (n^2 per direction, n^6 values).
+//
+// Per direction and element the ordered-pair tables are
+//   nn[a][b][k] = w N_a N_b,  dd = w N'_a N'_b,  dn = w N'_a N_b  (nd[a][b] = dn[b][a])
+// and the stages, for one test-z index a3 at a time (z pairs (a3, b3)):
+//   stage z  (9 sums over kz):  D0 = nn.cm  D1 = nn.Gxx  D2 = nn.Gyy  D3 = dd.Gzz
+//                               D4 = nn.Gxy D5 = nd.Gxz  D6 = dn.Gxz  D7 = nd.Gyz  D8 = dn.Gyz
+//   stage y  (5 sums over ky), grouped by the x factor they meet:
+//     CM  = nn D0                                  (mass, x factor nn)
+//     Cnn = dd D2 + nn D3 + dn D7 + nd D8          (Kyy, Kzz, Kyz; x factor nn)
+//     Cdd = nn D1                                  (Kxx; x factor dd)
+//     Cdn = nd D4 + nn D5                          (Kxy, Kxz; x factor dn)
+//     Cnd = dn D4 + nn D6                          (Kxy, Kxz; x factor nd)
+//   stage x  (sum over kx):  M = nn CM,  K = nn Cnn + dd Cdd + dn Cdn + nd Cnd.
+// The rows of one a3 are contiguous in M_e / K_e (n^2 rows of n^3), so the
+// stores of one stage x are one contiguous run per matrix.
+//
+// One 256-thread workgroup per element (grid-stride), the stages in LDS; the
+// next element's point coefficients are fetched into registers while the
+// current one is computed.  With CSR outputs the values are added with FP64
+// atomics at their structural positions.
+#include "common.h"
+#include "launch.h"
+
+namespace igaf {
+
+constexpr int kGeoThreads = 256;
+
+template <int P>
+struct GeoShape {
+    static constexpr int n = P + 1, Q = P + 1;
+    static constexpr int n2 = n * n, n3 = n2 * n, n5 = n3 * n2, n6 = n3 * n3;
+    static constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
+    static constexpr int NF = 7;                 // cm, Gxx, Gyy, Gzz, Gxy, Gxz, Gyz
+    static constexpr int TAB = n2 * Q;           // one ordered-pair table of one direction
+    static constexpr int DSZ = n * Q2;           // stage z result: [b3][kx][ky]
+    static constexpr int CSZ = n2 * n * Q;       // stage y result: [a2 b2][b3][kx]
+    static constexpr int NPF = (NF * Q3 + kGeoThreads - 1) / kGeoThreads;
+};
+
+template <int P, bool ATOMIC>
+__global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap rm,
+                                                             const double* __restrict__ cm,
+                                                             const double* __restrict__ G,
+                                                             double* __restrict__ Me,
+                                                             double* __restrict__ Ke,
+                                                             double* __restrict__ Mv,
+                                                             double* __restrict__ Kv)
+{
+    using Sh = GeoShape<P>;
+    constexpr int n = Sh::n, Q = Sh::Q, n3 = Sh::n3, Q3 = Sh::Q3, T = kGeoThreads;
+    __shared__ double fld[Sh::NF][Q3];
+    __shared__ double tab[3][3][Sh::TAB];        // [dir][nn, dd, dn][(a n + b) Q + k]
+    __shared__ double D[9][Sh::DSZ];
+    __shared__ double C[5][Sh::CSZ];
+
+    const int tid = threadIdx.x;
+    const int Kx = pd.d[0].K, Ky = pd.d[1].K;
+    const bool want_m = Me || Mv, want_k = Ke || Kv;
+
+    double pf[Sh::NPF];
+    auto fetch = [&](int64_t e) {
+#pragma unroll
+        for (int r = 0; r < Sh::NPF; ++r) {
+            const int i = tid + r * T;
+            double v = 0.0;
+            if (i < Q3) {
+                if (want_m) v = cm[e * Q3 + i];
+            } else if (i < Sh::NF * Q3) {
+                if (want_k) v = G[(e * 6 + (i / Q3 - 1)) * Q3 + i % Q3];
+            }
+            pf[r] = v;
+        }
+    };
+    if (blockIdx.x < pd.E) fetch(blockIdx.x);
+
+    for (int64_t e = blockIdx.x; e < pd.E; e += gridDim.x) {
+        const int ex = (int)(e % Kx);
+        const int ey = (int)((e / Kx) % Ky);
+        const int ez = (int)(e / ((int64_t)Kx * Ky));
+#pragma unroll
+        for (int r = 0; r < Sh::NPF; ++r)
+            if (tid + r * T < Sh::NF * Q3) (&fld[0][0])[tid + r * T] = pf[r];
+        for (int i = tid; i < 3 * Sh::TAB; i += T) {
+            const int d = i / Sh::TAB, r = i % Sh::TAB;
+            const int a = r / (n * Q), b = (r / Q) % n, k = r % Q;
+            const int ed = d == 0 ? ex : (d == 1 ? ey : ez);
+            const DirTables& t = pd.d[d];
+            const double w = t.wq[(int64_t)ed * Q + k];
+            const double Na = t.Nv[((int64_t)ed * n + a) * Q + k], Nb = t.Nv[((int64_t)ed * n + b) * Q + k];
+            const double Da = t.dN[((int64_t)ed * n + a) * Q + k], Db = t.dN[((int64_t)ed * n + b) * Q + k];
+            tab[d][0][r] = w * Na * Nb;
+            tab[d][1][r] = w * Da * Db;
+            tab[d][2][r] = w * Da * Nb;
+        }
+        __syncthreads();
+        if (e + gridDim.x < pd.E) fetch(e + gridDim.x);
+
+        for (int a3 = 0; a3 < n; ++a3) {
+            for (int i = tid; i < Sh::DSZ; i += T) {          // stage z
+                const int b3 = i / Sh::Q2, kx = (i / Q) % Q, ky = i % Q;
+                double d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int kz = 0; kz < Q; ++kz) {
+                    const int kk = kx + Q * (ky + Q * kz);
+                    const double nnz = tab[2][0][(a3 * n + b3) * Q + kz];
+                    const double ddz = tab[2][1][(a3 * n + b3) * Q + kz];
+                    const double dnz = tab[2][2][(a3 * n + b3) * Q + kz];
+                    const double ndz = tab[2][2][(b3 * n + a3) * Q + kz];
+                    d[0] += nnz * fld[0][kk];
+                    d[1] += nnz * fld[1][kk];
+                    d[2] += nnz * fld[2][kk];
+                    d[3] += ddz * fld[3][kk];
+                    d[4] += nnz * fld[4][kk];
+                    d[5] += ndz * fld[5][kk];
+                    d[6] += dnz * fld[5][kk];
+                    d[7] += ndz * fld[6][kk];
+                    d[8] += dnz * fld[6][kk];
+                }
+#pragma unroll
+                for (int f = 0; f < 9; ++f) D[f][i] = d[f];
+            }
+            __syncthreads();
+            for (int i = tid; i < Sh::CSZ; i += T) {          // stage y
+                const int yp = i / (n * Q), b3 = (i / Q) % n, kx = i % Q;
+                const int a2 = yp / n, b2 = yp % n;
+                double cM = 0.0, cnn = 0.0, cdd = 0.0, cdn = 0.0, cnd = 0.0;
+#pragma unroll
+                for (int ky = 0; ky < Q; ++ky) {
+                    const double nny = tab[1][0][yp * Q + ky];
+                    const double ddy = tab[1][1][yp * Q + ky];
+                    const double dny = tab[1][2][yp * Q + ky];
+                    const double ndy = tab[1][2][(b2 * n + a2) * Q + ky];
+                    const int j = (b3 * Q + kx) * Q + ky;
+                    cM += nny * D[0][j];
+                    cnn += ddy * D[2][j];
+                    cnn += nny * D[3][j];
+                    cnn += dny * D[7][j];
+                    cnn += ndy * D[8][j];
+                    cdd += nny * D[1][j];
+                    cdn += ndy * D[4][j];
+                    cdn += nny * D[5][j];
+                    cnd += dny * D[4][j];
+                    cnd += nny * D[6][j];
+                }
+                C[0][i] = cM;
+                C[1][i] = cnn;
+                C[2][i] = cdd;
+                C[3][i] = cdn;
+                C[4][i] = cnd;
+            }
+            __syncthreads();
+            const int64_t base = e * Sh::n6 + (int64_t)a3 * Sh::n5;
+            for (int r = tid; r < Sh::n5; r += T) {           // stage x + store
+                const int rb = r / n3, J = r % n3;
+                const int a1 = rb % n, a2 = rb / n;
+                const int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
+                const int ci = ((a2 * n + b2) * n + b3) * Q;
+                double m = 0.0, k = 0.0;
+#pragma unroll
+                for (int kx = 0; kx < Q; ++kx) {
+                    const double nnx = tab[0][0][(a1 * n + b1) * Q + kx];
+                    const double ddx = tab[0][1][(a1 * n + b1) * Q + kx];
+                    const double dnx = tab[0][2][(a1 * n + b1) * Q + kx];
+                    const double ndx = tab[0][2][(b1 * n + a1) * Q + kx];
+                    m += nnx * C[0][ci + kx];
+                    k += nnx * C[1][ci + kx];
+                    k += ddx * C[2][ci + kx];
+                    k += dnx * C[3][ci + kx];
+                    k += ndx * C[4][ci + kx];
+                }
+                if (Me) Me[base + r] = m;
+                if (Ke) Ke[base + r] = k;
+                if (ATOMIC) {
+                    const int64_t pos = rm.pos(ex + a1, ey + a2, ez + a3, ex + b1, ey + b2, ez + b3);
+                    if (Mv) unsafeAtomicAdd(Mv + pos, m);
+                    if (Kv) unsafeAtomicAdd(Kv + pos, k);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int P, bool ATOMIC>
+static int launch_geo_t(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
+                        double* Mv, double* Kv, hipStream_t st)
+{
+    static int slots = 0;
+    if (!slots) {
+        int dev = 0, ncu = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_element_geo<P, ATOMIC>, kGeoThreads, 0) !=
+                hipSuccess)
+            return -3;
+        slots = ncu * (per > 0 ? per : 1);
+    }
+    const int64_t blocks = pd.E < slots ? pd.E : slots;
+    hipLaunchKernelGGL((k_element_geo<P, ATOMIC>), dim3((unsigned)blocks), dim3(kGeoThreads), 0, st, pd,
+                       make_rowmap(pd), cm, G, Me, Ke, Mv, Kv);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_element_geo(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
+                       double* Mv, double* Kv, hipStream_t st)
+{
+    const bool atomic = Mv || Kv;
+    switch (pd.p) {
+#define IGAF_GEO(PP)                                                                  \
+    case PP:                                                                          \
+        return atomic ? launch_geo_t<PP, true>(pd, cm, G, Me, Ke, Mv, Kv, st)         \
+                      : launch_geo_t<PP, false>(pd, cm, G, Me, Ke, Mv, Kv, st);
+        IGAF_GEO(1)
+        IGAF_GEO(2)
+        IGAF_GEO(3)
+        IGAF_GEO(4)
+        IGAF_GEO(5)
+#undef IGAF_GEO
+    default:
+        return -4;
+    }
+}
+
+}  // namespace igaf

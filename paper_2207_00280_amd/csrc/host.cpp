@@ -515,6 +515,25 @@ igaf_status igaf_plan_timing(igaf_plan* plan, int32_t kernel, double* avg_ms, in
     return IGAF_OK;
 }
 
+igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm, const double* G,
+                                        double* Me, double* Ke, double* Mval, double* Kval,
+                                        void* stream)
+{
+    igaf_status st = check_hot(plan, IGAF_SUMFACT);
+    if (st) return st;
+    if (!Me && !Ke && !Mval && !Kval) return fail(IGAF_EINVAL, "all outputs are NULL");
+    if ((Me || Mval) && !cm) return fail(IGAF_EINVAL, "cm is NULL but a mass output is requested");
+    if ((Ke || Kval) && !G) return fail(IGAF_EINVAL, "G is NULL but a stiffness output is requested");
+    hipStream_t s = (hipStream_t)stream;
+    st = launched(launch_fill_zero(Mval, Mval ? plan->nnz : 0, s), "zero");
+    if (!st) st = launched(launch_fill_zero(Kval, Kval ? plan->nnz : 0, s), "zero");
+    if (!st)
+        st = launched(launch_element_geo(plan->dev, (Me || Mval) ? cm : nullptr, (Ke || Kval) ? G : nullptr,
+                                         Me, Ke, Mval, Kval, s),
+                      "mapped-geometry integration");
+    return st;
+}
+
 igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double* v,
                             double alphaM, double alphaK, double scale, double* grad, void* stream)
 {

@@ -41,6 +41,10 @@ int launch_gather(const PatchDev& pd, const double* Me, const double* Ke, double
 int launch_fill_zero(double* a, int64_t n, hipStream_t st);
 
 // y += alphaM M(kappa) u + alphaK K(kappa) u by FP64 atomics (y zeroed by the caller).
+// element matrices (and/or atomically assembled CSR values) on a mapped
+// geometry: cm [E][q^3], G [E][6][q^3]
+int launch_element_geo(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
+                       double* Mv, double* Kv, hipStream_t st);
 int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM,
                  double alphaK, double* y, hipStream_t st);
 

@@ -22,7 +22,7 @@ SYMBOLS = [
     "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_csr_pattern_host",
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes",
     "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
-    "igaf_integrate_assemble", "igaf_kappa_grad", "igaf_apply", "igaf_euler_workspace", "igaf_euler_step",
+    "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_apply", "igaf_euler_workspace", "igaf_euler_step",
     "igaf_batch_create", "igaf_batch_destroy",
     "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
     "igaf_batch_integrate_assemble_separate",
@@ -77,6 +77,7 @@ def lib():
     L.igaf_kappa_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, _vp, _vp]
     L.igaf_apply.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]
+    L.igaf_integrate_assemble_geo.argtypes = [_vp] * 8
     L.igaf_euler_workspace.argtypes = [_vp]
     L.igaf_euler_workspace.restype = ctypes.c_int64
     L.igaf_euler_step.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _vp,
@@ -301,6 +302,39 @@ class Plan:
                 _need_f64_cuda(t, nm, ne)
         _check(lib().igaf_integrate_assemble(self._h, int(method), _ptr(kappa), _ptr(Me), _ptr(Ke),
                                              _ptr(Mval), _ptr(Kval), _stream(stream)))
+        return Me, Ke, Mval, Kval
+
+    def integrate_assemble_geo(self, cm, G, want_elem=True, want_csr=True, want_m=True, want_k=True,
+                               Me=None, Ke=None, Mval=None, Kval=None, stream=None):
+        """Mapped geometry (igaf_integrate_assemble_geo): cm = kappa det J [E, q^3],
+        G = kappa det J J^-1 J^-T [E, 6, q^3] (xx yy zz xy xz yz).  Returns
+        (Me, Ke, Mval, Kval), None where not requested."""
+        if want_m:
+            _need_f64_cuda(cm, "cm", self.nelem * self.nqp)
+        if want_k:
+            _need_f64_cuda(G, "G", self.nelem * 6 * self.nqp)
+        n3 = self.elem_dim
+        if want_elem:
+            if want_m and Me is None:
+                Me = self._alloc(self.nelem, n3, n3)
+            if want_k and Ke is None:
+                Ke = self._alloc(self.nelem, n3, n3)
+        if want_csr:
+            if want_m and Mval is None:
+                Mval = self._alloc(self.nnz)
+            if want_k and Kval is None:
+                Kval = self._alloc(self.nnz)
+        Me = Me if (want_elem and want_m) else None
+        Ke = Ke if (want_elem and want_k) else None
+        Mval = Mval if (want_csr and want_m) else None
+        Kval = Kval if (want_csr and want_k) else None
+        for t, nm, ne in ((Me, "Me", self.nelem * n3 * n3), (Ke, "Ke", self.nelem * n3 * n3),
+                          (Mval, "Mval", self.nnz), (Kval, "Kval", self.nnz)):
+            if t is not None:
+                _need_f64_cuda(t, nm, ne)
+        _check(lib().igaf_integrate_assemble_geo(self._h, _ptr(cm if want_m else None),
+                                                 _ptr(G if want_k else None), _ptr(Me), _ptr(Ke),
+                                                 _ptr(Mval), _ptr(Kval), _stream(stream)))
         return Me, Ke, Mval, Kval
 
     def apply(self, kappa, u, alphaM=1.0, alphaK=1.0, y=None, stream=None):
