@@ -13,7 +13,8 @@ kernel alone (roofline of the dominant kernel), classical quadrature, the
 atomic assembly, the 128^3 streamed workload (p = 2, 3, 4), the 256-patch
 batched single launch against 256 separate launches (eager and
 graph-captured), the adjoint, the matrix-free operator apply and one forward
-Euler step (conjugate gradients on M) against the plain forward assembly;
+Euler step (conjugate gradients on M) against the plain forward assembly,
+the headline mesh on a curved geometry map;
 and the CPU oracle on a bounded sample of the headline workload.
 
 Prints ONE JSON line on stdout.  --mode kernel:<name> runs one kernel only
@@ -282,6 +283,51 @@ def bench_w5(ig, torch, stream, steps):
     return out
 
 
+def geo_flops(p):
+    """Flops per element of the mapped-geometry kernel (ordered pairs): stage z
+    9 n^2 q^3, stage y 10 n^4 q^2, stage x 5 n^6 q fused multiply-adds."""
+    n = q = p + 1
+    return 2 * (9 * n ** 2 * q ** 3 + 10 * n ** 4 * q ** 2 + 5 * n ** 6 * q)
+
+
+def bench_w6(ig, torch, stream, steps):
+    """W6: the headline mesh on a curved map (mapped_geometry, amp 0.1): the
+    element matrices from a per-point mass coefficient and stiffness tensor
+    (7 q^3 doubles in, 2 n^6 out per element; HBM-bound), then with the CSR
+    values gathered from them, and the CSR values alone (FP64 atomics)."""
+    cfg = W.W6
+    p, K = cfg["p"], cfg["K"]
+    plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
+    xs = [plan.quad_nodes(d)[0] for d in range(3)]
+    cm, G = W.mapped_geometry(xs[0], xs[1], xs[2], W.kappa_sine(*xs), amp=cfg["amp"])
+    cmd, Gd = torch.from_numpy(cm).cuda(), torch.from_numpy(G).cuda()
+    del cm, G
+    n3 = plan.elem_dim
+    Me = torch.empty(plan.nelem, n3, n3, dtype=torch.float64, device="cuda")
+    Ke = torch.empty_like(Me)
+    Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+    Kv = torch.empty_like(Mv)
+    ms_el = float(np.mean(timed(lambda: plan.integrate_assemble_geo(cmd, Gd, Me=Me, Ke=Ke, want_csr=False),
+                                steps, 2, stream)))
+    ms_all = float(np.mean(timed(lambda: plan.integrate_assemble_geo(cmd, Gd, Me=Me, Ke=Ke, Mval=Mv, Kval=Kv),
+                                 steps, 1, stream)))
+    ms_csr = float(np.mean(timed(lambda: plan.integrate_assemble_geo(cmd, Gd, want_elem=False, Mval=Mv, Kval=Kv),
+                                 max(2, steps // 2), 1, stream)))
+    b_el = plan.nelem * (7 * plan.nqp * 8 + 2 * n3 * n3 * 8)
+    f_el = plan.nelem * geo_flops(p)
+    roof = max(b_el / HBM_PEAK, f_el / FP64_PEAK)
+    out = {"elements": plan.nelem,
+           "element_matrices": {"ms": ms_el, "bytes": b_el, "flops": f_el, "GB/s": b_el / (ms_el * 1e-3) / 1e9,
+                                "roofline_ms": roof * 1e3, "frac": roof / (ms_el * 1e-3), "bound": "hbm"},
+           "element_matrices_and_csr_gathered_ms": ms_all,
+           "csr_only_atomic_ms": ms_csr}
+    log("W6 mapped geometry: element matrices %.3f ms (%.0f%% of HBM roofline), + CSR gathered %.3f ms, "
+        "CSR alone (atomics) %.3f ms" % (ms_el, 100 * out["element_matrices"]["frac"], ms_all, ms_csr))
+    del cmd, Gd, Me, Ke, Mv, Kv, plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_kernel_mode(name, ig, torch, steps):
     """Run one kernel `steps` times (no timing output) for profiler passes."""
     if name == "copy":
@@ -405,6 +451,7 @@ def main():
         out["w3_streamed_128c"] = bench_w3(ig, torch, stream, steps_x)
         out["w4_batched_256"] = bench_w4(ig, torch, stream, steps_x)
         out["w5_adjoint_apply_96c"] = bench_w5(ig, torch, stream, steps_x)
+        out["w6_mapped_geometry_64c"] = bench_w6(ig, torch, stream, steps_x)
     else:
         del h
         torch.cuda.empty_cache()

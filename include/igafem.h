@@ -204,8 +204,11 @@ igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const
  *      components xx, yy, zz, xy, xz, yz (required when Ke or Kval is)
  * Me, Ke   DEVICE [E][n^3][n^3] or NULL;  Mval, Kval DEVICE [nnz] or NULL,
  *      OVERWRITTEN with the assembled CSR values (structural pattern of
- *      igaf_csr_pattern), added with FP64 atomics: the last bits may vary
- *      from call to call.  At least one output.
+ *      igaf_csr_pattern).  At least one output.  When every requested CSR
+ *      output has its element matrices requested too, the CSR values are
+ *      summed from the stored matrices as in igaf_assemble (deterministic);
+ *      otherwise (CSR without element matrices) they are added with FP64
+ *      atomics and the last bits may vary from call to call.
  * Sum factorisation (Algorithm 2) with ordered per-direction pairs (the
  * cross terms of G are not symmetric in a pair); nquad = degree+1 in every
  * direction, else IGAF_EUNSUPPORTED.  cm = kappa, G = kappa I (the identity

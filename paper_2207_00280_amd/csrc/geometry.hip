@@ -14,8 +14,8 @@
 // and N_a N'_b in direction d, which are not symmetric in (a, b), so every
 // direction works with ordered pairs (n^2 per direction, n^6 values).
 //
-// Per direction and element the ordered-pair tables are
-//   nn[a][b][k] = w N_a N_b,  dd = w N'_a N'_b,  dn = w N'_a N_b  (nd[a][b] = dn[b][a])
+// Per direction and element the ordered-pair factors are
+//   nn[a][b][k] = w N_a N_b,  dd = w N'_a N'_b,  dn = w N'_a N_b,  nd = w N_a N'_b
 // and the stages, for one test-z index a3 at a time (z pairs (a3, b3)):
 //   stage z  (9 sums over kz):  D0 = nn.cm  D1 = nn.Gxx  D2 = nn.Gyy  D3 = dd.Gzz
 //                               D4 = nn.Gxy D5 = nd.Gxz  D6 = dn.Gxz  D7 = nd.Gyz  D8 = dn.Gyz
@@ -31,8 +31,8 @@
 //
 // One 256-thread workgroup per element (grid-stride), the stages in LDS; the
 // next element's point coefficients are fetched into registers while the
-// current one is computed.  With CSR outputs the values are added with FP64
-// atomics at their structural positions.
+// current one is computed.  CSR outputs requested without element matrices
+// are added here with FP64 atomics at their structural positions.
 #include "common.h"
 #include "launch.h"
 
@@ -43,15 +43,21 @@ constexpr int kGeoThreads = 256;
 template <int P>
 struct GeoShape {
     static constexpr int n = P + 1, Q = P + 1;
-    static constexpr int n2 = n * n, n3 = n2 * n, n5 = n3 * n2, n6 = n3 * n3;
+    static constexpr int n2 = n * n, n3 = n2 * n, n4 = n3 * n, n5 = n4 * n, n6 = n3 * n3;
     static constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
     static constexpr int NF = 7;                 // cm, Gxx, Gyy, Gzz, Gxy, Gxz, Gyz
-    static constexpr int TAB = n2 * Q;           // one ordered-pair table of one direction
-    static constexpr int DSZ = n * Q2;           // stage z result: [b3][kx][ky]
-    static constexpr int CSZ = n2 * n * Q;       // stage y result: [a2 b2][b3][kx]
+    static constexpr int TB = n * Q;             // one 1D table of one direction: [a][k]
+    static constexpr int DSZ = n * Q2;           // stage z result per field: [b3][kx][ky]
+    static constexpr int CSZ = n3 * Q;           // stage y result per kind: [a2][b2][b3][kx]
     static constexpr int NPF = (NF * Q3 + kGeoThreads - 1) / kGeoThreads;
 };
 
+// The ordered-pair factors are products of a weighted value of the test
+// function and a plain value of the trial function, e.g. nn[a][b][k] =
+// (w N_a)[k] N_b[k], dn = (w N'_a) N_b, nd = (w N_a) N'_b.  Each stage keeps
+// its thread on a fixed set of trial indices, folds the trial values into its
+// inputs once, and then loops over the test index, whose weighted values are
+// the same for every lane (LDS broadcast reads).
 template <int P, bool ATOMIC>
 __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap rm,
                                                              const double* __restrict__ cm,
@@ -64,7 +70,8 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
     using Sh = GeoShape<P>;
     constexpr int n = Sh::n, Q = Sh::Q, n3 = Sh::n3, Q3 = Sh::Q3, T = kGeoThreads;
     __shared__ double fld[Sh::NF][Q3];
-    __shared__ double tab[3][3][Sh::TAB];        // [dir][nn, dd, dn][(a n + b) Q + k]
+    __shared__ double raw[3][2][Sh::TB];         // [dir][N, N'][a Q + k]
+    __shared__ double wsc[3][2][Sh::TB];         // [dir][w N, w N'][a Q + k]
     __shared__ double D[9][Sh::DSZ];
     __shared__ double C[5][Sh::CSZ];
 
@@ -95,100 +102,120 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
 #pragma unroll
         for (int r = 0; r < Sh::NPF; ++r)
             if (tid + r * T < Sh::NF * Q3) (&fld[0][0])[tid + r * T] = pf[r];
-        for (int i = tid; i < 3 * Sh::TAB; i += T) {
-            const int d = i / Sh::TAB, r = i % Sh::TAB;
-            const int a = r / (n * Q), b = (r / Q) % n, k = r % Q;
+        for (int i = tid; i < 3 * Sh::TB; i += T) {
+            const int d = i / Sh::TB, r = i % Sh::TB;
             const int ed = d == 0 ? ex : (d == 1 ? ey : ez);
             const DirTables& t = pd.d[d];
-            const double w = t.wq[(int64_t)ed * Q + k];
-            const double Na = t.Nv[((int64_t)ed * n + a) * Q + k], Nb = t.Nv[((int64_t)ed * n + b) * Q + k];
-            const double Da = t.dN[((int64_t)ed * n + a) * Q + k], Db = t.dN[((int64_t)ed * n + b) * Q + k];
-            tab[d][0][r] = w * Na * Nb;
-            tab[d][1][r] = w * Da * Db;
-            tab[d][2][r] = w * Da * Nb;
+            const double w = t.wq[(int64_t)ed * Q + r % Q];
+            const double Nv = t.Nv[(int64_t)ed * Sh::TB + r], dN = t.dN[(int64_t)ed * Sh::TB + r];
+            raw[d][0][r] = Nv;
+            raw[d][1][r] = dN;
+            wsc[d][0][r] = w * Nv;
+            wsc[d][1][r] = w * dN;
         }
         __syncthreads();
         if (e + gridDim.x < pd.E) fetch(e + gridDim.x);
 
         for (int a3 = 0; a3 < n; ++a3) {
-            for (int i = tid; i < Sh::DSZ; i += T) {          // stage z
+            // stage z: thread on (b3, kx, ky)
+            for (int i = tid; i < Sh::DSZ; i += T) {
                 const int b3 = i / Sh::Q2, kx = (i / Q) % Q, ky = i % Q;
                 double d[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
                 for (int kz = 0; kz < Q; ++kz) {
                     const int kk = kx + Q * (ky + Q * kz);
-                    const double nnz = tab[2][0][(a3 * n + b3) * Q + kz];
-                    const double ddz = tab[2][1][(a3 * n + b3) * Q + kz];
-                    const double dnz = tab[2][2][(a3 * n + b3) * Q + kz];
-                    const double ndz = tab[2][2][(b3 * n + a3) * Q + kz];
-                    d[0] += nnz * fld[0][kk];
-                    d[1] += nnz * fld[1][kk];
-                    d[2] += nnz * fld[2][kk];
-                    d[3] += ddz * fld[3][kk];
-                    d[4] += nnz * fld[4][kk];
-                    d[5] += ndz * fld[5][kk];
-                    d[6] += dnz * fld[5][kk];
-                    d[7] += ndz * fld[6][kk];
-                    d[8] += dnz * fld[6][kk];
+                    const double Nb = raw[2][0][b3 * Q + kz], Db = raw[2][1][b3 * Q + kz];
+                    const double sN = wsc[2][0][a3 * Q + kz], sD = wsc[2][1][a3 * Q + kz];
+                    const double nn = sN * Nb, dd = sD * Db, dn = sD * Nb, nd = sN * Db;
+                    d[0] += nn * fld[0][kk];
+                    d[1] += nn * fld[1][kk];
+                    d[2] += nn * fld[2][kk];
+                    d[3] += dd * fld[3][kk];
+                    d[4] += nn * fld[4][kk];
+                    d[5] += nd * fld[5][kk];
+                    d[6] += dn * fld[5][kk];
+                    d[7] += nd * fld[6][kk];
+                    d[8] += dn * fld[6][kk];
                 }
 #pragma unroll
                 for (int f = 0; f < 9; ++f) D[f][i] = d[f];
             }
             __syncthreads();
-            for (int i = tid; i < Sh::CSZ; i += T) {          // stage y
-                const int yp = i / (n * Q), b3 = (i / Q) % n, kx = i % Q;
-                const int a2 = yp / n, b2 = yp % n;
-                double cM = 0.0, cnn = 0.0, cdd = 0.0, cdn = 0.0, cnd = 0.0;
+            // stage y: thread on (b2, b3, kx), loop over the test index a2
+            for (int i = tid; i < Sh::n2 * Q; i += T) {
+                const int b2 = i / (n * Q), b3 = (i / Q) % n, kx = i % Q;
+                double p0[Q], p1[Q], pa[Q], pb[Q], pc[Q], pd4[Q], pe[Q];
 #pragma unroll
                 for (int ky = 0; ky < Q; ++ky) {
-                    const double nny = tab[1][0][yp * Q + ky];
-                    const double ddy = tab[1][1][yp * Q + ky];
-                    const double dny = tab[1][2][yp * Q + ky];
-                    const double ndy = tab[1][2][(b2 * n + a2) * Q + ky];
                     const int j = (b3 * Q + kx) * Q + ky;
-                    cM += nny * D[0][j];
-                    cnn += ddy * D[2][j];
-                    cnn += nny * D[3][j];
-                    cnn += dny * D[7][j];
-                    cnn += ndy * D[8][j];
-                    cdd += nny * D[1][j];
-                    cdn += ndy * D[4][j];
-                    cdn += nny * D[5][j];
-                    cnd += dny * D[4][j];
-                    cnd += nny * D[6][j];
+                    const double Nb = raw[1][0][b2 * Q + ky], Db = raw[1][1][b2 * Q + ky];
+                    p0[ky] = Nb * D[0][j];
+                    p1[ky] = Nb * D[1][j];
+                    pa[ky] = Nb * D[3][j];
+                    pa[ky] += Db * D[8][j];
+                    pb[ky] = Db * D[2][j];
+                    pb[ky] += Nb * D[7][j];
+                    pc[ky] = Db * D[4][j];
+                    pc[ky] += Nb * D[5][j];
+                    pd4[ky] = Nb * D[4][j];
+                    pe[ky] = Nb * D[6][j];
                 }
-                C[0][i] = cM;
-                C[1][i] = cnn;
-                C[2][i] = cdd;
-                C[3][i] = cdn;
-                C[4][i] = cnd;
+                for (int a2 = 0; a2 < n; ++a2) {
+                    double cM = 0.0, cnn = 0.0, cdd = 0.0, cdn = 0.0, cnd = 0.0;
+#pragma unroll
+                    for (int ky = 0; ky < Q; ++ky) {
+                        const double sN = wsc[1][0][a2 * Q + ky], sD = wsc[1][1][a2 * Q + ky];
+                        cM += sN * p0[ky];
+                        cnn += sN * pa[ky];
+                        cnn += sD * pb[ky];
+                        cdd += sN * p1[ky];
+                        cdn += sN * pc[ky];
+                        cnd += sD * pd4[ky];
+                        cnd += sN * pe[ky];
+                    }
+                    const int o = ((a2 * n + b2) * n + b3) * Q + kx;
+                    C[0][o] = cM;
+                    C[1][o] = cnn;
+                    C[2][o] = cdd;
+                    C[3][o] = cdn;
+                    C[4][o] = cnd;
+                }
             }
             __syncthreads();
+            // stage x + store: thread on (a2, J), loop over the test index a1;
+            // lanes run along a row, so every store is a contiguous run
             const int64_t base = e * Sh::n6 + (int64_t)a3 * Sh::n5;
-            for (int r = tid; r < Sh::n5; r += T) {           // stage x + store
-                const int rb = r / n3, J = r % n3;
-                const int a1 = rb % n, a2 = rb / n;
+            for (int i = tid; i < Sh::n4; i += T) {
+                const int a2 = i / n3, J = i % n3;
                 const int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
                 const int ci = ((a2 * n + b2) * n + b3) * Q;
-                double m = 0.0, k = 0.0;
+                double u[Q], v[Q], wm[Q];
 #pragma unroll
                 for (int kx = 0; kx < Q; ++kx) {
-                    const double nnx = tab[0][0][(a1 * n + b1) * Q + kx];
-                    const double ddx = tab[0][1][(a1 * n + b1) * Q + kx];
-                    const double dnx = tab[0][2][(a1 * n + b1) * Q + kx];
-                    const double ndx = tab[0][2][(b1 * n + a1) * Q + kx];
-                    m += nnx * C[0][ci + kx];
-                    k += nnx * C[1][ci + kx];
-                    k += ddx * C[2][ci + kx];
-                    k += dnx * C[3][ci + kx];
-                    k += ndx * C[4][ci + kx];
+                    const double Nb = raw[0][0][b1 * Q + kx], Db = raw[0][1][b1 * Q + kx];
+                    u[kx] = Nb * C[1][ci + kx];
+                    u[kx] += Db * C[4][ci + kx];
+                    v[kx] = Db * C[2][ci + kx];
+                    v[kx] += Nb * C[3][ci + kx];
+                    wm[kx] = Nb * C[0][ci + kx];
                 }
-                if (Me) Me[base + r] = m;
-                if (Ke) Ke[base + r] = k;
-                if (ATOMIC) {
-                    const int64_t pos = rm.pos(ex + a1, ey + a2, ez + a3, ex + b1, ey + b2, ez + b3);
-                    if (Mv) unsafeAtomicAdd(Mv + pos, m);
-                    if (Kv) unsafeAtomicAdd(Kv + pos, k);
+                for (int a1 = 0; a1 < n; ++a1) {
+                    double m = 0.0, k = 0.0;
+#pragma unroll
+                    for (int kx = 0; kx < Q; ++kx) {
+                        const double sN = wsc[0][0][a1 * Q + kx], sD = wsc[0][1][a1 * Q + kx];
+                        m += sN * wm[kx];
+                        k += sN * u[kx];
+                        k += sD * v[kx];
+                    }
+                    const int64_t at = base + (int64_t)(a2 * n + a1) * n3 + J;
+                    if (Me) Me[at] = m;
+                    if (Ke) Ke[at] = k;
+                    if (ATOMIC) {
+                        const int64_t pos = rm.pos(ex + a1, ey + a2, ez + a3, ex + b1, ey + b2, ez + b3);
+                        if (Mv) unsafeAtomicAdd(Mv + pos, m);
+                        if (Kv) unsafeAtomicAdd(Kv + pos, k);
+                    }
                 }
             }
             __syncthreads();

@@ -525,12 +525,23 @@ igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm,
     if ((Me || Mval) && !cm) return fail(IGAF_EINVAL, "cm is NULL but a mass output is requested");
     if ((Ke || Kval) && !G) return fail(IGAF_EINVAL, "G is NULL but a stiffness output is requested");
     hipStream_t s = (hipStream_t)stream;
+    const double* c = (Me || Mval) ? cm : nullptr;
+    const double* g = (Ke || Kval) ? G : nullptr;
+    if ((!Mval || Me) && (!Kval || Ke)) {
+        // every requested CSR output has its element matrices: store them,
+        // then sum each CSR value from them (deterministic, no atomics)
+        st = launched(launch_element_geo(plan->dev, c, g, Me, Ke, nullptr, nullptr, s),
+                      "mapped-geometry integration");
+        if (!st && (Mval || Kval))
+            st = launched(launch_gather(plan->dev, Mval ? Me : nullptr, Kval ? Ke : nullptr, Mval, Kval, s),
+                          "assemble");
+        return st;
+    }
     st = launched(launch_fill_zero(Mval, Mval ? plan->nnz : 0, s), "zero");
     if (!st) st = launched(launch_fill_zero(Kval, Kval ? plan->nnz : 0, s), "zero");
     if (!st)
-        st = launched(launch_element_geo(plan->dev, (Me || Mval) ? cm : nullptr, (Ke || Kval) ? G : nullptr,
-                                         Me, Ke, Mval, Kval, s),
-                      "mapped-geometry integration");
+        st = launched(launch_element_geo(plan->dev, c, g, Me, Ke, Mval, Kval, s),
+                      "mapped-geometry integration + atomic assembly");
     return st;
 }
 

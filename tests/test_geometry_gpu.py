@@ -3,11 +3,11 @@
 On x = F(xi) the per-point factor of eq. (10) becomes cm = kappa det J for the
 mass and the tensor G = kappa det J J^-1 J^-T for the stiffness; the caller's
 side (workloads.mapped_geometry) evaluates them at the points.  The HIP path
-(sum factorisation with ordered per-direction pairs, CSR by FP64 atomics) is
-compared with the oracle's classical quadrature of the same integrands,
+(sum factorisation with ordered per-direction pairs; CSR values gathered from
+the stored element matrices, or added with FP64 atomics when none are stored)
+is compared with the oracle's classical quadrature of the same integrands,
 which the CPU suite pins by scaled knots, exact affine Kronecker forms and
-linear patch tests.  CSR values are added with atomics, so they are compared
-within rounding.
+linear patch tests.
 """
 import math
 
@@ -79,7 +79,10 @@ def test_geometry_vs_oracle(orc, ig, p, K, kind, geo):
     assert relfro(to_host(Mv), Mv_o) <= TOL and relfro(to_host(Kv), Kv_o) <= TOL
     rp, col = plan.csr_pattern()
     assert np.array_equal(to_host(rp), rp_o) and np.array_equal(to_host(col), col_o)
-    # one matrix at a time; element matrices only; CSR only
+    # with the element matrices stored the CSR values are gathered: bitwise repeatable
+    _, _, Mv_b, Kv_b = plan.integrate_assemble_geo(cmd, Gd)
+    assert np.array_equal(to_host(Mv_b), to_host(Mv)) and np.array_equal(to_host(Kv_b), to_host(Kv))
+    # one matrix at a time; element matrices only; CSR only (atomics)
     Me2, Ke2, _, _ = plan.integrate_assemble_geo(cmd, None, want_k=False, want_csr=False)
     assert Ke2 is None and relfro(to_host(Me2), Me_o) <= TOL
     _, _, Mv3, Kv3 = plan.integrate_assemble_geo(None, Gd, want_m=False, want_elem=False)
