@@ -266,18 +266,24 @@ def bench_w5(ig, torch, stream, steps):
     # apply, conjugate gradients on M to a relative residual of 1e-10
     dt = 0.1 / max(K) ** 2
     mu_next = torch.empty_like(u)
-    plan.euler_step(kap, u, dt, tol=1e-10, maxit=20000, out=mu_next)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, iters, relres = plan.euler_step(kap, u, dt, tol=1e-10, maxit=20000, out=mu_next)
-    torch.cuda.synchronize()
-    ms_e = (time.perf_counter() - t0) * 1e3
-    out["euler_step"] = {"ms": ms_e, "cg_iterations": iters, "relres": relres, "dt": dt,
-                         "ms_per_iteration": ms_e / max(1, iters)}
-    del mu_next
+    work = torch.empty(int(ig.lib().igaf_euler_workspace(plan._h)), dtype=torch.float64, device="cuda")
+    for name, pc in (("euler_step", ig.PRECOND_KRON), ("euler_step_plain_cg", ig.PRECOND_NONE)):
+        plan.euler_step(kap, u, dt, tol=1e-10, maxit=20000, precond=pc, out=mu_next, work=work)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, iters, relres = plan.euler_step(kap, u, dt, tol=1e-10, maxit=20000, precond=pc, out=mu_next,
+                                           work=work)
+        torch.cuda.synchronize()
+        ms_e = (time.perf_counter() - t0) * 1e3
+        out[name] = {"ms": ms_e, "cg_iterations": iters, "relres": relres, "dt": dt,
+                     "ms_per_iteration": ms_e / max(1, iters),
+                     "preconditioner": "kronecker 1D mass, diagonal scaling" if pc else "none"}
+    del mu_next, work
     log("W5: adjoint %.3f ms (%.0f%% of roofline), apply (M+K)u %.3f ms (%.0f%%), forward CSR %.3f ms, "
-        "Euler step %.1f ms (%d CG iterations)"
-        % (ms_a, 100 * out["adjoint"]["frac"], ms_y, 100 * out["apply"]["frac"], ms_f, ms_e, iters))
+        "Euler step %.1f ms (%d PCG iterations; plain CG %.1f ms, %d iterations)"
+        % (ms_a, 100 * out["adjoint"]["frac"], ms_y, 100 * out["apply"]["frac"], ms_f,
+           out["euler_step"]["ms"], out["euler_step"]["cg_iterations"], out["euler_step_plain_cg"]["ms"],
+           out["euler_step_plain_cg"]["cg_iterations"]))
     del kap, u, v, g, y, Mv, Kv, plan
     torch.cuda.empty_cache()
     return out

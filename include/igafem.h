@@ -249,15 +249,23 @@ igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double*
  * definite) is solved by conjugate gradients started from mu, each iteration
  * one matrix-free mass apply, until ||r|| <= tol ||b|| or after maxit
  * iterations (then IGAF_ENOCONV, mu_next holding the last iterate).
+ * precond: IGAF_PRECOND_NONE (plain CG) or IGAF_PRECOND_KRON: CG
+ * preconditioned by P = S (Mz (x) My (x) Mx) S, the Kronecker product of the
+ * 1D mass matrices of the plan (kappa = 1; each applied through its banded
+ * Cholesky factor, one sequential solve per grid line) scaled by
+ * S = diag(M(kappa))^1/2 / diag(Mz (x) My (x) Mx)^1/2, which carries the
+ * coefficient's variation.
  * kappa: device [E][q^3]; mu, mu_next: device [ndof] (may be the same
  * array); work: device scratch of igaf_euler_workspace(plan) doubles,
  * overwritten.  iters, relres: HOST outputs (iterations taken, final
- * ||r|| / ||b||), either may be NULL.  Synchronous: it waits on `stream` for
- * the residual of every iteration and returns when the step is done.
- * Needs nquad = degree + 1 in every direction. */
+ * ||r|| / ||b|| of the recursively updated residual), either may be NULL.
+ * Synchronous: it waits on `stream` for the residual of every iteration and
+ * returns when the step is done.  Needs nquad = degree + 1 in every
+ * direction. */
+enum { IGAF_PRECOND_NONE = 0, IGAF_PRECOND_KRON = 1 };
 int64_t igaf_euler_workspace(const igaf_plan* plan);
 igaf_status igaf_euler_step(const igaf_plan* plan, const double* kappa, const double* mu, double dt,
-                            double tol, int32_t maxit, double* mu_next, double* work,
+                            double tol, int32_t maxit, int32_t precond, double* mu_next, double* work,
                             int32_t* iters, double* relres, void* stream);
 
 /* ---------------------------------------------------------------- batches

@@ -5,6 +5,7 @@
 //   Wdd[e][s][k] = w_k (h_e/2) N'_a(x_k) N'_b(x_k)
 //   Nv[e][a][k]  = N_{e+a}(x_k),  dN[e][a][k] = N'_{e+a}(x_k)
 //   wq[e][k]     = w_k h_e/2
+//   Lm[i][.]     = banded Cholesky factor and diagonal of the 1D mass matrix
 //   pre[i]       = sum_{i' < i} L(i'),  L(i) = min(N-1, i+p) - max(0, i-p) + 1
 // with x_k the Gauss nodes mapped to element e.  Pair products depend only on
 // the unordered pair {a, b}, so S = (p+1)(p+2)/2 of them are stored.
@@ -28,6 +29,7 @@ struct DirTables {
     const double* Nv;
     const double* dN;
     const double* wq;
+    const double* Lm;     // [N][p+2]: 1/L_ii, L_{i,i-1..i-p}, M_ii of the 1D mass (kappa = 1)
     const int64_t* pre;   // [N+1]
     int K, N, Q;
 };

@@ -3,7 +3,12 @@
 //   M(kappa) mu_next = M(kappa) mu - dt K(kappa) mu.
 // The right-hand side is one matrix-free operator apply; the mass system is
 // solved by conjugate gradients (M is symmetric positive definite), each
-// iteration one matrix-free mass apply.  Every vector operation runs in the
+// iteration one matrix-free mass apply, optionally preconditioned by the
+// Kronecker product of the 1D mass matrices (kappa = 1), scaled on both
+// sides so that its diagonal matches diag(M(kappa)): the product carries the
+// B-spline basis (whose mass matrix conditioning grows quickly with p), the
+// diagonal scaling the coefficient's variation, and it is applied by three
+// sweeps of banded triangular solves along the grid lines.  Every vector operation runs in the
 // kernels below; the CG scalars stay in device memory (alpha, beta computed
 // on the device), and the host reads back only the residual norm for the
 // convergence test.  Dot products are two-stage and in a fixed order, so the
@@ -79,13 +84,13 @@ __global__ __launch_bounds__(256) void k_cg_xr(double* __restrict__ x, double* _
     }
 }
 
-// p = r + beta p (beta = S[3]); with first != 0: p = r
-__global__ __launch_bounds__(256) void k_cg_p(double* __restrict__ p, const double* __restrict__ r,
+// p = z + beta p (beta = S[3]); with first != 0: p = z
+__global__ __launch_bounds__(256) void k_cg_p(double* __restrict__ p, const double* __restrict__ z,
                                               const double* __restrict__ S, int64_t n, int first)
 {
     const double beta = first ? 0.0 : S[3];
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        p[i] = r[i] + beta * p[i];
+        p[i] = z[i] + beta * (first ? 0.0 : p[i]);
 }
 
 // r = b - r (r holds M x on entry); x = mu
@@ -113,22 +118,177 @@ int dot(const double* a, const double* c, int64_t n, double* partial, double* S,
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+// d[I] += sum over the elements carrying I of sum_q w_q kappa_q phi_I(x_q)^2
+// (the diagonal of M(kappa)); one workgroup per element, a thread per local
+// function, the q^3 sum taken one direction at a time.
+template <int P>
+__global__ __launch_bounds__(256) void k_mass_diag(PatchDev pd, const double* __restrict__ kappa,
+                                                   double* __restrict__ d)
+{
+    constexpr int n = P + 1, Q = P + 1, n3 = n * n * n, Q3 = Q * Q * Q;
+    __shared__ double kap[Q3];
+    __shared__ double sq[3][n * Q];   // w N_a^2 per direction, [a][k]
+    const int tid = threadIdx.x;
+    const int Kx = pd.d[0].K, Ky = pd.d[1].K, Nx = pd.d[0].N, Ny = pd.d[1].N;
+    for (int64_t e = blockIdx.x; e < pd.E; e += gridDim.x) {
+        const int ex = (int)(e % Kx), ey = (int)((e / Kx) % Ky), ez = (int)(e / ((int64_t)Kx * Ky));
+        for (int i = tid; i < Q3; i += 256) kap[i] = kappa[e * Q3 + i];
+        for (int i = tid; i < 3 * n * Q; i += 256) {
+            const int dd = i / (n * Q), r = i % (n * Q);
+            const int ed = dd == 0 ? ex : (dd == 1 ? ey : ez);
+            const double v = pd.d[dd].Nv[(int64_t)ed * n * Q + r];
+            sq[dd][r] = pd.d[dd].wq[(int64_t)ed * Q + r % Q] * v * v;
+        }
+        __syncthreads();
+        if (tid < n3) {
+            const int a1 = tid % n, a2 = (tid / n) % n, a3 = tid / (n * n);
+            double s = 0.0;
+            for (int kz = 0; kz < Q; ++kz) {
+                double sy = 0.0;
+                for (int ky = 0; ky < Q; ++ky) {
+                    double sx = 0.0;
+#pragma unroll
+                    for (int kx = 0; kx < Q; ++kx) sx += sq[0][a1 * Q + kx] * kap[kx + Q * (ky + Q * kz)];
+                    sy += sq[1][a2 * Q + ky] * sx;
+                }
+                s += sq[2][a3 * Q + kz] * sy;
+            }
+            atomicAdd(&d[(ex + a1) + (int64_t)Nx * ((ey + a2) + (int64_t)Ny * (ez + a3))], s);
+        }
+        __syncthreads();
+    }
+}
+
+// s[I] <- sqrt(diag(Mz (x) My (x) Mx)_I / s[I]) (s holds diag(M(kappa)) on entry)
+__global__ __launch_bounds__(256) void k_precond_scale(double* __restrict__ s, const double* __restrict__ Lx,
+                                                       const double* __restrict__ Ly,
+                                                       const double* __restrict__ Lz, int Nx, int Ny,
+                                                       int W, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int ix = (int)(i % Nx), iy = (int)((i / Nx) % Ny), iz = (int)(i / ((int64_t)Nx * Ny));
+        const double d0 = Lx[(int64_t)ix * W + W - 1] * Ly[(int64_t)iy * W + W - 1] * Lz[(int64_t)iz * W + W - 1];
+        s[i] = sqrt(d0 / s[i]);
+    }
+}
+
+// z = s * r (elementwise); with r == nullptr, z *= s
+__global__ __launch_bounds__(256) void k_scale(double* __restrict__ z, const double* __restrict__ r,
+                                               const double* __restrict__ s, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        z[i] = s[i] * (r ? r[i] : z[i]);
+}
+
+// In place v <- (L L^T)^-1 v along every grid line of one direction: a thread
+// per line, forward then backward substitution over the line's N values with
+// the banded factor (p sub-diagonals) kept as [1/L_ii, L_{i,i-1..i-p}, M_ii].
+// Line t starts at (t % inner) + (t / inner) inner N and steps by `inner`
+// (inner = 1, Nx, Nx Ny for x, y, z).
+template <int P>
+__global__ __launch_bounds__(256) void k_line_solve(double* __restrict__ v, const double* __restrict__ Lm,
+                                                    int N, int64_t nlines, int64_t inner)
+{
+    constexpr int W = P + 2;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nlines) return;
+    double* line = v + (t % inner) + (t / inner) * inner * N;
+    double ring[P];   // forward: y_{i-1-j}; backward: x_{i+1+j}
+#pragma unroll
+    for (int j = 0; j < P; ++j) ring[j] = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double* l = Lm + (int64_t)i * W;
+        double s = line[(int64_t)i * inner];
+#pragma unroll
+        for (int k = 1; k <= P; ++k) s -= l[k] * ring[k - 1];
+        s *= l[0];
+#pragma unroll
+        for (int j = P - 1; j > 0; --j) ring[j] = ring[j - 1];
+        ring[0] = s;
+        line[(int64_t)i * inner] = s;
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) ring[j] = 0.0;
+    for (int i = N - 1; i >= 0; --i) {
+        double s = line[(int64_t)i * inner];
+#pragma unroll
+        for (int k = 1; k <= P; ++k) {
+            const int r = i + k < N ? i + k : N - 1;   // past the end the ring holds 0
+            s -= Lm[(int64_t)r * W + k] * ring[k - 1];
+        }
+        s *= Lm[(int64_t)i * W];
+#pragma unroll
+        for (int j = P - 1; j > 0; --j) ring[j] = ring[j - 1];
+        ring[0] = s;
+        line[(int64_t)i * inner] = s;
+    }
+}
+
+template <int P>
+int launch_mass_diag_t(const PatchDev& pd, const double* kappa, double* d, hipStream_t st)
+{
+    const int64_t blocks = pd.E < 8192 ? pd.E : 8192;
+    hipLaunchKernelGGL(k_mass_diag<P>, dim3((unsigned)blocks), dim3(256), 0, st, pd, kappa, d);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <int P>
+int launch_line_solves_t(const PatchDev& pd, double* v, int64_t ndof, hipStream_t st)
+{
+    int64_t inner = 1;
+    for (int a = 0; a < 3; ++a) {
+        const int N = pd.d[a].N;
+        const int64_t nlines = ndof / N;
+        hipLaunchKernelGGL(k_line_solve<P>, dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, st, v,
+                           pd.d[a].Lm, N, nlines, inner);
+        inner *= N;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_mass_diag(const PatchDev& pd, const double* kappa, double* d, hipStream_t st)
+{
+    switch (pd.p) {
+    case 1: return launch_mass_diag_t<1>(pd, kappa, d, st);
+    case 2: return launch_mass_diag_t<2>(pd, kappa, d, st);
+    case 3: return launch_mass_diag_t<3>(pd, kappa, d, st);
+    case 4: return launch_mass_diag_t<4>(pd, kappa, d, st);
+    case 5: return launch_mass_diag_t<5>(pd, kappa, d, st);
+    default: return -4;
+    }
+}
+
+int launch_line_solves(const PatchDev& pd, double* v, int64_t ndof, hipStream_t st)
+{
+    switch (pd.p) {
+    case 1: return launch_line_solves_t<1>(pd, v, ndof, st);
+    case 2: return launch_line_solves_t<2>(pd, v, ndof, st);
+    case 3: return launch_line_solves_t<3>(pd, v, ndof, st);
+    case 4: return launch_line_solves_t<4>(pd, v, ndof, st);
+    case 5: return launch_line_solves_t<5>(pd, v, ndof, st);
+    default: return -4;
+    }
+}
+
 }  // namespace
 
-int64_t euler_workspace_doubles(int64_t ndof) { return 4 * ndof + kDotBlocks + 8; }
+int64_t euler_workspace_doubles(int64_t ndof) { return 6 * ndof + kDotBlocks + 8; }
 
-// Workspace: b | r | p | Ap (ndof each) | dot partials | CG scalars S[8]:
-// S[0] r.r, S[1] p.Ap, S[2] new r.r, S[3] beta, S[4] alpha.
-// Returns 0 (converged), 1 (maxit reached) or -3 (launch failure).
+// Workspace: b | r | p | Ap | z | s (ndof each) | dot partials | CG scalars S[8]:
+// S[0] r.z, S[1] p.Ap, S[2] new r.z, S[3] beta, S[4] alpha, S[5] r.r.
+// Without a preconditioner z is r itself.  Returns 0 (converged), 1 (maxit
+// reached) or -3 (launch failure).
 int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const double* mu, double dt,
-                   double tol, int maxit, double* x, double* work, int* iters, double* relres,
+                   double tol, int maxit, int precond, double* x, double* work, int* iters, double* relres,
                    hipStream_t st)
 {
     double* b = work;
     double* r = b + ndof;
     double* p = r + ndof;
     double* Ap = p + ndof;
-    double* partial = Ap + ndof;
+    double* z = precond ? Ap + ndof : r;
+    double* sc = Ap + 2 * ndof;
+    double* partial = Ap + 3 * ndof;
     double* S = partial + kDotBlocks;
     const int gv = grid_for(ndof);
     auto mass_apply = [&](const double* v, double* out, double aK) {
@@ -140,8 +300,22 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
                    ? 0
                    : -3;
     };
+    // z = P^-1 r = S^-1 (Mz (x) My (x) Mx)^-1 S^-1 r, with sc = S^-1
+    auto apply_precond = [&]() {
+        if (!precond) return 0;
+        hipLaunchKernelGGL(k_scale, dim3(gv), dim3(256), 0, st, z, r, sc, ndof);
+        if (launch_line_solves(pd, z, ndof, st)) return -3;
+        hipLaunchKernelGGL(k_scale, dim3(gv), dim3(256), 0, st, z, nullptr, sc, ndof);
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+    };
     *iters = 0;
     *relres = 0.0;
+    if (precond) {
+        if (launch_fill_zero(sc, ndof, st) || launch_mass_diag(pd, kappa, sc, st)) return -3;
+        const int W = pd.p + 2;
+        hipLaunchKernelGGL(k_precond_scale, dim3(gv), dim3(256), 0, st, sc, pd.d[0].Lm, pd.d[1].Lm,
+                           pd.d[2].Lm, pd.d[0].N, pd.d[1].N, W, ndof);
+    }
     // right-hand side b = M mu - dt K mu; r = M mu (x starts at mu)
     if (mass_apply(mu, b, -dt) || mass_apply(mu, r, 0.0)) return -3;
     double bb = 0.0, rr = 0.0;
@@ -151,20 +325,22 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
     if (bb == 0.0) {   // zero right-hand side: the solution is zero
         return launch_fill_zero(x, ndof, st) ? -3 : 0;
     }
-    if (dot(r, r, ndof, partial, S, 0, 0, st) || host_scalar(0, &rr)) return -3;
+    if (dot(r, r, ndof, partial, S, 5, 0, st) || host_scalar(5, &rr)) return -3;
     *relres = std::sqrt(rr / bb);
     if (*relres <= tol) return 0;
-    hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, r, S, ndof, 1);
+    if (apply_precond() || dot(r, z, ndof, partial, S, 0, 0, st)) return -3;
+    hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 1);
     for (int k = 1; k <= maxit; ++k) {
         if (mass_apply(p, Ap, 0.0)) return -3;
         if (dot(p, Ap, ndof, partial, S, 1, 1, st)) return -3;   // alpha
         hipLaunchKernelGGL(k_cg_xr, dim3(gv), dim3(256), 0, st, x, r, p, Ap, S, ndof);
-        if (dot(r, r, ndof, partial, S, 2, 2, st)) return -3;    // beta, new r.r
-        if (host_scalar(0, &rr)) return -3;
+        if (dot(r, r, ndof, partial, S, 5, 0, st) || host_scalar(5, &rr)) return -3;
         *iters = k;
         *relres = std::sqrt(rr / bb);
         if (*relres <= tol) return 0;
-        hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, r, S, ndof, 0);
+        if (apply_precond()) return -3;
+        if (dot(r, z, ndof, partial, S, 2, 2, st)) return -3;    // beta, new r.z
+        hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 0);
         if (hipGetLastError() != hipSuccess) return -3;
     }
     return 1;

@@ -221,6 +221,52 @@ igaf_status igaf_csr_pattern_host(const igaf_patch_desc* desc, int64_t* row_ptr,
     return IGAF_OK;
 }
 
+// The 1D mass matrix of every direction (kappa = 1, the plan's Gauss rule,
+// from the device basis tables) and its banded Cholesky factor L L^T, for the
+// preconditioner of the Euler step's mass solve.  Stored per DOF i as
+// [1/L_ii, L_{i,i-1}, ..., L_{i,i-p}, M_ii] (entries left of column 0 are 0).
+static igaf_status mass_factors(igaf_plan* P)
+{
+    const int p = P->p, n = P->n, B = p + 1, W = p + 2;
+    for (int a = 0; a < 3; ++a) {
+        const int K = P->K[a], Q = P->q[a], N = P->N[a];
+        std::vector<double> Nv((size_t)K * n * Q), wq((size_t)K * Q);
+        if (hipMemcpy(Nv.data(), P->dev.d[a].Nv, sizeof(double) * Nv.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(wq.data(), P->dev.d[a].wq, sizeof(double) * wq.size(), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(IGAF_EDEVICE, "copy of basis tables failed");
+        std::vector<double> A((size_t)N * B, 0.0);   // A[i*B + k] = M[i][i-k]
+        for (int e = 0; e < K; ++e)
+            for (int x = 0; x <= p; ++x)
+                for (int y = 0; y <= x; ++y)
+                    for (int k = 0; k < Q; ++k)
+                        A[(size_t)(e + x) * B + (x - y)] +=
+                            wq[(size_t)e * Q + k] * Nv[((size_t)e * n + x) * Q + k] * Nv[((size_t)e * n + y) * Q + k];
+        std::vector<double> L((size_t)N * B, 0.0);   // L[i*B + k] = L[i][i-k]
+        auto Lij = [&](int i, int j) { return L[(size_t)i * B + (i - j)]; };
+        for (int i = 0; i < N; ++i)
+            for (int j = std::max(0, i - p); j <= i; ++j) {
+                double v = A[(size_t)i * B + (i - j)];
+                for (int m = std::max(0, i - p); m < j; ++m) v -= Lij(i, m) * Lij(j, m);
+                if (j == i) {
+                    if (!(v > 0.0)) return fail(IGAF_EDEVICE, "1D mass matrix %d not positive definite", a);
+                    L[(size_t)i * B] = std::sqrt(v);
+                } else {
+                    L[(size_t)i * B + (i - j)] = v / Lij(j, j);
+                }
+            }
+        std::vector<double> out((size_t)N * W, 0.0);
+        for (int i = 0; i < N; ++i) {
+            out[(size_t)i * W] = 1.0 / L[(size_t)i * B];
+            for (int k = 1; k <= p; ++k) out[(size_t)i * W + k] = i - k >= 0 ? L[(size_t)i * B + k] : 0.0;
+            out[(size_t)i * W + p + 1] = A[(size_t)i * B];
+        }
+        if (hipMemcpy(const_cast<double*>(P->dev.d[a].Lm), out.data(), sizeof(double) * out.size(),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return fail(IGAF_EDEVICE, "upload of mass factors failed");
+    }
+    return IGAF_OK;
+}
+
 igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
 {
     if (!out) return fail(IGAF_EINVAL, "out is NULL");
@@ -242,14 +288,15 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
     }
     sizes_of(desc, &P->ndof, &P->E, &P->nqp, nullptr, &P->nnz);
 
-    // device layout: per direction [knots | xi | wr | Wnn | Wdd | Nv | dN | wq]
+    // device layout: per direction [knots | xi | wr | Wnn | Wdd | Nv | dN | wq | Lm]
     int64_t dcount = 0, icount = 0;
-    int64_t off[3][8];
+    int64_t off[3][9];
     for (int a = 0; a < 3; ++a) {
         int K = P->K[a], Q = P->q[a], nk = K + 2 * P->p + 1;
-        int64_t sz[8] = {nk, Q, Q, (int64_t)K * P->S * Q, (int64_t)K * P->S * Q,
-                         (int64_t)K * P->n * Q, (int64_t)K * P->n * Q, (int64_t)K * Q};
-        for (int j = 0; j < 8; ++j) {
+        int64_t sz[9] = {nk, Q, Q, (int64_t)K * P->S * Q, (int64_t)K * P->S * Q,
+                         (int64_t)K * P->n * Q, (int64_t)K * P->n * Q, (int64_t)K * Q,
+                         (int64_t)P->N[a] * (P->p + 2)};
+        for (int j = 0; j < 9; ++j) {
             off[a][j] = dcount;
             dcount += (sz[j] + 31) & ~int64_t(31);   // 256-byte aligned pieces
         }
@@ -317,6 +364,7 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
         D.Nv = base + off[a][5];
         D.dN = base + off[a][6];
         D.wq = base + off[a][7];
+        D.Lm = base + off[a][8];
         D.pre = P->dpre + ioff;
         D.K = K;
         D.N = N;
@@ -329,6 +377,7 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
     }
     if (rc == IGAF_OK && hipStreamSynchronize(nullptr) != hipSuccess)
         rc = fail(IGAF_EDEVICE, "basis-table kernel failed");
+    if (rc == IGAF_OK) rc = mass_factors(P);
     if (rc == IGAF_OK &&
         (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
          hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -574,17 +623,19 @@ int64_t igaf_euler_workspace(const igaf_plan* plan)
 }
 
 igaf_status igaf_euler_step(const igaf_plan* plan, const double* kappa, const double* mu, double dt,
-                            double tol, int32_t maxit, double* mu_next, double* work,
+                            double tol, int32_t maxit, int32_t precond, double* mu_next, double* work,
                             int32_t* iters, double* relres, void* stream)
 {
     igaf_status st = check_hot(plan, IGAF_SUMFACT);
     if (st) return st;
     if (!kappa || !mu || !mu_next || !work) return fail(IGAF_EINVAL, "kappa, mu, mu_next or work is NULL");
     if (!(tol >= 0.0) || maxit < 0) return fail(IGAF_EINVAL, "tol < 0 or maxit < 0");
+    if (precond != IGAF_PRECOND_NONE && precond != IGAF_PRECOND_KRON)
+        return fail(IGAF_EINVAL, "precond %d unknown", precond);
     int it = 0;
     double rr = 0.0;
-    int rc = run_euler_step(plan->dev, plan->ndof, kappa, mu, dt, tol, maxit, mu_next, work, &it, &rr,
-                            (hipStream_t)stream);
+    int rc = run_euler_step(plan->dev, plan->ndof, kappa, mu, dt, tol, maxit, precond, mu_next, work, &it,
+                            &rr, (hipStream_t)stream);
     if (iters) *iters = it;
     if (relres) *relres = rr;
     if (rc < 0) return fail(IGAF_EDEVICE, "Euler step: %s", hipGetErrorString(hipGetLastError()));

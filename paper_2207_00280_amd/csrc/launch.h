@@ -52,7 +52,7 @@ int launch_apply(const PatchDev& pd, const double* kappa, const double* u, doubl
 // Returns 0 (converged), 1 (maxit reached) or -3.
 int64_t euler_workspace_doubles(int64_t ndof);
 int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const double* mu, double dt,
-                   double tol, int maxit, double* x, double* work, int* iters, double* relres,
+                   double tol, int maxit, int precond, double* x, double* work, int* iters, double* relres,
                    hipStream_t st);
 
 int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,

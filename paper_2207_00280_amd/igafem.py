@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libigafem.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENOCONV = 0, -1, -2, -3, -4, -5
+PRECOND_NONE, PRECOND_KRON = 0, 1
 CLASSICAL, SUMFACT = 0, 1
 ASM_ROWS, ASM_ATOMIC = 0, 1
 MAX_DEGREE = 5
@@ -80,8 +81,9 @@ def lib():
     L.igaf_integrate_assemble_geo.argtypes = [_vp] * 8
     L.igaf_euler_workspace.argtypes = [_vp]
     L.igaf_euler_workspace.restype = ctypes.c_int64
-    L.igaf_euler_step.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _vp,
-                                  _vp, _i32p, ctypes.POINTER(ctypes.c_double), _vp]
+    L.igaf_euler_step.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                  ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_double), _vp]
     L.igaf_batch_create.argtypes = [ctypes.POINTER(PatchDesc), ctypes.c_int32, ctypes.POINTER(_vp)]
     L.igaf_batch_destroy.argtypes = [_vp]
     L.igaf_batch_destroy.restype = None
@@ -348,11 +350,14 @@ class Plan:
                                 _ptr(y), _stream(stream)))
         return y
 
-    def euler_step(self, kappa, mu, dt, tol=1e-12, maxit=1000, out=None, work=None, stream=None):
+    def euler_step(self, kappa, mu, dt, tol=1e-12, maxit=1000, precond=None, out=None, work=None,
+                   stream=None):
         """One forward Euler step M(kappa) mu_next = M(kappa) mu - dt K(kappa) mu
-        (igaf_euler_step, conjugate gradients on M).  Returns
-        (mu_next, iterations, relative residual); raises IgafError with status
-        ENOCONV if maxit is reached first."""
+        (igaf_euler_step, conjugate gradients on M; precond PRECOND_KRON (the
+        default) or PRECOND_NONE).  Returns (mu_next, iterations, relative
+        residual); raises IgafError with status ENOCONV if maxit is reached
+        first."""
+        precond = PRECOND_KRON if precond is None else int(precond)
         _need_f64_cuda(kappa, "kappa", self.nelem * self.nqp)
         _need_f64_cuda(mu, "mu", self.ndof)
         if out is None:
@@ -365,7 +370,7 @@ class Plan:
         it = ctypes.c_int32(0)
         rr = ctypes.c_double(0.0)
         _check(lib().igaf_euler_step(self._h, _ptr(kappa), _ptr(mu), float(dt), float(tol), int(maxit),
-                                     _ptr(out), _ptr(work), ctypes.byref(it), ctypes.byref(rr),
+                                     precond, _ptr(out), _ptr(work), ctypes.byref(it), ctypes.byref(rr),
                                      _stream(stream)))
         return out, it.value, rr.value
 
