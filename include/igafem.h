@@ -179,7 +179,8 @@ igaf_status igaf_element_matrices(const igaf_plan* plan, int32_t method, const d
 /* Global CSR values from stored element matrices (A = sum over elements of
  * A^gamma, Sec. 3.1; "insert local element into global"):  Mval, Kval [nnz]
  * are OVERWRITTEN.  A NULL output skips it; its input must then be NULL too.
- * Deterministic (each value is summed by one thread in element order). */
+ * Each CSR row is summed by one wavefront in element order (LDS adds in
+ * issue order), so repeated calls give the same bits. */
 igaf_status igaf_assemble(const igaf_plan* plan, const double* Me, const double* Ke,
                           double* Mval, double* Kval, void* stream);
 
