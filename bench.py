@@ -185,6 +185,10 @@ def bench_w4(ig, torch, stream, steps):
     b = sum(pl.nelem * pl.nqp * 8 for pl in B.plans) + 2 * nnz * 8
     f = sum(pl.nelem * sumfact_flops(pl.p) for pl in B.plans)
     troof = max(b / HBM_PEAK, f / FP64_PEAK)
+    ms_untuned = float(np.mean(timed(lambda: B.integrate_assemble(kaps, Ms, Ks), steps, 2, stream)))
+    t0 = time.perf_counter()
+    tuned = B.autotune(kaps, Ms, Ks, reps=2, stream=stream)
+    t_tune = time.perf_counter() - t0
     ms_b = float(np.mean(timed(lambda: B.integrate_assemble(kaps, Ms, Ks), steps, 2, stream)))
     ms_s = float(np.mean(timed(lambda: B.integrate_assemble(kaps, Ms, Ks, separate=True), steps, 2, stream)))
     # the 256 separate launches captured in one HIP graph and replayed
@@ -207,13 +211,14 @@ def bench_w4(ig, torch, stream, steps):
     info = B.info()
     out = {"patches": len(shapes), "elements": E, "nnz": nnz, "bytes": b, "flops": f,
            "roofline_ms": troof * 1e3,
-           "batched": {"ms": ms_b, "elements_per_s": E / (ms_b * 1e-3), "frac": troof / (ms_b * 1e-3)},
+           "batched": {"ms": ms_b, "elements_per_s": E / (ms_b * 1e-3), "frac": troof / (ms_b * 1e-3),
+                       "work_split": tuned, "autotune_s": t_tune, "untuned_ms": ms_untuned},
            "batched_graph": {"ms": ms_g2, "elements_per_s": E / (ms_g2 * 1e-3)},
            "separate_eager": {"ms": ms_s, "elements_per_s": E / (ms_s * 1e-3)},
            "separate_graph": {"ms": ms_g, "elements_per_s": E / (ms_g * 1e-3)},
            "launch": info, "create_s": t_create}
-    log("W4: batched %.2f ms, graph %.2f ms, separate %.2f ms, separate graph %.2f ms (%s)"
-        % (ms_b, ms_g2, ms_s, ms_g, info))
+    log("W4: batched %.2f ms (autotuned %s; %.2f ms untuned), graph %.2f ms, separate %.2f ms, "
+        "separate graph %.2f ms (%s)" % (ms_b, tuned, ms_untuned, ms_g2, ms_s, ms_g, info))
     del Ms, Ks, kaps, B, g, g2
     torch.cuda.empty_cache()
     return out

@@ -273,10 +273,12 @@ igaf_status igaf_euler_step(const igaf_plan* plan, const double* kappa, const do
  * Many independent patches (the paper's first concurrency level: parts of
  * the mesh computed concurrently) integrated and assembled to CSR (streamed
  * mode, M and K) by ONE kernel launch over one work list: one workgroup per
- * (patch, tile of row pencils) item, items sorted longest first. */
+ * (patch, tile of row pencils, x segment) item, items sorted longest first. */
 
 /* Build per-patch plans, the device patch table and the work list
- * (synchronous).  descs: HOST array of npatch descriptions. */
+ * (synchronous; one segment per tile and 16 items per XCD chunk until
+ * igaf_batch_autotune picks a split).  descs: HOST array of npatch
+ * descriptions. */
 igaf_status igaf_batch_create(const igaf_patch_desc* descs, int32_t npatch, igaf_batch** out);
 
 /* Release a batch (NULL is ignored). */
@@ -311,6 +313,30 @@ igaf_status igaf_batch_integrate_assemble_separate(igaf_batch* batch,
                                                    const double* const* kappa,
                                                    double* const* Mval, double* const* Kval,
                                                    void* stream);
+
+/* Autotuner of the batched launch (synchronous; not under stream capture).
+ * The launch's work split has two knobs: the x segments each tile of row
+ * pencils is cut into (1, 2, 4 or 8, never below 2(p+1) rows per segment; a
+ * segment that does not start at the patch boundary sweeps p warm-up
+ * elements first), which shortens the longest items at the cost of the
+ * warm-ups, and the number of consecutive items handed to one XCD (4, 16 or
+ * 64), which trades L2 sharing between neighbouring tiles against balance.
+ * Every combination is timed on the caller's arrays (one warm-up launch,
+ * then `reps` launches, 1..100, HIP events on `stream`, the median kept);
+ * the fastest is used by every later igaf_batch_integrate_assemble.  Mval,
+ * Kval are overwritten, with the same values every time: each CSR value is
+ * summed in one thread in a fixed order whatever the split. */
+igaf_status igaf_batch_autotune(igaf_batch* batch, const double* const* kappa, double* const* Mval,
+                                double* const* Kval, int32_t reps, void* stream);
+
+/* Set the work split by hand (synchronous): split in {1, 2, 4, 8}, chunk in
+ * {4, 16, 64}, else IGAF_EINVAL; e.g. to reuse an earlier tuning. */
+igaf_status igaf_batch_set_split(igaf_batch* batch, int32_t split, int32_t chunk);
+
+/* The work split in use: segments per tile (at most), items per XCD chunk,
+ * and the median launch time in ms when the autotuner chose it (0 before).
+ * Any output may be NULL. */
+igaf_status igaf_batch_split(const igaf_batch* batch, int32_t* split, int32_t* chunk, double* tuned_ms);
 
 #ifdef __cplusplus
 }

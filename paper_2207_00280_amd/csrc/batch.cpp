@@ -1,12 +1,16 @@
 // Batched integration + assembly of many independent patches (the paper's
 // first concurrency level: parts of the mesh computed concurrently) in ONE
 // launch.  Host side: per-patch plans, the device patch table and the work
-// list of (patch, tile) items, sorted longest first so that the hardware's
-// in-order workgroup dispatch balances the launch.
+// list of (patch, tile, x segment) items, sorted longest first so that the
+// hardware's in-order workgroup dispatch balances the launch, and the
+// autotuner that picks the work split (segments per tile, items per XCD
+// chunk) by timing the launch on the caller's data.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <iterator>
 #include <new>
 #include <vector>
 
@@ -17,24 +21,41 @@ using namespace igaf;
 
 namespace {
 
-// Every tile of every patch, longest first; stable, so that the tiles of one
-// patch stay in order (neighbouring tiles share kappa and tables in cache).
-std::vector<int2> build_items(const std::vector<igaf_plan*>& plans)
+constexpr int kMaxSplit = 8;          // x segments per tile, at most
+constexpr int kSplits[] = {1, 2, 4, 8};
+constexpr int kChunks[] = {4, 16, 64};
+constexpr int kDefaultChunk = 16;
+
+// Every (tile, x segment) of every patch, longest first; stable, so that the
+// tiles of one patch stay in order (neighbouring tiles share kappa and tables
+// in cache).  A patch's rows are cut into at most `split` segments of at
+// least 2(p+1) rows; a segment that does not start at row 0 sweeps p
+// warm-up elements first, which its cost includes.
+std::vector<int4> build_items(const std::vector<igaf_plan*>& plans, int split)
 {
     struct C {
         double cost;
-        int2 it;
+        int4 it;
     };
     std::vector<C> all;
     for (size_t i = 0; i < plans.size(); ++i) {
         const PatchDev& pd = plan_dev(plans[i]);
         int n = 0;
-        double c = 0.0;
-        if (rows_tile_info(pd.p, pd.d[1].N, pd.d[2].N, pd.d[0].K, &n, &c) != 0) continue;
-        for (int k = 0; k < n; ++k) all.push_back({c, make_int2((int)i, k)});
+        double per_elem = 0.0;
+        if (rows_tile_info(pd.p, pd.d[1].N, pd.d[2].N, &n, &per_elem) != 0) continue;
+        const int Nx = pd.d[0].N;
+        const int nseg = std::max(1, std::min(split, Nx / (2 * (pd.p + 1))));
+        const int seglen = (Nx + nseg - 1) / nseg;
+        for (int k = 0; k < n; ++k)
+            for (int sgi = 0; sgi < nseg; ++sgi) {
+                const int X0 = sgi * seglen, X1 = std::min(Nx, X0 + seglen);
+                if (X0 >= X1) continue;
+                const double cost = per_elem * (X1 - std::max(0, X0 - pd.p));
+                all.push_back({cost, make_int4((int)i, k, sgi, seglen)});
+            }
     }
     std::stable_sort(all.begin(), all.end(), [](const C& a, const C& b) { return a.cost > b.cost; });
-    std::vector<int2> items;
+    std::vector<int4> items;
     items.reserve(all.size());
     for (auto& c : all) items.push_back(c.it);
     return items;
@@ -46,9 +67,12 @@ struct igaf_batch {
     std::vector<igaf_plan*> plans;
     int device = 0;
     int nitems = 0;
+    int split = 1, chunk = kDefaultChunk;   // work split in use
+    double tuned_ms = 0.0;                  // its time when the autotuner chose it
+    size_t cap = 0;                         // items the device list can hold
     BatchPatch* d_patches = nullptr;
     BatchPatch* h_patches = nullptr;   // pinned staging of the device table
-    int2* d_items = nullptr;
+    int4* d_items = nullptr;
     bool uploaded = false;
 };
 
@@ -60,6 +84,21 @@ static void batch_free(igaf_batch* B)
     if (B->d_items) (void)hipFree(B->d_items);
     for (auto* p : B->plans) igaf_plan_destroy(p);
     delete B;
+}
+
+// Build and upload the work list of one split (synchronous: the previous list
+// may still be read by a queued launch).
+static bool set_work_list(igaf_batch* B, int split, int chunk)
+{
+    std::vector<int4> items = build_items(B->plans, split);
+    if (items.size() > B->cap) return false;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(B->d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return false;
+    B->nitems = (int)items.size();
+    B->split = split;
+    B->chunk = chunk;
+    return true;
 }
 
 static BatchPatch make_patch(const igaf_plan* p)
@@ -97,14 +136,11 @@ igaf_status igaf_batch_create(const igaf_patch_desc* descs, int32_t npatch, igaf
         batch_free(B);
         return set_error(IGAF_EDEVICE, "hipGetDevice failed");
     }
-    std::vector<int2> items = build_items(B->plans);
-    B->nitems = (int)items.size();
-    bool ok = hipMalloc(&B->d_items, sizeof(int2) * std::max<size_t>(1, items.size())) == hipSuccess &&
-              hipMemcpy(B->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice) ==
-                  hipSuccess &&
+    B->cap = std::max<size_t>(1, build_items(B->plans, kMaxSplit).size());
+    bool ok = hipMalloc(&B->d_items, sizeof(int4) * B->cap) == hipSuccess &&
               hipMalloc(&B->d_patches, sizeof(BatchPatch) * npatch) == hipSuccess &&
               hipHostMalloc(&B->h_patches, sizeof(BatchPatch) * npatch, hipHostMallocDefault) == hipSuccess &&
-              hipDeviceSynchronize() == hipSuccess;
+              set_work_list(B, 1, kDefaultChunk);
     if (!ok) {
         batch_free(B);
         return set_error(IGAF_ENOMEM, "batch device allocation failed");
@@ -131,8 +167,28 @@ igaf_status igaf_batch_info(const igaf_batch* B, int32_t* family, int32_t* grid,
 {
     if (!B) return set_error(IGAF_EINVAL, "batch is NULL");
     if (family) *family = 0;   // work items are tiles of row pencils
-    if (grid) *grid = rows_batch_grid(B->nitems);
+    if (grid) *grid = rows_batch_grid(B->nitems, B->chunk);
     if (nitems) *nitems = B->nitems;
+    return IGAF_OK;
+}
+
+igaf_status igaf_batch_set_split(igaf_batch* B, int32_t split, int32_t chunk)
+{
+    if (!B) return set_error(IGAF_EINVAL, "batch is NULL");
+    if (std::find(std::begin(kSplits), std::end(kSplits), split) == std::end(kSplits) ||
+        std::find(std::begin(kChunks), std::end(kChunks), chunk) == std::end(kChunks))
+        return set_error(IGAF_EINVAL, "split must be 1, 2, 4 or 8 and chunk 4, 16 or 64");
+    if (!set_work_list(B, split, chunk)) return set_error(IGAF_EDEVICE, "work list upload failed");
+    B->tuned_ms = 0.0;
+    return IGAF_OK;
+}
+
+igaf_status igaf_batch_split(const igaf_batch* B, int32_t* split, int32_t* chunk, double* tuned_ms)
+{
+    if (!B) return set_error(IGAF_EINVAL, "batch is NULL");
+    if (split) *split = B->split;
+    if (chunk) *chunk = B->chunk;
+    if (tuned_ms) *tuned_ms = B->tuned_ms;
     return IGAF_OK;
 }
 
@@ -168,8 +224,71 @@ igaf_status igaf_batch_integrate_assemble(igaf_batch* B, const double* const* ka
     if (hipMemcpyAsync(B->d_patches, B->h_patches, sizeof(BatchPatch) * n, hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return set_error(IGAF_EDEVICE, "patch table upload failed");
-    if (launch_rows_batch(B->d_patches, B->d_items, B->nitems, s))
+    if (launch_rows_batch(B->d_patches, B->d_items, B->nitems, B->chunk, s))
         return set_error(IGAF_EDEVICE, "batched launch failed");
+    return IGAF_OK;
+}
+
+igaf_status igaf_batch_autotune(igaf_batch* B, const double* const* kappa, double* const* Mval,
+                                double* const* Kval, int32_t reps, void* stream)
+{
+    if (!B || !kappa || (!Mval && !Kval)) return set_error(IGAF_EINVAL, "NULL argument");
+    if (reps < 1 || reps > 100) return set_error(IGAF_EINVAL, "reps outside [1, 100]");
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return set_error(IGAF_EINVAL, "the autotuner times launches: not under stream capture");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return set_error(IGAF_EDEVICE, "event creation failed");
+    }
+    igaf_status st = IGAF_OK;
+    int best_split = 1, best_chunk = kDefaultChunk;
+    double best = INFINITY;
+    int last_split = -1;
+    for (int split : kSplits) {
+        for (int chunk : kChunks) {
+            if (split != last_split) {
+                if (!set_work_list(B, split, chunk)) {
+                    st = set_error(IGAF_EDEVICE, "work list upload failed");
+                    break;
+                }
+                last_split = split;
+            } else {
+                B->chunk = chunk;   // same list, another launch mapping
+            }
+            std::vector<float> ms;
+            st = igaf_batch_integrate_assemble(B, kappa, Mval, Kval, stream);   // warm-up
+            for (int r = 0; r < reps && !st; ++r) {
+                float t = 0.f;
+                if (hipEventRecord(e0, s) != hipSuccess) { st = set_error(IGAF_EDEVICE, "event record failed"); break; }
+                st = igaf_batch_integrate_assemble(B, kappa, Mval, Kval, stream);
+                if (st) break;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+                    st = set_error(IGAF_EDEVICE, "timing failed");
+                    break;
+                }
+                ms.push_back(t);
+            }
+            if (st) break;
+            std::sort(ms.begin(), ms.end());
+            const double med = ms[ms.size() / 2];
+            if (med < best) {
+                best = med;
+                best_split = split;
+                best_chunk = chunk;
+            }
+        }
+        if (st) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!set_work_list(B, st ? 1 : best_split, st ? kDefaultChunk : best_chunk))
+        return set_error(IGAF_EDEVICE, "work list upload failed");
+    if (st) return st;
+    B->tuned_ms = best;
     return IGAF_OK;
 }
 

@@ -604,9 +604,11 @@ int launch_rows(const PatchDev& pd, const double* kappa, double* Mv, double* Kv,
 }
 
 // ---------------------------------------------------------------------------
-// Batched launch: one workgroup per work item (patch, tile) of a list sorted
-// longest first; every degree's tile is one workgroup of 256 threads, so one
-// kernel runs any of them.  Each tile sweeps all rows of its pencils.
+// Batched launch: one workgroup per work item (patch, tile, x segment) of a
+// list sorted longest first; every degree's tile is one workgroup of 256
+// threads, so one kernel runs any of them.  An item sweeps the rows of its
+// pencils in its x segment (after p warm-up elements when it does not start
+// at the patch boundary).
 
 template <int P> using TileOf = typename BatchCfg<P>::T;
 static_assert(TileOf<1>::NT == 256 && TileOf<2>::NT == 256 && TileOf<3>::NT == 256 &&
@@ -614,7 +616,6 @@ static_assert(TileOf<1>::NT == 256 && TileOf<2>::NT == 256 && TileOf<3>::NT == 2
               "the batched kernel runs every degree's tile with 256 threads");
 constexpr int kBatchLds = cmax(cmax(cmax(TileOf<1>::LDS, TileOf<2>::LDS), cmax(TileOf<3>::LDS, TileOf<4>::LDS)),
                                TileOf<5>::LDS);
-constexpr int kBatchChunk = 16;   // consecutive work items handed to one XCD
 
 template <class Tp>
 __device__ inline Tp uniform_ptr(Tp p)
@@ -647,17 +648,18 @@ __device__ inline void uniform_patch(const BatchPatch& src, PatchDev& pd, RowMap
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rows_tile_batch(
-    const BatchPatch* __restrict__ patches, const int2* __restrict__ items, int nitems)
+    const BatchPatch* __restrict__ patches, const int4* __restrict__ items, int nitems, int chunk)
 {
     __shared__ double lds[kBatchLds];
     // XCD x (which receives workgroups b = x mod 8) takes the item chunks
     // x, x+8, x+16, ...: neighbouring tiles share its L2, and the list stays
     // longest-first on every XCD
     const int x = blockIdx.x % 8, j = blockIdx.x / 8;
-    const int b = ((j / kBatchChunk) * 8 + x) * kBatchChunk + j % kBatchChunk;
+    const int b = ((j / chunk) * 8 + x) * chunk + j % chunk;
     if (b >= nitems) return;
-    const int2 it = items[b];
+    const int4 it = items[b];
     const int pid = uniform_int(it.x), tile = uniform_int(it.y);
+    const int seg = uniform_int(it.z), seglen = uniform_int(it.w);
     PatchDev pd;
     RowMap rm;
     const double* kappa;
@@ -667,8 +669,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     switch (pd.p) {
 #define IGAF_TB(PP)                                                                                 \
     case PP:                                                                                        \
-        tile_run<TileOf<PP>>(pd, rm, kappa, Mv, Kv, tile, 0, (Ny + TileOf<PP>::TY - 1) / TileOf<PP>::TY, \
-                             1 << 30, lds);                                                         \
+        tile_run<TileOf<PP>>(pd, rm, kappa, Mv, Kv, tile, seg, (Ny + TileOf<PP>::TY - 1) / TileOf<PP>::TY, \
+                             seglen, lds);                                                          \
         break;
         IGAF_TB(1)
         IGAF_TB(2)
@@ -681,39 +683,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 }
 
-int launch_rows_batch(const BatchPatch* patches, const int2* items, int nitems, hipStream_t st)
+int launch_rows_batch(const BatchPatch* patches, const int4* items, int nitems, int chunk, hipStream_t st)
 {
     if (nitems <= 0) return 0;
-    hipLaunchKernelGGL(k_rows_tile_batch, dim3(rows_batch_grid(nitems)), dim3(256), 0, st, patches,
-                       items, nitems);
+    if (chunk < 1) return -4;
+    hipLaunchKernelGGL(k_rows_tile_batch, dim3(rows_batch_grid(nitems, chunk)), dim3(256), 0, st, patches,
+                       items, nitems, chunk);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int rows_batch_grid(int nitems)
+int rows_batch_grid(int nitems, int chunk)
 {
-    return nitems <= 0 ? 0 : (nitems + 8 * kBatchChunk - 1) / (8 * kBatchChunk) * (8 * kBatchChunk);
+    return nitems <= 0 || chunk < 1 ? 0 : (nitems + 8 * chunk - 1) / (8 * chunk) * (8 * chunk);
 }
 
-// Tiles of a degree-p patch and the relative cost of one (a whole x sweep):
-// fused-multiply-add issue slots of its wavefronts per x element, times the
-// elements swept.  Used to sort the batch longest first.
+// Tiles of a degree-p patch and the relative cost of one element step of a
+// tile: fused-multiply-add issue slots of its wavefronts per x element (an
+// item costs this times the elements it sweeps).  Used to sort the batch
+// longest first.
 template <class T>
-static void tile_info_t(int Ny, int Nz, int Kx, int* ntile, double* cost)
+static void tile_info_t(int Ny, int Nz, int* ntile, double* per_elem)
 {
     *ntile = ((Ny + T::TY - 1) / T::TY) * ((Nz + T::TZ - 1) / T::TZ);
     constexpr double terms = (double)(T::P + 1) * (T::P + 1) * T::Q;
-    const double per_elem = T::NWZ * 2.0 * terms + T::NWY * 3.0 * terms + T::WX * 3.0 * terms;
-    *cost = per_elem * (Kx + T::P);
+    *per_elem = T::NWZ * 2.0 * terms + T::NWY * 3.0 * terms + T::WX * 3.0 * terms;
 }
 
-int rows_tile_info(int p, int Ny, int Nz, int Kx, int* ntile, double* cost)
+int rows_tile_info(int p, int Ny, int Nz, int* ntile, double* per_elem)
 {
     switch (p) {
-    case 1: tile_info_t<TileOf<1>>(Ny, Nz, Kx, ntile, cost); return 0;
-    case 2: tile_info_t<TileOf<2>>(Ny, Nz, Kx, ntile, cost); return 0;
-    case 3: tile_info_t<TileOf<3>>(Ny, Nz, Kx, ntile, cost); return 0;
-    case 4: tile_info_t<TileOf<4>>(Ny, Nz, Kx, ntile, cost); return 0;
-    case 5: tile_info_t<TileOf<5>>(Ny, Nz, Kx, ntile, cost); return 0;
+    case 1: tile_info_t<TileOf<1>>(Ny, Nz, ntile, per_elem); return 0;
+    case 2: tile_info_t<TileOf<2>>(Ny, Nz, ntile, per_elem); return 0;
+    case 3: tile_info_t<TileOf<3>>(Ny, Nz, ntile, per_elem); return 0;
+    case 4: tile_info_t<TileOf<4>>(Ny, Nz, ntile, per_elem); return 0;
+    case 5: tile_info_t<TileOf<5>>(Ny, Nz, ntile, per_elem); return 0;
     default: return -4;
     }
 }

@@ -26,7 +26,8 @@ SYMBOLS = [
     "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_apply", "igaf_euler_workspace", "igaf_euler_step",
     "igaf_batch_create", "igaf_batch_destroy",
     "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
-    "igaf_batch_integrate_assemble_separate",
+    "igaf_batch_integrate_assemble_separate", "igaf_batch_autotune", "igaf_batch_split",
+    "igaf_batch_set_split",
 ]
 
 
@@ -93,6 +94,9 @@ def lib():
     ptrs = ctypes.POINTER(_vp)
     L.igaf_batch_integrate_assemble.argtypes = [_vp, ptrs, ptrs, ptrs, _vp]
     L.igaf_batch_integrate_assemble_separate.argtypes = [_vp, ptrs, ptrs, ptrs, _vp]
+    L.igaf_batch_autotune.argtypes = [_vp, ptrs, ptrs, ptrs, ctypes.c_int32, _vp]
+    L.igaf_batch_split.argtypes = [_vp, _i32p, _i32p, ctypes.POINTER(ctypes.c_double)]
+    L.igaf_batch_set_split.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
     for name in SYMBOLS:
         f = getattr(L, name)
         if f.restype is ctypes.c_int:   # default restype -> status
@@ -423,6 +427,25 @@ class Batch:
         v = [ctypes.c_int32() for _ in range(3)]
         _check(lib().igaf_batch_info(self._h, *[ctypes.byref(x) for x in v]))
         return dict(zip(["family", "grid", "nitems"], [x.value for x in v]))
+
+    def split(self):
+        """The work split in use: segments per tile, items per XCD chunk, and
+        the autotuner's median time for it (0 before tuning)."""
+        a, b, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().igaf_batch_split(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t)))
+        return dict(split=a.value, chunk=b.value, ms=t.value)
+
+    def set_split(self, split, chunk):
+        _check(lib().igaf_batch_set_split(self._h, int(split), int(chunk)))
+
+    def autotune(self, kappas, Mvals, Kvals, reps=3, stream=None):
+        """Time every work split on these arrays and keep the fastest
+        (igaf_batch_autotune); returns split()."""
+        _check(lib().igaf_batch_autotune(self._h, _ptr_array(kappas),
+                                         _ptr_array(Mvals) if Mvals is not None else None,
+                                         _ptr_array(Kvals) if Kvals is not None else None, int(reps),
+                                         _stream(stream)))
+        return self.split()
 
     def integrate_assemble(self, kappas, Mvals, Kvals, separate=False, stream=None):
         f = lib().igaf_batch_integrate_assemble_separate if separate else lib().igaf_batch_integrate_assemble

@@ -96,6 +96,61 @@ def test_batch_graph_replay(ig):
         _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
 
 
+def test_batch_autotune(ig):
+    """The autotuner times every work split (segments per tile 1, 2, 4, 8;
+    items per XCD chunk 4, 16, 64) and keeps the fastest.  Patches long
+    enough in x to be cut into segments (K_x up to 40, p = 1..5): the values
+    after tuning equal the untuned launch bit for bit (each CSR value is
+    summed by one thread in a fixed order whatever the split), and match the
+    per-patch launches; a forced split of 8 segments also gives the same
+    bits."""
+    import torch
+
+    rng = np.random.default_rng(17)
+    specs = []
+    for i in range(10):
+        p = int(rng.integers(1, 6))
+        K = (int(rng.integers(20, 41)), int(rng.integers(2, 7)), int(rng.integers(2, 6)))
+        specs.append((p, K, [W.open_uniform_knots(k, p) for k in K]))
+    B = ig.Batch(specs)
+    assert B.split() == {"split": 1, "chunk": 16, "ms": 0.0}
+    kaps = [to_dev(W.kappa_lognormal(pl.nelem, pl.nqp, seed=300 + i)) for i, pl in enumerate(B.plans)]
+    Ms = [torch.empty(pl.nnz, dtype=torch.float64, device="cuda") for pl in B.plans]
+    Ks = [torch.empty(pl.nnz, dtype=torch.float64, device="cuda") for pl in B.plans]
+    B.integrate_assemble(kaps, Ms, Ks)
+    torch.cuda.synchronize()
+    ref = [m.clone() for m in Ms] + [k.clone() for k in Ks]
+    n_untuned = B.info()["nitems"]
+    sp = B.autotune(kaps, Ms, Ks, reps=1)
+    assert sp["split"] in (1, 2, 4, 8) and sp["chunk"] in (4, 16, 64) and sp["ms"] > 0
+    assert B.info()["nitems"] >= n_untuned
+    for t in Ms + Ks:
+        t.fill_(np.nan)
+    B.integrate_assemble(kaps, Ms, Ks)
+    torch.cuda.synchronize()
+    for a, b in zip(Ms + Ks, ref):
+        assert torch.equal(a, b)
+    Ms2 = [torch.empty_like(m) for m in Ms]
+    Ks2 = [torch.empty_like(k) for k in Ks]
+    B.integrate_assemble(kaps, Ms2, Ks2, separate=True)
+    torch.cuda.synchronize()
+    for a, b in zip(Ms + Ks, Ms2 + Ks2):
+        assert float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) <= 1e-12
+    for split, chunk in ((8, 4), (2, 64)):
+        B.set_split(split, chunk)
+        assert B.split()["split"] == split and B.info()["nitems"] > n_untuned
+        for t in Ms + Ks:
+            t.fill_(np.nan)
+        B.integrate_assemble(kaps, Ms, Ks)
+        torch.cuda.synchronize()
+        for a, b in zip(Ms + Ks, ref):
+            assert torch.equal(a, b), (split, chunk)
+    with pytest.raises(ig.IgafError):
+        B.autotune(kaps, Ms, Ks, reps=0)
+    with pytest.raises(ig.IgafError):
+        B.set_split(3, 16)
+
+
 def test_w4_batch_fullscale(orc, ig):
     """256 patches (seed 1): K_d ~ U{8..48}, p ~ U{2..5}, log-normal kappa.
     The batched launch equals the 256 per-patch launches value for value
