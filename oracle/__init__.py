@@ -51,6 +51,8 @@ def lib():
                                            ctypes.c_int64]
         L.orc_kappa_grad.argtypes = patch + [dp, dp, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, dp]
+        L.orc_kappa_grad_geo.argtypes = patch + [dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                                 ctypes.c_double, dp]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_set_num_threads.restype = None
@@ -213,13 +215,21 @@ def rows(P, kappa, dofs, G=None):
     return [(cols[r, :ln[r]].copy(), mv[r, :ln[r]].copy(), kv[r, :ln[r]].copy()) for r in range(len(dofs))]
 
 
-def kappa_grad(P, u, v, alphaM=1.0, alphaK=1.0, scale=1.0):
-    """Reference dL/dkappa at every quadrature point, [E, q^3]."""
+def kappa_grad(P, u, v, alphaM=1.0, alphaK=1.0, scale=1.0, cm0=None, G0=None):
+    """Reference dL/dkappa at every quadrature point, [E, q^3].  With cm0, G0
+    (mapped geometry, kappa scaling both coefficients: cm = kappa cm0,
+    G = kappa G0) the geometry's factors enter the point values."""
     u = _f64(u)
     v = _f64(v)
     assert u.size == P.ndof and v.size == P.ndof
     g = np.zeros((P.nelem, P.nq))
-    rc = lib().orc_kappa_grad(*P.args(), _dp(u), _dp(v), alphaM, alphaK, scale, _dp(g))
+    if G0 is not None:
+        cm0 = _f64(cm0).reshape(-1)
+        G0 = _geo_arg(P, G0)
+        rc = lib().orc_kappa_grad_geo(*P.args(), _dp(cm0), _dp(G0), _dp(u), _dp(v), alphaM, alphaK,
+                                      scale, _dp(g))
+    else:
+        rc = lib().orc_kappa_grad(*P.args(), _dp(u), _dp(v), alphaM, alphaK, scale, _dp(g))
     if rc != 0:
         raise ValueError("invalid patch")
     return g

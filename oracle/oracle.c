@@ -596,9 +596,33 @@ int orc_rows_geo(int p, const int* K, const int* q, const double* tx, const doub
 /* evaluated here point by point from the plain basis values.           */
 /* grad: [E][qz][qy][qx], scaled by `scale`.                            */
 /* ------------------------------------------------------------------ */
+static int kappa_grad_any(int p, const int* K, const int* q, const double* tx, const double* ty,
+                          const double* tz, const double* cm0, const double* G0, const double* u,
+                          const double* v, double alphaM, double alphaK, double scale, double* grad);
+
 int orc_kappa_grad(int p, const int* K, const int* q, const double* tx, const double* ty,
                    const double* tz, const double* u, const double* v, double alphaM,
                    double alphaK, double scale, double* grad)
+{
+    return kappa_grad_any(p, K, q, tx, ty, tz, NULL, NULL, u, v, alphaM, alphaK, scale, grad);
+}
+
+/* The same on a mapped geometry with kappa entering both coefficients
+ * linearly, cm = kappa cm0 and G = kappa G0 (cm0 = det J, G0 = det J J^-1 J^-T):
+ *   dL/dkappa_q = w_q (alphaM cm0 u_h v_h + alphaK grad u_h^T G0 grad v_h)(x_q),
+ * gradients with respect to the parameter coordinates.  cm0 [E][q^3],
+ * G0 [E][6][q^3] (xx yy zz xy xz yz). */
+int orc_kappa_grad_geo(int p, const int* K, const int* q, const double* tx, const double* ty,
+                       const double* tz, const double* cm0, const double* G0, const double* u,
+                       const double* v, double alphaM, double alphaK, double scale, double* grad)
+{
+    if (!cm0 || !G0) return -1;
+    return kappa_grad_any(p, K, q, tx, ty, tz, cm0, G0, u, v, alphaM, alphaK, scale, grad);
+}
+
+static int kappa_grad_any(int p, const int* K, const int* q, const double* tx, const double* ty,
+                          const double* tz, const double* cm0, const double* G0, const double* u,
+                          const double* v, double alphaM, double alphaK, double scale, double* grad)
 {
     if (orc_validate(p, K, q, tx, ty, tz)) return -1;
     orc_patch P = make_patch(p, K, q, tx, ty, tz);
@@ -633,8 +657,25 @@ int orc_kappa_grad(int p, const int* K, const int* q, const double* tx, const do
                 vg[0] += v[g] * fx; vg[1] += v[g] * fy; vg[2] += v[g] * fz;
             }
             double wq = X.w[k1] * Y.w[k2] * Z.w[k3];
-            double val = alphaM * uh * vh + alphaK * (ug[0] * vg[0] + ug[1] * vg[1] + ug[2] * vg[2]);
-            grad[e * qx * qy * qz + k1 + qx * (k2 + qy * k3)] = scale * wq * val;
+            int64_t nq = (int64_t)qx * qy * qz, kk = k1 + qx * (k2 + qy * k3);
+            double val;
+            if (G0) {
+                double Gm[3][3];
+                const double* g0 = G0 + e * 6 * nq + kk;
+                Gm[0][0] = g0[0];
+                Gm[1][1] = g0[nq];
+                Gm[2][2] = g0[2 * nq];
+                Gm[0][1] = Gm[1][0] = g0[3 * nq];
+                Gm[0][2] = Gm[2][0] = g0[4 * nq];
+                Gm[1][2] = Gm[2][1] = g0[5 * nq];
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) s += ug[a] * Gm[a][b] * vg[b];
+                val = alphaM * cm0[e * nq + kk] * uh * vh + alphaK * s;
+            } else {
+                val = alphaM * uh * vh + alphaK * (ug[0] * vg[0] + ug[1] * vg[1] + ug[2] * vg[2]);
+            }
+            grad[e * nq + kk] = scale * wq * val;
         }
     }
     return 0;

@@ -635,3 +635,40 @@ def test_geometry_linear_patch_tests(orc):
     for Kk in (Kd, Kd2):
         assert np.abs(Kk.sum(axis=1)).max() <= 1e-13 * np.abs(Kk).sum(axis=1).max()
         assert np.abs(Kk - Kk.T).max() <= 1e-14 * np.abs(Kk).max()
+
+
+def test_geometry_kappa_grad(orc):
+    """Gradient on a mapped geometry with cm = kappa cm0, G = kappa G0:
+    (1) L is linear in kappa, so L(kappa) = <kappa, g> where L comes from the
+        oracle's assembled matrices (element loops, not point values);
+    (2) u = v = 1: g = alphaM w cm0 (constant functions have no gradient);
+    (3) parametric linear u = c1.xi*, v = c2.xi* (Greville points):
+        g = w (alphaM cm0 u v + alphaK c1^T G0 c2) at every point."""
+    import scipy.sparse as sp
+
+    p, K = 2, (3, 4, 3)
+    knots = [_nonuniform_knots(k, p, 60 + d) for d, k in enumerate(K)]
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    xs, XI, wq = _points(orc, P)
+    cm0, G0 = W.mapped_geometry(xs[0][0], xs[1][0], xs[2][0], W.kappa_constant(P.nelem, P.nq), amp=0.1)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=14)
+    u = W.normal_vector(P.ndof, 15)
+    v = W.normal_vector(P.ndof, 16)
+    aM, aK = 0.7, 1.3
+    g = orc.kappa_grad(P, u, v, aM, aK, cm0=cm0, G0=G0)
+    rp, col, Mv, Kv = orc.assemble(P, kap * cm0, G=kap[:, None, :] * G0)
+    A = sp.csr_matrix((aM * Mv + aK * Kv, col, rp), shape=(P.ndof, P.ndof))
+    L = math.fsum((u * (A @ v)).tolist())
+    Lg = math.fsum((kap * g).ravel().tolist())
+    assert abs(L - Lg) <= 1e-13 * abs(L)
+    one = np.ones(P.ndof)
+    g1 = orc.kappa_grad(P, one, one, aM, aK, cm0=cm0, G0=G0)
+    np.testing.assert_allclose(g1, aM * wq * cm0, rtol=1e-13, atol=0)
+    gr = _greville_dofs(knots, p)
+    c1, c2 = np.array([0.4, -0.9, 1.2]), np.array([1.1, 0.3, -0.5])
+    gl = orc.kappa_grad(P, gr @ c1, gr @ c2, aM, aK, cm0=cm0, G0=G0)
+    Gq = np.zeros(G0.shape[:1] + G0.shape[2:] + (3, 3))
+    for c, (r, t) in enumerate([(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]):
+        Gq[..., r, t] = Gq[..., t, r] = G0[:, c, :]
+    ref = wq * (aM * cm0 * (XI @ c1) * (XI @ c2) + aK * np.einsum("a,...ab,b->...", c1, Gq, c2))
+    np.testing.assert_allclose(gl, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
