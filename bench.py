@@ -305,7 +305,8 @@ def bench_w6(ig, torch, stream, steps):
     """W6: the headline mesh on a curved map (mapped_geometry, amp 0.1): the
     element matrices from a per-point mass coefficient and stiffness tensor
     (7 q^3 doubles in, 2 n^6 out per element; HBM-bound), then with the CSR
-    values gathered from them, and the CSR values alone (FP64 atomics)."""
+    values gathered from them, the CSR values alone (FP64 atomics), and the
+    matrix-free apply and adjoint on the same geometry."""
     cfg = W.W6
     p, K = cfg["p"], cfg["K"]
     plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
@@ -324,6 +325,17 @@ def bench_w6(ig, torch, stream, steps):
                                  steps, 1, stream)))
     ms_csr = float(np.mean(timed(lambda: plan.integrate_assemble_geo(cmd, Gd, want_elem=False, Mval=Mv, Kval=Kv),
                                  max(2, steps // 2), 1, stream)))
+    del Me, Ke, Mv, Kv
+    torch.cuda.empty_cache()
+    # the matrix-free apply and the adjoint on the same geometry (kappa = 1
+    # here, so cm, G double as the geometry factors cm0, G0)
+    u = torch.from_numpy(W.normal_vector(plan.ndof, 3)).cuda()
+    v = torch.from_numpy(W.normal_vector(plan.ndof, 4)).cuda()
+    y = torch.empty_like(u)
+    g = torch.empty(plan.nelem, plan.nqp, dtype=torch.float64, device="cuda")
+    ms_ap = float(np.mean(timed(lambda: plan.apply_geo(cmd, Gd, u, 1.0, 1.0, y=y), steps, 2, stream)))
+    ms_ad = float(np.mean(timed(lambda: plan.kappa_grad_geo(cmd, Gd, u, v, grad=g), steps, 2, stream)))
+    del u, v, y, g
     b_el = plan.nelem * (7 * plan.nqp * 8 + 2 * n3 * n3 * 8)
     f_el = plan.nelem * geo_flops(p)
     roof = max(b_el / HBM_PEAK, f_el / FP64_PEAK)
@@ -331,10 +343,12 @@ def bench_w6(ig, torch, stream, steps):
            "element_matrices": {"ms": ms_el, "bytes": b_el, "flops": f_el, "GB/s": b_el / (ms_el * 1e-3) / 1e9,
                                 "roofline_ms": roof * 1e3, "frac": roof / (ms_el * 1e-3), "bound": "hbm"},
            "element_matrices_and_csr_gathered_ms": ms_all,
-           "csr_only_atomic_ms": ms_csr}
+           "csr_only_atomic_ms": ms_csr,
+           "apply_ms": ms_ap, "adjoint_ms": ms_ad}
     log("W6 mapped geometry: element matrices %.3f ms (%.0f%% of HBM roofline), + CSR gathered %.3f ms, "
-        "CSR alone (atomics) %.3f ms" % (ms_el, 100 * out["element_matrices"]["frac"], ms_all, ms_csr))
-    del cmd, Gd, Me, Ke, Mv, Kv, plan
+        "CSR alone (atomics) %.3f ms, apply %.3f ms, adjoint %.3f ms"
+        % (ms_el, 100 * out["element_matrices"]["frac"], ms_all, ms_csr, ms_ap, ms_ad))
+    del cmd, Gd, plan
     torch.cuda.empty_cache()
     return out
 

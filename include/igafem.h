@@ -243,6 +243,25 @@ igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double
 igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double* u,
                        double alphaM, double alphaK, double* y, void* stream);
 
+/* The operator apply on a mapped geometry (the coefficients of
+ * igaf_integrate_assemble_geo): y = alphaM M u + alphaK K u with
+ *   M_IJ = sum_q w_q cm_q phi_I phi_J,  K_IJ = sum_q w_q grad_xi phi_I^T G_q grad_xi phi_J.
+ * cm [E][q^3], G [E][6][q^3] (xx yy zz xy xz yz), u, y device [ndof]; y is
+ * OVERWRITTEN, must not overlap u, and is summed with FP64 atomics (last bits
+ * may vary between calls). */
+igaf_status igaf_apply_geo(const igaf_plan* plan, const double* cm, const double* G, const double* u,
+                           double alphaM, double alphaK, double* y, void* stream);
+
+/* The adjoint on a mapped geometry where kappa scales both coefficients,
+ * cm = kappa cm0 and G = kappa G0 (cm0 = det J, G0 = det J J^-1 J^-T):
+ * for L = alphaM u^T M(kappa) v + alphaK u^T K(kappa) v,
+ *   grad[e][q] = scale * w_q (alphaM cm0 u_h v_h + alphaK grad u_h^T G0 grad v_h)(x_q).
+ * cm0 [E][q^3], G0 [E][6][q^3], u, v device [ndof], grad device [E][q^3]
+ * OVERWRITTEN. */
+igaf_status igaf_kappa_grad_geo(const igaf_plan* plan, const double* cm0, const double* G0, const double* u,
+                                const double* v, double alphaM, double alphaK, double scale, double* grad,
+                                void* stream);
+
 /* One forward Euler step of the heat problem (Sec. 2.2, eq. Euler; the
  * matrix form of Sec. 2.4) with the coefficient kappa in both integrals:
  *   M(kappa) mu_next = M(kappa) mu - dt K(kappa) mu.

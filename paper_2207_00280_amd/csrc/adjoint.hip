@@ -70,12 +70,12 @@ struct AdjShape {
     static constexpr int RUN = 32;                                // elements per x-run
 };
 
-template <int P>
+// GEO: a mapped geometry; the point value takes the geometry factors cm0
+// (det J) and G0 (det J J^-1 J^-T, [E][6][q^3]) that kappa scales.
+template <int P, bool GEO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 : 2))) void k_kappa_grad(
-    PatchDev pd, const double* __restrict__ u,
-                                                    const double* __restrict__ v, double alphaM,
-                                                    double alphaK, double scale,
-                                                    double* __restrict__ grad)
+    PatchDev pd, const double* __restrict__ u, const double* __restrict__ v, double alphaM, double alphaK,
+    double scale, double* __restrict__ grad, const double* __restrict__ cm0, const double* __restrict__ G0)
 {
     using A = AdjShape<P>;
     constexpr int n = A::n, Q = A::Q, Q2 = A::Q2, Q3 = A::Q3, G = A::G, NXP = A::NXP;
@@ -233,10 +233,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                             ur[2][kz] = dy;
                             ur[3][kz] = dz;
                         } else {
-                            const double r = alphaM * ur[0][kz] * h +
-                                             alphaK * (ur[1][kz] * dx + ur[2][kz] * dy + ur[3][kz] * dz);
-                            if (zact && zg < ng)
-                                grad[e * Q3 + kz * Q2 + zky * Q + zkx] = scale * (wxl * wyl * wz_[kz]) * r;
+                            const int64_t pt = e * Q3 + kz * Q2 + zky * Q + zkx;
+                            double r;
+                            if constexpr (GEO) {
+                                const double* g0 = G0 + e * 6 * Q3 + kz * Q2 + zky * Q + zkx;
+                                const double gxx = g0[0], gyy = g0[Q3], gzz = g0[2 * Q3];
+                                const double gxy = g0[3 * Q3], gxz = g0[4 * Q3], gyz = g0[5 * Q3];
+                                const double vx = gxx * dx + gxy * dy + gxz * dz;
+                                const double vy = gxy * dx + gyy * dy + gyz * dz;
+                                const double vz = gxz * dx + gyz * dy + gzz * dz;
+                                r = alphaM * cm0[pt] * ur[0][kz] * h +
+                                    alphaK * (ur[1][kz] * vx + ur[2][kz] * vy + ur[3][kz] * vz);
+                            } else {
+                                r = alphaM * ur[0][kz] * h +
+                                    alphaK * (ur[1][kz] * dx + ur[2][kz] * dy + ur[3][kz] * dz);
+                            }
+                            if (zact && zg < ng) grad[pt] = scale * (wxl * wyl * wz_[kz]) * r;
                         }
                     }
                 }
@@ -246,16 +258,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 }
 
 int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,
-                      double alphaK, double scale, double* grad, hipStream_t st)
+                      double alphaK, double scale, double* grad, hipStream_t st, const double* cm0,
+                      const double* G0)
 {
     const int64_t runs = (int64_t)((pd.d[0].K + 31) / 32) * pd.d[1].K * pd.d[2].K;   // runs of 32 x elements
     int64_t blocks = (runs + 3) / 4;
     if (blocks > 8192) blocks = 8192;
+    const bool geo = G0 != nullptr;
     switch (pd.p) {
-#define IGAF_A(PP)                                                                         \
-    case PP:                                                                               \
-        hipLaunchKernelGGL((k_kappa_grad<PP>), dim3((unsigned)blocks), dim3(256), 0, st, pd, u, \
-                           v, alphaM, alphaK, scale, grad);                                \
+#define IGAF_A(PP)                                                                                    \
+    case PP:                                                                                          \
+        if (geo)                                                                                      \
+            hipLaunchKernelGGL((k_kappa_grad<PP, true>), dim3((unsigned)blocks), dim3(256), 0, st, pd, u, \
+                               v, alphaM, alphaK, scale, grad, cm0, G0);                             \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_kappa_grad<PP, false>), dim3((unsigned)blocks), dim3(256), 0, st, pd, \
+                               u, v, alphaM, alphaK, scale, grad, nullptr, nullptr);                 \
         break;
         IGAF_A(1)
         IGAF_A(2)

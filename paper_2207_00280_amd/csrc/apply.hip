@@ -69,10 +69,12 @@ struct ApplyShape {
     static constexpr int RUN = 32;                                // elements per x-run
 };
 
-template <int P>
+// GEO: a mapped geometry; `kappa` is the mass coefficient cm and Gt
+// ([E][6][q^3]) the stiffness tensor, applied to the parametric gradient.
+template <int P, bool GEO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 : 2))) void k_apply(
     PatchDev pd, const double* __restrict__ kappa, const double* __restrict__ u, double alphaM,
-    double alphaK, double* __restrict__ y)
+    double alphaK, double* __restrict__ y, const double* __restrict__ Gt)
 {
     using A = ApplyShape<P>;
     constexpr int n = A::n, Q = A::Q, Q2 = A::Q2, Q3 = A::Q3, G = A::G, NXP = A::NXP;
@@ -217,9 +219,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                         dy += nz * y1[a3];
                         dx += nz * y2[a3];
                     }
-                    const double c = kp[kz * Q2] * wxy * wz_[kz];
-                    const double t0 = alphaM * c * h, t1 = alphaK * c * dx, t2 = alphaK * c * dy,
-                                 t3 = alphaK * c * dz;
+                    double t0, t1, t2, t3;
+                    if constexpr (GEO) {
+                        const double wk = wxy * wz_[kz];
+                        const double* g = Gt + (exz + (int64_t)Kx * (ey + (int64_t)Ky * ez)) * 6 * Q3 + kz * Q2 +
+                                          zky * Q + zkx;
+                        const double gxx = g[0], gyy = g[Q3], gzz = g[2 * Q3];
+                        const double gxy = g[3 * Q3], gxz = g[4 * Q3], gyz = g[5 * Q3];
+                        t0 = alphaM * kp[kz * Q2] * wk * h;
+                        t1 = alphaK * wk * (gxx * dx + gxy * dy + gxz * dz);
+                        t2 = alphaK * wk * (gxy * dx + gyy * dy + gyz * dz);
+                        t3 = alphaK * wk * (gxz * dx + gyz * dy + gzz * dz);
+                    } else {
+                        const double c = kp[kz * Q2] * wxy * wz_[kz];
+                        t0 = alphaM * c * h;
+                        t1 = alphaK * c * dx;
+                        t2 = alphaK * c * dy;
+                        t3 = alphaK * c * dz;
+                    }
 #pragma unroll
                     for (int a3 = 0; a3 < n; ++a3) {
                         const double nz = Nz_[a3 * Q + kz], dzt = Dz_[a3 * Q + kz];
@@ -319,16 +336,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 }
 
 int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM,
-                 double alphaK, double* y, hipStream_t st)
+                 double alphaK, double* y, hipStream_t st, const double* G)
 {
     const int64_t runs = (int64_t)((pd.d[0].K + 31) / 32) * pd.d[1].K * pd.d[2].K;   // runs of 32 x elements
     int64_t blocks = (runs + 3) / 4;
     if (blocks > 8192) blocks = 8192;
+    const bool geo = G != nullptr;
     switch (pd.p) {
-#define IGAF_AP(PP)                                                                             \
-    case PP:                                                                                    \
-        hipLaunchKernelGGL((k_apply<PP>), dim3((unsigned)blocks), dim3(256), 0, st, pd, kappa, u, \
-                           alphaM, alphaK, y);                                                  \
+#define IGAF_AP(PP)                                                                                 \
+    case PP:                                                                                        \
+        if (geo)                                                                                    \
+            hipLaunchKernelGGL((k_apply<PP, true>), dim3((unsigned)blocks), dim3(256), 0, st, pd, kappa, \
+                               u, alphaM, alphaK, y, G);                                            \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_apply<PP, false>), dim3((unsigned)blocks), dim3(256), 0, st, pd,   \
+                               kappa, u, alphaM, alphaK, y, nullptr);                               \
         break;
         IGAF_AP(1)
         IGAF_AP(2)

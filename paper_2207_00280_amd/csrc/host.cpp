@@ -617,6 +617,31 @@ igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double*
     return launched(launch_apply(plan->dev, kappa, u, alphaM, alphaK, y, s), "operator apply");
 }
 
+igaf_status igaf_apply_geo(const igaf_plan* plan, const double* cm, const double* G, const double* u,
+                           double alphaM, double alphaK, double* y, void* stream)
+{
+    igaf_status st = check_hot(plan, IGAF_SUMFACT);
+    if (st) return st;
+    if (!cm || !G || !u || !y) return fail(IGAF_EINVAL, "cm, G, u or y is NULL");
+    if (u == y) return fail(IGAF_EINVAL, "y must not overlap u");
+    hipStream_t s = (hipStream_t)stream;
+    st = launched(launch_fill_zero(y, plan->ndof, s), "zero");
+    if (st) return st;
+    return launched(launch_apply(plan->dev, cm, u, alphaM, alphaK, y, s, G), "mapped-geometry apply");
+}
+
+igaf_status igaf_kappa_grad_geo(const igaf_plan* plan, const double* cm0, const double* G0, const double* u,
+                                const double* v, double alphaM, double alphaK, double scale, double* grad,
+                                void* stream)
+{
+    igaf_status st = check_hot(plan, IGAF_SUMFACT);
+    if (st) return st;
+    if (!cm0 || !G0 || !u || !v || !grad) return fail(IGAF_EINVAL, "cm0, G0, u, v or grad is NULL");
+    return launched(launch_kappa_grad(plan->dev, u, v, alphaM, alphaK, scale, grad, (hipStream_t)stream,
+                                      cm0, G0),
+                    "mapped-geometry kappa gradient");
+}
+
 int64_t igaf_euler_workspace(const igaf_plan* plan)
 {
     return plan ? euler_workspace_doubles(plan->ndof) : 0;

@@ -48,7 +48,7 @@ int launch_fill_zero(double* a, int64_t n, hipStream_t st);
 int launch_element_geo(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
                        double* Mv, double* Kv, hipStream_t st);
 int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM,
-                 double alphaK, double* y, hipStream_t st);
+                 double alphaK, double* y, hipStream_t st, const double* G = nullptr);
 
 // Forward Euler step: b = M mu - dt K mu, then CG on M x = b from x = mu.
 // Returns 0 (converged), 1 (maxit reached) or -3.
@@ -58,6 +58,7 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
                    hipStream_t st);
 
 int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,
-                      double alphaK, double scale, double* grad, hipStream_t st);
+                      double alphaK, double scale, double* grad, hipStream_t st,
+                      const double* cm0 = nullptr, const double* G0 = nullptr);
 
 }  // namespace igaf

@@ -23,7 +23,8 @@ SYMBOLS = [
     "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_csr_pattern_host",
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes",
     "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
-    "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_apply", "igaf_euler_workspace", "igaf_euler_step",
+    "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_apply",
+    "igaf_apply_geo", "igaf_kappa_grad_geo", "igaf_euler_workspace", "igaf_euler_step",
     "igaf_batch_create", "igaf_batch_destroy",
     "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
     "igaf_batch_integrate_assemble_separate", "igaf_batch_autotune", "igaf_batch_split",
@@ -80,6 +81,9 @@ def lib():
                                   ctypes.c_double, _vp, _vp]
     L.igaf_apply.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]
     L.igaf_integrate_assemble_geo.argtypes = [_vp] * 8
+    L.igaf_apply_geo.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]
+    L.igaf_kappa_grad_geo.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, _vp, _vp]
     L.igaf_euler_workspace.argtypes = [_vp]
     L.igaf_euler_workspace.restype = ctypes.c_int64
     L.igaf_euler_step.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
@@ -377,6 +381,32 @@ class Plan:
                                      precond, _ptr(out), _ptr(work), ctypes.byref(it), ctypes.byref(rr),
                                      _stream(stream)))
         return out, it.value, rr.value
+
+    def apply_geo(self, cm, G, u, alphaM=1.0, alphaK=1.0, y=None, stream=None):
+        """Mapped-geometry apply (igaf_apply_geo): y = alphaM M u + alphaK K u."""
+        _need_f64_cuda(cm, "cm", self.nelem * self.nqp)
+        _need_f64_cuda(G, "G", self.nelem * 6 * self.nqp)
+        _need_f64_cuda(u, "u", self.ndof)
+        if y is None:
+            y = self._alloc(self.ndof)
+        _need_f64_cuda(y, "y", self.ndof)
+        _check(lib().igaf_apply_geo(self._h, _ptr(cm), _ptr(G), _ptr(u), float(alphaM), float(alphaK),
+                                    _ptr(y), _stream(stream)))
+        return y
+
+    def kappa_grad_geo(self, cm0, G0, u, v, alphaM=1.0, alphaK=1.0, scale=1.0, grad=None, stream=None):
+        """Mapped-geometry adjoint (igaf_kappa_grad_geo): dL/dkappa when kappa
+        scales cm0 and G0."""
+        _need_f64_cuda(cm0, "cm0", self.nelem * self.nqp)
+        _need_f64_cuda(G0, "G0", self.nelem * 6 * self.nqp)
+        _need_f64_cuda(u, "u", self.ndof)
+        _need_f64_cuda(v, "v", self.ndof)
+        if grad is None:
+            grad = self._alloc(self.nelem, self.nqp)
+        _need_f64_cuda(grad, "grad", self.nelem * self.nqp)
+        _check(lib().igaf_kappa_grad_geo(self._h, _ptr(cm0), _ptr(G0), _ptr(u), _ptr(v), float(alphaM),
+                                         float(alphaK), float(scale), _ptr(grad), _stream(stream)))
+        return grad
 
     def kappa_grad(self, u, v, alphaM=1.0, alphaK=1.0, scale=1.0, grad=None, stream=None):
         _need_f64_cuda(u, "u", self.ndof)

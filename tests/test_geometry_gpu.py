@@ -182,3 +182,79 @@ def test_geometry_errors(ig):
     with pytest.raises(ig.IgafError) as ei:
         plan4.integrate_assemble_geo(to_dev(np.ones((plan4.nelem, plan4.nqp))), None, want_k=False)
     assert ei.value.status == ig.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("p,K,kind,geo", CASES)
+def test_geometry_apply_and_adjoint(orc, ig, p, K, kind, geo):
+    """Matrix-free apply and adjoint on a mapped geometry: y vs the oracle's
+    assembled geometry matrices times u; dL/dkappa (kappa scaling cm0 = det J
+    and G0 = det J J^-1 J^-T) vs the oracle's point-wise gradient."""
+    import scipy.sparse as sp
+
+    knots, K = _knots(p, K, kind, 170 + p)
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    plan = ig.Plan(p, K, knots)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=180 + p)
+    cm0, G0 = _coeffs(orc, P, W.kappa_constant(P.nelem, P.nq), **geo)
+    cm, G = kap * cm0, kap[:, None, :] * G0
+    u = W.normal_vector(P.ndof, 190 + p)
+    v = W.normal_vector(P.ndof, 200 + p)
+    rp, col, Mv, Kv = orc.assemble(P, cm, G=G)
+    M = sp.csr_matrix((Mv, col, rp), shape=(P.ndof, P.ndof))
+    Kk = sp.csr_matrix((Kv, col, rp), shape=(P.ndof, P.ndof))
+    cmd, Gd, ud = to_dev(cm), to_dev(G), to_dev(u)
+    for aM, aK in [(1.0, 0.0), (0.0, 1.0), (0.6, -1.4)]:
+        y = to_host(plan.apply_geo(cmd, Gd, ud, aM, aK))
+        assert relfro(y, aM * (M @ u) + aK * (Kk @ u)) <= TOL, (aM, aK)
+    g = to_host(plan.kappa_grad_geo(to_dev(cm0), to_dev(G0), ud, to_dev(v), 0.8, 1.2, 1.5))
+    go = orc.kappa_grad(P, u, v, 0.8, 1.2, 1.5, cm0=cm0, G0=G0)
+    assert relfro(g, go) <= TOL
+
+
+def test_identity_geometry_apply_adjoint_match_plain(ig):
+    """cm = kappa, G = kappa I gives igaf_apply's y; cm0 = 1, G0 = I gives
+    igaf_kappa_grad's gradient (different kernels' template branches)."""
+    p, K = 3, (9, 5, 6)
+    knots = [nonuniform_knots(k, p, 210 + d) for d, k in enumerate(K)]
+    plan = ig.Plan(p, K, knots)
+    kap = W.kappa_lognormal(plan.nelem, plan.nqp, seed=211)
+    I6 = np.zeros((plan.nelem, 6, plan.nqp))
+    I6[:, 0] = I6[:, 1] = I6[:, 2] = 1.0
+    u, v = to_dev(W.normal_vector(plan.ndof, 212)), to_dev(W.normal_vector(plan.ndof, 213))
+    kd = to_dev(kap)
+    y0 = to_host(plan.apply(kd, u, 0.9, 1.1))
+    y1 = to_host(plan.apply_geo(kd, to_dev(kap[:, None, :] * I6), u, 0.9, 1.1))
+    assert relfro(y1, y0) <= TOL
+    g0 = to_host(plan.kappa_grad(u, v, 0.9, 1.1, 2.0))
+    g1 = to_host(plan.kappa_grad_geo(to_dev(np.ones_like(kap)), to_dev(I6), u, v, 0.9, 1.1, 2.0))
+    assert relfro(g1, g0) <= TOL
+
+
+def test_geometry_apply_adjoint_fullscale(orc, ig):
+    """64^3 elements, p = 3, curved map: y = (M + K) u at 32 sampled DOFs vs
+    the oracle's complete rows, and u^T (M + K) v from the apply equals
+    <kappa, dL/dkappa> from the adjoint (L is linear in kappa), relative
+    1e-12."""
+    cfg = W.W6
+    p, K = cfg["p"], cfg["K"]
+    knots = [W.open_uniform_knots(k, p) for k in K]
+    plan = ig.Plan(p, K, knots)
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    xs = [orc.quad_nodes(P, d)[0] for d in range(3)]
+    kap = W.kappa_lognormal(plan.nelem, plan.nqp, seed=220)
+    cm0, G0 = W.mapped_geometry(xs[0], xs[1], xs[2], W.kappa_constant(plan.nelem, plan.nqp), amp=cfg["amp"])
+    cm, G = kap * cm0, kap[:, None, :] * G0
+    u = W.normal_vector(plan.ndof, 221)
+    v = W.normal_vector(plan.ndof, 222)
+    ud, vd = to_dev(u), to_dev(v)
+    y = to_host(plan.apply_geo(to_dev(cm), to_dev(G), ud, 1.0, 1.0))
+    rng = np.random.default_rng(223)
+    dofs = np.concatenate([[0, plan.ndof - 1], rng.choice(plan.ndof, 30, replace=False)])
+    for d, (c, m, k) in zip(dofs, orc.rows(P, cm, dofs, G=G)):
+        terms = (m + k) * u[c]
+        assert abs(y[d] - math.fsum(terms.tolist())) <= TOL * np.sum(np.abs(terms))
+    yv = to_host(plan.apply_geo(to_dev(cm), to_dev(G), vd, 1.0, 1.0))
+    L = math.fsum((u * yv).tolist())
+    g = to_host(plan.kappa_grad_geo(to_dev(cm0), to_dev(G0), ud, vd, 1.0, 1.0, 1.0))
+    Lg = math.fsum((g.reshape(-1) * kap.reshape(-1)).tolist())
+    assert abs(L - Lg) <= 1e-12 * abs(L)
