@@ -288,6 +288,14 @@ igaf_status igaf_euler_step(const igaf_plan* plan, const double* kappa, const do
                             double tol, int32_t maxit, int32_t precond, double* mu_next, double* work,
                             int32_t* iters, double* relres, void* stream);
 
+/* The same step on a mapped geometry: M from the mass coefficient cm, K from
+ * the stiffness tensor G (the coefficients of igaf_integrate_assemble_geo);
+ * the preconditioner's diagonal scaling takes diag(M(cm)).  Arguments as in
+ * igaf_euler_step, with cm [E][q^3] and G [E][6][q^3] in place of kappa. */
+igaf_status igaf_euler_step_geo(const igaf_plan* plan, const double* cm, const double* G, const double* mu,
+                                double dt, double tol, int32_t maxit, int32_t precond, double* mu_next,
+                                double* work, int32_t* iters, double* relres, void* stream);
+
 /* ---------------------------------------------------------------- batches
  * Many independent patches (the paper's first concurrency level: parts of
  * the mesh computed concurrently) integrated and assembled to CSR (streamed

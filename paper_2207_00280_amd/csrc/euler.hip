@@ -278,9 +278,12 @@ int64_t euler_workspace_doubles(int64_t ndof) { return 6 * ndof + kDotBlocks + 8
 // S[0] r.z, S[1] p.Ap, S[2] new r.z, S[3] beta, S[4] alpha, S[5] r.r.
 // Without a preconditioner z is r itself.  Returns 0 (converged), 1 (maxit
 // reached) or -3 (launch failure).
+// With G (a mapped geometry) `kappa` is the mass coefficient cm and G the
+// stiffness tensor: only the right-hand side sees G, the mass system and its
+// preconditioner take cm where the identity geometry takes kappa.
 int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const double* mu, double dt,
                    double tol, int maxit, int precond, double* x, double* work, int* iters, double* relres,
-                   hipStream_t st)
+                   hipStream_t st, const double* G)
 {
     double* b = work;
     double* r = b + ndof;
@@ -317,7 +320,9 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
                            pd.d[2].Lm, pd.d[0].N, pd.d[1].N, W, ndof);
     }
     // right-hand side b = M mu - dt K mu; r = M mu (x starts at mu)
-    if (mass_apply(mu, b, -dt) || mass_apply(mu, r, 0.0)) return -3;
+    if (launch_fill_zero(b, ndof, st) || launch_apply(pd, kappa, mu, 1.0, -dt, b, st, G) ||
+        mass_apply(mu, r, 0.0))
+        return -3;
     double bb = 0.0, rr = 0.0;
     if (dot(b, b, ndof, partial, S, 1, 0, st) || host_scalar(1, &bb)) return -3;
     hipLaunchKernelGGL(k_cg_init, dim3(gv), dim3(256), 0, st, r, b, x, mu, ndof);

@@ -647,26 +647,41 @@ int64_t igaf_euler_workspace(const igaf_plan* plan)
     return plan ? euler_workspace_doubles(plan->ndof) : 0;
 }
 
-igaf_status igaf_euler_step(const igaf_plan* plan, const double* kappa, const double* mu, double dt,
-                            double tol, int32_t maxit, int32_t precond, double* mu_next, double* work,
-                            int32_t* iters, double* relres, void* stream)
+static igaf_status euler_any(const igaf_plan* plan, const double* kappa, const double* G, const double* mu,
+                             double dt, double tol, int32_t maxit, int32_t precond, double* mu_next,
+                             double* work, int32_t* iters, double* relres, void* stream)
 {
     igaf_status st = check_hot(plan, IGAF_SUMFACT);
     if (st) return st;
-    if (!kappa || !mu || !mu_next || !work) return fail(IGAF_EINVAL, "kappa, mu, mu_next or work is NULL");
+    if (!kappa || !mu || !mu_next || !work) return fail(IGAF_EINVAL, "coefficient, mu, mu_next or work is NULL");
     if (!(tol >= 0.0) || maxit < 0) return fail(IGAF_EINVAL, "tol < 0 or maxit < 0");
     if (precond != IGAF_PRECOND_NONE && precond != IGAF_PRECOND_KRON)
         return fail(IGAF_EINVAL, "precond %d unknown", precond);
     int it = 0;
     double rr = 0.0;
     int rc = run_euler_step(plan->dev, plan->ndof, kappa, mu, dt, tol, maxit, precond, mu_next, work, &it,
-                            &rr, (hipStream_t)stream);
+                            &rr, (hipStream_t)stream, G);
     if (iters) *iters = it;
     if (relres) *relres = rr;
     if (rc < 0) return fail(IGAF_EDEVICE, "Euler step: %s", hipGetErrorString(hipGetLastError()));
     if (rc > 0) return fail(IGAF_ENOCONV, "Euler step: CG stopped at %d iterations, relative residual %.3e",
                             it, rr);
     return IGAF_OK;
+}
+
+igaf_status igaf_euler_step(const igaf_plan* plan, const double* kappa, const double* mu, double dt,
+                            double tol, int32_t maxit, int32_t precond, double* mu_next, double* work,
+                            int32_t* iters, double* relres, void* stream)
+{
+    return euler_any(plan, kappa, nullptr, mu, dt, tol, maxit, precond, mu_next, work, iters, relres, stream);
+}
+
+igaf_status igaf_euler_step_geo(const igaf_plan* plan, const double* cm, const double* G, const double* mu,
+                                double dt, double tol, int32_t maxit, int32_t precond, double* mu_next,
+                                double* work, int32_t* iters, double* relres, void* stream)
+{
+    if (!G) return fail(IGAF_EINVAL, "G is NULL");
+    return euler_any(plan, cm, G, mu, dt, tol, maxit, precond, mu_next, work, iters, relres, stream);
 }
 
 }  // extern "C"

@@ -55,7 +55,7 @@ int launch_apply(const PatchDev& pd, const double* kappa, const double* u, doubl
 int64_t euler_workspace_doubles(int64_t ndof);
 int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const double* mu, double dt,
                    double tol, int maxit, int precond, double* x, double* work, int* iters, double* relres,
-                   hipStream_t st);
+                   hipStream_t st, const double* G = nullptr);
 
 int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,
                       double alphaK, double scale, double* grad, hipStream_t st,

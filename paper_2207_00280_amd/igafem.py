@@ -24,7 +24,7 @@ SYMBOLS = [
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes",
     "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
     "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_apply",
-    "igaf_apply_geo", "igaf_kappa_grad_geo", "igaf_euler_workspace", "igaf_euler_step",
+    "igaf_apply_geo", "igaf_kappa_grad_geo", "igaf_euler_step_geo", "igaf_euler_workspace", "igaf_euler_step",
     "igaf_batch_create", "igaf_batch_destroy",
     "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
     "igaf_batch_integrate_assemble_separate", "igaf_batch_autotune", "igaf_batch_split",
@@ -89,6 +89,9 @@ def lib():
     L.igaf_euler_step.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                   ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_double), _vp]
+    L.igaf_euler_step_geo.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_double), _vp]
     L.igaf_batch_create.argtypes = [ctypes.POINTER(PatchDesc), ctypes.c_int32, ctypes.POINTER(_vp)]
     L.igaf_batch_destroy.argtypes = [_vp]
     L.igaf_batch_destroy.restype = None
@@ -365,6 +368,15 @@ class Plan:
         default) or PRECOND_NONE).  Returns (mu_next, iterations, relative
         residual); raises IgafError with status ENOCONV if maxit is reached
         first."""
+        return self._euler(kappa, None, mu, dt, tol, maxit, precond, out, work, stream)
+
+    def euler_step_geo(self, cm, G, mu, dt, tol=1e-12, maxit=1000, precond=None, out=None, work=None,
+                       stream=None):
+        """The Euler step on a mapped geometry (igaf_euler_step_geo)."""
+        return self._euler(cm, G, mu, dt, tol, maxit, precond, out, work, stream)
+
+    def _euler(self, kappa, G, mu, dt, tol, maxit, precond, out, work, stream):
+        """Shared body of euler_step / euler_step_geo (G None: identity geometry)."""
         precond = PRECOND_KRON if precond is None else int(precond)
         _need_f64_cuda(kappa, "kappa", self.nelem * self.nqp)
         _need_f64_cuda(mu, "mu", self.ndof)
@@ -377,9 +389,15 @@ class Plan:
         _need_f64_cuda(work, "work", nw)
         it = ctypes.c_int32(0)
         rr = ctypes.c_double(0.0)
-        _check(lib().igaf_euler_step(self._h, _ptr(kappa), _ptr(mu), float(dt), float(tol), int(maxit),
-                                     precond, _ptr(out), _ptr(work), ctypes.byref(it), ctypes.byref(rr),
-                                     _stream(stream)))
+        if G is None:
+            _check(lib().igaf_euler_step(self._h, _ptr(kappa), _ptr(mu), float(dt), float(tol), int(maxit),
+                                         precond, _ptr(out), _ptr(work), ctypes.byref(it), ctypes.byref(rr),
+                                         _stream(stream)))
+        else:
+            _need_f64_cuda(G, "G", self.nelem * 6 * self.nqp)
+            _check(lib().igaf_euler_step_geo(self._h, _ptr(kappa), _ptr(G), _ptr(mu), float(dt), float(tol),
+                                             int(maxit), precond, _ptr(out), _ptr(work), ctypes.byref(it),
+                                             ctypes.byref(rr), _stream(stream)))
         return out, it.value, rr.value
 
     def apply_geo(self, cm, G, u, alphaM=1.0, alphaK=1.0, y=None, stream=None):

@@ -117,3 +117,33 @@ def test_preconditioner_cuts_iterations(ig):
     assert r0 <= 1e-11 and r1 <= 1e-11
     assert 5 * it1 <= it0, (it0, it1)
     assert relfro(to_host(x1), to_host(x0)) <= 2e5 * 1e-11
+
+
+@pytest.mark.parametrize("p,K", [(1, (6, 5, 4)), (2, (5, 4, 4)), (3, (5, 4, 3)), (4, (3, 3, 2))])
+def test_euler_geometry_vs_direct_solve(orc, ig, p, K):
+    """Mapped geometry (curved map, log-normal kappa): mu_next vs scipy's direct
+    solve with the oracle's geometry matrices, within cond_2(M) times the
+    residual; 1^T M mu is conserved (K 1 = 0 on any geometry)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+
+    knots = [nonuniform_knots(k, p, 40 * p + d) for d, k in enumerate(K)]
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    plan = ig.Plan(p, K, knots)
+    xs = [orc.quad_nodes(P, d)[0] for d in range(3)]
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=50 + p)
+    cm, G = W.mapped_geometry(xs[0], xs[1], xs[2], kap, amp=0.1)
+    mu = W.normal_vector(P.ndof, 60 + p)
+    rp, col, Mo, Ko = orc.assemble(P, cm, G=G)
+    M = sp.csr_matrix((Mo, col, rp), shape=(P.ndof, P.ndof))
+    Kk = sp.csr_matrix((Ko, col, rp), shape=(P.ndof, P.ndof))
+    dt = 0.1 / max(K) ** 2
+    ref = spla.spsolve(M.tocsc(), M @ mu - dt * (Kk @ mu))
+    out, iters, relres = plan.euler_step_geo(to_dev(cm), to_dev(G), to_dev(mu), dt, tol=1e-13, maxit=5000)
+    assert relres <= 1e-13 and iters > 0
+    cond = np.linalg.cond(M.toarray())
+    x = to_host(out)
+    assert relfro(x, ref) <= cond * relres + 1e-13, (cond, relres)
+    s0, s1 = math.fsum((M @ mu).tolist()), math.fsum((M @ x).tolist())
+    b = M @ mu - dt * (Kk @ mu)
+    assert abs(s1 - s0) <= math.sqrt(P.ndof) * relres * np.linalg.norm(b) + 1e-13 * abs(s0)
