@@ -305,7 +305,8 @@ def bench_w6(ig, torch, stream, steps):
     """W6: the headline mesh on a curved map (mapped_geometry, amp 0.1): the
     element matrices from a per-point mass coefficient and stiffness tensor
     (7 q^3 doubles in, 2 n^6 out per element; HBM-bound), then with the CSR
-    values gathered from them, the CSR values alone (FP64 atomics), and the
+    values gathered from them, the CSR values alone (element-layer slabs
+    through the plan's workspace, gathered), and the
     matrix-free apply and adjoint on the same geometry."""
     cfg = W.W6
     p, K = cfg["p"], cfg["K"]
@@ -343,10 +344,10 @@ def bench_w6(ig, torch, stream, steps):
            "element_matrices": {"ms": ms_el, "bytes": b_el, "flops": f_el, "GB/s": b_el / (ms_el * 1e-3) / 1e9,
                                 "roofline_ms": roof * 1e3, "frac": roof / (ms_el * 1e-3), "bound": "hbm"},
            "element_matrices_and_csr_gathered_ms": ms_all,
-           "csr_only_atomic_ms": ms_csr,
+           "csr_only_ms": ms_csr,
            "apply_ms": ms_ap, "adjoint_ms": ms_ad}
     log("W6 mapped geometry: element matrices %.3f ms (%.0f%% of HBM roofline), + CSR gathered %.3f ms, "
-        "CSR alone (atomics) %.3f ms, apply %.3f ms, adjoint %.3f ms"
+        "CSR alone (slabs) %.3f ms, apply %.3f ms, adjoint %.3f ms"
         % (ms_el, 100 * out["element_matrices"]["frac"], ms_all, ms_csr, ms_ap, ms_ad))
     del cmd, Gd, plan
     torch.cuda.empty_cache()

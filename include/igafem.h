@@ -205,11 +205,15 @@ igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const
  *      components xx, yy, zz, xy, xz, yz (required when Ke or Kval is)
  * Me, Ke   DEVICE [E][n^3][n^3] or NULL;  Mval, Kval DEVICE [nnz] or NULL,
  *      OVERWRITTEN with the assembled CSR values (structural pattern of
- *      igaf_csr_pattern).  At least one output.  When every requested CSR
- *      output has its element matrices requested too, the CSR values are
- *      summed from the stored matrices as in igaf_assemble (deterministic);
- *      otherwise (CSR without element matrices) they are added with FP64
- *      atomics and the last bits may vary from call to call.
+ *      igaf_csr_pattern).  At least one output.  A CSR output whose element
+ *      matrices are requested too is summed from them as in igaf_assemble;
+ *      one without is summed the same way slab by slab of element layers
+ *      through a workspace the plan allocates at the first such call (at
+ *      most 2 GiB, freed with the plan; neighbouring slabs share p layers,
+ *      integrated twice).  Both are deterministic and give the same bits.
+ *      If that first call runs under stream capture, or the workspace
+ *      cannot hold p+1 layers, the values are added with FP64 atomics
+ *      instead (the last bits may then vary between calls).
  * Sum factorisation (Algorithm 2) with ordered per-direction pairs (the
  * cross terms of G are not symmetric in a pair); nquad = degree+1 in every
  * direction, else IGAF_EUNSUPPORTED.  cm = kappa, G = kappa I (the identity

@@ -65,8 +65,10 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
                                                              double* __restrict__ Me,
                                                              double* __restrict__ Ke,
                                                              double* __restrict__ Mv,
-                                                             double* __restrict__ Kv)
+                                                             double* __restrict__ Kv, int64_t e0,
+                                                             int64_t e1)
 {
+    // elements [e0, e1); element e's matrices go to slot e - e0 of Me, Ke
     using Sh = GeoShape<P>;
     constexpr int n = Sh::n, Q = Sh::Q, n3 = Sh::n3, Q3 = Sh::Q3, T = kGeoThreads;
     __shared__ double fld[Sh::NF][Q3];
@@ -93,9 +95,9 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
             pf[r] = v;
         }
     };
-    if (blockIdx.x < pd.E) fetch(blockIdx.x);
+    if (e0 + blockIdx.x < e1) fetch(e0 + blockIdx.x);
 
-    for (int64_t e = blockIdx.x; e < pd.E; e += gridDim.x) {
+    for (int64_t e = e0 + blockIdx.x; e < e1; e += gridDim.x) {
         const int ex = (int)(e % Kx);
         const int ey = (int)((e / Kx) % Ky);
         const int ez = (int)(e / ((int64_t)Kx * Ky));
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
             wsc[d][1][r] = w * dN;
         }
         __syncthreads();
-        if (e + gridDim.x < pd.E) fetch(e + gridDim.x);
+        if (e + gridDim.x < e1) fetch(e + gridDim.x);
 
         for (int a3 = 0; a3 < n; ++a3) {
             // stage z: thread on (b3, kx, ky)
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
             __syncthreads();
             // stage x + store: thread on (a2, J), loop over the test index a1;
             // lanes run along a row, so every store is a contiguous run
-            const int64_t base = e * Sh::n6 + (int64_t)a3 * Sh::n5;
+            const int64_t base = (e - e0) * Sh::n6 + (int64_t)a3 * Sh::n5;
             for (int i = tid; i < Sh::n4; i += T) {
                 const int a2 = i / n3, J = i % n3;
                 const int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
 
 template <int P, bool ATOMIC>
 static int launch_geo_t(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
-                        double* Mv, double* Kv, hipStream_t st)
+                        double* Mv, double* Kv, int64_t e0, int64_t e1, hipStream_t st)
 {
     static int slots = 0;
     if (!slots) {
@@ -237,21 +239,23 @@ static int launch_geo_t(const PatchDev& pd, const double* cm, const double* G, d
             return -3;
         slots = ncu * (per > 0 ? per : 1);
     }
-    const int64_t blocks = pd.E < slots ? pd.E : slots;
+    if (e1 <= e0) return 0;
+    const int64_t blocks = e1 - e0 < slots ? e1 - e0 : slots;
     hipLaunchKernelGGL((k_element_geo<P, ATOMIC>), dim3((unsigned)blocks), dim3(kGeoThreads), 0, st, pd,
-                       make_rowmap(pd), cm, G, Me, Ke, Mv, Kv);
+                       make_rowmap(pd), cm, G, Me, Ke, Mv, Kv, e0, e1);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 int launch_element_geo(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
-                       double* Mv, double* Kv, hipStream_t st)
+                       double* Mv, double* Kv, hipStream_t st, int64_t e0, int64_t e1)
 {
     const bool atomic = Mv || Kv;
+    if (e1 < 0) e1 = pd.E;
     switch (pd.p) {
-#define IGAF_GEO(PP)                                                                  \
-    case PP:                                                                          \
-        return atomic ? launch_geo_t<PP, true>(pd, cm, G, Me, Ke, Mv, Kv, st)         \
-                      : launch_geo_t<PP, false>(pd, cm, G, Me, Ke, Mv, Kv, st);
+#define IGAF_GEO(PP)                                                                          \
+    case PP:                                                                                  \
+        return atomic ? launch_geo_t<PP, true>(pd, cm, G, Me, Ke, Mv, Kv, e0, e1, st)         \
+                      : launch_geo_t<PP, false>(pd, cm, G, Me, Ke, Mv, Kv, e0, e1, st);
         IGAF_GEO(1)
         IGAF_GEO(2)
         IGAF_GEO(3)

@@ -146,6 +146,10 @@ struct igaf_plan {
     // opt-in kernel interval log of igaf_integrate_assemble (timing events)
     bool timing = false;
     std::vector<hipEvent_t> tev[2];   // [element | csr]: start, end, start, end, ...
+    // mapped-geometry CSR without stored element matrices: element matrices
+    // of a slab of element layers (allocated at the first such call)
+    double* geo_ws = nullptr;
+    int geo_ws_layers = 0;
 };
 
 namespace {
@@ -401,6 +405,7 @@ void igaf_plan_destroy(igaf_plan* plan)
     if (plan->side) (void)hipStreamDestroy(plan->side);
     (void)hipFree(plan->dmem);
     (void)hipFree(plan->dpre);
+    if (plan->geo_ws) (void)hipFree(plan->geo_ws);
     delete plan;
 }
 
@@ -564,6 +569,53 @@ igaf_status igaf_plan_timing(igaf_plan* plan, int32_t kernel, double* avg_ms, in
     return IGAF_OK;
 }
 
+// Mapped-geometry CSR values whose element matrices the caller does not
+// store: slab by slab of z row layers, the element matrices of the element
+// layers those rows touch go to the plan's workspace (at most
+// kGeoWorkspaceBytes, allocated at the first call), and the rows are
+// gathered from it; the p element layers shared by neighbouring slabs are
+// integrated twice.  Returns 1 when no workspace can be had (too thin, or a
+// stream capture is running at the first call): the caller then adds the
+// values with atomics.
+static constexpr int64_t kGeoWorkspaceBytes = int64_t(2) << 30;
+
+static int geo_csr_slabs(igaf_plan* P, const double* cm, const double* G, double* Mval, double* Kval,
+                         hipStream_t s)
+{
+    const int p = P->p;
+    const int64_t n6 = (int64_t)P->n * P->n * P->n * P->n * P->n * P->n;
+    const int64_t layer = (int64_t)P->K[0] * P->K[1];   // elements per z layer
+    if (!P->geo_ws) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 1;
+        int64_t layers = kGeoWorkspaceBytes / (layer * 2 * n6 * (int64_t)sizeof(double));
+        layers = std::min<int64_t>(layers, P->K[2]);
+        if (layers < std::min(P->K[2], p + 1)) return 1;
+        if (hipMalloc(&P->geo_ws, sizeof(double) * 2 * n6 * layer * layers) != hipSuccess) {
+            P->geo_ws = nullptr;
+            (void)hipGetLastError();
+            return 1;
+        }
+        P->geo_ws_layers = (int)layers;
+    }
+    const int L = P->geo_ws_layers;
+    const int T = L >= P->K[2] ? P->N[2] : L - p;   // row layers per slab
+    double* Mw = P->geo_ws;
+    double* Kw = Mw + n6 * layer * L;
+    const int64_t rowlayer = (int64_t)P->N[0] * P->N[1];
+    for (int z0 = 0; z0 < P->N[2]; z0 += T) {
+        const int z1 = std::min(P->N[2], z0 + T);
+        const int L0 = std::max(0, z0 - p), L1 = std::min(P->K[2], z1);   // element layers of the rows
+        const int64_t e0 = (int64_t)L0 * layer, e1 = (int64_t)L1 * layer;
+        if (launch_element_geo(P->dev, Mval ? cm : nullptr, Kval ? G : nullptr, Mval ? Mw : nullptr,
+                               Kval ? Kw : nullptr, nullptr, nullptr, s, e0, e1) ||
+            launch_gather(P->dev, Mval ? Mw : nullptr, Kval ? Kw : nullptr, Mval, Kval, s, z0 * rowlayer,
+                          z1 * rowlayer, e0))
+            return -3;
+    }
+    return 0;
+}
+
 igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm, const double* G,
                                         double* Me, double* Ke, double* Mval, double* Kval,
                                         void* stream)
@@ -574,22 +626,32 @@ igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm,
     if ((Me || Mval) && !cm) return fail(IGAF_EINVAL, "cm is NULL but a mass output is requested");
     if ((Ke || Kval) && !G) return fail(IGAF_EINVAL, "G is NULL but a stiffness output is requested");
     hipStream_t s = (hipStream_t)stream;
-    const double* c = (Me || Mval) ? cm : nullptr;
-    const double* g = (Ke || Kval) ? G : nullptr;
-    if ((!Mval || Me) && (!Kval || Ke)) {
-        // every requested CSR output has its element matrices: store them,
-        // then sum each CSR value from them (deterministic, no atomics)
-        st = launched(launch_element_geo(plan->dev, c, g, Me, Ke, nullptr, nullptr, s),
+    igaf_plan* P = const_cast<igaf_plan*>(plan);
+    // dense element matrices into the caller's arrays, and the CSR values
+    // that have theirs gathered from them (deterministic, no atomics)
+    if (Me || Ke) {
+        st = launched(launch_element_geo(plan->dev, Me ? cm : nullptr, Ke ? G : nullptr, Me, Ke, nullptr,
+                                         nullptr, s),
                       "mapped-geometry integration");
-        if (!st && (Mval || Kval))
-            st = launched(launch_gather(plan->dev, Mval ? Me : nullptr, Kval ? Ke : nullptr, Mval, Kval, s),
-                          "assemble");
-        return st;
+        double* gm = Mval && Me ? Mval : nullptr;
+        double* gk = Kval && Ke ? Kval : nullptr;
+        if (!st && (gm || gk))
+            st = launched(launch_gather(plan->dev, gm ? Me : nullptr, gk ? Ke : nullptr, gm, gk, s), "assemble");
+        if (st) return st;
     }
-    st = launched(launch_fill_zero(Mval, Mval ? plan->nnz : 0, s), "zero");
-    if (!st) st = launched(launch_fill_zero(Kval, Kval ? plan->nnz : 0, s), "zero");
+    // the CSR values without stored element matrices: slabs through the
+    // plan's workspace, else FP64 atomics
+    double* sm = Mval && !Me ? Mval : nullptr;
+    double* sk = Kval && !Ke ? Kval : nullptr;
+    if (!sm && !sk) return IGAF_OK;
+    const int rc = geo_csr_slabs(P, cm, G, sm, sk, s);
+    if (rc < 0) return launched(rc, "mapped-geometry slab assembly");
+    if (rc == 0) return IGAF_OK;
+    st = launched(launch_fill_zero(sm, sm ? plan->nnz : 0, s), "zero");
+    if (!st) st = launched(launch_fill_zero(sk, sk ? plan->nnz : 0, s), "zero");
     if (!st)
-        st = launched(launch_element_geo(plan->dev, c, g, Me, Ke, Mval, Kval, s),
+        st = launched(launch_element_geo(plan->dev, sm ? cm : nullptr, sk ? G : nullptr, nullptr, nullptr, sm,
+                                         sk, s),
                       "mapped-geometry integration + atomic assembly");
     return st;
 }

@@ -36,17 +36,21 @@ int launch_rows_batch(const BatchPatch* patches, const int4* items, int nitems, 
 int rows_batch_grid(int nitems, int chunk);
 int rows_tile_info(int p, int Ny, int Nz, int* ntile, double* per_elem);
 
-// CSR values gathered from stored element matrices: overwrites Mval / Kval.
+// CSR values gathered from stored element matrices: overwrites Mval / Kval
+// for the rows [g0, g1) (all rows by default); element e's matrices are read
+// from slot e - eoff.
 int launch_gather(const PatchDev& pd, const double* Me, const double* Ke, double* Mval,
-                  double* Kval, hipStream_t st);
+                  double* Kval, hipStream_t st, int64_t g0 = 0, int64_t g1 = -1, int64_t eoff = 0);
 
 int launch_fill_zero(double* a, int64_t n, hipStream_t st);
 
-// y += alphaM M(kappa) u + alphaK K(kappa) u by FP64 atomics (y zeroed by the caller).
 // element matrices (and/or atomically assembled CSR values) on a mapped
-// geometry: cm [E][q^3], G [E][6][q^3]
+// geometry: cm [E][q^3], G [E][6][q^3]; elements [e0, e1) (all by default),
+// element e's matrices written to slot e - e0
 int launch_element_geo(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
-                       double* Mv, double* Kv, hipStream_t st);
+                       double* Mv, double* Kv, hipStream_t st, int64_t e0 = 0, int64_t e1 = -1);
+// y += alphaM M(kappa) u + alphaK K(kappa) u by FP64 atomics (y zeroed by the
+// caller); with G, kappa is the mass coefficient cm and G the stiffness tensor
 int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM,
                  double alphaK, double* y, hipStream_t st, const double* G = nullptr);
 

@@ -134,6 +134,11 @@ def test_geometry_fullscale(orc, ig):
         assert relfro(Me_s[i], mo[0]) <= TOL and relfro(Ke_s[i], ko[0]) <= TOL, e
     del Me, Ke
     torch.cuda.empty_cache()
+    # CSR alone: slabs of element layers through the plan's workspace (several
+    # slabs at this size), the same gather: the same bits
+    _, _, Mv2, Kv2 = plan.integrate_assemble_geo(cmd, Gd, want_elem=False)
+    assert torch.equal(Mv2, Mv) and torch.equal(Kv2, Kv)
+    del Mv2, Kv2
     rp = to_host(plan.csr_pattern()[0])
     Mv_h, Kv_h = to_host(Mv), to_host(Kv)
     N = P.N
@@ -162,6 +167,36 @@ def test_geometry_fullscale(orc, ig):
     k1 = Kc @ np.ones(plan.ndof)
     rowabs = np.abs(Kc) @ np.ones(plan.ndof)
     assert np.max(np.abs(k1)) <= 64 * np.finfo(float).eps * np.max(rowabs)
+
+
+def test_geometry_csr_under_capture(ig):
+    """A CSR-only call captured in a HIP graph before the plan has its slab
+    workspace adds the values with FP64 atomics instead: replays (with eager
+    work between them) match the eager slab path within rounding."""
+    import torch
+
+    p, K = 2, (6, 5, 7)
+    knots = [nonuniform_knots(k, p, 230 + d) for d, k in enumerate(K)]
+    plan = ig.Plan(p, K, knots)
+    xs = [plan.quad_nodes(d)[0] for d in range(3)]
+    cm, G = W.mapped_geometry(xs[0], xs[1], xs[2], W.kappa_lognormal(plan.nelem, plan.nqp, seed=231), amp=0.1)
+    cmd, Gd = to_dev(cm), to_dev(G)
+    Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+    Kv = torch.empty_like(Mv)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.integrate_assemble_geo(cmd, Gd, want_elem=False, Mval=Mv, Kval=Kv, stream=s)
+    plan2 = ig.Plan(p, K, knots)
+    _, _, Mr, Kr = plan2.integrate_assemble_geo(cmd, Gd, want_elem=False)
+    for r in range(2):
+        Mv.fill_(np.nan)
+        Kv.fill_(np.nan)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert relfro(to_host(Mv), to_host(Mr)) <= TOL and relfro(to_host(Kv), to_host(Kr)) <= TOL, r
+        _ = torch.ones(1000, device="cuda").sum().item()
 
 
 def test_geometry_errors(ig):
