@@ -119,39 +119,49 @@ int dot(const double* a, const double* c, int64_t n, double* partial, double* S,
 }
 
 // d[I] += sum over the elements carrying I of sum_q w_q kappa_q phi_I(x_q)^2
-// (the diagonal of M(kappa)); one workgroup per element, a thread per local
-// function, the q^3 sum taken one direction at a time.
+// (the diagonal of M(kappa)); a workgroup takes EPB = 256 / n^3 elements at a
+// time (at least one), a thread per local function, the q^3 sum taken one
+// direction at a time.
 template <int P>
 __global__ __launch_bounds__(256) void k_mass_diag(PatchDev pd, const double* __restrict__ kappa,
                                                    double* __restrict__ d)
 {
     constexpr int n = P + 1, Q = P + 1, n3 = n * n * n, Q3 = Q * Q * Q;
-    __shared__ double kap[Q3];
-    __shared__ double sq[3][n * Q];   // w N_a^2 per direction, [a][k]
+    constexpr int EPB = 256 / n3 > 0 ? 256 / n3 : 1;
+    __shared__ double kap[EPB][Q3];
+    __shared__ double sq[EPB][3][n * Q];   // w N_a^2 per direction, [a][k]
     const int tid = threadIdx.x;
     const int Kx = pd.d[0].K, Ky = pd.d[1].K, Nx = pd.d[0].N, Ny = pd.d[1].N;
-    for (int64_t e = blockIdx.x; e < pd.E; e += gridDim.x) {
-        const int ex = (int)(e % Kx), ey = (int)((e / Kx) % Ky), ez = (int)(e / ((int64_t)Kx * Ky));
-        for (int i = tid; i < Q3; i += 256) kap[i] = kappa[e * Q3 + i];
-        for (int i = tid; i < 3 * n * Q; i += 256) {
-            const int dd = i / (n * Q), r = i % (n * Q);
+    for (int64_t eb = (int64_t)blockIdx.x * EPB; eb < pd.E; eb += (int64_t)gridDim.x * EPB) {
+        for (int i = tid; i < EPB * Q3; i += 256) {
+            const int64_t e = eb + i / Q3;
+            kap[i / Q3][i % Q3] = e < pd.E ? kappa[e * Q3 + i % Q3] : 0.0;
+        }
+        for (int i = tid; i < EPB * 3 * n * Q; i += 256) {
+            const int sub = i / (3 * n * Q), j = i % (3 * n * Q);
+            const int64_t e = eb + sub < pd.E ? eb + sub : pd.E - 1;
+            const int ex = (int)(e % Kx), ey = (int)((e / Kx) % Ky), ez = (int)(e / ((int64_t)Kx * Ky));
+            const int dd = j / (n * Q), r = j % (n * Q);
             const int ed = dd == 0 ? ex : (dd == 1 ? ey : ez);
             const double v = pd.d[dd].Nv[(int64_t)ed * n * Q + r];
-            sq[dd][r] = pd.d[dd].wq[(int64_t)ed * Q + r % Q] * v * v;
+            sq[sub][dd][r] = pd.d[dd].wq[(int64_t)ed * Q + r % Q] * v * v;
         }
         __syncthreads();
-        if (tid < n3) {
-            const int a1 = tid % n, a2 = (tid / n) % n, a3 = tid / (n * n);
+        const int sub = tid / n3, l = tid % n3;
+        const int64_t e = eb + sub;
+        if (sub < EPB && e < pd.E) {
+            const int ex = (int)(e % Kx), ey = (int)((e / Kx) % Ky), ez = (int)(e / ((int64_t)Kx * Ky));
+            const int a1 = l % n, a2 = (l / n) % n, a3 = l / (n * n);
             double s = 0.0;
             for (int kz = 0; kz < Q; ++kz) {
                 double sy = 0.0;
                 for (int ky = 0; ky < Q; ++ky) {
                     double sx = 0.0;
 #pragma unroll
-                    for (int kx = 0; kx < Q; ++kx) sx += sq[0][a1 * Q + kx] * kap[kx + Q * (ky + Q * kz)];
-                    sy += sq[1][a2 * Q + ky] * sx;
+                    for (int kx = 0; kx < Q; ++kx) sx += sq[sub][0][a1 * Q + kx] * kap[sub][kx + Q * (ky + Q * kz)];
+                    sy += sq[sub][1][a2 * Q + ky] * sx;
                 }
-                s += sq[2][a3 * Q + kz] * sy;
+                s += sq[sub][2][a3 * Q + kz] * sy;
             }
             atomicAdd(&d[(ex + a1) + (int64_t)Nx * ((ey + a2) + (int64_t)Ny * (ez + a3))], s);
         }
@@ -227,7 +237,9 @@ __global__ __launch_bounds__(256) void k_line_solve(double* __restrict__ v, cons
 template <int P>
 int launch_mass_diag_t(const PatchDev& pd, const double* kappa, double* d, hipStream_t st)
 {
-    const int64_t blocks = pd.E < 8192 ? pd.E : 8192;
+    constexpr int n3 = (P + 1) * (P + 1) * (P + 1), EPB = 256 / n3 > 0 ? 256 / n3 : 1;
+    const int64_t groups = (pd.E + EPB - 1) / EPB;
+    const int64_t blocks = groups < 8192 ? groups : 8192;
     hipLaunchKernelGGL(k_mass_diag<P>, dim3((unsigned)blocks), dim3(256), 0, st, pd, kappa, d);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
