@@ -144,6 +144,11 @@ igaf_status igaf_plan_sizes(const igaf_plan* plan, int64_t* ndof, int64_t* nelem
  * can evaluate kappa at the physical quadrature points (eq. 10). */
 igaf_status igaf_quad_nodes(const igaf_plan* plan, int32_t dir, double* x_host, double* w_host);
 
+/* Every quadrature point of the patch, xyz_host[E][qz][qy][qx][3] (HOST,
+ * E q^3 3 doubles, caller-owned), in the layout of kappa: (x, y, z) of the
+ * mapped Gauss nodes, e = ex + Kx (ey + Ky ez). */
+igaf_status igaf_quad_points(const igaf_plan* plan, double* xyz_host);
+
 /* Choose how CSR values are formed by the calls below (IGAF_ASM_ROWS or
  * IGAF_ASM_ATOMIC).  Both give the same matrix up to rounding order;
  * IGAF_ASM_ROWS is deterministic. */

@@ -431,6 +431,26 @@ igaf_status igaf_quad_nodes(const igaf_plan* plan, int32_t dir, double* x, doubl
     return IGAF_OK;
 }
 
+igaf_status igaf_quad_points(const igaf_plan* plan, double* xyz)
+{
+    if (!plan) return fail(IGAF_EINVAL, "plan is NULL");
+    if (!xyz) return fail(IGAF_EINVAL, "xyz_host is NULL");
+    const int qx = plan->q[0], qy = plan->q[1], qz = plan->q[2];
+    const int Kx = plan->K[0], Ky = plan->K[1];
+    for (int64_t e = 0; e < plan->E; ++e) {
+        const int ex = (int)(e % Kx), ey = (int)((e / Kx) % Ky), ez = (int)(e / ((int64_t)Kx * Ky));
+        double* o = xyz + e * plan->nqp * 3;
+        for (int kz = 0; kz < qz; ++kz)
+            for (int ky = 0; ky < qy; ++ky)
+                for (int kx = 0; kx < qx; ++kx, o += 3) {
+                    o[0] = plan->xnode[0][(size_t)ex * qx + kx];
+                    o[1] = plan->xnode[1][(size_t)ey * qy + ky];
+                    o[2] = plan->xnode[2][(size_t)ez * qz + kz];
+                }
+    }
+    return IGAF_OK;
+}
+
 igaf_status igaf_plan_set_assembly(igaf_plan* plan, int32_t mode)
 {
     if (!plan) return fail(IGAF_EINVAL, "plan is NULL");

@@ -21,7 +21,7 @@ MAX_DEGREE = 5
 
 SYMBOLS = [
     "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_csr_pattern_host",
-    "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes",
+    "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes", "igaf_quad_points",
     "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
     "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_apply",
     "igaf_apply_geo", "igaf_kappa_grad_geo", "igaf_euler_step_geo", "igaf_euler_workspace", "igaf_euler_step",
@@ -70,6 +70,7 @@ def lib():
     L.igaf_plan_destroy.restype = None
     L.igaf_plan_sizes.argtypes = [_vp] + [_i64p] * 5
     L.igaf_quad_nodes.argtypes = [_vp, ctypes.c_int32, _dp, _dp]
+    L.igaf_quad_points.argtypes = [_vp, _dp]
     L.igaf_plan_set_assembly.argtypes = [_vp, ctypes.c_int32]
     L.igaf_plan_set_timing.argtypes = [_vp, ctypes.c_int32]
     L.igaf_plan_timing.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _i32p]
@@ -233,6 +234,12 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def quad_points(self):
+        """Every quadrature point, [E, q^3, 3] (x, y, z), in kappa's layout."""
+        xyz = np.zeros((self.nelem, self.nqp, 3))
+        _check(lib().igaf_quad_points(self._h, xyz.ctypes.data_as(_dp)))
+        return xyz
 
     def quad_nodes(self, d):
         x = np.zeros(self.K[d] * self.q[d])
@@ -529,6 +536,27 @@ def _autograd():
 
 
 _KBL = None
+
+
+def integrate(p, K, knots, kappa, method=SUMFACT, want_elem=True, want_csr=True, q=None):
+    """One-shot integration and assembly of a patch: builds the plan, runs
+    igaf_integrate_assemble and returns torch tensors as a dict with keys
+    Me, Ke ([E, n^3, n^3] or None), row_ptr, col, Mval, Kval (CSR; None when
+    want_csr is False) and the plan.  kappa: CUDA float64 [E, q^3]."""
+    plan = Plan(p, K, knots, q)
+    Me, Ke, Mv, Kv = plan.integrate_assemble(kappa, method=method, want_elem=want_elem, want_csr=want_csr)
+    rp, col = plan.csr_pattern() if want_csr else (None, None)
+    return dict(Me=Me, Ke=Ke, row_ptr=rp, col=col, Mval=Mv, Kval=Kv, plan=plan)
+
+
+def __getattr__(name):
+    # the autograd class needs torch; it is built on first access
+    if name == "KappaBilinearLoss":
+        global _KBL
+        if _KBL is None:
+            _KBL = _autograd()
+        return _KBL
+    raise AttributeError(name)
 
 
 def kappa_bilinear_loss(kappa, u, v, plan, alphaM=1.0, alphaK=1.0):

@@ -145,3 +145,30 @@ def test_unsupported_quadrature(ig):
     with pytest.raises(ig.IgafError) as ei:
         plan.element_matrices(kap)
     assert ei.value.status == ig.EUNSUPPORTED
+
+
+def test_quad_points_and_one_shot_integrate(orc, ig):
+    """igaf_quad_points gives every point in kappa's layout (kappa evaluated
+    there equals kappa_sine on the per-direction nodes); the one-shot
+    integrate() returns the same matrices as the plan path and the oracle."""
+    import torch
+
+    p, K = 2, (4, 3, 5)
+    knots = [nonuniform_knots(k, p, 240 + d) for d, k in enumerate(K)]
+    plan = ig.Plan(p, K, knots)
+    xyz = plan.quad_points()
+    xs = [plan.quad_nodes(d)[0] for d in range(3)]
+    kap_nodes = W.kappa_sine(*xs)
+    kap_pts = 1.0 + 0.5 * np.sin(2 * np.pi * xyz[..., 0]) * np.sin(2 * np.pi * xyz[..., 1]) * \
+        np.sin(2 * np.pi * xyz[..., 2])
+    np.testing.assert_allclose(kap_pts, kap_nodes, rtol=0, atol=1e-15)
+    kd = to_dev(kap_nodes)
+    r = ig.integrate(p, K, knots, kd)
+    Me, Ke, Mv, Kv = plan.integrate_assemble(kd)
+    for a, b in ((r["Me"], Me), (r["Ke"], Ke), (r["Mval"], Mv), (r["Kval"], Kv)):
+        assert torch.equal(a, b)
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    rp_o, col_o, Mv_o, Kv_o = orc.assemble(P, kap_nodes)
+    assert np.array_equal(to_host(r["row_ptr"]), rp_o) and np.array_equal(to_host(r["col"]), col_o)
+    assert relfro(to_host(r["Mval"]), Mv_o) <= TOL and relfro(to_host(r["Kval"]), Kv_o) <= TOL
+    assert ig.KappaBilinearLoss is ig.KappaBilinearLoss
