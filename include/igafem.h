@@ -13,7 +13,11 @@
  * Cox-de Boor B-spline (eqs. cox1/cox2) on an open knot vector (eq.
  * knot_vector), integrated by the tensor Gauss rule of eq. (10).  The
  * coefficient kappa is given at every quadrature point and enters eq. (10)
- * in the slot of J(x^n), next to the element Jacobian.
+ * in the slot of J(x^n), next to the element Jacobian.  Around that it
+ * provides the adjoint dL/dkappa, the matrix-free operator apply and one
+ * forward Euler step of the heat problem (Sec. 2.2), a batched launch over
+ * many patches, and the same calls on a mapped geometry (the *_geo entry
+ * points, with the pulled-back coefficients given per point).
  *
  * CONVENTIONS (fixed where the paper leaves them open)
  *   - element e_d = 0..K_d-1 of direction d spans [t_d[e_d+p], t_d[e_d+p+1]]
@@ -40,10 +44,12 @@
  *   A plan may be used from one host thread at a time.
  *
  * ERRORS
- *   Every igaf_status is IGAF_OK (0) or negative; on error nothing has been
- *   launched and outputs are untouched (except IGAF_ENOCONV, whose outputs
- *   hold the last iterate), and igaf_last_error() returns a thread-local
- *   message describing the last failure on this thread.
+ *   Every igaf_status is IGAF_OK (0) or negative, and igaf_last_error()
+ *   returns a thread-local message describing the last failure on this
+ *   thread.  Argument errors (IGAF_EINVAL, IGAF_EUNSUPPORTED) are found
+ *   before anything is launched, so outputs are untouched; after
+ *   IGAF_EDEVICE the outputs are undefined; after IGAF_ENOCONV they hold the
+ *   last iterate.
  *
  * PRECISION: FP64 throughout.  Supported hot-kernel shapes: 1 <= p <= 5 with
  * nquad = p+1 in every direction (other Gauss orders are rejected with
@@ -126,9 +132,11 @@ igaf_status igaf_csr_pattern_host(const igaf_patch_desc* desc, int64_t* row_ptr_
 /* Validate `desc`, build the Gauss rule and the per-element 1D tables on the
  * current device (Cox-de Boor values and derivatives at the mapped Gauss
  * nodes, weights w*h/2 folded in, pair products N_a N_b and N_a' N_b' for the
- * (p+1)(p+2)/2 unordered pairs of each element and direction).  The knot
- * arrays are copied; the caller may free them afterwards.  Synchronous
- * (blocks until the tables are built).  *out receives the plan. */
+ * (p+1)(p+2)/2 unordered pairs of each element and direction), and per
+ * direction the banded Cholesky factor of the 1D mass matrix (the Euler
+ * step's preconditioner).  The knot arrays are copied; the caller may free
+ * them afterwards.  Synchronous (blocks until the tables are built).  *out
+ * receives the plan. */
 igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out);
 
 /* Release a plan and its device memory (NULL is ignored).  The caller must
