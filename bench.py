@@ -91,7 +91,10 @@ def traffic_for_current_kernel():
 
 def cpu_baseline(nsample, chunk=4096):
     """The CPU oracle (classical quadrature, M_e and K_e) on the first
-    `nsample` elements of the headline workload, all host threads."""
+    `nsample` elements of the headline workload, all host threads; then, as
+    context, one thread on 4 096 elements (per-core rate), the W1 mesh, the
+    W3 degrees on 512-element meshes (rates extrapolated to 128^3) and the W5
+    reference gradient on every point."""
     import oracle
 
     P = oracle.Patch(3, (64, 64, 64), (4, 4, 4), [W.open_uniform_knots(64, 3)] * 3)
@@ -101,15 +104,46 @@ def cpu_baseline(nsample, chunk=4096):
     for e0 in range(0, nsample, chunk):
         oracle.element_matrices(P, kap, e0, min(nsample, e0 + chunk))
     dt = time.perf_counter() - t0
-    return {"value": nsample / dt, "unit": "element matrices/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "first %d of the 262144 elements of the headline workload (classical "
-                      "quadrature, M_e and K_e, no assembly), %.1f s" % (nsample, dt)}
+    cores = oracle.num_threads()
+    out = {"value": nsample / dt, "unit": "element matrices/s", "cores": cores, "kind": "oracle",
+           "sample": "first %d of the 262144 elements of the headline workload (classical "
+                     "quadrature, M_e and K_e, no assembly), %.1f s" % (nsample, dt)}
+    extra = {}
+    oracle.set_num_threads(1)
+    t0 = time.perf_counter()
+    oracle.element_matrices(P, kap, 0, 4096)
+    extra["w2_one_thread_elements_per_s"] = 4096 / (time.perf_counter() - t0)
+    oracle.set_num_threads(cores)
+    P1 = oracle.Patch(2, (8, 8, 8), (3, 3, 3), [W.open_uniform_knots(8, 2)] * 3)
+    t0 = time.perf_counter()
+    oracle.assemble(P1, W.kappa_constant(512, 27))
+    extra["w1_full_mesh_s"] = time.perf_counter() - t0
+    for p in (2, 3, 4):
+        # the per-element cost does not depend on the mesh: 8^3 elements of the
+        # same degree and rule stand for the 128^3 mesh
+        Pp = oracle.Patch(p, (8, 8, 8), (p + 1,) * 3, [W.open_uniform_knots(8, p)] * 3)
+        kp = W.kappa_lognormal(Pp.nelem, Pp.nq, seed=0)
+        t0 = time.perf_counter()
+        oracle.element_matrices(Pp, kp)
+        rate = Pp.nelem / (time.perf_counter() - t0)
+        extra["w3_p%d_elements_per_s_extrapolated" % p] = rate
+        extra["w3_p%d_whole_mesh_s_extrapolated" % p] = 128 ** 3 / rate
+    u = W.normal_vector(99 ** 3, 3)
+    v = W.normal_vector(99 ** 3, 4)
+    P5 = oracle.Patch(3, (96, 96, 96), (4, 4, 4), [W.open_uniform_knots(96, 3)] * 3)
+    t0 = time.perf_counter()
+    oracle.kappa_grad(P5, u, v)
+    dt5 = time.perf_counter() - t0
+    extra["w5_gradient_all_points_s"] = dt5
+    extra["w5_gradient_points_per_s"] = P5.nelem * P5.nq / dt5
+    out["context"] = extra
+    return out
 
 
 def measured_peaks(torch, stream):
     """Write and copy bandwidth of plain torch kernels on 8 GiB / 4 GiB
-    buffers on this GPU (context for the HBM fractions)."""
+    buffers, and the FP64 rate of a library DGEMM (torch.matmul, 8192^2) on
+    this GPU (context for the HBM and FP64 fractions)."""
     a = torch.empty(1 << 30, dtype=torch.float64, device="cuda")
     ms_f = min(timed(lambda: a.fill_(1.0), 5, 1, stream))
     b = a[: 1 << 29]
@@ -117,8 +151,16 @@ def measured_peaks(torch, stream):
     ms_c = min(timed(lambda: c.copy_(b), 5, 1, stream))
     del a, b, c
     torch.cuda.empty_cache()
+    m = 8192
+    x = torch.rand(m, m, dtype=torch.float64, device="cuda")
+    y = torch.rand(m, m, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(x)
+    ms_g = min(timed(lambda: torch.matmul(x, y, out=z), 3, 1, stream))
+    del x, y, z
+    torch.cuda.empty_cache()
     return {"write_GB/s": 8 * (1 << 30) / (ms_f * 1e-3) / 1e9,
-            "copy_GB/s": 2 * 8 * (1 << 29) / (ms_c * 1e-3) / 1e9}
+            "copy_GB/s": 2 * 8 * (1 << 29) / (ms_c * 1e-3) / 1e9,
+            "fp64_dgemm_TFLOP/s": 2.0 * m ** 3 / (ms_g * 1e-3) / 1e12}
 
 
 class Headline:
@@ -426,6 +468,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_median": float(np.median(ms)),
+        "ms_min": float(min(ms)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -468,10 +512,20 @@ def main():
                                   "frac_fp64_8n6q3": E * 8 * 4 ** 6 * 4 ** 3 / (ms_cl * 1e-3) / FP64_PEAK},
             "csr_atomic": {"ms": ms_at, "GB/s": csr_b / (ms_at * 1e-3) / 1e9},
         }
+        rp_t = torch.empty(plan.ndof + 1, dtype=torch.int64, device="cuda")
+        col_t = torch.empty(nnz, dtype=torch.int32, device="cuda")
+        out["kernels"]["csr_pattern"] = {"ms": float(np.mean(timed(
+            lambda: plan.csr_pattern(rp_t, col_t), 3, 1, stream))), "note": "built once per plan, not in the step"}
+        del rp_t, col_t
         log(json.dumps(out["kernels"]))
         del h
         torch.cuda.empty_cache()
         out["measured_peaks"] = measured_peaks(torch, stream)
+        mp = out["measured_peaks"]
+        out["kernels"]["element_sumfact"]["frac_measured_write"] = \
+            out["kernels"]["element_sumfact"]["GB/s"] / mp["write_GB/s"]
+        out["kernels"]["element_classical"]["frac_measured_dgemm"] = \
+            out["kernels"]["element_classical"]["flops_8n6q3"] / (ms_cl * 1e-3) / 1e12 / mp["fp64_dgemm_TFLOP/s"]
         log("measured peaks: %s" % json.dumps(out["measured_peaks"]))
         steps_x = max(3, args.steps // 4)
         out["w3_streamed_128c"] = bench_w3(ig, torch, stream, steps_x)

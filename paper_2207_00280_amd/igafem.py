@@ -261,10 +261,11 @@ class Plan:
         _check(lib().igaf_plan_timing(self._h, int(kernel), ctypes.byref(a), ctypes.byref(n)))
         return a.value, n.value
 
-    def csr_pattern(self, stream=None):
+    def csr_pattern(self, row_ptr=None, col=None, stream=None):
+        """The structural CSR pattern into (new, or the given) device arrays."""
         torch = _torch()
-        rp = torch.empty(self.ndof + 1, dtype=torch.int64, device="cuda")
-        col = torch.empty(self.nnz, dtype=torch.int32, device="cuda")
+        rp = torch.empty(self.ndof + 1, dtype=torch.int64, device="cuda") if row_ptr is None else row_ptr
+        col = torch.empty(self.nnz, dtype=torch.int32, device="cuda") if col is None else col
         _check(lib().igaf_csr_pattern(self._h, _ptr(rp), _ptr(col), _stream(stream)))
         return rp, col
 
