@@ -539,7 +539,7 @@ igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const
                                    "element matrices");
         timing_mark(mp, 0, s);
         timing_mark(mp, 1, plan->side);
-        st = launched(launch_rows(plan->dev, kappa, Mval, Kval, plan->side), "row assembly");
+        st = launched(launch_rows(plan->dev, kappa, Mval, Kval, plan->side, false), "row assembly");
         timing_mark(mp, 1, plan->side);
         if (hipEventRecord(plan->ev_join, plan->side) != hipSuccess ||
             hipStreamWaitEvent(s, plan->ev_join, 0) != hipSuccess)

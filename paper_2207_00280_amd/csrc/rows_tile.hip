@@ -84,7 +84,10 @@ struct Tile {
     static constexpr int NW = PIPE ? NWZY + WX : cmax(NWZY, WX);
     static constexpr int NT = 64 * NW;
     static constexpr int XW0 = PIPE ? NWZY : 0;         // first stage-x wavefront
-    static constexpr int NTS = PIPE ? 64 * WX : NT;     // threads that store rows
+    // pipelined: the stage-z wavefronts without stage-y work (HW0..NWZY-1)
+    // store rows beside the stage-x wavefronts
+    static constexpr int HW0 = PIPE && NWY < NWZY ? NWY : NWZY;
+    static constexpr int NTS = PIPE ? 64 * (WX + NWZY - HW0) : NT;   // threads that store rows
     // D[zr][t][oz][ly][ky][kx]
     static constexpr int DOZ = pad16(NZI, Q);
     static constexpr int DT = O * DOZ;
@@ -100,6 +103,7 @@ struct Tile {
     static constexpr int SROW = O * O * O + 1;
     static constexpr int SSZ = NPEN * 2 * SROW;
     static constexpr int SIT = (O * O * O + NTS - 1) / NTS;   // store passes per row
+    static constexpr int SGP = PIPE ? NPEN : 1;         // pencils whose LDS reads go out together
     // LDS (doubles).  Sequential: [D | staged rows] [C]; the rows reuse D,
     // dead after stage y.  Pipelined: [D] [C0] [C1] [staged rows].
     static constexpr int OFF_C = PIPE ? DSZ : cmax(DSZ, SSZ);
@@ -377,37 +381,51 @@ __device__ __forceinline__ void pencil_rows(const TileCtx& c, int lane, int64_t&
 }
 
 // Each pencil's staged row ix as one contiguous segment, by the NTS storing
-// threads (ts = 0..NTS-1); all LDS reads of a pencil are issued before its
-// stores.
-template <class T>
+// threads (ts = 0..NTS-1).  The LDS reads of SGP pencils are issued before
+// their stores: all pencils in the pipelined schedule (one wait per row),
+// one at a time in the sequential one, whose registers hold the ring.  NT:
+// streaming (non-temporal) stores, faster when the kernel has the memory
+// system to itself, slower beside the element kernel's store stream.
+template <class T, bool NT>
 __device__ __forceinline__ void store_row(const TileCtx& c, const double* STG, int ix, int ts,
                                           int64_t pbase, int plen)
 {
-    constexpr int P = T::P;
+    constexpr int P = T::P, SIT = T::SIT, GP = T::SGP;
     const int Lx = band_len(ix, P, c.Nx);
     const int64_t px = band_prefix(ix, P, c.Nx);
 #pragma unroll 1
-    for (int pen = 0; pen < T::NPEN; ++pen) {
-        const int Lyz = __builtin_amdgcn_readlane(plen, pen);
-        if (Lyz == 0) continue;   // pencil outside the patch
-        const int L = Lx * Lyz;
-        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)pbase, pen);
-        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(pbase >> 32), pen);
-        const int64_t rs = (int64_t)(((uint64_t)hi << 32) | lo) + (int64_t)Lyz * px;
-        const double* st = STG + pen * 2 * T::SROW;
-        double vm[T::SIT], vk[T::SIT];
+    for (int p0 = 0; p0 < T::NPEN; p0 += GP) {
+        double vm[GP][SIT], vk[GP][SIT];
 #pragma unroll
-        for (int j = 0; j < T::SIT; ++j) {
-            const int i = min(ts + j * T::NTS, T::SROW - 1);
-            vm[j] = st[i];
-            vk[j] = st[T::SROW + i];
+        for (int g = 0; g < GP; ++g) {
+            const double* st = STG + (p0 + g) * 2 * T::SROW;
+#pragma unroll
+            for (int j = 0; j < SIT; ++j) {
+                const int i = min(ts + j * T::NTS, T::SROW - 1);
+                vm[g][j] = st[i];
+                vk[g][j] = st[T::SROW + i];
+            }
         }
 #pragma unroll
-        for (int j = 0; j < T::SIT; ++j) {
-            const int i = ts + j * T::NTS;
-            if (i < L) {
-                if (c.Mv) c.Mv[rs + i] = vm[j];
-                if (c.Kv) c.Kv[rs + i] = vk[j];
+        for (int g = 0; g < GP; ++g) {
+            const int pen = p0 + g;
+            const int Lyz = __builtin_amdgcn_readlane(plen, pen);   // 0: pencil outside the patch
+            const int L = Lx * Lyz;
+            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)pbase, pen);
+            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(pbase >> 32), pen);
+            const int64_t rs = (int64_t)(((uint64_t)hi << 32) | lo) + (int64_t)Lyz * px;
+#pragma unroll
+            for (int j = 0; j < SIT; ++j) {
+                const int i = ts + j * T::NTS;
+                if (i < L) {
+                    if constexpr (NT) {
+                        if (c.Mv) __builtin_nontemporal_store(vm[g][j], c.Mv + rs + i);
+                        if (c.Kv) __builtin_nontemporal_store(vk[g][j], c.Kv + rs + i);
+                    } else {
+                        if (c.Mv) c.Mv[rs + i] = vm[g][j];
+                        if (c.Kv) c.Kv[rs + i] = vk[g][j];
+                    }
+                }
             }
         }
     }
@@ -415,7 +433,7 @@ __device__ __forceinline__ void store_row(const TileCtx& c, const double* STG, i
 
 // One tile (pencils iy0.., iz0..) over the rows [seg*seglen, (seg+1)*seglen)
 // of a patch, by one workgroup of T::NT threads with T::LDS doubles of LDS.
-template <class T>
+template <class T, bool NT>
 __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
                                          const double* __restrict__ kappa,
                                          double* __restrict__ Mv, double* __restrict__ Kv,
@@ -487,7 +505,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
             if (emit) {
                 if (w < T::WX) x_row<T>(c, xt, ring, ix, STG);
                 __syncthreads();
-                store_row<T>(c, STG, ix, tid, pbase, plen);
+                store_row<T, NT>(c, STG, ix, tid, pbase, plen);
                 __syncthreads();   // the next stage z rewrites the staged rows
             }
         }
@@ -500,6 +518,10 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
             const ZThread<T> zt(c, w, lane);
             double kw[P + 1][Q];
             if (w < T::NWZ && xs < xe) z_load<T>(c, zt, xs, kw);
+            int64_t pbase = 0;
+            int plen = 0;
+            if (w >= T::HW0) pencil_rows<T>(c, lane, pbase, plen);
+            const int ts = 64 * (T::WX + w - T::HW0) + lane;
             for (int t = xs; t <= X1; ++t) {
                 const bool el = t < xe;
                 const int z0 = opaque_zero_t();
@@ -508,7 +530,11 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
                     if (t + 1 < xe) z_load<T>(c, zt, t + 1, kw);
                 }
                 __syncthreads();
-                if (el && w < T::NWY) y_stage<T>(c, w, lane, D, C0 + (t & 1) * T::CSZ, z0);
+                if (w < T::NWY) {
+                    if (el) y_stage<T>(c, w, lane, D, C0 + (t & 1) * T::CSZ, z0);
+                } else if (w >= T::HW0 && t - 1 >= X0) {
+                    store_row<T, NT>(c, STG, t - 1, ts, pbase, plen);
+                }
                 __syncthreads();
             }
         } else {
@@ -530,7 +556,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
                     if (emit) x_row<T>(c, xt, ring, r, STG);
                 }
                 __syncthreads();
-                if (emit) store_row<T>(c, STG, r, wx * 64 + lane, pbase, plen);
+                if (emit) store_row<T, NT>(c, STG, r, wx * 64 + lane, pbase, plen);
                 __syncthreads();
             }
         }
@@ -542,7 +568,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
 // [x*nb8, (x+1)*nb8): neighbouring tiles (which share kappa) share one L2.
 __device__ inline int xcd_tile(int b, int nb8) { return (b % 8) * nb8 + b / 8; }
 
-template <class T>
+template <class T, bool NT>
 __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE))) void k_rows_tile(
     PatchDev pd, RowMap rm, const double* __restrict__ kappa, double* __restrict__ Mv,
     double* __restrict__ Kv, int nty, int ntz, int nseg, int seglen, int nb8)
@@ -551,12 +577,12 @@ __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE)))
     const int ntile = nty * ntz;
     const int b = xcd_tile(blockIdx.x, nb8);
     if (b >= ntile * nseg) return;   // whole workgroup
-    tile_run<T>(pd, rm, kappa, Mv, Kv, b % ntile, b / ntile, nty, seglen, lds);
+    tile_run<T, NT>(pd, rm, kappa, Mv, Kv, b % ntile, b / ntile, nty, seglen, lds);
 }
 
 template <class T>
 static int launch_rows_tile_t(const PatchDev& pd, const double* kappa, double* Mv, double* Kv,
-                              hipStream_t st)
+                              hipStream_t st, bool nt)
 {
     RowMap rm = make_rowmap(pd);
     const int Nx = pd.d[0].N, Ny = pd.d[1].N, Nz = pd.d[2].N;
@@ -569,7 +595,7 @@ static int launch_rows_tile_t(const PatchDev& pd, const double* kappa, double* M
         int dev = 0, ncu = 0, per = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rows_tile<T>, T::NT, 0) != hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rows_tile<T, true>, T::NT, 0) != hipSuccess)
             return -3;
         slots = ncu * (per > 0 ? per : 1);
     }
@@ -586,19 +612,24 @@ static int launch_rows_tile_t(const PatchDev& pd, const double* kappa, double* M
     }
     const int seglen = (Nx + nseg - 1) / nseg;
     const int nb = ntile * nseg, nb8 = (nb + 7) / 8;
-    hipLaunchKernelGGL(k_rows_tile<T>, dim3(nb8 * 8), dim3(T::NT), 0, st, pd, rm, kappa, Mv, Kv,
-                       nty, ntz, nseg, seglen, nb8);
+    if (nt)
+        hipLaunchKernelGGL((k_rows_tile<T, true>), dim3(nb8 * 8), dim3(T::NT), 0, st, pd, rm, kappa, Mv, Kv,
+                           nty, ntz, nseg, seglen, nb8);
+    else
+        hipLaunchKernelGGL((k_rows_tile<T, false>), dim3(nb8 * 8), dim3(T::NT), 0, st, pd, rm, kappa, Mv, Kv,
+                           nty, ntz, nseg, seglen, nb8);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_rows(const PatchDev& pd, const double* kappa, double* Mv, double* Kv, hipStream_t st)
+int launch_rows(const PatchDev& pd, const double* kappa, double* Mv, double* Kv, hipStream_t st,
+                bool stream_stores)
 {
     switch (pd.p) {
-    case 1: return launch_rows_tile_t<TileCfg<1>::T>(pd, kappa, Mv, Kv, st);
-    case 2: return launch_rows_tile_t<TileCfg<2>::T>(pd, kappa, Mv, Kv, st);
-    case 3: return launch_rows_tile_t<TileCfg<3>::T>(pd, kappa, Mv, Kv, st);
-    case 4: return launch_rows_tile_t<TileCfg<4>::T>(pd, kappa, Mv, Kv, st);
-    case 5: return launch_rows_tile_t<TileCfg<5>::T>(pd, kappa, Mv, Kv, st);
+    case 1: return launch_rows_tile_t<TileCfg<1>::T>(pd, kappa, Mv, Kv, st, stream_stores);
+    case 2: return launch_rows_tile_t<TileCfg<2>::T>(pd, kappa, Mv, Kv, st, stream_stores);
+    case 3: return launch_rows_tile_t<TileCfg<3>::T>(pd, kappa, Mv, Kv, st, stream_stores);
+    case 4: return launch_rows_tile_t<TileCfg<4>::T>(pd, kappa, Mv, Kv, st, stream_stores);
+    case 5: return launch_rows_tile_t<TileCfg<5>::T>(pd, kappa, Mv, Kv, st, stream_stores);
     default: return -4;
     }
 }
@@ -669,7 +700,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     switch (pd.p) {
 #define IGAF_TB(PP)                                                                                 \
     case PP:                                                                                        \
-        tile_run<TileOf<PP>>(pd, rm, kappa, Mv, Kv, tile, seg, (Ny + TileOf<PP>::TY - 1) / TileOf<PP>::TY, \
+        tile_run<TileOf<PP>, true>(pd, rm, kappa, Mv, Kv, tile, seg, (Ny + TileOf<PP>::TY - 1) / TileOf<PP>::TY, \
                              seglen, lds);                                                          \
         break;
         IGAF_TB(1)
