@@ -485,7 +485,8 @@ def main():
                           "unit": "GB/s", "frac": step_bytes / (ms_step * 1e-3) / HBM_PEAK},
     }
     # roofline of the dominant kernel (the element-matrix kernel, HBM-store-bound), from
-    # its HIP-event intervals inside the timed steps (it runs beside the CSR kernel)
+    # its HIP-event intervals inside the timed steps (the CSR kernel follows it on the
+    # same stream)
     alg_el = bytes_kappa + bytes_elem
     out["roofline"] = {"bound": "hbm", "achieved": alg_el / (el_ms * 1e-3) / 1e9,
                        "peak": HBM_PEAK / 1e9, "unit": "GB/s",

@@ -140,9 +140,6 @@ struct igaf_plan {
     PatchDev dev;
     int device = 0;
     int asm_mode = IGAF_ASM_ROWS;
-    // side stream + events: the CSR kernel runs beside the element kernel
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // opt-in kernel interval log of igaf_integrate_assemble (timing events)
     bool timing = false;
     std::vector<hipEvent_t> tev[2];   // [element | csr]: start, end, start, end, ...
@@ -322,7 +319,7 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
     int64_t ioff = 0;
     P->dev.p = P->p;
     // element kernels: two 256-lane workgroups per CU saturate the HBM store
-    // path and leave LDS for the CSR kernel running beside them
+    // path
     int ncu = 256;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess)
         ncu = 256;
@@ -382,11 +379,6 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
     if (rc == IGAF_OK && hipStreamSynchronize(nullptr) != hipSuccess)
         rc = fail(IGAF_EDEVICE, "basis-table kernel failed");
     if (rc == IGAF_OK) rc = mass_factors(P);
-    if (rc == IGAF_OK &&
-        (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
-         hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
-         hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess))
-        rc = fail(IGAF_EDEVICE, "stream/event creation failed");
     if (rc != IGAF_OK) {
         igaf_plan_destroy(P);
         return rc;
@@ -399,10 +391,6 @@ void igaf_plan_destroy(igaf_plan* plan)
 {
     if (!plan) return;
     timing_clear(plan);
-    if (plan->side) (void)hipStreamSynchronize(plan->side);
-    if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
-    if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
-    if (plan->side) (void)hipStreamDestroy(plan->side);
     (void)hipFree(plan->dmem);
     (void)hipFree(plan->dpre);
     if (plan->geo_ws) (void)hipFree(plan->geo_ws);
@@ -525,34 +513,16 @@ igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const
                                "integrate+atomic assembly");
         return st;
     }
-    if ((Me || Ke) && (Mval || Kval)) {
-        // fork: the element kernel (HBM-store-bound) is queued first on the
-        // caller's stream, the CSR rows kernel (latency-bound) on the plan's
-        // side stream, so its workgroups fill the CU slots the element kernel
-        // leaves; the caller's stream then waits for both.
-        if (hipEventRecord(plan->ev_fork, s) != hipSuccess ||
-            hipStreamWaitEvent(plan->side, plan->ev_fork, 0) != hipSuccess)
-            return fail(IGAF_EDEVICE, "stream fork failed");
-        igaf_plan* mp = const_cast<igaf_plan*>(plan);
-        timing_mark(mp, 0, s);
-        igaf_status st2 = launched(launch_element(plan->dev, method, kappa, Me, Ke, nullptr, nullptr, s),
-                                   "element matrices");
-        timing_mark(mp, 0, s);
-        timing_mark(mp, 1, plan->side);
-        st = launched(launch_rows(plan->dev, kappa, Mval, Kval, plan->side, false), "row assembly");
-        timing_mark(mp, 1, plan->side);
-        if (hipEventRecord(plan->ev_join, plan->side) != hipSuccess ||
-            hipStreamWaitEvent(s, plan->ev_join, 0) != hipSuccess)
-            return fail(IGAF_EDEVICE, "stream join failed");
-        return st ? st : st2;
-    }
+    // dense element matrices first, then the CSR rows kernel on the same
+    // stream: one after the other measured faster than the two side by side
+    // on two streams (they compete for the same CU slots)
     igaf_plan* mp = const_cast<igaf_plan*>(plan);
     if (Me || Ke) {
         timing_mark(mp, 0, s);
         st = launched(launch_element(plan->dev, method, kappa, Me, Ke, nullptr, nullptr, s),
                       "element matrices");
         timing_mark(mp, 0, s);
-        return st;
+        if (st || !(Mval || Kval)) return st;
     }
     timing_mark(mp, 1, s);
     st = launched(launch_rows(plan->dev, kappa, Mval, Kval, s), "row assembly");

@@ -23,10 +23,9 @@ int launch_element(const PatchDev& pd, int method, const double* kappa, double* 
                    double* Mval_atomic, double* Kval_atomic, hipStream_t st);
 
 // CSR values by owner-computes rows (no atomics), one workgroup per tile of
-// row pencils: overwrites Mval / Kval.  stream_stores: non-temporal stores
-// (false when the kernel runs beside the element kernel).
+// row pencils: overwrites Mval / Kval.
 int launch_rows(const PatchDev& pd, const double* kappa, double* Mval, double* Kval,
-                hipStream_t st, bool stream_stores = true);
+                hipStream_t st);
 
 // Batched CSR rows: one workgroup per (patch, tile, x segment, segment
 // length) item of `items`, which the host sorts longest first, `chunk`

@@ -383,10 +383,9 @@ __device__ __forceinline__ void pencil_rows(const TileCtx& c, int lane, int64_t&
 // Each pencil's staged row ix as one contiguous segment, by the NTS storing
 // threads (ts = 0..NTS-1).  The LDS reads of SGP pencils are issued before
 // their stores: all pencils in the pipelined schedule (one wait per row),
-// one at a time in the sequential one, whose registers hold the ring.  NT:
-// streaming (non-temporal) stores, faster when the kernel has the memory
-// system to itself, slower beside the element kernel's store stream.
-template <class T, bool NT>
+// one at a time in the sequential one, whose registers hold the ring.  The
+// stores are non-temporal: nothing in the kernel reads a CSR value back.
+template <class T>
 __device__ __forceinline__ void store_row(const TileCtx& c, const double* STG, int ix, int ts,
                                           int64_t pbase, int plen)
 {
@@ -418,13 +417,8 @@ __device__ __forceinline__ void store_row(const TileCtx& c, const double* STG, i
             for (int j = 0; j < SIT; ++j) {
                 const int i = ts + j * T::NTS;
                 if (i < L) {
-                    if constexpr (NT) {
-                        if (c.Mv) __builtin_nontemporal_store(vm[g][j], c.Mv + rs + i);
-                        if (c.Kv) __builtin_nontemporal_store(vk[g][j], c.Kv + rs + i);
-                    } else {
-                        if (c.Mv) c.Mv[rs + i] = vm[g][j];
-                        if (c.Kv) c.Kv[rs + i] = vk[g][j];
-                    }
+                    if (c.Mv) __builtin_nontemporal_store(vm[g][j], c.Mv + rs + i);
+                    if (c.Kv) __builtin_nontemporal_store(vk[g][j], c.Kv + rs + i);
                 }
             }
         }
@@ -433,7 +427,7 @@ __device__ __forceinline__ void store_row(const TileCtx& c, const double* STG, i
 
 // One tile (pencils iy0.., iz0..) over the rows [seg*seglen, (seg+1)*seglen)
 // of a patch, by one workgroup of T::NT threads with T::LDS doubles of LDS.
-template <class T, bool NT>
+template <class T>
 __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
                                          const double* __restrict__ kappa,
                                          double* __restrict__ Mv, double* __restrict__ Kv,
@@ -505,7 +499,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
             if (emit) {
                 if (w < T::WX) x_row<T>(c, xt, ring, ix, STG);
                 __syncthreads();
-                store_row<T, NT>(c, STG, ix, tid, pbase, plen);
+                store_row<T>(c, STG, ix, tid, pbase, plen);
                 __syncthreads();   // the next stage z rewrites the staged rows
             }
         }
@@ -533,7 +527,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
                 if (w < T::NWY) {
                     if (el) y_stage<T>(c, w, lane, D, C0 + (t & 1) * T::CSZ, z0);
                 } else if (w >= T::HW0 && t - 1 >= X0) {
-                    store_row<T, NT>(c, STG, t - 1, ts, pbase, plen);
+                    store_row<T>(c, STG, t - 1, ts, pbase, plen);
                 }
                 __syncthreads();
             }
@@ -556,7 +550,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
                     if (emit) x_row<T>(c, xt, ring, r, STG);
                 }
                 __syncthreads();
-                if (emit) store_row<T, NT>(c, STG, r, wx * 64 + lane, pbase, plen);
+                if (emit) store_row<T>(c, STG, r, wx * 64 + lane, pbase, plen);
                 __syncthreads();
             }
         }
@@ -568,7 +562,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
 // [x*nb8, (x+1)*nb8): neighbouring tiles (which share kappa) share one L2.
 __device__ inline int xcd_tile(int b, int nb8) { return (b % 8) * nb8 + b / 8; }
 
-template <class T, bool NT>
+template <class T>
 __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE))) void k_rows_tile(
     PatchDev pd, RowMap rm, const double* __restrict__ kappa, double* __restrict__ Mv,
     double* __restrict__ Kv, int nty, int ntz, int nseg, int seglen, int nb8)
@@ -577,12 +571,12 @@ __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE)))
     const int ntile = nty * ntz;
     const int b = xcd_tile(blockIdx.x, nb8);
     if (b >= ntile * nseg) return;   // whole workgroup
-    tile_run<T, NT>(pd, rm, kappa, Mv, Kv, b % ntile, b / ntile, nty, seglen, lds);
+    tile_run<T>(pd, rm, kappa, Mv, Kv, b % ntile, b / ntile, nty, seglen, lds);
 }
 
 template <class T>
 static int launch_rows_tile_t(const PatchDev& pd, const double* kappa, double* Mv, double* Kv,
-                              hipStream_t st, bool nt)
+                              hipStream_t st)
 {
     RowMap rm = make_rowmap(pd);
     const int Nx = pd.d[0].N, Ny = pd.d[1].N, Nz = pd.d[2].N;
@@ -595,7 +589,7 @@ static int launch_rows_tile_t(const PatchDev& pd, const double* kappa, double* M
         int dev = 0, ncu = 0, per = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rows_tile<T, true>, T::NT, 0) != hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rows_tile<T>, T::NT, 0) != hipSuccess)
             return -3;
         slots = ncu * (per > 0 ? per : 1);
     }
@@ -612,24 +606,19 @@ static int launch_rows_tile_t(const PatchDev& pd, const double* kappa, double* M
     }
     const int seglen = (Nx + nseg - 1) / nseg;
     const int nb = ntile * nseg, nb8 = (nb + 7) / 8;
-    if (nt)
-        hipLaunchKernelGGL((k_rows_tile<T, true>), dim3(nb8 * 8), dim3(T::NT), 0, st, pd, rm, kappa, Mv, Kv,
-                           nty, ntz, nseg, seglen, nb8);
-    else
-        hipLaunchKernelGGL((k_rows_tile<T, false>), dim3(nb8 * 8), dim3(T::NT), 0, st, pd, rm, kappa, Mv, Kv,
-                           nty, ntz, nseg, seglen, nb8);
+    hipLaunchKernelGGL(k_rows_tile<T>, dim3(nb8 * 8), dim3(T::NT), 0, st, pd, rm, kappa, Mv, Kv,
+                       nty, ntz, nseg, seglen, nb8);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_rows(const PatchDev& pd, const double* kappa, double* Mv, double* Kv, hipStream_t st,
-                bool stream_stores)
+int launch_rows(const PatchDev& pd, const double* kappa, double* Mv, double* Kv, hipStream_t st)
 {
     switch (pd.p) {
-    case 1: return launch_rows_tile_t<TileCfg<1>::T>(pd, kappa, Mv, Kv, st, stream_stores);
-    case 2: return launch_rows_tile_t<TileCfg<2>::T>(pd, kappa, Mv, Kv, st, stream_stores);
-    case 3: return launch_rows_tile_t<TileCfg<3>::T>(pd, kappa, Mv, Kv, st, stream_stores);
-    case 4: return launch_rows_tile_t<TileCfg<4>::T>(pd, kappa, Mv, Kv, st, stream_stores);
-    case 5: return launch_rows_tile_t<TileCfg<5>::T>(pd, kappa, Mv, Kv, st, stream_stores);
+    case 1: return launch_rows_tile_t<TileCfg<1>::T>(pd, kappa, Mv, Kv, st);
+    case 2: return launch_rows_tile_t<TileCfg<2>::T>(pd, kappa, Mv, Kv, st);
+    case 3: return launch_rows_tile_t<TileCfg<3>::T>(pd, kappa, Mv, Kv, st);
+    case 4: return launch_rows_tile_t<TileCfg<4>::T>(pd, kappa, Mv, Kv, st);
+    case 5: return launch_rows_tile_t<TileCfg<5>::T>(pd, kappa, Mv, Kv, st);
     default: return -4;
     }
 }
@@ -700,7 +689,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     switch (pd.p) {
 #define IGAF_TB(PP)                                                                                 \
     case PP:                                                                                        \
-        tile_run<TileOf<PP>, true>(pd, rm, kappa, Mv, Kv, tile, seg, (Ny + TileOf<PP>::TY - 1) / TileOf<PP>::TY, \
+        tile_run<TileOf<PP>>(pd, rm, kappa, Mv, Kv, tile, seg, (Ny + TileOf<PP>::TY - 1) / TileOf<PP>::TY, \
                              seglen, lds);                                                          \
         break;
         IGAF_TB(1)
