@@ -491,7 +491,7 @@ def main():
     out["roofline"] = {"bound": "hbm", "achieved": alg_el / (el_ms * 1e-3) / 1e9,
                        "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                        "frac": alg_el / (el_ms * 1e-3) / HBM_PEAK, "traffic": traffic_for_current_kernel(),
-                       "kernel": "igaf::k_element<3,1,false> (sum factorisation, dense M_e/K_e store)",
+                       "kernel": "igaf::k_element_ws<3> (sum factorisation, dense M_e/K_e store)",
                        "bytes_per_launch": alg_el, "ms": el_ms, "launches": el_n,
                        "csr_kernel_in_step_ms": csr_ms}
     if args.mode == "full":

@@ -18,6 +18,8 @@
 //
 // One 256-thread workgroup per element (grid-stride); the stages live in LDS,
 // separated by barriers (the paper's Foata classes become barrier phases).
+// For odd p with dense outputs (k_element_ws) half of the workgroup stores
+// the previous element while the other half contracts the current one.
 #include "common.h"
 #include "launch.h"
 
@@ -230,14 +232,169 @@ __global__ __launch_bounds__(kElemThreads) void k_element(PatchDev pd, RowMap rm
     }
 }
 
+// Sum factorisation with the dense store split off (odd p, dense outputs
+// only): wavefronts 0-1 contract element t (stages z, y, x into V[t & 1])
+// while wavefronts 2-3 expand and store element t-1 from V[(t-1) & 1], a
+// quarter of it between each pair of the iteration's four barriers, so the
+// store stream does not stop for the contractions.
+template <int P>
+__global__ __launch_bounds__(kElemThreads) void k_element_ws(PatchDev pd, const double* __restrict__ kappa,
+                                                             double* __restrict__ Me,
+                                                             double* __restrict__ Ke)
+{
+    using Sh = ElemShape<P>;
+    constexpr int n = Sh::n, Q = Sh::Q, S = Sh::S, n3 = Sh::n3, Q3 = Sh::Q3;
+    constexpr int TC = 128, TS = kElemThreads - TC;   // contracting / storing threads
+    static_assert(Sh::VFULL && n3 % 2 == 0, "paired stores of the full value set");
+    __shared__ double kap[Q3];
+    __shared__ double tw[3][2][S * Q];                 // [dir][nn, dd][s*Q + k]
+    __shared__ double D[2][S * Q * Q];                 // [nn, dd][(zp*Q + kx)*Q + ky]
+    __shared__ double C[2][S * S * Q];                 // [a, bc][(yp*S + zp)*Q + kx]
+    __shared__ double V[2][2][Sh::S3];                 // [buffer][M, K]
+
+    const int tid = threadIdx.x;
+    const int Kx = pd.d[0].K, Ky = pd.d[1].K;
+    // elements e0, e0 + G, ... of this workgroup
+    const int64_t G = gridDim.x, e0 = blockIdx.x;
+    const int nt = e0 < pd.E ? (int)((pd.E - 1 - e0) / G + 1) : 0;
+    auto elem = [&](int t) { return e0 + (int64_t)t * G; };
+
+    if (tid < TC) {
+        constexpr int NKP = (Q3 + TC - 1) / TC, NTW = (6 * S * Q + TC - 1) / TC;
+        double pk[NKP], pt[NTW];
+        auto fetch = [&](int64_t e) {
+            const int ex = (int)(e % Kx);
+            const int ey = (int)((e / Kx) % Ky);
+            const int ez = (int)(e / ((int64_t)Kx * Ky));
+#pragma unroll
+            for (int r = 0; r < NKP; ++r) {
+                const int i = tid + r * TC;
+                pk[r] = i < Q3 ? kappa[e * Q3 + i] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < NTW; ++r) {
+                const int i = tid + r * TC;
+                double val = 0.0;
+                if (i < 6 * S * Q) {
+                    const int d = i / (2 * S * Q), rr = i % (2 * S * Q);
+                    const int which = rr / (S * Q), j = rr % (S * Q);
+                    const int ed = d == 0 ? ex : (d == 1 ? ey : ez);
+                    const double* src = which ? pd.d[d].Wdd : pd.d[d].Wnn;
+                    val = src[(int64_t)ed * S * Q + j];
+                }
+                pt[r] = val;
+            }
+        };
+        if (nt > 0) fetch(elem(0));
+        for (int t = 0; t <= nt; ++t) {
+            const bool el = t < nt;
+            if (el) {
+#pragma unroll
+                for (int r = 0; r < NKP; ++r)
+                    if (tid + r * TC < Q3) kap[tid + r * TC] = pk[r];
+#pragma unroll
+                for (int r = 0; r < NTW; ++r)
+                    if (tid + r * TC < 6 * S * Q) (&tw[0][0][0])[tid + r * TC] = pt[r];
+            }
+            __syncthreads();
+            if (el) {
+                if (t + 1 < nt) fetch(elem(t + 1));
+                for (int i = tid; i < S * Q * Q; i += TC) {   // stage z
+                    const int zp = i / (Q * Q), kx = (i / Q) % Q, ky = i % Q;
+                    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+                    for (int kz = 0; kz < Q; ++kz) {
+                        const double c = kap[kx + Q * (ky + Q * kz)];
+                        d0 += tw[2][0][zp * Q + kz] * c;
+                        d1 += tw[2][1][zp * Q + kz] * c;
+                    }
+                    D[0][i] = d0;
+                    D[1][i] = d1;
+                }
+            }
+            __syncthreads();
+            if (el) {
+                for (int i = tid; i < S * S * Q; i += TC) {   // stage y
+                    const int yp = i / (S * Q), zp = (i / Q) % S, kx = i % Q;
+                    double ca = 0.0, cb = 0.0;
+#pragma unroll
+                    for (int ky = 0; ky < Q; ++ky) {
+                        const double wn = tw[1][0][yp * Q + ky], wd = tw[1][1][yp * Q + ky];
+                        const double d0 = D[0][(zp * Q + kx) * Q + ky], d1 = D[1][(zp * Q + kx) * Q + ky];
+                        ca += wn * d0;
+                        cb += wd * d0 + wn * d1;
+                    }
+                    C[0][i] = ca;
+                    C[1][i] = cb;
+                }
+            }
+            __syncthreads();
+            if (el) {
+                double* const Vm = V[t & 1][0];
+                double* const Vk = V[t & 1][1];
+                for (int i = tid; i < Sh::S3; i += TC) {       // stage x
+                    const int xp = i % S, yp = (i / S) % S, zp = i / (S * S);
+                    double m = 0.0, k = 0.0;
+#pragma unroll
+                    for (int kx = 0; kx < Q; ++kx) {
+                        const double ca = C[0][(yp * S + zp) * Q + kx];
+                        const double cb = C[1][(yp * S + zp) * Q + kx];
+                        const double wn = tw[0][0][xp * Q + kx], wd = tw[0][1][xp * Q + kx];
+                        m += wn * ca;
+                        k += wd * ca + wn * cb;
+                    }
+                    Vm[i] = m;
+                    Vk[i] = k;
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        constexpr int NI2 = Sh::n6 / 2;                      // two consecutive row entries per item
+        constexpr int PER = (NI2 + 4 * TS - 1) / (4 * TS);   // items per thread between two barriers
+        const int ts = tid - TC;
+        for (int t = 0; t <= nt; ++t) {
+            const bool st = t >= 1;
+            const int64_t e = elem(t - 1);
+            const double* const Vm = V[(t - 1) & 1][0];
+            const double* const Vk = V[(t - 1) & 1][1];
+#pragma unroll 1
+            for (int ph = 0; ph < 4; ++ph) {
+                if (st) {
+#pragma unroll
+                    for (int r = 0; r < PER; ++r) {
+                        const int i2 = ts + (ph * PER + r) * TS;
+                        if (i2 < NI2) {
+                            const int i = 2 * i2, I = i / n3, J = i % n3;
+                            const int a1 = I % n, a2 = (I / n) % n, a3 = I / (n * n);
+                            const int b2 = (J / n) % n, b3 = J / (n * n), b1 = J % n;
+                            const int vyz = S * (pair_index(a2, b2) + S * pair_index(a3, b3));
+                            const int v0 = pair_index(a1, b1) + vyz, v1 = pair_index(a1, b1 + 1) + vyz;
+                            if (Me)
+                                *reinterpret_cast<double2*>(Me + e * Sh::n6 + i) = make_double2(Vm[v0], Vm[v1]);
+                            if (Ke)
+                                *reinterpret_cast<double2*>(Ke + e * Sh::n6 + i) = make_double2(Vk[v0], Vk[v1]);
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
 template <int P, int METHOD, bool ATOMIC>
 static int launch_element_t(const PatchDev& pd, const double* kappa, double* Me, double* Ke,
                             double* Mv, double* Kv, hipStream_t st)
 {
     RowMap rm = make_rowmap(pd);
     int64_t blocks = pd.E < pd.elem_grid ? pd.E : pd.elem_grid;
-    hipLaunchKernelGGL((k_element<P, METHOD, ATOMIC>), dim3((unsigned)blocks), dim3(kElemThreads), 0,
-                       st, pd, rm, kappa, Me, Ke, Mv, Kv);
+    if constexpr (METHOD == 1 && !ATOMIC && ElemShape<P>::VFULL && ElemShape<P>::n3 % 2 == 0)
+        hipLaunchKernelGGL(k_element_ws<P>, dim3((unsigned)blocks), dim3(kElemThreads), 0, st, pd, kappa, Me,
+                           Ke);
+    else
+        hipLaunchKernelGGL((k_element<P, METHOD, ATOMIC>), dim3((unsigned)blocks), dim3(kElemThreads), 0,
+                           st, pd, rm, kappa, Me, Ke, Mv, Kv);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
