@@ -67,20 +67,26 @@ struct ApplyShape {
     static constexpr int YA3 = ppad16(Q2, Q), YF = n * YA3, YG = 3 * YF;
     static constexpr int WS = pmax(G * XG, G * YG);               // doubles per wavefront
     static constexpr int RUN = 32;                                // elements per x-run
+    // p <= 3: the run's finished DOF values, [a2 + n a3][ex - ex0], added to
+    // y in one pass at the end of the run
+    static constexpr int RB = NXP == 1 ? RUN * n * n : 0;
 };
 
 // GEO: a mapped geometry; `kappa` is the mass coefficient cm and Gt
 // ([E][6][q^3]) the stiffness tensor, applied to the parametric gradient.
-template <int P, bool GEO>
+// MASS (alphaK = 0, the conjugate-gradient products of the Euler step): the
+// gradient fields are neither interpolated nor contracted back.
+template <int P, bool GEO, bool MASS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 : 2))) void k_apply(
     PatchDev pd, const double* __restrict__ kappa, const double* __restrict__ u, double alphaM,
     double alphaK, double* __restrict__ y, const double* __restrict__ Gt)
 {
     using A = ApplyShape<P>;
     constexpr int n = A::n, Q = A::Q, Q2 = A::Q2, Q3 = A::Q3, G = A::G, NXP = A::NXP;
-    __shared__ double lds[4][A::WS];
+    __shared__ double lds[4][A::WS + A::RB];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
     double* const B = lds[w];
+    double* const RB = lds[w] + A::WS;
     const int Kx = pd.d[0].K, Ky = pd.d[1].K, Kz = pd.d[2].K;
     const int Nx = pd.d[0].N, Ny = pd.d[1].N;
     const double* __restrict__ Nvx = pd.d[0].Nv;
@@ -145,12 +151,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                     for (int a1 = 0; a1 < n; ++a1) {
                         const int64_t t = ((int64_t)ex * n + a1) * Q + xkx[ps];
                         s0 += uw[ps][a1] * Nvx[t];
-                        s1 += uw[ps][a1] * dNx[t];
+                        if constexpr (!MASS) s1 += uw[ps][a1] * dNx[t];
                     }
                     if (act) {
                         double* xp = B + g * A::XG + xa3[ps] * A::XA3 + xa2[ps] * Q + xkx[ps];
                         xp[0] = s0;
-                        xp[A::XF] = s1;
+                        if constexpr (!MASS) xp[A::XF] = s1;
                     }
 #pragma unroll
                     for (int a1 = 0; a1 + 1 < n; ++a1) uw[ps][a1] = uw[ps][a1 + 1];
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
                 for (int a2 = 0; a2 < n; ++a2) {
                     x0[a2] = xp[a2 * Q];
-                    x1[a2] = xp[A::XF + a2 * Q];
+                    x1[a2] = MASS ? 0.0 : xp[A::XF + a2 * Q];
                 }
                 ap_wave_sync();   // every read of X before the writes of Y over it
                 double* yp = B + yg * A::YG + ya3 * A::YA3 + ykx;
@@ -176,15 +182,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                     double o0 = 0.0, o1 = 0.0, o2 = 0.0;
 #pragma unroll
                     for (int a2 = 0; a2 < n; ++a2) {
-                        const double ny = Ny_[a2 * Q + ky], dy = Dy_[a2 * Q + ky];
+                        const double ny = Ny_[a2 * Q + ky];
                         o0 += ny * x0[a2];
-                        o1 += dy * x0[a2];
-                        o2 += ny * x1[a2];
+                        if constexpr (!MASS) {
+                            o1 += Dy_[a2 * Q + ky] * x0[a2];
+                            o2 += ny * x1[a2];
+                        }
                     }
                     if (yact && yg < ng) {
                         yp[ky * Q] = o0;
-                        yp[A::YF + ky * Q] = o1;
-                        yp[2 * A::YF + ky * Q] = o2;
+                        if constexpr (!MASS) {
+                            yp[A::YF + ky * Q] = o1;
+                            yp[2 * A::YF + ky * Q] = o2;
+                        }
                     }
                 }
             }
@@ -199,8 +209,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
                 for (int a3 = 0; a3 < n; ++a3) {
                     y0[a3] = yp[a3 * A::YA3];
-                    y1[a3] = yp[A::YF + a3 * A::YA3];
-                    y2[a3] = yp[2 * A::YF + a3 * A::YA3];
+                    y1[a3] = MASS ? 0.0 : yp[A::YF + a3 * A::YA3];
+                    y2[a3] = MASS ? 0.0 : yp[2 * A::YF + a3 * A::YA3];
                 }
                 const int exz = exg + min(zg, ng - 1);
                 const double wxy = wqx[(int64_t)exz * Q + zkx] * wyl;
@@ -213,14 +223,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                     double h = 0.0, dz = 0.0, dy = 0.0, dx = 0.0;
 #pragma unroll
                     for (int a3 = 0; a3 < n; ++a3) {
-                        const double nz = Nz_[a3 * Q + kz], dzt = Dz_[a3 * Q + kz];
+                        const double nz = Nz_[a3 * Q + kz];
                         h += nz * y0[a3];
-                        dz += dzt * y0[a3];
-                        dy += nz * y1[a3];
-                        dx += nz * y2[a3];
+                        if constexpr (!MASS) {
+                            dz += Dz_[a3 * Q + kz] * y0[a3];
+                            dy += nz * y1[a3];
+                            dx += nz * y2[a3];
+                        }
                     }
                     double t0, t1, t2, t3;
-                    if constexpr (GEO) {
+                    if constexpr (MASS) {
+                        // the same products, in the same order, as the full forms below
+                        if constexpr (GEO) t0 = alphaM * kp[kz * Q2] * (wxy * wz_[kz]) * h;
+                        else t0 = alphaM * (kp[kz * Q2] * wxy * wz_[kz]) * h;
+                        t1 = t2 = t3 = 0.0;
+                    } else if constexpr (GEO) {
                         const double wk = wxy * wz_[kz];
                         const double* g = Gt + (exz + (int64_t)Kx * (ey + (int64_t)Ky * ez)) * 6 * Q3 + kz * Q2 +
                                           zky * Q + zkx;
@@ -239,11 +256,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                     }
 #pragma unroll
                     for (int a3 = 0; a3 < n; ++a3) {
-                        const double nz = Nz_[a3 * Q + kz], dzt = Dz_[a3 * Q + kz];
+                        const double nz = Nz_[a3 * Q + kz];
                         s0[a3] += nz * t0;
-                        s0[a3] += dzt * t3;
-                        s1[a3] += nz * t1;
-                        s2[a3] += nz * t2;
+                        if constexpr (!MASS) {
+                            s0[a3] += Dz_[a3 * Q + kz] * t3;
+                            s1[a3] += nz * t1;
+                            s2[a3] += nz * t2;
+                        }
                     }
                 }
                 ap_wave_sync();   // every read of Y before the writes of S over it
@@ -253,8 +272,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
                     for (int a3 = 0; a3 < n; ++a3) {
                         sp[a3 * A::YA3] = s0[a3];
-                        sp[A::YF + a3 * A::YA3] = s1[a3];
-                        sp[2 * A::YF + a3 * A::YA3] = s2[a3];
+                        if constexpr (!MASS) {
+                            sp[A::YF + a3 * A::YA3] = s1[a3];
+                            sp[2 * A::YF + a3 * A::YA3] = s2[a3];
+                        }
                     }
                 }
             }
@@ -268,8 +289,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
                 for (int ky = 0; ky < Q; ++ky) {
                     v0[ky] = sp[ky * Q];
-                    v1[ky] = sp[A::YF + ky * Q];
-                    v2[ky] = sp[2 * A::YF + ky * Q];
+                    v1[ky] = MASS ? 0.0 : sp[A::YF + ky * Q];
+                    v2[ky] = MASS ? 0.0 : sp[2 * A::YF + ky * Q];
                 }
                 ap_wave_sync();   // every read of S before the writes of R over it
                 // R[g][f2][a3][a2][kx] in the X layout
@@ -279,14 +300,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                     double r0 = 0.0, r1 = 0.0;
 #pragma unroll
                     for (int ky = 0; ky < Q; ++ky) {
-                        const double ny = Ny_[a2 * Q + ky], dy = Dy_[a2 * Q + ky];
+                        const double ny = Ny_[a2 * Q + ky];
                         r0 += ny * v0[ky];
-                        r0 += dy * v2[ky];
-                        r1 += ny * v1[ky];
+                        if constexpr (!MASS) {
+                            r0 += Dy_[a2 * Q + ky] * v2[ky];
+                            r1 += ny * v1[ky];
+                        }
                     }
                     if (yact && yg < ng) {
                         rp[a2 * Q] = r0;
-                        rp[A::XF + a2 * Q] = r1;
+                        if constexpr (!MASS) rp[A::XF + a2 * Q] = r1;
                     }
                 }
             }
@@ -306,16 +329,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                     for (int kx = 0; kx < Q; ++kx) {
                         const int64_t t = ((int64_t)ex * n + ta1[ps]) * Q + kx;
                         acc += Nvx[t] * rp[kx];
-                        acc += dNx[t] * rp[A::XF + kx];
+                        if constexpr (!MASS) acc += dNx[t] * rp[A::XF + kx];
                     }
                     const int64_t I = (ex + ta1[ps]) + (int64_t)Nx * ((ey + ta2[ps]) + (int64_t)Ny * (ez + ta3[ps]));
                     if constexpr (NXP == 1) {
                         // DOF ex (a1 = 0) has all its contributions of the run
-                        // now (later elements touch DOFs beyond ex): add it to y,
-                        // then move every partial sum down one lane, so that lane
-                        // a1 holds DOF ex + 1 + a1 for the next element
+                        // now (later elements touch DOFs beyond ex): keep it for
+                        // the run's adds to y, then move every partial sum down
+                        // one lane, so that lane a1 holds DOF ex + 1 + a1 for
+                        // the next element.  (An atomic here would make every
+                        // later table load of the run wait for it: loads and
+                        // stores share one in-order counter.)
                         racc += acc;
-                        if (act && ta1[0] == 0) atomicAdd(&y[I], racc);
+                        if (act && ta1[0] == 0) RB[(ta2[0] + n * ta3[0]) * A::RUN + (ex - ex0)] = racc;
                         const double nxt = __shfl(racc, lane + 1);
                         racc = ta1[0] + 1 < n ? nxt : 0.0;
                     } else if (act) {
@@ -331,6 +357,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
             const int64_t I = (ex1 - 1 + ta1[0] + 1) + (int64_t)Nx * ((ey + ta2[0]) + (int64_t)Ny * (ez + ta3[0]));
             if (act && ta1[0] + 1 < n) atomicAdd(&y[I], racc);
             racc = 0.0;
+            // the run's finished DOFs: lanes along x, so each add instruction
+            // covers runs of consecutive y entries
+            const int len = ex1 - ex0;
+            for (int i = lane; i < n * n * A::RUN; i += 64) {
+                const int r = i / A::RUN, e = i % A::RUN;
+                if (e < len)
+                    atomicAdd(&y[(ex0 + e) + (int64_t)Nx * ((ey + r % n) + (int64_t)Ny * (ez + r / n))], RB[i]);
+            }
         }
     }
 }
@@ -341,16 +375,20 @@ int launch_apply(const PatchDev& pd, const double* kappa, const double* u, doubl
     const int64_t runs = (int64_t)((pd.d[0].K + 31) / 32) * pd.d[1].K * pd.d[2].K;   // runs of 32 x elements
     int64_t blocks = (runs + 3) / 4;
     if (blocks > 8192) blocks = 8192;
-    const bool geo = G != nullptr;
+    const bool geo = G != nullptr, mass = alphaK == 0.0;
     switch (pd.p) {
-#define IGAF_AP(PP)                                                                                 \
-    case PP:                                                                                        \
-        if (geo)                                                                                    \
-            hipLaunchKernelGGL((k_apply<PP, true>), dim3((unsigned)blocks), dim3(256), 0, st, pd, kappa, \
-                               u, alphaM, alphaK, y, G);                                            \
-        else                                                                                        \
-            hipLaunchKernelGGL((k_apply<PP, false>), dim3((unsigned)blocks), dim3(256), 0, st, pd,   \
-                               kappa, u, alphaM, alphaK, y, nullptr);                               \
+#define IGAF_AP1(PP, GG, MM)                                                                          \
+    hipLaunchKernelGGL((k_apply<PP, GG, MM>), dim3((unsigned)blocks), dim3(256), 0, st, pd, kappa, u, alphaM, \
+                       alphaK, y, G)
+#define IGAF_AP(PP)                                                                                   \
+    case PP:                                                                                          \
+        if (geo) {                                                                                    \
+            if (mass) IGAF_AP1(PP, true, true);                                                       \
+            else IGAF_AP1(PP, true, false);                                                           \
+        } else {                                                                                      \
+            if (mass) IGAF_AP1(PP, false, true);                                                      \
+            else IGAF_AP1(PP, false, false);                                                          \
+        }                                                                                             \
         break;
         IGAF_AP(1)
         IGAF_AP(2)
@@ -358,6 +396,7 @@ int launch_apply(const PatchDev& pd, const double* kappa, const double* u, doubl
         IGAF_AP(4)
         IGAF_AP(5)
 #undef IGAF_AP
+#undef IGAF_AP1
     default:
         return -4;
     }

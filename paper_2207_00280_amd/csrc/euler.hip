@@ -239,7 +239,9 @@ int launch_mass_diag_t(const PatchDev& pd, const double* kappa, double* d, hipSt
 {
     constexpr int n3 = (P + 1) * (P + 1) * (P + 1), EPB = 256 / n3 > 0 ? 256 / n3 : 1;
     const int64_t groups = (pd.E + EPB - 1) / EPB;
-    const int64_t blocks = groups < 8192 ? groups : 8192;
+    // a workgroup per group of elements: each ends with its atomic adds, so
+    // many resident workgroups hide their latency
+    const int64_t blocks = groups < (1 << 20) ? groups : (1 << 20);
     hipLaunchKernelGGL(k_mass_diag<P>, dim3((unsigned)blocks), dim3(256), 0, st, pd, kappa, d);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
