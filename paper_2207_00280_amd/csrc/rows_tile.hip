@@ -518,7 +518,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
             const int ts = 64 * (T::WX + w - T::HW0) + lane;
             for (int t = xs; t <= X1; ++t) {
                 const bool el = t < xe;
-                const int z0 = opaque_zero_t();
+                const int z0 = 0;   // no ring here: table bases may stay in registers
                 if (el && w < T::NWZ) {
                     z_stage<T, true>(c, zt, t, kw, D, z0);
                     if (t + 1 < xe) z_load<T>(c, zt, t + 1, kw);

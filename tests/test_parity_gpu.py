@@ -86,6 +86,24 @@ def test_element_matrices(orc, ig, p, K, nonuni):
         assert em.max() <= TOL * np.abs(Me_o).max()
 
 
+@pytest.mark.parametrize("p,K", [(1, (9, 9, 8)), (3, (9, 9, 7)), (2, (9, 8, 8))])
+def test_element_matrices_single_output(orc, ig, p, K):
+    """Sum factorisation with one output requested (M only, then K only; the
+    other pointer NULL) and more elements than workgroups, not a multiple of
+    them (567-648 elements against 512 workgroups: some take two elements,
+    some one), vs the oracle."""
+    knots = [W.open_uniform_knots(k, p) for k in K]
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=300 + p)
+    plan = ig.Plan(p, K, knots)
+    Me_o, Ke_o = orc.element_matrices(P, kap)
+    kd = to_dev(kap)
+    Me, Ke, _, _ = plan.integrate_assemble(kd, want_k=False, want_csr=False)
+    assert Ke is None and relfro(to_host(Me), Me_o) <= TOL
+    Me, Ke, _, _ = plan.integrate_assemble(kd, want_m=False, want_csr=False)
+    assert Me is None and relfro(to_host(Ke), Ke_o) <= TOL
+
+
 @pytest.mark.parametrize("p,K,nonuni", CASES)
 def test_csr_assembly(orc, ig, p, K, nonuni):
     """CSR values by owner-computed rows, by FP64 atomics and by gathering the
