@@ -179,7 +179,7 @@ __device__ __forceinline__ void z_stage(const TileCtx& c, const ZThread<T>& zt, 
                                         const double (&kw)[T::P + 1][T::Q], double* D, int z0)
 {
     constexpr int P = T::P, Q = T::Q, O = T::O, S = T::S, Q2 = T::Q2, Q3 = T::Q3;
-    const int iz = c.iz0 + zt.zr + z0;   // opaque: table bases are recomputed per element
+    const int iz = c.iz0 + zt.zr + z0;   // z0 opaque (sequential): table bases recomputed per element
     const double* kcol = c.kappa + ((int64_t)ex + (int64_t)c.Kx * zt.key) * Q3 + zt.off;
     double d0[O], d1[O];
 #pragma unroll
