@@ -11,7 +11,7 @@ before the timed region; inputs are synthetic (seeded).
 The same run also times, on the same GPU: the element kernel and the CSR
 kernel alone (roofline of the dominant kernel), classical quadrature, the
 atomic assembly, the 128^3 streamed workload (p = 2, 3, 4), the 256-patch
-batched single launch against 256 separate launches (eager and
+batched launches (one per degree) against 256 separate launches (eager and
 graph-captured), the adjoint, the matrix-free operator apply and one forward
 Euler step (conjugate gradients on M) against the plain forward assembly,
 the headline mesh on a curved geometry map;

@@ -316,8 +316,10 @@ igaf_status igaf_euler_step_geo(const igaf_plan* plan, const double* cm, const d
 /* ---------------------------------------------------------------- batches
  * Many independent patches (the paper's first concurrency level: parts of
  * the mesh computed concurrently) integrated and assembled to CSR (streamed
- * mode, M and K) by ONE kernel launch over one work list: one workgroup per
- * (patch, tile of row pencils, x segment) item, items sorted longest first. */
+ * mode, M and K) from one work list by one kernel launch per degree present
+ * (each degree's tile has its own block size and LDS): one workgroup per
+ * (patch, tile of row pencils, x segment) item, items grouped by degree and
+ * sorted longest first within a degree. */
 
 /* Build per-patch plans, the device patch table and the work list
  * (synchronous; one segment per tile and 16 items per XCD chunk until
@@ -332,13 +334,14 @@ void igaf_batch_destroy(igaf_batch* batch);
 const igaf_plan* igaf_batch_plan(const igaf_batch* batch, int32_t i);
 
 /* The launch shape: family (kind of work item; 0 = a tile of row pencils,
- * the only kind), grid (workgroups of 256 threads launched, the item count
- * rounded up to whole XCD chunks), number of work items.  Any output may be
- * NULL. */
+ * the only kind), grid (workgroups launched over all degrees, each degree's
+ * item count rounded up to whole XCD chunks), number of work items.  Any
+ * output may be NULL. */
 igaf_status igaf_batch_info(const igaf_batch* batch, int32_t* family, int32_t* grid,
                             int32_t* nitems);
 
-/* One launch: for every patch i, Mval[i], Kval[i] (device [nnz_i])
+/* One launch per degree present, in order on `stream`: for every patch i,
+ * Mval[i], Kval[i] (device [nnz_i])
  * are OVERWRITTEN with the assembled mass and stiffness values for kappa[i]
  * (device [E_i][q_i^3]).  kappa, Mval, Kval are HOST arrays of npatch device
  * pointers; Mval[i] / Kval[i] may be NULL to skip that matrix.  The pointer

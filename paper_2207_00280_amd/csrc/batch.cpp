@@ -1,10 +1,12 @@
 // Batched integration + assembly of many independent patches (the paper's
-// first concurrency level: parts of the mesh computed concurrently) in ONE
-// launch.  Host side: per-patch plans, the device patch table and the work
-// list of (patch, tile, x segment) items, sorted longest first so that the
-// hardware's in-order workgroup dispatch balances the launch, and the
-// autotuner that picks the work split (segments per tile, items per XCD
-// chunk) by timing the launch on the caller's data.
+// first concurrency level: parts of the mesh computed concurrently) in one
+// launch per degree present (each with that degree's tile, whose block size
+// and LDS differ).  Host side: per-patch plans, the device patch table and
+// the work list of (patch, tile, x segment) items, grouped by degree and
+// sorted longest first within a degree so that the hardware's in-order
+// workgroup dispatch balances each launch, and the autotuner that picks the
+// work split (segments per tile, items per XCD chunk) by timing the launches
+// on the caller's data.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,15 +27,24 @@ constexpr int kMaxSplit = 8;          // x segments per tile, at most
 constexpr int kSplits[] = {1, 2, 4, 8};
 constexpr int kChunks[] = {4, 16, 64};
 constexpr int kDefaultChunk = 16;
+constexpr int kMaxDegree = 5;
 
-// Every (tile, x segment) of every patch, longest first; stable, so that the
-// tiles of one patch stay in order (neighbouring tiles share kappa and tables
-// in cache).  A patch's rows are cut into at most `split` segments of at
-// least 2(p+1) rows; a segment that does not start at row 0 sweeps p
-// warm-up elements first, which its cost includes.
-std::vector<int4> build_items(const std::vector<igaf_plan*>& plans, int split)
+// A work list: items of degree p at [off[p], off[p + 1]).
+struct WorkList {
+    std::vector<int4> items;
+    int off[kMaxDegree + 2] = {};
+};
+
+// Every (tile, x segment) of every patch, grouped by degree and longest first
+// within a degree; stable, so that the tiles of one patch stay in order
+// (neighbouring tiles share kappa and tables in cache).  A patch's rows are
+// cut into at most `split` segments of at least 2(p+1) rows; a segment that
+// does not start at row 0 sweeps p warm-up elements first, which its cost
+// includes.
+WorkList build_items(const std::vector<igaf_plan*>& plans, int split)
 {
     struct C {
+        int p;
         double cost;
         int4 it;
     };
@@ -51,14 +62,19 @@ std::vector<int4> build_items(const std::vector<igaf_plan*>& plans, int split)
                 const int X0 = sgi * seglen, X1 = std::min(Nx, X0 + seglen);
                 if (X0 >= X1) continue;
                 const double cost = per_elem * (X1 - std::max(0, X0 - pd.p));
-                all.push_back({cost, make_int4((int)i, k, sgi, seglen)});
+                all.push_back({pd.p, cost, make_int4((int)i, k, sgi, seglen)});
             }
     }
-    std::stable_sort(all.begin(), all.end(), [](const C& a, const C& b) { return a.cost > b.cost; });
-    std::vector<int4> items;
-    items.reserve(all.size());
-    for (auto& c : all) items.push_back(c.it);
-    return items;
+    std::stable_sort(all.begin(), all.end(),
+                     [](const C& a, const C& b) { return a.p != b.p ? a.p < b.p : a.cost > b.cost; });
+    WorkList w;
+    w.items.reserve(all.size());
+    for (auto& c : all) {
+        w.items.push_back(c.it);
+        ++w.off[c.p + 1];
+    }
+    for (int p = 1; p <= kMaxDegree + 1; ++p) w.off[p] += w.off[p - 1];
+    return w;
 }
 
 }  // namespace
@@ -67,6 +83,7 @@ struct igaf_batch {
     std::vector<igaf_plan*> plans;
     int device = 0;
     int nitems = 0;
+    int off[kMaxDegree + 2] = {};           // items of degree p: [off[p], off[p + 1])
     int split = 1, chunk = kDefaultChunk;   // work split in use
     double tuned_ms = 0.0;                  // its time when the autotuner chose it
     size_t cap = 0;                         // items the device list can hold
@@ -90,12 +107,13 @@ static void batch_free(igaf_batch* B)
 // may still be read by a queued launch).
 static bool set_work_list(igaf_batch* B, int split, int chunk)
 {
-    std::vector<int4> items = build_items(B->plans, split);
-    if (items.size() > B->cap) return false;
+    WorkList w = build_items(B->plans, split);
+    if (w.items.size() > B->cap) return false;
     if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(B->d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(B->d_items, w.items.data(), sizeof(int4) * w.items.size(), hipMemcpyHostToDevice) != hipSuccess)
         return false;
-    B->nitems = (int)items.size();
+    B->nitems = (int)w.items.size();
+    std::copy(std::begin(w.off), std::end(w.off), B->off);
     B->split = split;
     B->chunk = chunk;
     return true;
@@ -136,7 +154,7 @@ igaf_status igaf_batch_create(const igaf_patch_desc* descs, int32_t npatch, igaf
         batch_free(B);
         return set_error(IGAF_EDEVICE, "hipGetDevice failed");
     }
-    B->cap = std::max<size_t>(1, build_items(B->plans, kMaxSplit).size());
+    B->cap = std::max<size_t>(1, build_items(B->plans, kMaxSplit).items.size());
     bool ok = hipMalloc(&B->d_items, sizeof(int4) * B->cap) == hipSuccess &&
               hipMalloc(&B->d_patches, sizeof(BatchPatch) * npatch) == hipSuccess &&
               hipHostMalloc(&B->h_patches, sizeof(BatchPatch) * npatch, hipHostMallocDefault) == hipSuccess &&
@@ -167,7 +185,10 @@ igaf_status igaf_batch_info(const igaf_batch* B, int32_t* family, int32_t* grid,
 {
     if (!B) return set_error(IGAF_EINVAL, "batch is NULL");
     if (family) *family = 0;   // work items are tiles of row pencils
-    if (grid) *grid = rows_batch_grid(B->nitems, B->chunk);
+    if (grid) {
+        *grid = 0;
+        for (int p = 1; p <= kMaxDegree; ++p) *grid += rows_batch_grid(B->off[p + 1] - B->off[p], B->chunk);
+    }
     if (nitems) *nitems = B->nitems;
     return IGAF_OK;
 }
@@ -224,8 +245,9 @@ igaf_status igaf_batch_integrate_assemble(igaf_batch* B, const double* const* ka
     if (hipMemcpyAsync(B->d_patches, B->h_patches, sizeof(BatchPatch) * n, hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return set_error(IGAF_EDEVICE, "patch table upload failed");
-    if (launch_rows_batch(B->d_patches, B->d_items, B->nitems, B->chunk, s))
-        return set_error(IGAF_EDEVICE, "batched launch failed");
+    for (int p = kMaxDegree; p >= 1; --p)   // the costliest degrees first
+        if (launch_rows_batch(p, B->d_patches, B->d_items + B->off[p], B->off[p + 1] - B->off[p], B->chunk, s))
+            return set_error(IGAF_EDEVICE, "batched launch failed");
     return IGAF_OK;
 }
 

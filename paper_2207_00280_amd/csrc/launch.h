@@ -27,12 +27,13 @@ int launch_element(const PatchDev& pd, int method, const double* kappa, double* 
 int launch_rows(const PatchDev& pd, const double* kappa, double* Mval, double* Kval,
                 hipStream_t st);
 
-// Batched CSR rows: one workgroup per (patch, tile, x segment, segment
-// length) item of `items`, which the host sorts longest first, `chunk`
-// consecutive items per XCD; rows_batch_grid is the launch's workgroup
-// count, rows_tile_info the tiles of a patch and the relative cost of one
-// element step of a tile.
-int launch_rows_batch(const BatchPatch* patches, const int4* items, int nitems, int chunk, hipStream_t st);
+// Batched CSR rows of the degree-p patches: one workgroup per (patch, tile,
+// x segment, segment length) item of `items` (all of degree p), which the
+// host sorts longest first, `chunk` consecutive items per XCD;
+// rows_batch_grid is the launch's workgroup count, rows_tile_info the tiles
+// of a patch and the relative cost of one element step of a tile.
+int launch_rows_batch(int p, const BatchPatch* patches, const int4* items, int nitems, int chunk,
+                      hipStream_t st);
 int rows_batch_grid(int nitems, int chunk);
 int rows_tile_info(int p, int Ny, int Nz, int* ntile, double* per_elem);
 

@@ -122,15 +122,6 @@ template <> struct TileCfg<3> { using T = Tile<3, 2, 2, 4, false, true>; };
 template <> struct TileCfg<4> { using T = Tile<4, 2, 2, 2, true, true>; };
 template <> struct TileCfg<5> { using T = Tile<5, 2, 1, 2, false, true>; };
 
-// The batched kernel runs every degree's tile with the same 256 threads: the
-// sequential schedule.
-template <int P> struct BatchCfg;
-template <> struct BatchCfg<1> { using T = Tile<1, 4, 4, 2, true, false>; };
-template <> struct BatchCfg<2> { using T = Tile<2, 4, 2, 2, true, false>; };
-template <> struct BatchCfg<3> { using T = Tile<3, 2, 2, 2, false, false>; };
-template <> struct BatchCfg<4> { using T = Tile<4, 3, 1, 2, true, false>; };
-template <> struct BatchCfg<5> { using T = Tile<5, 2, 1, 2, false, false>; };
-
 // Per-workgroup constants of one tile.
 struct TileCtx {
     const double* kappa;
@@ -624,18 +615,10 @@ int launch_rows(const PatchDev& pd, const double* kappa, double* Mv, double* Kv,
 }
 
 // ---------------------------------------------------------------------------
-// Batched launch: one workgroup per work item (patch, tile, x segment) of a
-// list sorted longest first; every degree's tile is one workgroup of 256
-// threads, so one kernel runs any of them.  An item sweeps the rows of its
-// pencils in its x segment (after p warm-up elements when it does not start
-// at the patch boundary).
-
-template <int P> using TileOf = typename BatchCfg<P>::T;
-static_assert(TileOf<1>::NT == 256 && TileOf<2>::NT == 256 && TileOf<3>::NT == 256 &&
-                  TileOf<4>::NT == 256 && TileOf<5>::NT == 256,
-              "the batched kernel runs every degree's tile with 256 threads");
-constexpr int kBatchLds = cmax(cmax(cmax(TileOf<1>::LDS, TileOf<2>::LDS), cmax(TileOf<3>::LDS, TileOf<4>::LDS)),
-                               TileOf<5>::LDS);
+// Batched launch: one launch per degree present, each with that degree's
+// tile, one workgroup per work item (patch, tile, x segment) of a list sorted
+// longest first.  An item sweeps the rows of its pencils in its x segment
+// (after p warm-up elements when it does not start at the patch boundary).
 
 template <class Tp>
 __device__ inline Tp uniform_ptr(Tp p)
@@ -667,16 +650,17 @@ __device__ inline void uniform_patch(const BatchPatch& src, PatchDev& pd, RowMap
     Kv = uniform_ptr(src.Kv);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rows_tile_batch(
+template <class T>
+__global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE))) void k_rows_tile_items(
     const BatchPatch* __restrict__ patches, const int4* __restrict__ items, int nitems, int chunk)
 {
-    __shared__ double lds[kBatchLds];
+    __shared__ double lds[T::LDS];
     // XCD x (which receives workgroups b = x mod 8) takes the item chunks
     // x, x+8, x+16, ...: neighbouring tiles share its L2, and the list stays
     // longest-first on every XCD
     const int x = blockIdx.x % 8, j = blockIdx.x / 8;
     const int b = ((j / chunk) * 8 + x) * chunk + j % chunk;
-    if (b >= nitems) return;
+    if (b >= nitems) return;   // whole workgroup
     const int4 it = items[b];
     const int pid = uniform_int(it.x), tile = uniform_int(it.y);
     const int seg = uniform_int(it.z), seglen = uniform_int(it.w);
@@ -685,31 +669,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const double* kappa;
     double *Mv, *Kv;
     uniform_patch(patches[pid], pd, rm, kappa, Mv, Kv);
-    const int Ny = pd.d[1].N;
-    switch (pd.p) {
-#define IGAF_TB(PP)                                                                                 \
-    case PP:                                                                                        \
-        tile_run<TileOf<PP>>(pd, rm, kappa, Mv, Kv, tile, seg, (Ny + TileOf<PP>::TY - 1) / TileOf<PP>::TY, \
-                             seglen, lds);                                                          \
-        break;
-        IGAF_TB(1)
-        IGAF_TB(2)
-        IGAF_TB(3)
-        IGAF_TB(4)
-        IGAF_TB(5)
-#undef IGAF_TB
-    default:
-        break;
-    }
+    tile_run<T>(pd, rm, kappa, Mv, Kv, tile, seg, (pd.d[1].N + T::TY - 1) / T::TY, seglen, lds);
 }
 
-int launch_rows_batch(const BatchPatch* patches, const int4* items, int nitems, int chunk, hipStream_t st)
+template <class T>
+static int launch_items_t(const BatchPatch* patches, const int4* items, int nitems, int chunk, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rows_tile_items<T>, dim3(rows_batch_grid(nitems, chunk)), dim3(T::NT), 0, st, patches,
+                       items, nitems, chunk);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_rows_batch(int p, const BatchPatch* patches, const int4* items, int nitems, int chunk,
+                      hipStream_t st)
 {
     if (nitems <= 0) return 0;
     if (chunk < 1) return -4;
-    hipLaunchKernelGGL(k_rows_tile_batch, dim3(rows_batch_grid(nitems, chunk)), dim3(256), 0, st, patches,
-                       items, nitems, chunk);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+    switch (p) {
+    case 1: return launch_items_t<TileCfg<1>::T>(patches, items, nitems, chunk, st);
+    case 2: return launch_items_t<TileCfg<2>::T>(patches, items, nitems, chunk, st);
+    case 3: return launch_items_t<TileCfg<3>::T>(patches, items, nitems, chunk, st);
+    case 4: return launch_items_t<TileCfg<4>::T>(patches, items, nitems, chunk, st);
+    case 5: return launch_items_t<TileCfg<5>::T>(patches, items, nitems, chunk, st);
+    default: return -4;
+    }
 }
 
 int rows_batch_grid(int nitems, int chunk)
@@ -719,8 +702,8 @@ int rows_batch_grid(int nitems, int chunk)
 
 // Tiles of a degree-p patch and the relative cost of one element step of a
 // tile: fused-multiply-add issue slots of its wavefronts per x element (an
-// item costs this times the elements it sweeps).  Used to sort the batch
-// longest first.
+// item costs this times the elements it sweeps).  Used to sort each degree's
+// items longest first.
 template <class T>
 static void tile_info_t(int Ny, int Nz, int* ntile, double* per_elem)
 {
@@ -732,11 +715,11 @@ static void tile_info_t(int Ny, int Nz, int* ntile, double* per_elem)
 int rows_tile_info(int p, int Ny, int Nz, int* ntile, double* per_elem)
 {
     switch (p) {
-    case 1: tile_info_t<TileOf<1>>(Ny, Nz, ntile, per_elem); return 0;
-    case 2: tile_info_t<TileOf<2>>(Ny, Nz, ntile, per_elem); return 0;
-    case 3: tile_info_t<TileOf<3>>(Ny, Nz, ntile, per_elem); return 0;
-    case 4: tile_info_t<TileOf<4>>(Ny, Nz, ntile, per_elem); return 0;
-    case 5: tile_info_t<TileOf<5>>(Ny, Nz, ntile, per_elem); return 0;
+    case 1: tile_info_t<TileCfg<1>::T>(Ny, Nz, ntile, per_elem); return 0;
+    case 2: tile_info_t<TileCfg<2>::T>(Ny, Nz, ntile, per_elem); return 0;
+    case 3: tile_info_t<TileCfg<3>::T>(Ny, Nz, ntile, per_elem); return 0;
+    case 4: tile_info_t<TileCfg<4>::T>(Ny, Nz, ntile, per_elem); return 0;
+    case 5: tile_info_t<TileCfg<5>::T>(Ny, Nz, ntile, per_elem); return 0;
     default: return -4;
     }
 }

@@ -1,5 +1,6 @@
 """Batched launch (igaf_batch_integrate_assemble): many independent
-patches of uneven sizes and degrees in one launch.
+patches of uneven sizes and degrees from one work list (one launch per
+degree).
 
 Checked against the oracle (small patches, every CSR value), against the
 per-patch launches (the 256-patch workload, every value), and under HIP graph
@@ -38,7 +39,7 @@ def _small_specs(seed):
 
 def test_batch_small_vs_oracle(orc, ig):
     """12 seeded patches (p = 1..5, K_d = 1..5 (1..3 at p >= 4), uniform and non-uniform knots)
-    in one launch, every CSR value vs the oracle's assembly."""
+    in one batched call, every CSR value vs the oracle's assembly."""
     import torch
 
     specs = _small_specs(3)
