@@ -29,8 +29,9 @@
 // Two schedules run these stages.  Sequential: every wavefront takes part in
 // each stage in turn, four workgroup barriers per element.  Pipelined: stage-z/y
 // wavefronts compute element ex (kappa of ex+1 already in their registers)
-// while stage-x wavefronts finish and store row ex-1, with C double-buffered
-// and two barriers per element; the two roles run separate loops, so the
+// while stage-x wavefronts finish and store row ex-1, with one C buffer
+// (stage y rewrites it only after the barrier that ends stage x's reads of
+// it) and two barriers per element; the two roles run separate loops, so the
 // register ring and the kappa prefetch never share a wavefront's registers.
 // Stages z and y use wave-uniform tables (scalar loads); stage x's tables
 // depend on ix only.  o* in [0, 2p] are column offsets j = i + o - p.
@@ -105,10 +106,11 @@ struct Tile {
     static constexpr int SIT = (O * O * O + NTS - 1) / NTS;   // store passes per row
     static constexpr int SGP = PIPE ? NPEN : 1;         // pencils whose LDS reads go out together
     // LDS (doubles).  Sequential: [D | staged rows] [C]; the rows reuse D,
-    // dead after stage y.  Pipelined: [D] [C0] [C1] [staged rows].
+    // dead after stage y.  Pipelined: [D] [C] [staged rows]; one C suffices:
+    // stage y writes it after the barrier that follows the stage-x reads.
     static constexpr int OFF_C = PIPE ? DSZ : cmax(DSZ, SSZ);
-    static constexpr int OFF_S = PIPE ? DSZ + 2 * CSZ : 0;
-    static constexpr int LDS = PIPE ? DSZ + 2 * CSZ + SSZ : cmax(DSZ, SSZ) + CSZ;
+    static constexpr int OFF_S = PIPE ? DSZ + CSZ : 0;
+    static constexpr int LDS = PIPE ? DSZ + CSZ + SSZ : cmax(DSZ, SSZ) + CSZ;
     static_assert(NW <= 16, "workgroup too large");
 };
 
@@ -120,7 +122,7 @@ template <> struct TileCfg<1> { using T = Tile<1, 4, 4, 4, true, false>; };
 template <> struct TileCfg<2> { using T = Tile<2, 4, 2, 4, true, true>; };
 template <> struct TileCfg<3> { using T = Tile<3, 2, 2, 4, false, true>; };
 template <> struct TileCfg<4> { using T = Tile<4, 2, 2, 2, true, true>; };
-template <> struct TileCfg<5> { using T = Tile<5, 2, 1, 2, false, true>; };
+template <> struct TileCfg<5> { using T = Tile<5, 3, 1, 2, false, true>; };
 
 // Per-workgroup constants of one tile.
 struct TileCtx {
@@ -516,7 +518,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
                 }
                 __syncthreads();
                 if (w < T::NWY) {
-                    if (el) y_stage<T>(c, w, lane, D, C0 + (t & 1) * T::CSZ, z0);
+                    if (el) y_stage<T>(c, w, lane, D, C0, z0);
                 } else if (w >= T::HW0 && t - 1 >= X0) {
                     store_row<T>(c, STG, t - 1, ts, pbase, plen);
                 }
@@ -537,7 +539,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
                 const int r = t - 1;   // row finished in this iteration
                 const bool live = r >= xs, emit = r >= X0;
                 if (live) {
-                    x_shift<T>(xt, ring, r < xe ? C0 + (r & 1) * T::CSZ : nullptr);
+                    x_shift<T>(xt, ring, r < xe ? C0 : nullptr);
                     if (emit) x_row<T>(c, xt, ring, r, STG);
                 }
                 __syncthreads();
