@@ -586,12 +586,15 @@ static int launch_rows_tile_t(const PatchDev& pd, const double* kappa, double* M
             return -3;
         slots = ncu * (per > 0 ? per : 1);
     }
+    // cost in element steps: the items spread over the slots, plus one item
+    // as the tail; a segment pays ~4p/3 steps of warm-up and start-up (fitted
+    // to sweeps of the segment count at 64^3 and 128^3)
     int nseg = 1;
     double best = 1e300;
     for (int s = 1; s <= 16 && (Nx + s - 1) / s >= 2 * T::P + 2; ++s) {
         const int64_t items = (int64_t)ntile * s;
-        const double rounds = (double)((items + slots - 1) / slots);
-        const double cost = rounds * ((Nx + s - 1) / s + 0.5 * T::P);
+        const double item = (Nx + s - 1) / s + 4.0 * T::P / 3.0;
+        const double cost = (double)items * item / slots + item;
         if (cost < best - 1e-9) {
             best = cost;
             nseg = s;
