@@ -68,6 +68,11 @@ struct AdjShape {
     static constexpr int YA3 = apad16(Q2, Q), YF = n * YA3, YG = 3 * YF;
     static constexpr int WS = amax(G * XG, G * YG);               // doubles per wavefront
     static constexpr int RUN = 32;                                // elements per x-run
+    // the x value / derivative tables of one group ([g][a][k], G n Q <= 64
+    // values each), staged in LDS: one load per lane and table per group,
+    // issued a group ahead
+    static constexpr int TBN = G * n * Q;
+    static_assert(TBN <= 64, "one table value per lane");
 };
 
 // GEO: a mapped geometry; the point value takes the geometry factors cm0
@@ -79,9 +84,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 {
     using A = AdjShape<P>;
     constexpr int n = A::n, Q = A::Q, Q2 = A::Q2, Q3 = A::Q3, G = A::G, NXP = A::NXP;
-    __shared__ double lds[4][A::WS];
+    __shared__ double lds[4][A::WS + 128];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
     double* const B = lds[w];
+    double* const TB = lds[w] + A::WS;   // [Nv | dN] of the group's elements
     const int Kx = pd.d[0].K, Ky = pd.d[1].K, Kz = pd.d[2].K;
     const int Nx = pd.d[0].N, Ny = pd.d[1].N;
     const double* __restrict__ Nvx = pd.d[0].Nv;
@@ -128,8 +134,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                 vw[ps][a1] = v[g0[ps] + ex0 + a1];
             }
         }
+        // x tables of the group starting at element exg, this lane's value
+        const int64_t tlast = (int64_t)Kx * n * Q - 1;
+        double tnv = Nvx[min((int64_t)ex0 * n * Q + lane, tlast)];
+        double tdn = dNx[min((int64_t)ex0 * n * Q + lane, tlast)];
         for (int exg = ex0; exg < ex1; exg += G) {
             const int ng = min(G, ex1 - exg);   // elements in this group
+            TB[lane] = tnv;
+            TB[64 + lane] = tdn;
+            adj_wave_sync();
+            if (exg + G < ex1) {   // the next group's tables, a group ahead
+                tnv = Nvx[min((int64_t)(exg + G) * n * Q + lane, tlast)];
+                tdn = dNx[min((int64_t)(exg + G) * n * Q + lane, tlast)];
+            }
 
             double ur[4][Q];                    // u, du/dx, du/dy, du/dz at this lane's points
             // field f = 0: u, f = 1: v
@@ -150,9 +167,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
                         for (int a1 = 0; a1 < n; ++a1) {
                             const double c = f == 0 ? uw[ps][a1] : vw[ps][a1];
-                            const int64_t t = ((int64_t)ex * n + a1) * Q + xkx[ps];
-                            s0 += c * Nvx[t];
-                            s1 += c * dNx[t];
+                            const int t = (g * n + a1) * Q + xkx[ps];
+                            s0 += c * TB[t];
+                            s1 += c * TB[64 + t];
                         }
                         if (act) {
                             double* xp = B + g * A::XG + xa3[ps] * A::XA3 + xa2[ps] * Q + xkx[ps];

@@ -70,6 +70,11 @@ struct ApplyShape {
     // p <= 3: the run's finished DOF values, [a2 + n a3][ex - ex0], added to
     // y in one pass at the end of the run
     static constexpr int RB = NXP == 1 ? RUN * n * n : 0;
+    // the x value / derivative tables of one group ([g][a][k], G n Q <= 64
+    // values each), staged in LDS: one load per lane and table per group,
+    // issued a group ahead
+    static constexpr int TBN = G * n * Q;
+    static_assert(TBN <= 64, "one table value per lane");
 };
 
 // GEO: a mapped geometry; `kappa` is the mass coefficient cm and Gt
@@ -83,10 +88,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 {
     using A = ApplyShape<P>;
     constexpr int n = A::n, Q = A::Q, Q2 = A::Q2, Q3 = A::Q3, G = A::G, NXP = A::NXP;
-    __shared__ double lds[4][A::WS + A::RB];
+    __shared__ double lds[4][A::WS + A::RB + 128];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
     double* const B = lds[w];
     double* const RB = lds[w] + A::WS;
+    double* const TB = lds[w] + A::WS + A::RB;   // [Nv | dN] of the group's elements
     const int Kx = pd.d[0].K, Ky = pd.d[1].K, Kz = pd.d[2].K;
     const int Nx = pd.d[0].N, Ny = pd.d[1].N;
     const double* __restrict__ Nvx = pd.d[0].Nv;
@@ -136,8 +142,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
             for (int a1 = 0; a1 < n; ++a1) uw[ps][a1] = u[g0[ps] + ex0 + a1];
         }
+        // x tables of the group starting at element exg, this lane's value
+        const int64_t tlast = (int64_t)Kx * n * Q - 1;
+        double tnv = Nvx[min((int64_t)ex0 * n * Q + lane, tlast)];
+        double tdn = MASS ? 0.0 : dNx[min((int64_t)ex0 * n * Q + lane, tlast)];
         for (int exg = ex0; exg < ex1; exg += G) {
             const int ng = min(G, ex1 - exg);   // elements in this group
+            TB[lane] = tnv;
+            TB[64 + lane] = tdn;
+            ap_wave_sync();
+            if (exg + G < ex1) {   // the next group's tables, a group ahead
+                tnv = Nvx[min((int64_t)(exg + G) * n * Q + lane, tlast)];
+                if constexpr (!MASS) tdn = dNx[min((int64_t)(exg + G) * n * Q + lane, tlast)];
+            }
             // ---- stage x, one element of the group at a time
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -149,9 +166,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
                     for (int a1 = 0; a1 < n; ++a1) {
-                        const int64_t t = ((int64_t)ex * n + a1) * Q + xkx[ps];
-                        s0 += uw[ps][a1] * Nvx[t];
-                        if constexpr (!MASS) s1 += uw[ps][a1] * dNx[t];
+                        const int t = (g * n + a1) * Q + xkx[ps];
+                        s0 += uw[ps][a1] * TB[t];
+                        if constexpr (!MASS) s1 += uw[ps][a1] * TB[64 + t];
                     }
                     if (act) {
                         double* xp = B + g * A::XG + xa3[ps] * A::XA3 + xa2[ps] * Q + xkx[ps];
@@ -327,9 +344,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                     double acc = 0.0;
 #pragma unroll
                     for (int kx = 0; kx < Q; ++kx) {
-                        const int64_t t = ((int64_t)ex * n + ta1[ps]) * Q + kx;
-                        acc += Nvx[t] * rp[kx];
-                        if constexpr (!MASS) acc += dNx[t] * rp[A::XF + kx];
+                        const int t = (g * n + ta1[ps]) * Q + kx;
+                        acc += TB[t] * rp[kx];
+                        if constexpr (!MASS) acc += TB[64 + t] * rp[A::XF + kx];
                     }
                     const int64_t I = (ex + ta1[ps]) + (int64_t)Nx * ((ey + ta2[ps]) + (int64_t)Ny * (ez + ta3[ps]));
                     if constexpr (NXP == 1) {
