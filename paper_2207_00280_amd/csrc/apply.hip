@@ -146,8 +146,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
         const int64_t tlast = (int64_t)Kx * n * Q - 1;
         double tnv = Nvx[min((int64_t)ex0 * n * Q + lane, tlast)];
         double tdn = MASS ? 0.0 : dNx[min((int64_t)ex0 * n * Q + lane, tlast)];
+        // the u values a group shifts into the window (x = exg + n + g), also
+        // loaded a group ahead
+        double unx[NXP][G];
+#pragma unroll
+        for (int ps = 0; ps < NXP; ++ps)
+#pragma unroll
+            for (int g = 0; g < G; ++g) unx[ps][g] = u[g0[ps] + min(ex0 + n + g, Nx - 1)];
+        const int64_t krow = (int64_t)Kx * (ey + (int64_t)Ky * ez);
         for (int exg = ex0; exg < ex1; exg += G) {
             const int ng = min(G, ex1 - exg);   // elements in this group
+            // this lane's kappa (every kz) and x weight for stage z, loaded at
+            // the group's start (a group ahead cost more in registers than it
+            // hid)
+            const int exz = exg + min(zg, ng - 1);
+            double kc[Q];
+            {
+                const double* kp = kappa + (exz + krow) * Q3 + zky * Q + zkx;
+#pragma unroll
+                for (int kz = 0; kz < Q; ++kz) kc[kz] = kp[kz * Q2];
+            }
+            const double wxc = wqx[(int64_t)exz * Q + zkx];
+            double ucur[NXP][G];
+#pragma unroll
+            for (int ps = 0; ps < NXP; ++ps)
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    ucur[ps][g] = unx[ps][g];
+                    unx[ps][g] = u[g0[ps] + min(exg + G + n + g, Nx - 1)];
+                }
             TB[lane] = tnv;
             TB[64 + lane] = tdn;
             ap_wave_sync();
@@ -177,7 +204,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                     }
 #pragma unroll
                     for (int a1 = 0; a1 + 1 < n; ++a1) uw[ps][a1] = uw[ps][a1 + 1];
-                    uw[ps][n - 1] = u[g0[ps] + min(ex + n, Nx - 1)];
+                    uw[ps][n - 1] = ucur[ps][g];
                 }
             }
             ap_wave_sync();
@@ -229,9 +256,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                     y1[a3] = MASS ? 0.0 : yp[A::YF + a3 * A::YA3];
                     y2[a3] = MASS ? 0.0 : yp[2 * A::YF + a3 * A::YA3];
                 }
-                const int exz = exg + min(zg, ng - 1);
-                const double wxy = wqx[(int64_t)exz * Q + zkx] * wyl;
-                const double* kp = kappa + (exz + (int64_t)Kx * (ey + (int64_t)Ky * ez)) * Q3 + zky * Q + zkx;
+                const double wxy = wxc * wyl;
                 double s0[n], s1[n], s2[n];   // transposed stage z: [a3]
 #pragma unroll
                 for (int a3 = 0; a3 < n; ++a3) s0[a3] = s1[a3] = s2[a3] = 0.0;
@@ -251,8 +276,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                     double t0, t1, t2, t3;
                     if constexpr (MASS) {
                         // the same products, in the same order, as the full forms below
-                        if constexpr (GEO) t0 = alphaM * kp[kz * Q2] * (wxy * wz_[kz]) * h;
-                        else t0 = alphaM * (kp[kz * Q2] * wxy * wz_[kz]) * h;
+                        if constexpr (GEO) t0 = alphaM * kc[kz] * (wxy * wz_[kz]) * h;
+                        else t0 = alphaM * (kc[kz] * wxy * wz_[kz]) * h;
                         t1 = t2 = t3 = 0.0;
                     } else if constexpr (GEO) {
                         const double wk = wxy * wz_[kz];
@@ -260,12 +285,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                                           zky * Q + zkx;
                         const double gxx = g[0], gyy = g[Q3], gzz = g[2 * Q3];
                         const double gxy = g[3 * Q3], gxz = g[4 * Q3], gyz = g[5 * Q3];
-                        t0 = alphaM * kp[kz * Q2] * wk * h;
+                        t0 = alphaM * kc[kz] * wk * h;
                         t1 = alphaK * wk * (gxx * dx + gxy * dy + gxz * dz);
                         t2 = alphaK * wk * (gxy * dx + gyy * dy + gyz * dz);
                         t3 = alphaK * wk * (gxz * dx + gyz * dy + gzz * dz);
                     } else {
-                        const double c = kp[kz * Q2] * wxy * wz_[kz];
+                        const double c = kc[kz] * wxy * wz_[kz];
                         t0 = alphaM * c * h;
                         t1 = alphaK * c * dx;
                         t2 = alphaK * c * dy;
