@@ -194,43 +194,84 @@ __global__ __launch_bounds__(256) void k_scale(double* __restrict__ z, const dou
 // per line, forward then backward substitution over the line's N values with
 // the banded factor (p sub-diagonals) kept as [1/L_ii, L_{i,i-1..i-p}, M_ii].
 // Line t starts at (t % inner) + (t / inner) inner N and steps by `inner`
-// (inner = 1, Nx, Nx Ny for x, y, z).
+// (inner = 1, Nx, Nx Ny for x, y, z).  The substitution is serial along the
+// line, so the line's values are read kLineChunk at a time, one chunk ahead of the
+// arithmetic: each load then overlaps a chunk of steps instead of one.
+constexpr int kLineChunk = 8;
+
 template <int P>
-__global__ __launch_bounds__(256) void k_line_solve(double* __restrict__ v, const double* __restrict__ Lm,
-                                                    int N, int64_t nlines, int64_t inner)
+__global__ __launch_bounds__(64) void k_line_solve(double* __restrict__ v, const double* __restrict__ Lm,
+                                                   int N, int64_t nlines, int64_t inner)
 {
-    constexpr int W = P + 2;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    constexpr int W = P + 2, LSD = kLineChunk;
+    const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (t >= nlines) return;
     double* line = v + (t % inner) + (t / inner) * inner * N;
+    const int nch = (N + LSD - 1) / LSD;
+    double cur[LSD], nxt[LSD];
     double ring[P];   // forward: y_{i-1-j}; backward: x_{i+1+j}
+    // forward substitution, chunks in increasing i
+#pragma unroll
+    for (int j = 0; j < LSD; ++j) cur[j] = j < N ? line[(int64_t)j * inner] : 0.0;
 #pragma unroll
     for (int j = 0; j < P; ++j) ring[j] = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const double* l = Lm + (int64_t)i * W;
-        double s = line[(int64_t)i * inner];
+    for (int c = 0; c < nch; ++c) {
+        const int i0 = c * LSD;
 #pragma unroll
-        for (int k = 1; k <= P; ++k) s -= l[k] * ring[k - 1];
-        s *= l[0];
-#pragma unroll
-        for (int j = P - 1; j > 0; --j) ring[j] = ring[j - 1];
-        ring[0] = s;
-        line[(int64_t)i * inner] = s;
-    }
-#pragma unroll
-    for (int j = 0; j < P; ++j) ring[j] = 0.0;
-    for (int i = N - 1; i >= 0; --i) {
-        double s = line[(int64_t)i * inner];
-#pragma unroll
-        for (int k = 1; k <= P; ++k) {
-            const int r = i + k < N ? i + k : N - 1;   // past the end the ring holds 0
-            s -= Lm[(int64_t)r * W + k] * ring[k - 1];
+        for (int j = 0; j < LSD; ++j) {
+            const int i = i0 + LSD + j;
+            nxt[j] = i < N ? line[(int64_t)i * inner] : 0.0;
         }
-        s *= Lm[(int64_t)i * W];
 #pragma unroll
-        for (int j = P - 1; j > 0; --j) ring[j] = ring[j - 1];
-        ring[0] = s;
-        line[(int64_t)i * inner] = s;
+        for (int j = 0; j < LSD; ++j) {
+            const int i = i0 + j;
+            if (i < N) {
+                const double* l = Lm + (int64_t)i * W;
+                double s = cur[j];
+#pragma unroll
+                for (int k = 1; k <= P; ++k) s -= l[k] * ring[k - 1];
+                s *= l[0];
+#pragma unroll
+                for (int q = P - 1; q > 0; --q) ring[q] = ring[q - 1];
+                ring[0] = s;
+                line[(int64_t)i * inner] = s;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < LSD; ++j) cur[j] = nxt[j];
+    }
+    // backward substitution, chunks in decreasing i; chunk c holds
+    // i = N-1-c LSD-j, j = 0..LSD-1
+#pragma unroll
+    for (int j = 0; j < LSD; ++j) cur[j] = N - 1 - j >= 0 ? line[(int64_t)(N - 1 - j) * inner] : 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) ring[j] = 0.0;
+    for (int c = 0; c < nch; ++c) {
+        const int i0 = N - 1 - c * LSD;
+#pragma unroll
+        for (int j = 0; j < LSD; ++j) {
+            const int i = i0 - LSD - j;
+            nxt[j] = i >= 0 ? line[(int64_t)i * inner] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < LSD; ++j) {
+            const int i = i0 - j;
+            if (i >= 0) {
+                double s = cur[j];
+#pragma unroll
+                for (int k = 1; k <= P; ++k) {
+                    const int r = i + k < N ? i + k : N - 1;   // past the end the ring holds 0
+                    s -= Lm[(int64_t)r * W + k] * ring[k - 1];
+                }
+                s *= Lm[(int64_t)i * W];
+#pragma unroll
+                for (int q = P - 1; q > 0; --q) ring[q] = ring[q - 1];
+                ring[0] = s;
+                line[(int64_t)i * inner] = s;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < LSD; ++j) cur[j] = nxt[j];
     }
 }
 
@@ -253,7 +294,7 @@ int launch_line_solves_t(const PatchDev& pd, double* v, int64_t ndof, hipStream_
     for (int a = 0; a < 3; ++a) {
         const int N = pd.d[a].N;
         const int64_t nlines = ndof / N;
-        hipLaunchKernelGGL(k_line_solve<P>, dim3((unsigned)((nlines + 255) / 256)), dim3(256), 0, st, v,
+        hipLaunchKernelGGL(k_line_solve<P>, dim3((unsigned)((nlines + 63) / 64)), dim3(64), 0, st, v,
                            pd.d[a].Lm, N, nlines, inner);
         inner *= N;
     }
