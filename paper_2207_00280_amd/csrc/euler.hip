@@ -119,53 +119,71 @@ int dot(const double* a, const double* c, int64_t n, double* partial, double* S,
 }
 
 // d[I] += sum over the elements carrying I of sum_q w_q kappa_q phi_I(x_q)^2
-// (the diagonal of M(kappa)); a workgroup takes EPB = 256 / n^3 elements at a
-// time (at least one), a thread per local function, the q^3 sum taken one
-// direction at a time.
+// (the diagonal of M(kappa)).  A workgroup takes a run of up to XR elements
+// along x in one (ey, ez) row, a thread per (element, local function) pair,
+// the q^3 sum taken one direction at a time; the run's contributions are
+// summed in LDS (neighbouring elements share p of their n DOF columns) and
+// each DOF the run touches gets one atomic add: (XR + p) n^2 instead of
+// XR n^3.
+template <int P>
+struct DiagRun {
+    static constexpr int n = P + 1, Q = P + 1, n2 = n * n, n3 = n2 * n, Q3 = Q * Q * Q;
+    static constexpr int XR = 256 / n3 >= 4 ? 4 * (256 / n3) : 4;   // elements per run
+};
+
 template <int P>
 __global__ __launch_bounds__(256) void k_mass_diag(PatchDev pd, const double* __restrict__ kappa,
                                                    double* __restrict__ d)
 {
-    constexpr int n = P + 1, Q = P + 1, n3 = n * n * n, Q3 = Q * Q * Q;
-    constexpr int EPB = 256 / n3 > 0 ? 256 / n3 : 1;
-    __shared__ double kap[EPB][Q3];
-    __shared__ double sq[EPB][3][n * Q];   // w N_a^2 per direction, [a][k]
+    using R = DiagRun<P>;
+    constexpr int n = R::n, Q = R::Q, n2 = R::n2, n3 = R::n3, Q3 = R::Q3, XR = R::XR;
+    __shared__ double kap[XR][Q3];
+    __shared__ double sq[XR + 2][n * Q];   // w N_a^2: x tables of the run's elements, then y, z
+    __shared__ double acc[(XR + P) * n2];  // [ex - ex0 + a1][a2 + n a3]
     const int tid = threadIdx.x;
     const int Kx = pd.d[0].K, Ky = pd.d[1].K, Nx = pd.d[0].N, Ny = pd.d[1].N;
-    for (int64_t eb = (int64_t)blockIdx.x * EPB; eb < pd.E; eb += (int64_t)gridDim.x * EPB) {
-        for (int i = tid; i < EPB * Q3; i += 256) {
-            const int64_t e = eb + i / Q3;
-            kap[i / Q3][i % Q3] = e < pd.E ? kappa[e * Q3 + i % Q3] : 0.0;
+    const int nch = (Kx + XR - 1) / XR;
+    const int64_t nruns = (int64_t)nch * Ky * pd.d[2].K;
+    for (int64_t run = blockIdx.x; run < nruns; run += gridDim.x) {
+        const int ch = (int)(run % nch);
+        const int ey = (int)((run / nch) % Ky), ez = (int)(run / ((int64_t)nch * Ky));
+        const int ex0 = ch * XR, len = min(XR, Kx - ex0);
+        const int64_t e0 = ex0 + (int64_t)Kx * (ey + (int64_t)Ky * ez);   // the run's elements: e0 + s
+        for (int i = tid; i < XR * Q3; i += 256) {
+            const int sidx = i / Q3;
+            kap[sidx][i % Q3] = sidx < len ? kappa[(e0 + sidx) * Q3 + i % Q3] : 0.0;
         }
-        for (int i = tid; i < EPB * 3 * n * Q; i += 256) {
-            const int sub = i / (3 * n * Q), j = i % (3 * n * Q);
-            const int64_t e = eb + sub < pd.E ? eb + sub : pd.E - 1;
-            const int ex = (int)(e % Kx), ey = (int)((e / Kx) % Ky), ez = (int)(e / ((int64_t)Kx * Ky));
-            const int dd = j / (n * Q), r = j % (n * Q);
-            const int ed = dd == 0 ? ex : (dd == 1 ? ey : ez);
+        for (int i = tid; i < (XR + 2) * n * Q; i += 256) {
+            const int tb = i / (n * Q), r = i % (n * Q);
+            const int dd = tb < XR ? 0 : tb - XR + 1;
+            const int ed = dd == 0 ? min(ex0 + tb, Kx - 1) : (dd == 1 ? ey : ez);
             const double v = pd.d[dd].Nv[(int64_t)ed * n * Q + r];
-            sq[sub][dd][r] = pd.d[dd].wq[(int64_t)ed * Q + r % Q] * v * v;
+            sq[tb][r] = pd.d[dd].wq[(int64_t)ed * Q + r % Q] * v * v;
         }
+        for (int i = tid; i < (XR + P) * n2; i += 256) acc[i] = 0.0;
         __syncthreads();
-        const int sub = tid / n3, l = tid % n3;
-        const int64_t e = eb + sub;
-        if (sub < EPB && e < pd.E) {
-            const int ex = (int)(e % Kx), ey = (int)((e / Kx) % Ky), ez = (int)(e / ((int64_t)Kx * Ky));
-            const int a1 = l % n, a2 = (l / n) % n, a3 = l / (n * n);
-            double s = 0.0;
+        for (int i = tid; i < len * n3; i += 256) {
+            const int sidx = i / n3, l = i % n3;
+            const int a1 = l % n, a2 = (l / n) % n, a3 = l / n2;
+            double sum = 0.0;
             for (int kz = 0; kz < Q; ++kz) {
                 double sy = 0.0;
                 for (int ky = 0; ky < Q; ++ky) {
                     double sx = 0.0;
 #pragma unroll
-                    for (int kx = 0; kx < Q; ++kx) sx += sq[sub][0][a1 * Q + kx] * kap[sub][kx + Q * (ky + Q * kz)];
-                    sy += sq[sub][1][a2 * Q + ky] * sx;
+                    for (int kx = 0; kx < Q; ++kx) sx += sq[sidx][a1 * Q + kx] * kap[sidx][kx + Q * (ky + Q * kz)];
+                    sy += sq[XR][a2 * Q + ky] * sx;
                 }
-                s += sq[sub][2][a3 * Q + kz] * sy;
+                sum += sq[XR + 1][a3 * Q + kz] * sy;
             }
-            atomicAdd(&d[(ex + a1) + (int64_t)Nx * ((ey + a2) + (int64_t)Ny * (ez + a3))], s);
+            atomicAdd(&acc[(sidx + a1) * n2 + a2 + n * a3], sum);
         }
         __syncthreads();
+        for (int i = tid; i < (len + P) * n2; i += 256) {
+            const int c = i / n2, r = i % n2;
+            atomicAdd(&d[(ex0 + c) + (int64_t)Nx * ((ey + r % n) + (int64_t)Ny * (ez + r / n))], acc[i]);
+        }
+        __syncthreads();   // acc, kap and sq are rewritten by the next run
     }
 }
 
@@ -278,11 +296,9 @@ __global__ __launch_bounds__(64) void k_line_solve(double* __restrict__ v, const
 template <int P>
 int launch_mass_diag_t(const PatchDev& pd, const double* kappa, double* d, hipStream_t st)
 {
-    constexpr int n3 = (P + 1) * (P + 1) * (P + 1), EPB = 256 / n3 > 0 ? 256 / n3 : 1;
-    const int64_t groups = (pd.E + EPB - 1) / EPB;
-    // a workgroup per group of elements: each ends with its atomic adds, so
-    // many resident workgroups hide their latency
-    const int64_t blocks = groups < (1 << 20) ? groups : (1 << 20);
+    constexpr int XR = DiagRun<P>::XR;
+    const int64_t runs = (int64_t)((pd.d[0].K + XR - 1) / XR) * pd.d[1].K * pd.d[2].K;
+    const int64_t blocks = runs < (1 << 20) ? runs : (1 << 20);
     hipLaunchKernelGGL(k_mass_diag<P>, dim3((unsigned)blocks), dim3(256), 0, st, pd, kappa, d);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
