@@ -256,7 +256,9 @@ igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double
  * global matrix formed.  kappa: device [E][q^3]; u, y: device [ndof]; y is
  * OVERWRITTEN and must not overlap u.  The element results are added into y
  * with FP64 atomics, so the summation order, and the last bits of y, may
- * differ between calls.  Needs nquad = degree + 1 in every direction. */
+ * differ between calls.  alphaK == 0 takes a mass-only kernel that neither
+ * interpolates nor contracts grad u (so non-finite gradients of u do not
+ * reach y).  Needs nquad = degree + 1 in every direction. */
 igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double* u,
                        double alphaM, double alphaK, double* y, void* stream);
 
