@@ -298,9 +298,12 @@ igaf_status igaf_kappa_grad_geo(const igaf_plan* plan, const double* cm0, const 
  * array); work: device scratch of igaf_euler_workspace(plan) doubles,
  * overwritten.  iters, relres: HOST outputs (iterations taken, final
  * ||r|| / ||b|| of the recursively updated residual), either may be NULL.
- * Synchronous: it waits on `stream` for the residual of every iteration and
- * returns when the step is done.  Needs nquad = degree + 1 in every
- * direction. */
+ * Synchronous: it reads the residual of every iteration back through a
+ * pinned slot of the plan (while the GPU runs the next iteration's work up
+ * to its update of mu_next) and returns when the step is done; the work
+ * after the last iteration may still run on `stream` then, touching only
+ * `work`.  Calls on one plan that overlap (other threads or streams) race on
+ * that slot.  Needs nquad = degree + 1 in every direction. */
 enum { IGAF_PRECOND_NONE = 0, IGAF_PRECOND_KRON = 1 };
 int64_t igaf_euler_workspace(const igaf_plan* plan);
 igaf_status igaf_euler_step(const igaf_plan* plan, const double* kappa, const double* mu, double dt,

@@ -354,7 +354,7 @@ int64_t euler_workspace_doubles(int64_t ndof) { return 6 * ndof + kDotBlocks + 8
 // preconditioner take cm where the identity geometry takes kappa.
 int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const double* mu, double dt,
                    double tol, int maxit, int precond, double* x, double* work, int* iters, double* relres,
-                   hipStream_t st, const double* G)
+                   hipStream_t st, double* rb, hipEvent_t ev, const double* G)
 {
     double* b = work;
     double* r = b + ndof;
@@ -406,18 +406,32 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
     if (*relres <= tol) return 0;
     if (apply_precond() || dot(r, z, ndof, partial, S, 0, 0, st)) return -3;
     hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 1);
+    if (mass_apply(p, Ap, 0.0)) return -3;
+    if (dot(p, Ap, ndof, partial, S, 1, 1, st)) return -3;       // alpha
+    // Each iteration's r.r is read back through a pinned slot while the GPU
+    // already runs the next iteration's work up to its update of x and r
+    // (preconditioner, r.z, search direction, M p, p.Ap): the same kernels
+    // in the same order, with the host's stopping test off the GPU's path.
+    // After the last iteration that work is left unused.
     for (int k = 1; k <= maxit; ++k) {
-        if (mass_apply(p, Ap, 0.0)) return -3;
-        if (dot(p, Ap, ndof, partial, S, 1, 1, st)) return -3;   // alpha
         hipLaunchKernelGGL(k_cg_xr, dim3(gv), dim3(256), 0, st, x, r, p, Ap, S, ndof);
-        if (dot(r, r, ndof, partial, S, 5, 0, st) || host_scalar(5, &rr)) return -3;
+        if (dot(r, r, ndof, partial, S, 5, 0, st)) return -3;
+        if (hipMemcpyAsync(rb, S + 5, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipEventRecord(ev, st) != hipSuccess)
+            return -3;
+        if (k < maxit) {
+            if (apply_precond()) return -3;
+            if (dot(r, z, ndof, partial, S, 2, 2, st)) return -3;    // beta, new r.z
+            hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 0);
+            if (hipGetLastError() != hipSuccess) return -3;
+            if (mass_apply(p, Ap, 0.0)) return -3;
+            if (dot(p, Ap, ndof, partial, S, 1, 1, st)) return -3;   // alpha
+        }
+        if (hipEventSynchronize(ev) != hipSuccess) return -3;
+        rr = *rb;
         *iters = k;
         *relres = std::sqrt(rr / bb);
         if (*relres <= tol) return 0;
-        if (apply_precond()) return -3;
-        if (dot(r, z, ndof, partial, S, 2, 2, st)) return -3;    // beta, new r.z
-        hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 0);
-        if (hipGetLastError() != hipSuccess) return -3;
     }
     return 1;
 }

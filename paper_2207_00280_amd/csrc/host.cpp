@@ -147,6 +147,9 @@ struct igaf_plan {
     // of a slab of element layers (allocated at the first such call)
     double* geo_ws = nullptr;
     int geo_ws_layers = 0;
+    // Euler step: pinned slot and event for the residual read-back of CG
+    double* rb_host = nullptr;
+    hipEvent_t rb_ev = nullptr;
 };
 
 namespace {
@@ -379,6 +382,9 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
     if (rc == IGAF_OK && hipStreamSynchronize(nullptr) != hipSuccess)
         rc = fail(IGAF_EDEVICE, "basis-table kernel failed");
     if (rc == IGAF_OK) rc = mass_factors(P);
+    if (rc == IGAF_OK && (hipHostMalloc((void**)&P->rb_host, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+                          hipEventCreateWithFlags(&P->rb_ev, hipEventDisableTiming) != hipSuccess))
+        rc = fail(IGAF_EDEVICE, "pinned read-back slot or event creation failed");
     if (rc != IGAF_OK) {
         igaf_plan_destroy(P);
         return rc;
@@ -394,6 +400,8 @@ void igaf_plan_destroy(igaf_plan* plan)
     (void)hipFree(plan->dmem);
     (void)hipFree(plan->dpre);
     if (plan->geo_ws) (void)hipFree(plan->geo_ws);
+    if (plan->rb_ev) (void)hipEventDestroy(plan->rb_ev);
+    if (plan->rb_host) (void)hipHostFree(plan->rb_host);
     delete plan;
 }
 
@@ -712,7 +720,7 @@ static igaf_status euler_any(const igaf_plan* plan, const double* kappa, const d
     int it = 0;
     double rr = 0.0;
     int rc = run_euler_step(plan->dev, plan->ndof, kappa, mu, dt, tol, maxit, precond, mu_next, work, &it,
-                            &rr, (hipStream_t)stream, G);
+                            &rr, (hipStream_t)stream, plan->rb_host, plan->rb_ev, G);
     if (iters) *iters = it;
     if (relres) *relres = rr;
     if (rc < 0) return fail(IGAF_EDEVICE, "Euler step: %s", hipGetErrorString(hipGetLastError()));

@@ -56,11 +56,12 @@ int launch_apply(const PatchDev& pd, const double* kappa, const double* u, doubl
                  double alphaK, double* y, hipStream_t st, const double* G = nullptr);
 
 // Forward Euler step: b = M mu - dt K mu, then CG on M x = b from x = mu.
+// rb: pinned host slot for the residual read-back, ev: an event for it.
 // Returns 0 (converged), 1 (maxit reached) or -3.
 int64_t euler_workspace_doubles(int64_t ndof);
 int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const double* mu, double dt,
                    double tol, int maxit, int precond, double* x, double* work, int* iters, double* relres,
-                   hipStream_t st, const double* G = nullptr);
+                   hipStream_t st, double* rb, hipEvent_t ev, const double* G = nullptr);
 
 int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,
                       double alphaK, double scale, double* grad, hipStream_t st,
