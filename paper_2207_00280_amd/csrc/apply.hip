@@ -54,6 +54,8 @@ __device__ inline void ap_wave_sync()
 
 }  // namespace
 
+constexpr int kApplyRun = 32;   // elements per x-run of one wavefront
+
 template <int P>
 struct ApplyShape {
     static constexpr int n = P + 1, Q = P + 1, Q2 = Q * Q, Q3 = Q2 * Q;
@@ -66,7 +68,7 @@ struct ApplyShape {
     static constexpr int XA3 = ppad16(n * Q, Q), XF = n * XA3, XG = 2 * XF;
     static constexpr int YA3 = ppad16(Q2, Q), YF = n * YA3, YG = 3 * YF;
     static constexpr int WS = pmax(G * XG, G * YG);               // doubles per wavefront
-    static constexpr int RUN = 32;                                // elements per x-run
+    static constexpr int RUN = kApplyRun;                         // elements per x-run
     // p <= 3: the run's finished DOF values, [a2 + n a3][ex - ex0], added to
     // y in one pass at the end of the run
     static constexpr int RB = NXP == 1 ? RUN * n * n : 0;
@@ -186,7 +188,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if (g >= ng) break;   // wave-uniform
-                const int ex = exg + g;
 #pragma unroll
                 for (int ps = 0; ps < NXP; ++ps) {
                     const bool act = ps * 64 + lane < A::NXI;
@@ -414,7 +415,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM,
                  double alphaK, double* y, hipStream_t st, const double* G)
 {
-    const int64_t runs = (int64_t)((pd.d[0].K + 31) / 32) * pd.d[1].K * pd.d[2].K;   // runs of 32 x elements
+    const int64_t runs = (int64_t)((pd.d[0].K + kApplyRun - 1) / kApplyRun) * pd.d[1].K * pd.d[2].K;
     int64_t blocks = (runs + 3) / 4;
     if (blocks > 8192) blocks = 8192;
     const bool geo = G != nullptr, mass = alphaK == 0.0;

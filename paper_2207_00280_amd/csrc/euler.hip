@@ -71,26 +71,44 @@ __global__ __launch_bounds__(kDotThreads) void k_dot_final(const double* __restr
     }
 }
 
-// x += alpha p, r -= alpha Ap (alpha = S[4])
-__global__ __launch_bounds__(256) void k_cg_xr(double* __restrict__ x, double* __restrict__ r,
-                                               const double* __restrict__ p,
-                                               const double* __restrict__ Ap,
-                                               const double* __restrict__ S, int64_t n)
+// x += alpha p, r -= alpha Ap (alpha = S[4]), and the first stage of r.r:
+// the grid and the order of k_dot_partial, so the partials are the same
+__global__ __launch_bounds__(kDotThreads) void k_cg_xr_rr(double* __restrict__ x, double* __restrict__ r,
+                                                          const double* __restrict__ p,
+                                                          const double* __restrict__ Ap,
+                                                          const double* __restrict__ S, int64_t n,
+                                                          double* __restrict__ partial)
 {
+    __shared__ double red[kDotThreads];
     const double alpha = S[4];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kDotThreads) {
         x[i] += alpha * p[i];
-        r[i] -= alpha * Ap[i];
+        const double ri = r[i] - alpha * Ap[i];
+        r[i] = ri;
+        s += ri * ri;
     }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kDotThreads / 2; h > 0; h /= 2) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// p = z + beta p (beta = S[3]); with first != 0: p = z
+// p = z + beta p (beta = S[3]); with first != 0: p = z.  Ap = 0 for the mass
+// apply that follows (it adds into Ap).
 __global__ __launch_bounds__(256) void k_cg_p(double* __restrict__ p, const double* __restrict__ z,
-                                              const double* __restrict__ S, int64_t n, int first)
+                                              const double* __restrict__ S, int64_t n, int first,
+                                              double* __restrict__ Ap)
 {
     const double beta = first ? 0.0 : S[3];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         p[i] = z[i] + beta * (first ? 0.0 : p[i]);
+        Ap[i] = 0.0;
+    }
 }
 
 // r = b - r (r holds M x on entry); x = mu
@@ -368,6 +386,9 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
     auto mass_apply = [&](const double* v, double* out, double aK) {
         return launch_fill_zero(out, ndof, st) || launch_apply(pd, kappa, v, 1.0, aK, out, st) ? -3 : 0;
     };
+    auto mass_apply_zeroed = [&](const double* v, double* out) {   // out already zero
+        return launch_apply(pd, kappa, v, 1.0, 0.0, out, st) ? -3 : 0;
+    };
     auto host_scalar = [&](int slot, double* out) {
         return hipMemcpyAsync(out, S + slot, sizeof(double), hipMemcpyDeviceToHost, st) == hipSuccess &&
                        hipStreamSynchronize(st) == hipSuccess
@@ -405,8 +426,8 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
     *relres = std::sqrt(rr / bb);
     if (*relres <= tol) return 0;
     if (apply_precond() || dot(r, z, ndof, partial, S, 0, 0, st)) return -3;
-    hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 1);
-    if (mass_apply(p, Ap, 0.0)) return -3;
+    hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 1, Ap);
+    if (mass_apply_zeroed(p, Ap)) return -3;
     if (dot(p, Ap, ndof, partial, S, 1, 1, st)) return -3;       // alpha
     // Each iteration's r.r is read back through a pinned slot while the GPU
     // already runs the next iteration's work up to its update of x and r
@@ -414,17 +435,19 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
     // in the same order, with the host's stopping test off the GPU's path.
     // After the last iteration that work is left unused.
     for (int k = 1; k <= maxit; ++k) {
-        hipLaunchKernelGGL(k_cg_xr, dim3(gv), dim3(256), 0, st, x, r, p, Ap, S, ndof);
-        if (dot(r, r, ndof, partial, S, 5, 0, st)) return -3;
+        hipLaunchKernelGGL(k_cg_xr_rr, dim3(kDotBlocks), dim3(kDotThreads), 0, st, x, r, p, Ap, S, ndof,
+                           partial);
+        hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kDotThreads), 0, st, partial, kDotBlocks, S, 5, 0);
+        if (hipGetLastError() != hipSuccess) return -3;
         if (hipMemcpyAsync(rb, S + 5, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipEventRecord(ev, st) != hipSuccess)
             return -3;
         if (k < maxit) {
             if (apply_precond()) return -3;
             if (dot(r, z, ndof, partial, S, 2, 2, st)) return -3;    // beta, new r.z
-            hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 0);
+            hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 0, Ap);
             if (hipGetLastError() != hipSuccess) return -3;
-            if (mass_apply(p, Ap, 0.0)) return -3;
+            if (mass_apply_zeroed(p, Ap)) return -3;
             if (dot(p, Ap, ndof, partial, S, 1, 1, st)) return -3;   // alpha
         }
         if (hipEventSynchronize(ev) != hipSuccess) return -3;
