@@ -147,3 +147,34 @@ def test_euler_geometry_vs_direct_solve(orc, ig, p, K):
     s0, s1 = math.fsum((M @ mu).tolist()), math.fsum((M @ x).tolist())
     b = M @ mu - dt * (Kk @ mu)
     assert abs(s1 - s0) <= math.sqrt(P.ndof) * relres * np.linalg.norm(b) + 1e-13 * abs(s0)
+
+
+def test_euler_overlapped_stop_leaves_result(ig):
+    """The stopping test of CG reads r.r back while the GPU already prepares
+    the next iteration (preconditioner, search direction, M p); that work
+    must not touch mu_next.  The converged result equals the iterate of a run
+    stopped by maxit at the same iteration count (no work past its last
+    update of mu_next), up to the summation order of the apply's atomics:
+    one more CG update would move it by ~tol."""
+    import torch
+
+    p, K = 3, (24, 20, 16)
+    plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
+    kap = to_dev(W.kappa_lognormal(plan.nelem, plan.nqp, seed=61))
+    mu = to_dev(W.normal_vector(plan.ndof, 62))
+    dt = 0.1 / 24 ** 2
+    x1, it, rr = plan.euler_step(kap, mu, dt, tol=1e-10, maxit=5000, precond=ig.PRECOND_KRON)
+    torch.cuda.synchronize()
+    assert rr <= 1e-10 and it > 1
+    x2 = torch.empty_like(mu)
+    with pytest.raises(ig.IgafError) as ei:
+        plan.euler_step(kap, mu, dt, tol=0.0, maxit=it, precond=ig.PRECOND_KRON, out=x2)
+    assert ei.value.status == ig.ENOCONV
+    torch.cuda.synchronize()
+    assert relfro(to_host(x1), to_host(x2)) <= 1e-14
+    # one iteration fewer is measurably different (the comparison has teeth)
+    x3 = torch.empty_like(mu)
+    with pytest.raises(ig.IgafError):
+        plan.euler_step(kap, mu, dt, tol=0.0, maxit=it - 1, precond=ig.PRECOND_KRON, out=x3)
+    torch.cuda.synchronize()
+    assert relfro(to_host(x3), to_host(x1)) > 1e-13
