@@ -154,8 +154,10 @@ def test_euler_overlapped_stop_leaves_result(ig):
     the next iteration (preconditioner, search direction, M p); that work
     must not touch mu_next.  The converged result equals the iterate of a run
     stopped by maxit at the same iteration count (no work past its last
-    update of mu_next), up to the summation order of the apply's atomics:
-    one more CG update would move it by ~tol."""
+    update of mu_next).  The bound is taken from the run itself: a stray
+    update of mu_next would move it by about one CG step, i.e. by about the
+    distance to the iterate one iteration earlier; the two runs may differ
+    only by the rounding of the apply's sums, far below that step."""
     import torch
 
     p, K = 3, (24, 20, 16)
@@ -170,11 +172,10 @@ def test_euler_overlapped_stop_leaves_result(ig):
     with pytest.raises(ig.IgafError) as ei:
         plan.euler_step(kap, mu, dt, tol=0.0, maxit=it, precond=ig.PRECOND_KRON, out=x2)
     assert ei.value.status == ig.ENOCONV
-    torch.cuda.synchronize()
-    assert relfro(to_host(x1), to_host(x2)) <= 1e-14
-    # one iteration fewer is measurably different (the comparison has teeth)
     x3 = torch.empty_like(mu)
     with pytest.raises(ig.IgafError):
         plan.euler_step(kap, mu, dt, tol=0.0, maxit=it - 1, precond=ig.PRECOND_KRON, out=x3)
     torch.cuda.synchronize()
-    assert relfro(to_host(x3), to_host(x1)) > 1e-13
+    step = relfro(to_host(x3), to_host(x1))
+    assert step > 0.0
+    assert relfro(to_host(x1), to_host(x2)) <= 1e-2 * step, (relfro(to_host(x1), to_host(x2)), step)
