@@ -290,7 +290,9 @@ def bench_w5(ig, torch, stream, steps):
     Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
     Kv = torch.empty_like(Mv)
     ms_a = float(np.mean(timed(lambda: plan.kappa_grad(u, v, grad=g), steps, 2, stream)))
-    ms_y = float(np.mean(timed(lambda: plan.apply(kap, u, 1.0, 1.0, y=y), steps, 2, stream)))
+    wk = torch.empty(plan.apply_workspace(), dtype=torch.float64, device="cuda")
+    ms_y = float(np.mean(timed(lambda: plan.apply(kap, u, 1.0, 1.0, y=y, work=wk), steps, 2, stream)))
+    ms_m = float(np.mean(timed(lambda: plan.apply(kap, u, 1.0, 0.0, y=y, work=wk), steps, 2, stream)))
     ms_f = float(np.mean(timed(lambda: plan.integrate_assemble(kap, want_elem=False, Mval=Mv, Kval=Kv),
                                steps, 2, stream)))
     q3, n3 = plan.nqp, (p + 1) ** 3
@@ -308,7 +310,8 @@ def bench_w5(ig, torch, stream, steps):
                        "speedup_vs_forward": ms_f / ms_a},
            "apply": {"ms": ms_y, "bytes": b_y, "flops": f_y, "roofline_ms": roof_y * 1e3,
                      "frac": roof_y / (ms_y * 1e-3), "bound": "fp64" if f_y / FP64_PEAK > b_y / HBM_PEAK else "hbm",
-                     "speedup_vs_forward": ms_f / ms_y}}
+                     "speedup_vs_forward": ms_f / ms_y},
+           "apply_mass_only_ms": ms_m}
     # one forward Euler step M mu_next = (M - dt K) mu: right-hand side by the
     # apply, conjugate gradients on M to a relative residual of 1e-10
     dt = 0.1 / max(K) ** 2
@@ -326,12 +329,12 @@ def bench_w5(ig, torch, stream, steps):
                      "ms_per_iteration": ms_e / max(1, iters),
                      "preconditioner": "kronecker 1D mass, diagonal scaling" if pc else "none"}
     del mu_next, work
-    log("W5: adjoint %.3f ms (%.0f%% of roofline), apply (M+K)u %.3f ms (%.0f%%), forward CSR %.3f ms, "
+    log("W5: adjoint %.3f ms (%.0f%% of roofline), apply (M+K)u %.3f ms (%.0f%%), Mu %.3f ms, forward CSR %.3f ms, "
         "Euler step %.1f ms (%d PCG iterations; plain CG %.1f ms, %d iterations)"
-        % (ms_a, 100 * out["adjoint"]["frac"], ms_y, 100 * out["apply"]["frac"], ms_f,
+        % (ms_a, 100 * out["adjoint"]["frac"], ms_y, 100 * out["apply"]["frac"], ms_m, ms_f,
            out["euler_step"]["ms"], out["euler_step"]["cg_iterations"], out["euler_step_plain_cg"]["ms"],
            out["euler_step_plain_cg"]["cg_iterations"]))
-    del kap, u, v, g, y, Mv, Kv, plan
+    del kap, u, v, g, y, wk, Mv, Kv, plan
     torch.cuda.empty_cache()
     return out
 
@@ -376,9 +379,10 @@ def bench_w6(ig, torch, stream, steps):
     v = torch.from_numpy(W.normal_vector(plan.ndof, 4)).cuda()
     y = torch.empty_like(u)
     g = torch.empty(plan.nelem, plan.nqp, dtype=torch.float64, device="cuda")
-    ms_ap = float(np.mean(timed(lambda: plan.apply_geo(cmd, Gd, u, 1.0, 1.0, y=y), steps, 2, stream)))
+    wk = torch.empty(plan.apply_workspace(), dtype=torch.float64, device="cuda")
+    ms_ap = float(np.mean(timed(lambda: plan.apply_geo(cmd, Gd, u, 1.0, 1.0, y=y, work=wk), steps, 2, stream)))
     ms_ad = float(np.mean(timed(lambda: plan.kappa_grad_geo(cmd, Gd, u, v, grad=g), steps, 2, stream)))
-    del u, v, y, g
+    del u, v, y, g, wk
     b_el = plan.nelem * (7 * plan.nqp * 8 + 2 * n3 * n3 * 8)
     f_el = plan.nelem * geo_flops(p)
     roof = max(b_el / HBM_PEAK, f_el / FP64_PEAK)
@@ -421,7 +425,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=262144,
                     help="elements of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--mode", default="full",
-                    help="full | headline | kernel:{element,csr,classical,headline,copy}")
+                    help="full | headline | w3 | w4 | w5 | w6 | kernel:{element,csr,classical,headline,copy}")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -437,6 +441,11 @@ def main():
     torch.cuda.set_device(0)
     if args.mode.startswith("kernel:"):
         run_kernel_mode(args.mode.split(":", 1)[1], ig, torch, args.steps)
+        return
+    if args.mode in ("w3", "w4", "w5", "w6"):
+        # one secondary workload alone (its JSON object on stdout)
+        fn = {"w3": bench_w3, "w4": bench_w4, "w5": bench_w5, "w6": bench_w6}[args.mode]
+        print(json.dumps({args.mode: fn(ig, torch, torch.cuda.current_stream(), args.steps)}), flush=True)
         return
     stream = torch.cuda.current_stream()
     h = Headline(ig, torch)

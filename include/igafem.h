@@ -254,22 +254,25 @@ igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double
  * grad u to the quadrature points, weight by kappa w, contract back against
  * the test functions; the element sum of Sec. 3.1), with no element or
  * global matrix formed.  kappa: device [E][q^3]; u, y: device [ndof]; y is
- * OVERWRITTEN and must not overlap u.  The element results are added into y
- * with FP64 atomics, so the summation order, and the last bits of y, may
- * differ between calls.  alphaK == 0 takes a mass-only kernel that neither
+ * OVERWRITTEN and must not overlap u.  work: device scratch of
+ * igaf_apply_workspace(plan) doubles, overwritten (each run of elements
+ * along x writes its DOF values there; each y_I is then summed from them in
+ * a fixed order, so repeated calls give the same bits).  Calls that overlap
+ * on one `work` race.  alphaK == 0 takes a mass-only kernel that neither
  * interpolates nor contracts grad u (so non-finite gradients of u do not
  * reach y).  Needs nquad = degree + 1 in every direction. */
+int64_t igaf_apply_workspace(const igaf_plan* plan);
 igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double* u,
-                       double alphaM, double alphaK, double* y, void* stream);
+                       double alphaM, double alphaK, double* y, double* work, void* stream);
 
 /* The operator apply on a mapped geometry (the coefficients of
  * igaf_integrate_assemble_geo): y = alphaM M u + alphaK K u with
  *   M_IJ = sum_q w_q cm_q phi_I phi_J,  K_IJ = sum_q w_q grad_xi phi_I^T G_q grad_xi phi_J.
  * cm [E][q^3], G [E][6][q^3] (xx yy zz xy xz yz), u, y device [ndof]; y is
- * OVERWRITTEN, must not overlap u, and is summed with FP64 atomics (last bits
- * may vary between calls). */
+ * OVERWRITTEN and must not overlap u; work as in igaf_apply (same size,
+ * same fixed-order sums). */
 igaf_status igaf_apply_geo(const igaf_plan* plan, const double* cm, const double* G, const double* u,
-                           double alphaM, double alphaK, double* y, void* stream);
+                           double alphaM, double alphaK, double* y, double* work, void* stream);
 
 /* The adjoint on a mapped geometry where kappa scales both coefficients,
  * cm = kappa cm0 and G = kappa G0 (cm0 = det J, G0 = det J J^-1 J^-T):
@@ -296,7 +299,9 @@ igaf_status igaf_kappa_grad_geo(const igaf_plan* plan, const double* cm0, const 
  * coefficient's variation.
  * kappa: device [E][q^3]; mu, mu_next: device [ndof] (may be the same
  * array); work: device scratch of igaf_euler_workspace(plan) doubles,
- * overwritten.  iters, relres: HOST outputs (iterations taken, final
+ * overwritten.  Every reduction (the applies, the diagonal of M(kappa), the
+ * dot products) runs in a fixed order, so repeated steps give the same
+ * bits.  iters, relres: HOST outputs (iterations taken, final
  * ||r|| / ||b|| of the recursively updated residual), either may be NULL.
  * Synchronous: it reads the residual of every iteration back through a
  * pinned slot of the plan (while the GPU runs the next iteration's work up
@@ -326,9 +331,9 @@ igaf_status igaf_euler_step_geo(const igaf_plan* plan, const double* cm, const d
  * (patch, tile of row pencils, x segment) item, items grouped by degree and
  * sorted longest first within a degree. */
 
-/* Build per-patch plans, the device patch table and the work list
- * (synchronous; one segment per tile and 16 items per XCD chunk until
- * igaf_batch_autotune picks a split).  descs: HOST array of npatch
+/* Build per-patch plans, the device patch table and the work lists of every
+ * split (synchronous; one segment per tile and 16 items per XCD chunk until
+ * igaf_batch_autotune or igaf_batch_set_split picks another split).  descs: HOST array of npatch
  * descriptions. */
 igaf_status igaf_batch_create(const igaf_patch_desc* descs, int32_t npatch, igaf_batch** out);
 
@@ -354,7 +359,11 @@ igaf_status igaf_batch_info(const igaf_batch* batch, int32_t* family, int32_t* g
  * the batch owns; when they differ from the previous call the host first
  * waits for `stream`.  The call may be captured in a HIP graph once it has
  * run eagerly with the same pointers (changing them during capture returns
- * IGAF_EINVAL).  Overlapping calls on one batch from different streams race. */
+ * IGAF_EINVAL).  A replay keeps the work split it was captured with (each
+ * split has its own immutable work list) but copies the pointer tables the
+ * batch holds at replay time, i.e. those of the latest call: after an eager
+ * call with other pointers, replays read and write those arrays.
+ * Overlapping calls on one batch from different streams race. */
 igaf_status igaf_batch_integrate_assemble(igaf_batch* batch, const double* const* kappa,
                                           double* const* Mval, double* const* Kval,
                                           void* stream);
@@ -381,8 +390,9 @@ igaf_status igaf_batch_integrate_assemble_separate(igaf_batch* batch,
 igaf_status igaf_batch_autotune(igaf_batch* batch, const double* const* kappa, double* const* Mval,
                                 double* const* Kval, int32_t reps, void* stream);
 
-/* Set the work split by hand (synchronous): split in {1, 2, 4, 8}, chunk in
- * {4, 16, 64}, else IGAF_EINVAL; e.g. to reuse an earlier tuning. */
+/* Set the work split by hand: split in {1, 2, 4, 8}, chunk in {4, 16, 64},
+ * else IGAF_EINVAL; e.g. to reuse an earlier tuning.  Host-only (the work
+ * lists of every split are uploaded at creation); later calls use it. */
 igaf_status igaf_batch_set_split(igaf_batch* batch, int32_t split, int32_t chunk);
 
 /* The work split in use: segments per tile (at most), items per XCD chunk,

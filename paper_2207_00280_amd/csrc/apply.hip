@@ -7,9 +7,7 @@
 // factorisation (x -> y -> z, value and derivative tables, as Algorithm 2
 // contracts), weighted point by point, and contracted back against the test
 // functions in the transposed order (z -> y -> x); no element or global
-// matrix is formed.  The n^3 element results are added into y with FP64
-// atomics (y is zeroed first), so the order of the additions, and the last
-// bits of y, vary between runs.
+// matrix is formed.
 //
 // Work layout as in the adjoint: one 64-lane wavefront per x-run of elements
 // (fixed ey, ez), elements in groups of G = 64 / n^2:
@@ -20,10 +18,21 @@
 //              weighted there by kappa w (alphaM, alphaK folded in), then
 //              contracted back over kz (transposed stage z);
 //   stage y^T: lane (g, kx, a3), every a2;
-//   stage x^T: lane (a1, a2, a3), one element at a time, every kx.  At
-//              p <= 3 (one pass) the lanes of one DOF row along x pass their
-//              partial sums down as the run advances, so each DOF takes one
-//              atomic add per run instead of one per element (p+1 fewer).
+//   stage x^T: lane (a1, a2, a3), one element at a time, every kx.
+// The run's results are summed per DOF in LDS, in element order: at p <= 3
+// (one pass of 64 lanes per element) the lanes of one DOF row along x pass
+// their partial sums down as the run advances and a DOF is written once it
+// is complete; at p = 4, 5 each element's values are added into the run's
+// LDS rows.  A run touches the n^2 DOF rows (ey + a2, ez + a3) over x in
+// [ex0, ex1 + p); at its end those values go to the run's slot of a
+// workspace with plain coalesced stores.  A second kernel then forms each
+// y_I from the slots of the (at most (p+1)^2, or 2 (p+1)^2 where x-runs
+// meet) runs that touch it, in a fixed order: no atomics, so repeated calls
+// give the same bits.
+//
+// The diagonal mode computes d_I = sum_q c_q phi_I(x_q)^2 = diag(M(kappa))
+// with the same transposed stages, squared tables and no u (the Euler step's
+// preconditioner scaling).
 #include "common.h"
 #include "launch.h"
 
@@ -69,9 +78,9 @@ struct ApplyShape {
     static constexpr int YA3 = ppad16(Q2, Q), YF = n * YA3, YG = 3 * YF;
     static constexpr int WS = pmax(G * XG, G * YG);               // doubles per wavefront
     static constexpr int RUN = kApplyRun;                         // elements per x-run
-    // p <= 3: the run's finished DOF values, [a2 + n a3][ex - ex0], added to
-    // y in one pass at the end of the run
-    static constexpr int RB = NXP == 1 ? RUN * n * n : 0;
+    // the run's DOF values [a2 + n a3][x - ex0], x - ex0 < RUN + p
+    static constexpr int RL = RUN + P;
+    static constexpr int RB = n * n * RL;
     // the x value / derivative tables of one group ([g][a][k], G n Q <= 64
     // values each), staged in LDS: one load per lane and table per group,
     // issued a group ahead
@@ -79,15 +88,21 @@ struct ApplyShape {
     static_assert(TBN <= 64, "one table value per lane");
 };
 
+enum { AP_FULL = 0, AP_MASS = 1, AP_DIAG = 2 };
+
 // GEO: a mapped geometry; `kappa` is the mass coefficient cm and Gt
 // ([E][6][q^3]) the stiffness tensor, applied to the parametric gradient.
-// MASS (alphaK = 0, the conjugate-gradient products of the Euler step): the
-// gradient fields are neither interpolated nor contracted back.
-template <int P, bool GEO, bool MASS>
+// MODE AP_MASS (alphaK = 0, the conjugate-gradient products of the Euler
+// step): the gradient fields are neither interpolated nor contracted back.
+// MODE AP_DIAG: alphaM diag(M(kappa)), u unused.
+// W: the runs' slots, RB doubles per run (run = ch + nchunk (ey + Ky ez)).
+template <int P, bool GEO, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 : 2))) void k_apply(
     PatchDev pd, const double* __restrict__ kappa, const double* __restrict__ u, double alphaM,
-    double alphaK, double* __restrict__ y, const double* __restrict__ Gt)
+    double alphaK, double* __restrict__ W, const double* __restrict__ Gt)
 {
+    constexpr bool MASS = MODE != AP_FULL;   // no gradient fields
+    constexpr bool DIAG = MODE == AP_DIAG;   // no u: point values kappa w, squared tables
     using A = ApplyShape<P>;
     constexpr int n = A::n, Q = A::Q, Q2 = A::Q2, Q3 = A::Q3, G = A::G, NXP = A::NXP;
     __shared__ double lds[4][A::WS + A::RB + 128];
@@ -132,9 +147,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
         const ctab Dz0 = as_ctab(pd.d[2].dN) + (int64_t)ez * n * Q;
         const ctab wz0 = as_ctab(pd.d[2].wq) + (int64_t)ez * Q;
         const double wyl = pd.d[1].wq[(int64_t)ey * Q + zky];   // this lane's y weight
+        const int len = ex1 - ex0;
         // stage x^T with one pass (p <= 3): lane (a1, a2, a3) holds the partial
         // sum of DOF (ex + a1, ey + a2, ez + a3) over the run's elements so far
         double racc = 0.0;
+        if constexpr (NXP > 1) {   // several passes: the run's rows accumulate in LDS
+            for (int i = lane; i < A::RB; i += 64) RB[i] = 0.0;
+        }
         // sliding window of u along x at (a2, a3) of every stage-x item
         double uw[NXP][n];
         int64_t g0[NXP];
@@ -142,7 +161,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
         for (int ps = 0; ps < NXP; ++ps) {
             g0[ps] = (int64_t)Nx * ((ey + xa2[ps]) + (int64_t)Ny * (ez + xa3[ps]));
 #pragma unroll
-            for (int a1 = 0; a1 < n; ++a1) uw[ps][a1] = u[g0[ps] + ex0 + a1];
+            for (int a1 = 0; a1 < n; ++a1) uw[ps][a1] = DIAG ? 0.0 : u[g0[ps] + ex0 + a1];
         }
         // x tables of the group starting at element exg, this lane's value
         const int64_t tlast = (int64_t)Kx * n * Q - 1;
@@ -154,7 +173,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
         for (int ps = 0; ps < NXP; ++ps)
 #pragma unroll
-            for (int g = 0; g < G; ++g) unx[ps][g] = u[g0[ps] + min(ex0 + n + g, Nx - 1)];
+            for (int g = 0; g < G; ++g) unx[ps][g] = DIAG ? 0.0 : u[g0[ps] + min(ex0 + n + g, Nx - 1)];
         const int64_t krow = (int64_t)Kx * (ey + (int64_t)Ky * ez);
         for (int exg = ex0; exg < ex1; exg += G) {
             const int ng = min(G, ex1 - exg);   // elements in this group
@@ -175,7 +194,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     ucur[ps][g] = unx[ps][g];
-                    unx[ps][g] = u[g0[ps] + min(exg + G + n + g, Nx - 1)];
+                    if constexpr (!DIAG) unx[ps][g] = u[g0[ps] + min(exg + G + n + g, Nx - 1)];
                 }
             TB[lane] = tnv;
             TB[64 + lane] = tdn;
@@ -187,7 +206,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
             // ---- stage x, one element of the group at a time
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                if (g >= ng) break;   // wave-uniform
+                if (DIAG || g >= ng) break;   // wave-uniform
 #pragma unroll
                 for (int ps = 0; ps < NXP; ++ps) {
                     const bool act = ps * 64 + lane < A::NXI;
@@ -210,7 +229,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
             }
             ap_wave_sync();
             // ---- stage y: lane (g, kx, a3), every ky
-            {
+            if constexpr (!DIAG) {
                 const int z0 = ap_opaque_zero();
                 const ctab Ny_ = Ny0 + z0, Dy_ = Dy0 + z0;
                 double x0[n], x1[n];
@@ -253,7 +272,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                 const double* yp = B + zg * A::YG + zky * Q + zkx;
 #pragma unroll
                 for (int a3 = 0; a3 < n; ++a3) {
-                    y0[a3] = yp[a3 * A::YA3];
+                    y0[a3] = DIAG ? 0.0 : yp[a3 * A::YA3];
                     y1[a3] = MASS ? 0.0 : yp[A::YF + a3 * A::YA3];
                     y2[a3] = MASS ? 0.0 : yp[2 * A::YF + a3 * A::YA3];
                 }
@@ -275,7 +294,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                         }
                     }
                     double t0, t1, t2, t3;
-                    if constexpr (MASS) {
+                    if constexpr (DIAG) {
+                        t0 = alphaM * (kc[kz] * wxy * wz_[kz]);
+                        t1 = t2 = t3 = 0.0;
+                    } else if constexpr (MASS) {
                         // the same products, in the same order, as the full forms below
                         if constexpr (GEO) t0 = alphaM * kc[kz] * (wxy * wz_[kz]) * h;
                         else t0 = alphaM * (kc[kz] * wxy * wz_[kz]) * h;
@@ -300,7 +322,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
                     for (int a3 = 0; a3 < n; ++a3) {
                         const double nz = Nz_[a3 * Q + kz];
-                        s0[a3] += nz * t0;
+                        s0[a3] += (DIAG ? nz * nz : nz) * t0;
                         if constexpr (!MASS) {
                             s0[a3] += Dz_[a3 * Q + kz] * t3;
                             s1[a3] += nz * t1;
@@ -344,7 +366,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
                     for (int ky = 0; ky < Q; ++ky) {
                         const double ny = Ny_[a2 * Q + ky];
-                        r0 += ny * v0[ky];
+                        r0 += (DIAG ? ny * ny : ny) * v0[ky];
                         if constexpr (!MASS) {
                             r0 += Dy_[a2 * Q + ky] * v2[ky];
                             r1 += ny * v1[ky];
@@ -358,7 +380,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
             }
             ap_wave_sync();
             // ---- stage x^T, one element at a time: lane (a1, a2, a3), every
-            // kx, and the element's contribution added into y
+            // kx, and the element's contribution added into the run's rows
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 if (g >= ng) break;   // wave-uniform
@@ -371,79 +393,127 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
 #pragma unroll
                     for (int kx = 0; kx < Q; ++kx) {
                         const int t = (g * n + ta1[ps]) * Q + kx;
-                        acc += TB[t] * rp[kx];
+                        const double nx = TB[t];
+                        acc += (DIAG ? nx * nx : nx) * rp[kx];
                         if constexpr (!MASS) acc += TB[64 + t] * rp[A::XF + kx];
                     }
-                    const int64_t I = (ex + ta1[ps]) + (int64_t)Nx * ((ey + ta2[ps]) + (int64_t)Ny * (ez + ta3[ps]));
                     if constexpr (NXP == 1) {
                         // DOF ex (a1 = 0) has all its contributions of the run
-                        // now (later elements touch DOFs beyond ex): keep it for
-                        // the run's adds to y, then move every partial sum down
-                        // one lane, so that lane a1 holds DOF ex + 1 + a1 for
-                        // the next element.  (An atomic here would make every
-                        // later table load of the run wait for it: loads and
-                        // stores share one in-order counter.)
+                        // now (later elements touch DOFs beyond ex): keep it in
+                        // the run's rows, then move every partial sum down one
+                        // lane, so that lane a1 holds DOF ex + 1 + a1 for the
+                        // next element
                         racc += acc;
-                        if (act && ta1[0] == 0) RB[(ta2[0] + n * ta3[0]) * A::RUN + (ex - ex0)] = racc;
+                        if (act && ta1[0] == 0) RB[(ta2[0] + n * ta3[0]) * A::RL + (ex - ex0)] = racc;
                         const double nxt = __shfl(racc, lane + 1);
                         racc = ta1[0] + 1 < n ? nxt : 0.0;
                     } else if (act) {
-                        atomicAdd(&y[I], acc);
+                        RB[(ta2[ps] + n * ta3[ps]) * A::RL + (ex - ex0 + ta1[ps])] += acc;
                     }
                 }
+                // the next element's adds read what other lanes wrote
+                if constexpr (NXP > 1) ap_wave_sync();
             }
             ap_wave_sync();   // every read of R before the next group's stage x writes
         }
+        // DOFs ex1 .. ex1 + p - 1 (x - ex0 = len + a1) take the rest of their
+        // contributions from the next run
         if constexpr (NXP == 1) {
-            // DOFs ex1 .. ex1 + p - 1 also take contributions from the next run
-            const bool act = lane < A::NXI;
-            const int64_t I = (ex1 - 1 + ta1[0] + 1) + (int64_t)Nx * ((ey + ta2[0]) + (int64_t)Ny * (ez + ta3[0]));
-            if (act && ta1[0] + 1 < n) atomicAdd(&y[I], racc);
+            if (lane < A::NXI && ta1[0] + 1 < n) RB[(ta2[0] + n * ta3[0]) * A::RL + len + ta1[0]] = racc;
             racc = 0.0;
-            // the run's finished DOFs: lanes along x, so each add instruction
-            // covers runs of consecutive y entries
-            const int len = ex1 - ex0;
-            for (int i = lane; i < n * n * A::RUN; i += 64) {
-                const int r = i / A::RUN, e = i % A::RUN;
-                if (e < len)
-                    atomicAdd(&y[(ex0 + e) + (int64_t)Nx * ((ey + r % n) + (int64_t)Ny * (ez + r / n))], RB[i]);
-            }
         }
+        ap_wave_sync();
+        // the run's slot: rows of RL values, the first len + p of each written
+        double* __restrict__ wr = W + (int64_t)run * A::RB;
+        for (int i = lane; i < A::RB; i += 64)
+            if (i % A::RL < len + P) wr[i] = RB[i];
+        ap_wave_sync();   // every read of the rows before the next run rewrites them
     }
 }
 
-int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM,
-                 double alphaK, double* y, hipStream_t st, const double* G)
+// y_I = the sum of the slots of the runs touching DOF I = (ix, iy, iz): runs
+// (chunk c, ey = iy - a2, ez = iz - a3) for a3, a2 = 0..p in that order, and
+// where ix is one of the first p DOFs of chunk c > 0 the slot of chunk c - 1
+// (at x - ex0 = ix - (c - 1) RUN >= RUN) before chunk c's.  One thread per DOF,
+// consecutive DOFs along x in consecutive lanes.
+template <int P>
+__global__ __launch_bounds__(256) void k_apply_sum(const double* __restrict__ W, double* __restrict__ y, int Kx,
+                                                   int Ky, int Kz, int64_t ndof)
+{
+    using A = ApplyShape<P>;
+    constexpr int n = A::n, RUN = A::RUN, RL = A::RL, RB = A::RB;
+    const int Nx = Kx + P, Ny = Ky + P;
+    const int nchunk = (Kx + RUN - 1) / RUN;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ndof; i += (int64_t)gridDim.x * 256) {
+        const int ix = (int)(i % Nx), iy = (int)((i / Nx) % Ny), iz = (int)(i / ((int64_t)Nx * Ny));
+        const int c = min(ix / RUN, nchunk - 1), xl = ix - c * RUN;
+        const bool prev = c > 0 && xl < P;
+        double s = 0.0;
+#pragma unroll
+        for (int a3 = 0; a3 < n; ++a3) {
+            const int ez = iz - a3;
+            if (ez < 0 || ez >= Kz) continue;
+#pragma unroll
+            for (int a2 = 0; a2 < n; ++a2) {
+                const int ey = iy - a2;
+                if (ey < 0 || ey >= Ky) continue;
+                const double* w =
+                    W + ((int64_t)c + (int64_t)nchunk * (ey + (int64_t)Ky * ez)) * RB + (a2 + n * a3) * RL;
+                if (prev) s += w[xl + RUN - RB];
+                s += w[xl];
+            }
+        }
+        y[i] = s;
+    }
+}
+
+int64_t apply_workspace_doubles(const PatchDev& pd)
+{
+    const int64_t n = pd.p + 1;
+    const int64_t runs = (int64_t)((pd.d[0].K + kApplyRun - 1) / kApplyRun) * pd.d[1].K * pd.d[2].K;
+    return runs * n * n * (kApplyRun + pd.p);
+}
+
+template <int P, bool GEO, int MODE>
+static int launch_apply_t(const PatchDev& pd, const double* kappa, const double* u, double alphaM, double alphaK,
+                          double* y, double* W, hipStream_t st, const double* G)
 {
     const int64_t runs = (int64_t)((pd.d[0].K + kApplyRun - 1) / kApplyRun) * pd.d[1].K * pd.d[2].K;
     int64_t blocks = (runs + 3) / 4;
     if (blocks > 8192) blocks = 8192;
-    const bool geo = G != nullptr, mass = alphaK == 0.0;
-    switch (pd.p) {
-#define IGAF_AP1(PP, GG, MM)                                                                          \
-    hipLaunchKernelGGL((k_apply<PP, GG, MM>), dim3((unsigned)blocks), dim3(256), 0, st, pd, kappa, u, alphaM, \
-                       alphaK, y, G)
-#define IGAF_AP(PP)                                                                                   \
-    case PP:                                                                                          \
-        if (geo) {                                                                                    \
-            if (mass) IGAF_AP1(PP, true, true);                                                       \
-            else IGAF_AP1(PP, true, false);                                                           \
-        } else {                                                                                      \
-            if (mass) IGAF_AP1(PP, false, true);                                                      \
-            else IGAF_AP1(PP, false, false);                                                          \
-        }                                                                                             \
-        break;
-        IGAF_AP(1)
-        IGAF_AP(2)
-        IGAF_AP(3)
-        IGAF_AP(4)
-        IGAF_AP(5)
-#undef IGAF_AP
-#undef IGAF_AP1
-    default:
-        return -4;
-    }
+    hipLaunchKernelGGL((k_apply<P, GEO, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, pd, kappa, u, alphaM,
+                       alphaK, W, G);
+    int64_t sb = (pd.ndof + 255) / 256;
+    if (sb > 8192) sb = 8192;
+    hipLaunchKernelGGL(k_apply_sum<P>, dim3((unsigned)sb), dim3(256), 0, st, W, y, pd.d[0].K, pd.d[1].K,
+                       pd.d[2].K, pd.ndof);
     return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <int P>
+static int launch_apply_p(const PatchDev& pd, const double* kappa, const double* u, double alphaM, double alphaK,
+                          double* y, double* W, hipStream_t st, const double* G, bool diag)
+{
+    if (diag) return launch_apply_t<P, false, AP_DIAG>(pd, kappa, u, alphaM, alphaK, y, W, st, nullptr);
+    if (G) {
+        if (alphaK == 0.0) return launch_apply_t<P, true, AP_MASS>(pd, kappa, u, alphaM, alphaK, y, W, st, G);
+        return launch_apply_t<P, true, AP_FULL>(pd, kappa, u, alphaM, alphaK, y, W, st, G);
+    }
+    if (alphaK == 0.0) return launch_apply_t<P, false, AP_MASS>(pd, kappa, u, alphaM, alphaK, y, W, st, nullptr);
+    return launch_apply_t<P, false, AP_FULL>(pd, kappa, u, alphaM, alphaK, y, W, st, nullptr);
+}
+
+int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM, double alphaK,
+                 double* y, double* W, hipStream_t st, const double* G, bool diag)
+{
+    switch (pd.p) {
+    case 1: return launch_apply_p<1>(pd, kappa, u, alphaM, alphaK, y, W, st, G, diag);
+    case 2: return launch_apply_p<2>(pd, kappa, u, alphaM, alphaK, y, W, st, G, diag);
+    case 3: return launch_apply_p<3>(pd, kappa, u, alphaM, alphaK, y, W, st, G, diag);
+    case 4: return launch_apply_p<4>(pd, kappa, u, alphaM, alphaK, y, W, st, G, diag);
+    case 5: return launch_apply_p<5>(pd, kappa, u, alphaM, alphaK, y, W, st, G, diag);
+    default: return -4;
+    }
 }
 
 }  // namespace igaf

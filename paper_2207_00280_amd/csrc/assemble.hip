@@ -2,6 +2,10 @@
 // the global matrix is the sum of the element matrices, each added at the
 // positions of its functions), and a fill kernel for outputs that are
 // accumulated into.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "common.h"
 #include "launch.h"
 
@@ -111,6 +115,27 @@ int launch_fill_zero(double* a, int64_t n, hipStream_t st)
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, st, a, n);
     return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int device_slots(const void* kernel, int threads)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find({dev, kernel});
+        if (it != cache.end()) return it->second;
+    }
+    int ncu = 0, per = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess)
+        return 0;
+    const int slots = ncu * (per > 0 ? per : 1);
+    std::lock_guard<std::mutex> lock(mu);
+    cache[{dev, kernel}] = slots;
+    return slots;
 }
 
 }  // namespace igaf

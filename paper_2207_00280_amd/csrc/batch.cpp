@@ -23,7 +23,6 @@ using namespace igaf;
 
 namespace {
 
-constexpr int kMaxSplit = 8;          // x segments per tile, at most
 constexpr int kSplits[] = {1, 2, 4, 8};
 constexpr int kChunks[] = {4, 16, 64};
 constexpr int kDefaultChunk = 16;
@@ -83,13 +82,17 @@ struct igaf_batch {
     std::vector<igaf_plan*> plans;
     int device = 0;
     int nitems = 0;
-    int off[kMaxDegree + 2] = {};           // items of degree p: [off[p], off[p + 1])
+    int off[kMaxDegree + 2] = {};           // items of degree p: [off[p], off[p + 1]) of `items`
     int split = 1, chunk = kDefaultChunk;   // work split in use
     double tuned_ms = 0.0;                  // its time when the autotuner chose it
-    size_t cap = 0;                         // items the device list can hold
+    // one immutable device list per split (kSplits order), uploaded at
+    // creation: a re-split only selects another list, so a graph captured
+    // with an earlier split keeps reading the items it was captured with
+    WorkList lists[std::size(kSplits)];
+    int4* d_lists = nullptr;
+    const int4* items = nullptr;            // the list of the split in use
     BatchPatch* d_patches = nullptr;
     BatchPatch* h_patches = nullptr;   // pinned staging of the device table
-    int4* d_items = nullptr;
     bool uploaded = false;
 };
 
@@ -98,25 +101,42 @@ static void batch_free(igaf_batch* B)
     if (!B) return;
     if (B->d_patches) (void)hipFree(B->d_patches);
     if (B->h_patches) (void)hipHostFree(B->h_patches);
-    if (B->d_items) (void)hipFree(B->d_items);
+    if (B->d_lists) (void)hipFree(B->d_lists);
     for (auto* p : B->plans) igaf_plan_destroy(p);
     delete B;
 }
 
-// Build and upload the work list of one split (synchronous: the previous list
-// may still be read by a queued launch).
-static bool set_work_list(igaf_batch* B, int split, int chunk)
+// Build every split's work list and upload them into one device buffer
+// (synchronous, at creation).
+static bool upload_work_lists(igaf_batch* B)
 {
-    WorkList w = build_items(B->plans, split);
-    if (w.items.size() > B->cap) return false;
-    if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(B->d_items, w.items.data(), sizeof(int4) * w.items.size(), hipMemcpyHostToDevice) != hipSuccess)
-        return false;
-    B->nitems = (int)w.items.size();
-    std::copy(std::begin(w.off), std::end(w.off), B->off);
+    size_t total = 0;
+    for (size_t k = 0; k < std::size(kSplits); ++k) {
+        B->lists[k] = build_items(B->plans, kSplits[k]);
+        total += B->lists[k].items.size();
+    }
+    if (hipMalloc(&B->d_lists, sizeof(int4) * std::max<size_t>(1, total)) != hipSuccess) return false;
+    size_t base = 0;
+    for (auto& w : B->lists) {
+        if (!w.items.empty() &&
+            hipMemcpy(B->d_lists + base, w.items.data(), sizeof(int4) * w.items.size(), hipMemcpyHostToDevice) !=
+                hipSuccess)
+            return false;
+        base += w.items.size();
+    }
+    return true;
+}
+
+// Select the work list of one split and the chunking of its launches.
+static void set_work_list(igaf_batch* B, int split, int chunk)
+{
+    size_t base = 0, k = 0;
+    for (; kSplits[k] != split; ++k) base += B->lists[k].items.size();
+    B->items = B->d_lists + base;
+    B->nitems = (int)B->lists[k].items.size();
+    std::copy(std::begin(B->lists[k].off), std::end(B->lists[k].off), B->off);
     B->split = split;
     B->chunk = chunk;
-    return true;
 }
 
 static BatchPatch make_patch(const igaf_plan* p)
@@ -154,15 +174,13 @@ igaf_status igaf_batch_create(const igaf_patch_desc* descs, int32_t npatch, igaf
         batch_free(B);
         return set_error(IGAF_EDEVICE, "hipGetDevice failed");
     }
-    B->cap = std::max<size_t>(1, build_items(B->plans, kMaxSplit).items.size());
-    bool ok = hipMalloc(&B->d_items, sizeof(int4) * B->cap) == hipSuccess &&
-              hipMalloc(&B->d_patches, sizeof(BatchPatch) * npatch) == hipSuccess &&
-              hipHostMalloc(&B->h_patches, sizeof(BatchPatch) * npatch, hipHostMallocDefault) == hipSuccess &&
-              set_work_list(B, 1, kDefaultChunk);
+    bool ok = upload_work_lists(B) && hipMalloc(&B->d_patches, sizeof(BatchPatch) * npatch) == hipSuccess &&
+              hipHostMalloc(&B->h_patches, sizeof(BatchPatch) * npatch, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         batch_free(B);
         return set_error(IGAF_ENOMEM, "batch device allocation failed");
     }
+    set_work_list(B, 1, kDefaultChunk);
     for (int i = 0; i < npatch; ++i) B->h_patches[i] = make_patch(B->plans[i]);
     *out = B;
     return IGAF_OK;
@@ -199,7 +217,7 @@ igaf_status igaf_batch_set_split(igaf_batch* B, int32_t split, int32_t chunk)
     if (std::find(std::begin(kSplits), std::end(kSplits), split) == std::end(kSplits) ||
         std::find(std::begin(kChunks), std::end(kChunks), chunk) == std::end(kChunks))
         return set_error(IGAF_EINVAL, "split must be 1, 2, 4 or 8 and chunk 4, 16 or 64");
-    if (!set_work_list(B, split, chunk)) return set_error(IGAF_EDEVICE, "work list upload failed");
+    set_work_list(B, split, chunk);
     B->tuned_ms = 0.0;
     return IGAF_OK;
 }
@@ -246,7 +264,7 @@ igaf_status igaf_batch_integrate_assemble(igaf_batch* B, const double* const* ka
         hipSuccess)
         return set_error(IGAF_EDEVICE, "patch table upload failed");
     for (int p = kMaxDegree; p >= 1; --p)   // the costliest degrees first
-        if (launch_rows_batch(p, B->d_patches, B->d_items + B->off[p], B->off[p + 1] - B->off[p], B->chunk, s))
+        if (launch_rows_batch(p, B->d_patches, B->items + B->off[p], B->off[p + 1] - B->off[p], B->chunk, s))
             return set_error(IGAF_EDEVICE, "batched launch failed");
     return IGAF_OK;
 }
@@ -268,18 +286,9 @@ igaf_status igaf_batch_autotune(igaf_batch* B, const double* const* kappa, doubl
     igaf_status st = IGAF_OK;
     int best_split = 1, best_chunk = kDefaultChunk;
     double best = INFINITY;
-    int last_split = -1;
     for (int split : kSplits) {
         for (int chunk : kChunks) {
-            if (split != last_split) {
-                if (!set_work_list(B, split, chunk)) {
-                    st = set_error(IGAF_EDEVICE, "work list upload failed");
-                    break;
-                }
-                last_split = split;
-            } else {
-                B->chunk = chunk;   // same list, another launch mapping
-            }
+            set_work_list(B, split, chunk);
             std::vector<float> ms;
             st = igaf_batch_integrate_assemble(B, kappa, Mval, Kval, stream);   // warm-up
             for (int r = 0; r < reps && !st; ++r) {
@@ -307,8 +316,7 @@ igaf_status igaf_batch_autotune(igaf_batch* B, const double* const* kappa, doubl
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (!set_work_list(B, st ? 1 : best_split, st ? kDefaultChunk : best_chunk))
-        return set_error(IGAF_EDEVICE, "work list upload failed");
+    set_work_list(B, st ? 1 : best_split, st ? kDefaultChunk : best_chunk);
     if (st) return st;
     B->tuned_ms = best;
     return IGAF_OK;

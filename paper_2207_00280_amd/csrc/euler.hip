@@ -11,8 +11,9 @@
 // sweeps of banded triangular solves along the grid lines.  Every vector operation runs in the
 // kernels below; the CG scalars stay in device memory (alpha, beta computed
 // on the device), and the host reads back only the residual norm for the
-// convergence test.  Dot products are two-stage and in a fixed order, so the
-// iteration is deterministic up to the atomics of the apply.
+// convergence test.  Dot products are two-stage and in a fixed order and the
+// apply sums every DOF in a fixed order, so the iteration is deterministic:
+// repeated steps give the same bits.
 #include <cmath>
 
 #include "common.h"
@@ -98,17 +99,13 @@ __global__ __launch_bounds__(kDotThreads) void k_cg_xr_rr(double* __restrict__ x
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// p = z + beta p (beta = S[3]); with first != 0: p = z.  Ap = 0 for the mass
-// apply that follows (it adds into Ap).
+// p = z + beta p (beta = S[3]); with first != 0: p = z
 __global__ __launch_bounds__(256) void k_cg_p(double* __restrict__ p, const double* __restrict__ z,
-                                              const double* __restrict__ S, int64_t n, int first,
-                                              double* __restrict__ Ap)
+                                              const double* __restrict__ S, int64_t n, int first)
 {
     const double beta = first ? 0.0 : S[3];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         p[i] = z[i] + beta * (first ? 0.0 : p[i]);
-        Ap[i] = 0.0;
-    }
 }
 
 // r = b - r (r holds M x on entry); x = mu
@@ -134,75 +131,6 @@ int dot(const double* a, const double* c, int64_t n, double* partial, double* S,
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(kDotThreads), 0, st, a, c, n, partial);
     hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kDotThreads), 0, st, partial, kDotBlocks, S, slot, mode);
     return hipGetLastError() == hipSuccess ? 0 : -3;
-}
-
-// d[I] += sum over the elements carrying I of sum_q w_q kappa_q phi_I(x_q)^2
-// (the diagonal of M(kappa)).  A workgroup takes a run of up to XR elements
-// along x in one (ey, ez) row, a thread per (element, local function) pair,
-// the q^3 sum taken one direction at a time; the run's contributions are
-// summed in LDS (neighbouring elements share p of their n DOF columns) and
-// each DOF the run touches gets one atomic add: (XR + p) n^2 instead of
-// XR n^3.
-template <int P>
-struct DiagRun {
-    static constexpr int n = P + 1, Q = P + 1, n2 = n * n, n3 = n2 * n, Q3 = Q * Q * Q;
-    static constexpr int XR = 256 / n3 >= 4 ? 4 * (256 / n3) : 4;   // elements per run
-};
-
-template <int P>
-__global__ __launch_bounds__(256) void k_mass_diag(PatchDev pd, const double* __restrict__ kappa,
-                                                   double* __restrict__ d)
-{
-    using R = DiagRun<P>;
-    constexpr int n = R::n, Q = R::Q, n2 = R::n2, n3 = R::n3, Q3 = R::Q3, XR = R::XR;
-    __shared__ double kap[XR][Q3];
-    __shared__ double sq[XR + 2][n * Q];   // w N_a^2: x tables of the run's elements, then y, z
-    __shared__ double acc[(XR + P) * n2];  // [ex - ex0 + a1][a2 + n a3]
-    const int tid = threadIdx.x;
-    const int Kx = pd.d[0].K, Ky = pd.d[1].K, Nx = pd.d[0].N, Ny = pd.d[1].N;
-    const int nch = (Kx + XR - 1) / XR;
-    const int64_t nruns = (int64_t)nch * Ky * pd.d[2].K;
-    for (int64_t run = blockIdx.x; run < nruns; run += gridDim.x) {
-        const int ch = (int)(run % nch);
-        const int ey = (int)((run / nch) % Ky), ez = (int)(run / ((int64_t)nch * Ky));
-        const int ex0 = ch * XR, len = min(XR, Kx - ex0);
-        const int64_t e0 = ex0 + (int64_t)Kx * (ey + (int64_t)Ky * ez);   // the run's elements: e0 + s
-        for (int i = tid; i < XR * Q3; i += 256) {
-            const int sidx = i / Q3;
-            kap[sidx][i % Q3] = sidx < len ? kappa[(e0 + sidx) * Q3 + i % Q3] : 0.0;
-        }
-        for (int i = tid; i < (XR + 2) * n * Q; i += 256) {
-            const int tb = i / (n * Q), r = i % (n * Q);
-            const int dd = tb < XR ? 0 : tb - XR + 1;
-            const int ed = dd == 0 ? min(ex0 + tb, Kx - 1) : (dd == 1 ? ey : ez);
-            const double v = pd.d[dd].Nv[(int64_t)ed * n * Q + r];
-            sq[tb][r] = pd.d[dd].wq[(int64_t)ed * Q + r % Q] * v * v;
-        }
-        for (int i = tid; i < (XR + P) * n2; i += 256) acc[i] = 0.0;
-        __syncthreads();
-        for (int i = tid; i < len * n3; i += 256) {
-            const int sidx = i / n3, l = i % n3;
-            const int a1 = l % n, a2 = (l / n) % n, a3 = l / n2;
-            double sum = 0.0;
-            for (int kz = 0; kz < Q; ++kz) {
-                double sy = 0.0;
-                for (int ky = 0; ky < Q; ++ky) {
-                    double sx = 0.0;
-#pragma unroll
-                    for (int kx = 0; kx < Q; ++kx) sx += sq[sidx][a1 * Q + kx] * kap[sidx][kx + Q * (ky + Q * kz)];
-                    sy += sq[XR][a2 * Q + ky] * sx;
-                }
-                sum += sq[XR + 1][a3 * Q + kz] * sy;
-            }
-            atomicAdd(&acc[(sidx + a1) * n2 + a2 + n * a3], sum);
-        }
-        __syncthreads();
-        for (int i = tid; i < (len + P) * n2; i += 256) {
-            const int c = i / n2, r = i % n2;
-            atomicAdd(&d[(ex0 + c) + (int64_t)Nx * ((ey + r % n) + (int64_t)Ny * (ez + r / n))], acc[i]);
-        }
-        __syncthreads();   // acc, kap and sq are rewritten by the next run
-    }
 }
 
 // s[I] <- sqrt(diag(Mz (x) My (x) Mx)_I / s[I]) (s holds diag(M(kappa)) on entry)
@@ -312,16 +240,6 @@ __global__ __launch_bounds__(64) void k_line_solve(double* __restrict__ v, const
 }
 
 template <int P>
-int launch_mass_diag_t(const PatchDev& pd, const double* kappa, double* d, hipStream_t st)
-{
-    constexpr int XR = DiagRun<P>::XR;
-    const int64_t runs = (int64_t)((pd.d[0].K + XR - 1) / XR) * pd.d[1].K * pd.d[2].K;
-    const int64_t blocks = runs < (1 << 20) ? runs : (1 << 20);
-    hipLaunchKernelGGL(k_mass_diag<P>, dim3((unsigned)blocks), dim3(256), 0, st, pd, kappa, d);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
-}
-
-template <int P>
 int launch_line_solves_t(const PatchDev& pd, double* v, int64_t ndof, hipStream_t st)
 {
     int64_t inner = 1;
@@ -333,18 +251,6 @@ int launch_line_solves_t(const PatchDev& pd, double* v, int64_t ndof, hipStream_
         inner *= N;
     }
     return hipGetLastError() == hipSuccess ? 0 : -3;
-}
-
-int launch_mass_diag(const PatchDev& pd, const double* kappa, double* d, hipStream_t st)
-{
-    switch (pd.p) {
-    case 1: return launch_mass_diag_t<1>(pd, kappa, d, st);
-    case 2: return launch_mass_diag_t<2>(pd, kappa, d, st);
-    case 3: return launch_mass_diag_t<3>(pd, kappa, d, st);
-    case 4: return launch_mass_diag_t<4>(pd, kappa, d, st);
-    case 5: return launch_mass_diag_t<5>(pd, kappa, d, st);
-    default: return -4;
-    }
 }
 
 int launch_line_solves(const PatchDev& pd, double* v, int64_t ndof, hipStream_t st)
@@ -361,9 +267,13 @@ int launch_line_solves(const PatchDev& pd, double* v, int64_t ndof, hipStream_t 
 
 }  // namespace
 
-int64_t euler_workspace_doubles(int64_t ndof) { return 6 * ndof + kDotBlocks + 8; }
+int64_t euler_workspace_doubles(const PatchDev& pd, int64_t ndof)
+{
+    return 6 * ndof + kDotBlocks + 8 + apply_workspace_doubles(pd);
+}
 
-// Workspace: b | r | p | Ap | z | s (ndof each) | dot partials | CG scalars S[8]:
+// Workspace: b | r | p | Ap | z | s (ndof each) | dot partials | CG scalars S[8]
+// | the operator apply's run slots:
 // S[0] r.z, S[1] p.Ap, S[2] new r.z, S[3] beta, S[4] alpha, S[5] r.r.
 // Without a preconditioner z is r itself.  Returns 0 (converged), 1 (maxit
 // reached) or -3 (launch failure).
@@ -382,12 +292,10 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
     double* sc = Ap + 2 * ndof;
     double* partial = Ap + 3 * ndof;
     double* S = partial + kDotBlocks;
+    double* Wap = S + 8;
     const int gv = grid_for(ndof);
-    auto mass_apply = [&](const double* v, double* out, double aK) {
-        return launch_fill_zero(out, ndof, st) || launch_apply(pd, kappa, v, 1.0, aK, out, st) ? -3 : 0;
-    };
-    auto mass_apply_zeroed = [&](const double* v, double* out) {   // out already zero
-        return launch_apply(pd, kappa, v, 1.0, 0.0, out, st) ? -3 : 0;
+    auto mass_apply = [&](const double* v, double* out) {
+        return launch_apply(pd, kappa, v, 1.0, 0.0, out, Wap, st) ? -3 : 0;
     };
     auto host_scalar = [&](int slot, double* out) {
         return hipMemcpyAsync(out, S + slot, sizeof(double), hipMemcpyDeviceToHost, st) == hipSuccess &&
@@ -406,15 +314,13 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
     *iters = 0;
     *relres = 0.0;
     if (precond) {
-        if (launch_fill_zero(sc, ndof, st) || launch_mass_diag(pd, kappa, sc, st)) return -3;
+        if (launch_apply(pd, kappa, nullptr, 1.0, 0.0, sc, Wap, st, nullptr, true)) return -3;   // diag(M)
         const int W = pd.p + 2;
         hipLaunchKernelGGL(k_precond_scale, dim3(gv), dim3(256), 0, st, sc, pd.d[0].Lm, pd.d[1].Lm,
                            pd.d[2].Lm, pd.d[0].N, pd.d[1].N, W, ndof);
     }
     // right-hand side b = M mu - dt K mu; r = M mu (x starts at mu)
-    if (launch_fill_zero(b, ndof, st) || launch_apply(pd, kappa, mu, 1.0, -dt, b, st, G) ||
-        mass_apply(mu, r, 0.0))
-        return -3;
+    if (launch_apply(pd, kappa, mu, 1.0, -dt, b, Wap, st, G) || mass_apply(mu, r)) return -3;
     double bb = 0.0, rr = 0.0;
     if (dot(b, b, ndof, partial, S, 1, 0, st) || host_scalar(1, &bb)) return -3;
     hipLaunchKernelGGL(k_cg_init, dim3(gv), dim3(256), 0, st, r, b, x, mu, ndof);
@@ -426,8 +332,8 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
     *relres = std::sqrt(rr / bb);
     if (*relres <= tol) return 0;
     if (apply_precond() || dot(r, z, ndof, partial, S, 0, 0, st)) return -3;
-    hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 1, Ap);
-    if (mass_apply_zeroed(p, Ap)) return -3;
+    hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 1);
+    if (mass_apply(p, Ap)) return -3;
     if (dot(p, Ap, ndof, partial, S, 1, 1, st)) return -3;       // alpha
     // Each iteration's r.r is read back through a pinned slot while the GPU
     // already runs the next iteration's work up to its update of x and r
@@ -445,9 +351,9 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
         if (k < maxit) {
             if (apply_precond()) return -3;
             if (dot(r, z, ndof, partial, S, 2, 2, st)) return -3;    // beta, new r.z
-            hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 0, Ap);
+            hipLaunchKernelGGL(k_cg_p, dim3(gv), dim3(256), 0, st, p, z, S, ndof, 0);
             if (hipGetLastError() != hipSuccess) return -3;
-            if (mass_apply_zeroed(p, Ap)) return -3;
+            if (mass_apply(p, Ap)) return -3;
             if (dot(p, Ap, ndof, partial, S, 1, 1, st)) return -3;   // alpha
         }
         if (hipEventSynchronize(ev) != hipSuccess) return -3;

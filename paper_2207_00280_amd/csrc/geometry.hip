@@ -229,16 +229,8 @@ template <int P, bool ATOMIC>
 static int launch_geo_t(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
                         double* Mv, double* Kv, int64_t e0, int64_t e1, hipStream_t st)
 {
-    static int slots = 0;
-    if (!slots) {
-        int dev = 0, ncu = 0, per = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_element_geo<P, ATOMIC>, kGeoThreads, 0) !=
-                hipSuccess)
-            return -3;
-        slots = ncu * (per > 0 ? per : 1);
-    }
+    const int slots = device_slots((const void*)k_element_geo<P, ATOMIC>, kGeoThreads);
+    if (!slots) return -3;
     if (e1 <= e0) return 0;
     const int64_t blocks = e1 - e0 < slots ? e1 - e0 : slots;
     hipLaunchKernelGGL((k_element_geo<P, ATOMIC>), dim3((unsigned)blocks), dim3(kGeoThreads), 0, st, pd,

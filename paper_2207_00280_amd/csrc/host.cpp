@@ -664,30 +664,31 @@ igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double
                                       (hipStream_t)stream), "kappa gradient");
 }
 
+int64_t igaf_apply_workspace(const igaf_plan* plan)
+{
+    return plan && plan_hot_supported(plan) ? apply_workspace_doubles(plan->dev) : 0;
+}
+
 igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double* u,
-                       double alphaM, double alphaK, double* y, void* stream)
+                       double alphaM, double alphaK, double* y, double* work, void* stream)
 {
     igaf_status st = check_hot(plan, IGAF_SUMFACT);
     if (st) return st;
-    if (!kappa || !u || !y) return fail(IGAF_EINVAL, "kappa, u or y is NULL");
+    if (!kappa || !u || !y || !work) return fail(IGAF_EINVAL, "kappa, u, y or work is NULL");
     if (u == y) return fail(IGAF_EINVAL, "y must not overlap u");
-    hipStream_t s = (hipStream_t)stream;
-    st = launched(launch_fill_zero(y, plan->ndof, s), "zero");
-    if (st) return st;
-    return launched(launch_apply(plan->dev, kappa, u, alphaM, alphaK, y, s), "operator apply");
+    return launched(launch_apply(plan->dev, kappa, u, alphaM, alphaK, y, work, (hipStream_t)stream),
+                    "operator apply");
 }
 
 igaf_status igaf_apply_geo(const igaf_plan* plan, const double* cm, const double* G, const double* u,
-                           double alphaM, double alphaK, double* y, void* stream)
+                           double alphaM, double alphaK, double* y, double* work, void* stream)
 {
     igaf_status st = check_hot(plan, IGAF_SUMFACT);
     if (st) return st;
-    if (!cm || !G || !u || !y) return fail(IGAF_EINVAL, "cm, G, u or y is NULL");
+    if (!cm || !G || !u || !y || !work) return fail(IGAF_EINVAL, "cm, G, u, y or work is NULL");
     if (u == y) return fail(IGAF_EINVAL, "y must not overlap u");
-    hipStream_t s = (hipStream_t)stream;
-    st = launched(launch_fill_zero(y, plan->ndof, s), "zero");
-    if (st) return st;
-    return launched(launch_apply(plan->dev, cm, u, alphaM, alphaK, y, s, G), "mapped-geometry apply");
+    return launched(launch_apply(plan->dev, cm, u, alphaM, alphaK, y, work, (hipStream_t)stream, G),
+                    "mapped-geometry apply");
 }
 
 igaf_status igaf_kappa_grad_geo(const igaf_plan* plan, const double* cm0, const double* G0, const double* u,
@@ -704,7 +705,7 @@ igaf_status igaf_kappa_grad_geo(const igaf_plan* plan, const double* cm0, const 
 
 int64_t igaf_euler_workspace(const igaf_plan* plan)
 {
-    return plan ? euler_workspace_doubles(plan->ndof) : 0;
+    return plan && plan_hot_supported(plan) ? euler_workspace_doubles(plan->dev, plan->ndof) : 0;
 }
 
 static igaf_status euler_any(const igaf_plan* plan, const double* kappa, const double* G, const double* mu,

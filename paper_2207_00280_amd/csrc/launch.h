@@ -45,20 +45,29 @@ int launch_gather(const PatchDev& pd, const double* Me, const double* Ke, double
 
 int launch_fill_zero(double* a, int64_t n, hipStream_t st);
 
+// Workgroups of `kernel` (launched with `threads` threads and no dynamic LDS)
+// that the current device runs at once: compute units times the occupancy.
+// Cached per (device, kernel); returns 0 if the device cannot be queried.
+int device_slots(const void* kernel, int threads);
+
 // element matrices (and/or atomically assembled CSR values) on a mapped
 // geometry: cm [E][q^3], G [E][6][q^3]; elements [e0, e1) (all by default),
 // element e's matrices written to slot e - e0
 int launch_element_geo(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
                        double* Mv, double* Kv, hipStream_t st, int64_t e0 = 0, int64_t e1 = -1);
-// y += alphaM M(kappa) u + alphaK K(kappa) u by FP64 atomics (y zeroed by the
-// caller); with G, kappa is the mass coefficient cm and G the stiffness tensor
-int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM,
-                 double alphaK, double* y, hipStream_t st, const double* G = nullptr);
+// y = alphaM M(kappa) u + alphaK K(kappa) u (overwritten; no atomics: each
+// x-run of elements writes its DOF values to its slot of W, then one thread
+// per DOF sums the slots in a fixed order); with G, kappa is the mass
+// coefficient cm and G the stiffness tensor; with diag, y = alphaM
+// diag(M(kappa)) and u is not read.  W: apply_workspace_doubles(pd) doubles.
+int64_t apply_workspace_doubles(const PatchDev& pd);
+int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM, double alphaK,
+                 double* y, double* W, hipStream_t st, const double* G = nullptr, bool diag = false);
 
 // Forward Euler step: b = M mu - dt K mu, then CG on M x = b from x = mu.
 // rb: pinned host slot for the residual read-back, ev: an event for it.
 // Returns 0 (converged), 1 (maxit reached) or -3.
-int64_t euler_workspace_doubles(int64_t ndof);
+int64_t euler_workspace_doubles(const PatchDev& pd, int64_t ndof);
 int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const double* mu, double dt,
                    double tol, int maxit, int precond, double* x, double* work, int* iters, double* relres,
                    hipStream_t st, double* rb, hipEvent_t ev, const double* G = nullptr);

@@ -577,15 +577,8 @@ static int launch_rows_tile_t(const PatchDev& pd, const double* kappa, double* M
     const int ntile = nty * ntz;
     // x segments: enough workgroups to keep every slot busy to the end, each
     // segment paying p warm-up elements (stages z and y only)
-    static int slots = 0;
-    if (!slots) {
-        int dev = 0, ncu = 0, per = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rows_tile<T>, T::NT, 0) != hipSuccess)
-            return -3;
-        slots = ncu * (per > 0 ? per : 1);
-    }
+    const int slots = device_slots((const void*)k_rows_tile<T>, T::NT);
+    if (!slots) return -3;
     // cost in element steps: the items spread over the slots, plus one item
     // as the tail; a segment pays ~4p/3 steps of warm-up and start-up (fitted
     // to sweeps of the segment count at 64^3 and 128^3)
@@ -674,6 +667,7 @@ __global__ __launch_bounds__(T::NT) __attribute__((amdgpu_waves_per_eu(T::WPE)))
     const double* kappa;
     double *Mv, *Kv;
     uniform_patch(patches[pid], pd, rm, kappa, Mv, Kv);
+    if (pd.p != T::P) return;   // not an item of this degree (whole workgroup)
     tile_run<T>(pd, rm, kappa, Mv, Kv, tile, seg, (pd.d[1].N + T::TY - 1) / T::TY, seglen, lds);
 }
 

@@ -7,9 +7,13 @@ namespace igaf {
 
 // One thread per (element e, Gauss point k) of one direction.  The p+1
 // functions that are non-zero on span s = e+p are built with the local
-// triangular form of the Cox-de Boor recursion (every denominator is a knot
-// difference that contains the span, so none is zero while the span is not
-// empty); the derivative uses the standard B-spline derivative formula with
+// triangular form of the Cox-de Boor recursion, the published scheme of
+// Piegl and Tiller (The NURBS Book, 2nd ed., Algorithms A2.2 "BasisFuns" and
+// A2.3 "DersBasisFuns": the ndu triangle holding the values of each degree
+// above its diagonal and the knot differences below it, with the left/right
+// distance arrays).  Every denominator is a knot difference that contains the
+// span, so none is zero while the span is not empty; the first derivative
+// uses the standard B-spline derivative formula (the same book, eq. 2.9) with
 // the degree p-1 values of the same triangle.  A span of zero length (a
 // repeated interior knot) has zero Gauss weights: all of its tables are zero,
 // so the element adds nothing anywhere.

@@ -23,7 +23,8 @@ SYMBOLS = [
     "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_csr_pattern_host",
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes", "igaf_quad_points",
     "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
-    "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_apply",
+    "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_apply_workspace",
+    "igaf_apply",
     "igaf_apply_geo", "igaf_kappa_grad_geo", "igaf_euler_step_geo", "igaf_euler_workspace", "igaf_euler_step",
     "igaf_batch_create", "igaf_batch_destroy",
     "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
@@ -80,9 +81,11 @@ def lib():
     L.igaf_integrate_assemble.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
     L.igaf_kappa_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, _vp, _vp]
-    L.igaf_apply.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]
+    L.igaf_apply_workspace.argtypes = [_vp]
+    L.igaf_apply_workspace.restype = ctypes.c_int64
+    L.igaf_apply.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]
     L.igaf_integrate_assemble_geo.argtypes = [_vp] * 8
-    L.igaf_apply_geo.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]
+    L.igaf_apply_geo.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]
     L.igaf_kappa_grad_geo.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, _vp, _vp]
     L.igaf_euler_workspace.argtypes = [_vp]
@@ -269,9 +272,15 @@ class Plan:
         _check(lib().igaf_csr_pattern(self._h, _ptr(rp), _ptr(col), _stream(stream)))
         return rp, col
 
-    def _alloc(self, *shape):
+    def _alloc(self, *shape, stream=None):
+        """A float64 device tensor; with an explicit stream it is allocated on
+        that stream, so that the caching allocator does not hand its memory to
+        other streams while work queued on `stream` may still use it."""
         torch = _torch()
-        return torch.empty(*shape, dtype=torch.float64, device="cuda")
+        if stream is None:
+            return torch.empty(*shape, dtype=torch.float64, device="cuda")
+        with torch.cuda.stream(stream):
+            return torch.empty(*shape, dtype=torch.float64, device="cuda")
 
     def element_matrices(self, kappa, method=SUMFACT, want_m=True, want_k=True, Me=None, Ke=None,
                          stream=None):
@@ -358,15 +367,29 @@ class Plan:
                                                  _ptr(Mval), _ptr(Kval), _stream(stream)))
         return Me, Ke, Mval, Kval
 
-    def apply(self, kappa, u, alphaM=1.0, alphaK=1.0, y=None, stream=None):
+    def apply_workspace(self):
+        """Doubles of scratch igaf_apply needs (the runs' slots)."""
+        return int(lib().igaf_apply_workspace(self._h))
+
+    def _apply_work(self, work, stream):
+        nw = self.apply_workspace()
+        if work is None:
+            work = self._alloc(nw, stream=stream)
+        _need_f64_cuda(work, "work", None)
+        if work.numel() < nw:
+            raise ValueError("work has %d elements, needs %d" % (work.numel(), nw))
+        return work
+
+    def apply(self, kappa, u, alphaM=1.0, alphaK=1.0, y=None, work=None, stream=None):
         """y = alphaM M(kappa) u + alphaK K(kappa) u, matrix-free (igaf_apply)."""
         _need_f64_cuda(kappa, "kappa", self.nelem * self.nqp)
         _need_f64_cuda(u, "u", self.ndof)
         if y is None:
-            y = self._alloc(self.ndof)
+            y = self._alloc(self.ndof, stream=stream)
         _need_f64_cuda(y, "y", self.ndof)
+        work = self._apply_work(work, stream)
         _check(lib().igaf_apply(self._h, _ptr(kappa), _ptr(u), float(alphaM), float(alphaK),
-                                _ptr(y), _stream(stream)))
+                                _ptr(y), _ptr(work), _stream(stream)))
         return y
 
     def euler_step(self, kappa, mu, dt, tol=1e-12, maxit=1000, precond=None, out=None, work=None,
@@ -389,11 +412,12 @@ class Plan:
         _need_f64_cuda(kappa, "kappa", self.nelem * self.nqp)
         _need_f64_cuda(mu, "mu", self.ndof)
         if out is None:
-            out = self._alloc(self.ndof)
+            out = self._alloc(self.ndof, stream=stream)
         _need_f64_cuda(out, "out", self.ndof)
         nw = int(lib().igaf_euler_workspace(self._h))
         if work is None:
-            work = self._alloc(nw)
+            # work after the last iteration may still run on `stream`: allocate there
+            work = self._alloc(nw, stream=stream)
         _need_f64_cuda(work, "work", nw)
         it = ctypes.c_int32(0)
         rr = ctypes.c_double(0.0)
@@ -408,16 +432,17 @@ class Plan:
                                              ctypes.byref(rr), _stream(stream)))
         return out, it.value, rr.value
 
-    def apply_geo(self, cm, G, u, alphaM=1.0, alphaK=1.0, y=None, stream=None):
+    def apply_geo(self, cm, G, u, alphaM=1.0, alphaK=1.0, y=None, work=None, stream=None):
         """Mapped-geometry apply (igaf_apply_geo): y = alphaM M u + alphaK K u."""
         _need_f64_cuda(cm, "cm", self.nelem * self.nqp)
         _need_f64_cuda(G, "G", self.nelem * 6 * self.nqp)
         _need_f64_cuda(u, "u", self.ndof)
         if y is None:
-            y = self._alloc(self.ndof)
+            y = self._alloc(self.ndof, stream=stream)
         _need_f64_cuda(y, "y", self.ndof)
+        work = self._apply_work(work, stream)
         _check(lib().igaf_apply_geo(self._h, _ptr(cm), _ptr(G), _ptr(u), float(alphaM), float(alphaK),
-                                    _ptr(y), _stream(stream)))
+                                    _ptr(y), _ptr(work), _stream(stream)))
         return y
 
     def kappa_grad_geo(self, cm0, G0, u, v, alphaM=1.0, alphaK=1.0, scale=1.0, grad=None, stream=None):

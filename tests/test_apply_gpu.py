@@ -4,9 +4,8 @@ y = alphaM M(kappa) u + alphaK K(kappa) u without forming any matrix.  The
 oracle's assembled matrices (the plain definition: the sum of the element
 matrices of Algorithm 1) give y = A u entry by entry on small patches; at
 full size the oracle's complete rows give sampled entries one by one, and
-closed forms pin K 1 = 0 and 1^T M 1 = sum_q w_q kappa_q.  The element
-results are added with atomics, so y is compared within rounding, not
-bitwise.
+closed forms pin K 1 = 0 and 1^T M 1 = sum_q w_q kappa_q.  Each y_I is
+summed in a fixed order (no atomics), so repeated calls give the same bits.
 """
 import math
 
@@ -115,6 +114,36 @@ def test_apply_fullscale(orc, ig):
     assert abs(L - Lg) <= 1e-12 * abs(L)
 
 
+@pytest.mark.parametrize("p,K", [(1, (70, 2, 3)), (3, (70, 3, 2)), (5, (37, 2, 1))])
+def test_apply_run_boundaries(orc, ig, p, K):
+    """K_x beyond one run of 32 elements, with a ragged last run: DOFs where
+    two runs meet take both runs' values.  Every entry of y vs the oracle's
+    A u, and two calls (fresh workspaces, the second filled with NaN first)
+    give the same bits."""
+    import torch
+
+    knots = [nonuniform_knots(k, p, 7 * p + d) for d, k in enumerate(K)]
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    plan = ig.Plan(p, K, knots)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=21 + p)
+    u = W.normal_vector(P.ndof, 22 + p)
+    rp, col, Mo, Ko = orc.assemble(P, kap)
+    ref = 0.8 * (_csr(rp, col, Mo, P.ndof) @ u) - 1.7 * (_csr(rp, col, Ko, P.ndof) @ u)
+    kd, ud = to_dev(kap), to_dev(u)
+    y1 = plan.apply(kd, ud, 0.8, -1.7)
+    w = torch.full((plan.apply_workspace(),), float("nan"), dtype=torch.float64, device="cuda")
+    y2 = torch.full_like(y1, float("nan"))
+    plan.apply(kd, ud, 0.8, -1.7, y=y2, work=w)
+    torch.cuda.synchronize()
+    assert relfro(to_host(y1), ref) <= 1e-12
+    assert torch.equal(y1, y2)
+    m1 = plan.apply(kd, ud, 1.0, 0.0)
+    m2 = plan.apply(kd, ud, 1.0, 0.0, work=w)
+    torch.cuda.synchronize()
+    assert relfro(to_host(m1), _csr(rp, col, Mo, P.ndof) @ u) <= 1e-12
+    assert torch.equal(m1, m2)
+
+
 def test_apply_errors(ig):
     """NULL, aliased and wrongly sized arguments are refused before any launch."""
     import torch
@@ -123,8 +152,14 @@ def test_apply_errors(ig):
     plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
     kd = to_dev(np.ones((plan.nelem, plan.nqp)))
     u = to_dev(np.ones(plan.ndof))
+    y = to_dev(np.zeros(plan.ndof))
+    w = to_dev(np.zeros(plan.apply_workspace()))
     L = ig.lib()
-    assert L.igaf_apply(plan._h, None, u.data_ptr(), 1.0, 1.0, u.data_ptr(), None) == ig.EINVAL
-    assert L.igaf_apply(plan._h, kd.data_ptr(), u.data_ptr(), 1.0, 1.0, u.data_ptr(), None) == ig.EINVAL
+    assert L.igaf_apply(plan._h, None, u.data_ptr(), 1.0, 1.0, y.data_ptr(), w.data_ptr(), None) == ig.EINVAL
+    assert L.igaf_apply(plan._h, kd.data_ptr(), u.data_ptr(), 1.0, 1.0, u.data_ptr(), w.data_ptr(),
+                        None) == ig.EINVAL
+    assert L.igaf_apply(plan._h, kd.data_ptr(), u.data_ptr(), 1.0, 1.0, y.data_ptr(), None, None) == ig.EINVAL
+    with pytest.raises(ValueError):
+        plan.apply(kd, u, work=to_dev(np.zeros(plan.apply_workspace() - 1)))
     with pytest.raises(ValueError):
         plan.apply(kd, torch.ones(plan.ndof + 1, dtype=torch.float64, device="cuda"))

@@ -69,7 +69,8 @@ def test_batch_small_vs_oracle(orc, ig):
 
 def test_batch_graph_replay(ig):
     """The batched launch captured in a HIP graph: three replays, with
-    eager work between them, each equal to the eager result."""
+    eager work between them, each equal to the eager result; a replay after a
+    re-split (and an eager call with the new split) still equals it."""
     import torch
 
     specs = _small_specs(7)
@@ -95,6 +96,23 @@ def test_batch_graph_replay(ig):
         for a, b in zip(got, ref):
             assert torch.equal(a, b), r
         _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+    # a re-split after capture selects another work list; the graph keeps the
+    # list it was captured with, and an eager call with the new split and the
+    # same pointers gives the same bits
+    B.set_split(8, 4)
+    for t in Ms + Ks:
+        t.fill_(-1.0)
+    B.integrate_assemble(kaps, Ms, Ks)
+    torch.cuda.synchronize()
+    for a, b in zip(Ms + Ks, ref):
+        assert torch.equal(a, b)
+    for t in Ms + Ks:
+        t.fill_(-1.0)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for a, b in zip(Ms + Ks, ref):
+        assert torch.equal(a, b)
 
 
 def test_batch_autotune(ig):
