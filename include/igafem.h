@@ -265,6 +265,20 @@ int64_t igaf_apply_workspace(const igaf_plan* plan);
 igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double* u,
                        double alphaM, double alphaK, double* y, double* work, void* stream);
 
+/* The operator apply of igaf_apply (same kernels, same bits) for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops): the runs' slots live in a static device array of the library
+ * (64 MiB, 8 388 608 doubles, one per device, held until the process ends;
+ * its address is looked up when a plan is created on the device), so the
+ * call allocates nothing and takes no workspace.  Patches needing more than
+ * that (igaf_apply_workspace(plan) > 8 388 608, e.g. beyond about 480 000
+ * elements at p = 3) are rejected with IGAF_EUNSUPPORTED before any launch.
+ * Every call on one device shares the array and leaves its last contents
+ * there (nothing in it needs clearing: each call writes every slot value it
+ * reads): calls that overlap on one device (other streams or threads) race. */
+igaf_status igaf_apply_static(const igaf_plan* plan, const double* kappa, const double* u,
+                              double alphaM, double alphaK, double* y, void* stream);
+
 /* The operator apply on a mapped geometry (the coefficients of
  * igaf_integrate_assemble_geo): y = alphaM M u + alphaK K u with
  *   M_IJ = sum_q w_q cm_q phi_I phi_J,  K_IJ = sum_q w_q grad_xi phi_I^T G_q grad_xi phi_J.

@@ -33,6 +33,9 @@
 // The diagonal mode computes d_I = sum_q c_q phi_I(x_q)^2 = diag(M(kappa))
 // with the same transposed stages, squared tables and no u (the Euler step's
 // preconditioner scaling).
+#include <mutex>
+#include <vector>
+
 #include "common.h"
 #include "launch.h"
 
@@ -465,6 +468,42 @@ __global__ __launch_bounds__(256) void k_apply_sum(const double* __restrict__ W,
         }
         y[i] = s;
     }
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free apply (igaf_apply_static): the runs' slots in a
+// file-scope device array of fixed size instead of a caller workspace.  Every
+// device the library runs on holds its own copy until the process ends; its
+// address is looked up once per device (apply_scratch_init, called when a
+// plan is created) and only that address is handed to the kernels.
+constexpr int64_t kApplyScratchDoubles = int64_t(8) << 20;   // 64 MiB
+static __device__ __align__(256) double scratch[kApplyScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;   // per device id
+}  // namespace
+
+int apply_scratch_init()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return -3;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((size_t)dev < g_scratch_ptr.size() && g_scratch_ptr[dev]) return 0;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return -3;
+    if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize(dev + 1, nullptr);
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    return 0;
+}
+
+double* apply_scratch(int64_t* capacity)
+{
+    *capacity = kApplyScratchDoubles;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (size_t)dev < g_scratch_ptr.size() ? g_scratch_ptr[dev] : nullptr;
 }
 
 int64_t apply_workspace_doubles(const PatchDev& pd)

@@ -310,6 +310,10 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
         delete P;
         return fail(IGAF_EDEVICE, "hipGetDevice failed (no GPU?)");
     }
+    if (apply_scratch_init() != 0) {   // once per device: the static scratch's address
+        delete P;
+        return fail(IGAF_EDEVICE, "static scratch lookup failed: %s", hipGetErrorString(hipGetLastError()));
+    }
     if (hipMalloc(&P->dmem, sizeof(double) * dcount) != hipSuccess) {
         delete P;
         return fail(IGAF_ENOMEM, "hipMalloc of %lld doubles failed", (long long)dcount);
@@ -678,6 +682,26 @@ igaf_status igaf_apply(const igaf_plan* plan, const double* kappa, const double*
     if (u == y) return fail(IGAF_EINVAL, "y must not overlap u");
     return launched(launch_apply(plan->dev, kappa, u, alphaM, alphaK, y, work, (hipStream_t)stream),
                     "operator apply");
+}
+
+igaf_status igaf_apply_static(const igaf_plan* plan, const double* kappa, const double* u, double alphaM,
+                              double alphaK, double* y, void* stream)
+{
+    igaf_status st = check_hot(plan, IGAF_SUMFACT);
+    if (st) return st;
+    if (!kappa || !u || !y) return fail(IGAF_EINVAL, "kappa, u or y is NULL");
+    if (u == y) return fail(IGAF_EINVAL, "y must not overlap u");
+    int64_t cap = 0;
+    double* w = apply_scratch(&cap);
+    const int64_t need = apply_workspace_doubles(plan->dev);
+    if (need > cap)
+        return fail(IGAF_EUNSUPPORTED,
+                    "igaf_apply_static: this patch needs %lld doubles of scratch, the static array holds %lld "
+                    "(igaf_apply takes a workspace of any size)",
+                    (long long)need, (long long)cap);
+    if (!w) return fail(IGAF_EDEVICE, "igaf_apply_static: no scratch address on the current device");
+    return launched(launch_apply(plan->dev, kappa, u, alphaM, alphaK, y, w, (hipStream_t)stream),
+                    "operator apply (static scratch)");
 }
 
 igaf_status igaf_apply_geo(const igaf_plan* plan, const double* cm, const double* G, const double* u,

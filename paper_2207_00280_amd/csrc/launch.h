@@ -61,6 +61,11 @@ int launch_element_geo(const PatchDev& pd, const double* cm, const double* G, do
 // coefficient cm and G the stiffness tensor; with diag, y = alphaM
 // diag(M(kappa)) and u is not read.  W: apply_workspace_doubles(pd) doubles.
 int64_t apply_workspace_doubles(const PatchDev& pd);
+// The static device scratch of the allocation-free apply: look up its
+// address on the current device (once per device; 0 or -3), and get it
+// (nullptr before the lookup) with its capacity in doubles.
+int apply_scratch_init();
+double* apply_scratch(int64_t* capacity);
 int launch_apply(const PatchDev& pd, const double* kappa, const double* u, double alphaM, double alphaK,
                  double* y, double* W, hipStream_t st, const double* G = nullptr, bool diag = false);
 

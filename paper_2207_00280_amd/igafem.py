@@ -24,7 +24,7 @@ SYMBOLS = [
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes", "igaf_quad_points",
     "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
     "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_apply_workspace",
-    "igaf_apply",
+    "igaf_apply", "igaf_apply_static",
     "igaf_apply_geo", "igaf_kappa_grad_geo", "igaf_euler_step_geo", "igaf_euler_workspace", "igaf_euler_step",
     "igaf_batch_create", "igaf_batch_destroy",
     "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
@@ -84,6 +84,7 @@ def lib():
     L.igaf_apply_workspace.argtypes = [_vp]
     L.igaf_apply_workspace.restype = ctypes.c_int64
     L.igaf_apply.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]
+    L.igaf_apply_static.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]
     L.igaf_integrate_assemble_geo.argtypes = [_vp] * 8
     L.igaf_apply_geo.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]
     L.igaf_kappa_grad_geo.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
@@ -431,6 +432,16 @@ class Plan:
                                              int(maxit), precond, _ptr(out), _ptr(work), ctypes.byref(it),
                                              ctypes.byref(rr), _stream(stream)))
         return out, it.value, rr.value
+
+    def apply_static(self, kappa, u, y, alphaM=1.0, alphaK=1.0, stream=None):
+        """igaf_apply_static: the apply with the library's static scratch (no
+        workspace, nothing allocated); y must be given."""
+        _need_f64_cuda(kappa, "kappa", self.nelem * self.nqp)
+        _need_f64_cuda(u, "u", self.ndof)
+        _need_f64_cuda(y, "y", self.ndof)
+        _check(lib().igaf_apply_static(self._h, _ptr(kappa), _ptr(u), float(alphaM), float(alphaK), _ptr(y),
+                                       _stream(stream)))
+        return y
 
     def apply_geo(self, cm, G, u, alphaM=1.0, alphaK=1.0, y=None, work=None, stream=None):
         """Mapped-geometry apply (igaf_apply_geo): y = alphaM M u + alphaK K u."""

@@ -143,6 +143,7 @@ def test_null_arguments():
     assert L.igaf_kappa_grad(None, None, None, 1.0, 1.0, 1.0, None, None) == ig.EINVAL
     assert L.igaf_apply(None, None, None, 1.0, 1.0, None, None, None) == ig.EINVAL
     assert L.igaf_apply_workspace(None) == 0
+    assert L.igaf_apply_static(None, None, None, 1.0, 1.0, None, None) == ig.EINVAL
     assert L.igaf_euler_step(None, None, None, 0.1, 1e-12, 10, 1, None, None, None, None, None) == ig.EINVAL
     assert L.igaf_euler_workspace(None) == 0
     assert L.igaf_assemble(None, None, None, None, None, None) == ig.EINVAL
