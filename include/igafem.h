@@ -239,12 +239,28 @@ igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm,
 /* Adjoint of L(kappa) = alphaM u^T M(kappa) v + alphaK u^T K(kappa) v with
  * respect to kappa at every quadrature point (L is linear in kappa through
  * the J(x^n) slot of eq. 10):
- *   grad[e][q] = scale * w_q (alphaM u_h v_h + alphaK grad u_h . grad v_h)(x_q),
- * u_h = sum_I u_I phi_I.  u, v: device [ndof]; grad: device [E][q^3],
- * OVERWRITTEN.  No element matrix is formed or stored. */
+ *   grad[e][q] = s * w_q (alphaM u_h v_h + alphaK grad u_h . grad v_h)(x_q),
+ * u_h = sum_I u_I phi_I, s = scale * (*scale_dev) with scale_dev a DEVICE
+ * scalar (double[1], read on the device when the kernel runs, e.g. the
+ * incoming gradient of an autograd backward) or s = scale when scale_dev is
+ * NULL.  u, v: device [ndof]; grad: device [E][q^3], OVERWRITTEN.  No element
+ * matrix is formed or stored. */
 igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double* v,
-                            double alphaM, double alphaK, double scale, double* grad,
-                            void* stream);
+                            double alphaM, double alphaK, double scale, const double* scale_dev,
+                            double* grad, void* stream);
+
+/* The value of that bilinear form,
+ *   L[0] = alphaM u^T M(kappa) v + alphaK u^T K(kappa) v = sum_q kappa_q dL/dkappa_q
+ * (Euler's identity for a function linear in kappa), computed matrix-free
+ * with the adjoint's interpolation: each wavefront sums kappa_q dL/dkappa_q
+ * over its points into a partial-sum buffer the plan owns (4096 doubles,
+ * allocated with the plan), and one workgroup adds the partials; every sum
+ * runs in a fixed order, so repeated calls give the same bits.  kappa:
+ * device [E][q^3]; u, v: device [ndof]; L: DEVICE double[1], OVERWRITTEN.
+ * Calls on one plan that overlap (other streams or threads) race on the
+ * partial sums. */
+igaf_status igaf_bilinear_form(const igaf_plan* plan, const double* kappa, const double* u, const double* v,
+                               double alphaM, double alphaK, double* L, void* stream);
 
 /* Matrix-free operator apply, the step after assembly that an explicit time
  * step takes (the forward Euler step of Sec. 2.2, in the matrix form of

@@ -77,10 +77,17 @@ struct AdjShape {
 
 // GEO: a mapped geometry; the point value takes the geometry factors cm0
 // (det J) and G0 (det J J^-1 J^-T, [E][6][q^3]) that kappa scales.
-template <int P, bool GEO>
+// scale_dev (nullable): a device scalar the gradient is also multiplied by.
+// LOSS: no gradient is stored; each wavefront sums kappa_q g_q over its
+// points (in its own fixed order), reduces the sum over its lanes in a fixed
+// butterfly and writes it to part[wavefront] (the value of L, Euler's
+// identity for a function linear in kappa).
+template <int P, bool GEO, bool LOSS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 : 2))) void k_kappa_grad(
     PatchDev pd, const double* __restrict__ u, const double* __restrict__ v, double alphaM, double alphaK,
-    double scale, double* __restrict__ grad, const double* __restrict__ cm0, const double* __restrict__ G0)
+    double scale, const double* __restrict__ scale_dev, double* __restrict__ grad,
+    const double* __restrict__ cm0, const double* __restrict__ G0, const double* __restrict__ kappa,
+    double* __restrict__ part)
 {
     using A = AdjShape<P>;
     constexpr int n = A::n, Q = A::Q, Q2 = A::Q2, Q3 = A::Q3, G = A::G, NXP = A::NXP;
@@ -95,6 +102,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
     const double* __restrict__ wqx = pd.d[0].wq;
     const int nchunk = (Kx + A::RUN - 1) / A::RUN;
     const int nruns = nchunk * Ky * Kz;
+    if (!LOSS && scale_dev) scale *= scale_dev[0];
+    double lacc = 0.0;   // LOSS: this lane's sum of kappa_q g_q
 
     // fixed lane roles
     int xkx[NXP], xa2[NXP], xa3[NXP];   // stage x: item i = kx + Q (a2 + n a3)
@@ -265,18 +274,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P <= 3 ? 4 
                                 r = alphaM * ur[0][kz] * h +
                                     alphaK * (ur[1][kz] * dx + ur[2][kz] * dy + ur[3][kz] * dz);
                             }
-                            if (zact && zg < ng) grad[pt] = scale * (wxl * wyl * wz_[kz]) * r;
+                            if (zact && zg < ng) {
+                                if constexpr (LOSS) lacc += kappa[pt] * ((wxl * wyl * wz_[kz]) * r);
+                                else grad[pt] = scale * (wxl * wyl * wz_[kz]) * r;
+                            }
                         }
                     }
                 }
             }
         }
     }
+    if constexpr (LOSS) {
+#pragma unroll
+        for (int off = 32; off > 0; off /= 2) lacc += __shfl_xor(lacc, off);
+        if (lane == 0) part[blockIdx.x * 4 + w] = lacc;
+    }
+}
+
+// L = scale * (the sum of part[0..nparts)), in a fixed order
+__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ part, int nparts, double scale,
+                                                    double* __restrict__ L)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h /= 2) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) L[0] = scale * red[0];
 }
 
 int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,
-                      double alphaK, double scale, double* grad, hipStream_t st, const double* cm0,
-                      const double* G0)
+                      double alphaK, double scale, const double* scale_dev, double* grad, hipStream_t st,
+                      const double* cm0, const double* G0)
 {
     const int64_t runs = (int64_t)((pd.d[0].K + 31) / 32) * pd.d[1].K * pd.d[2].K;   // runs of 32 x elements
     int64_t blocks = (runs + 3) / 4;
@@ -286,11 +319,12 @@ int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, doub
 #define IGAF_A(PP)                                                                                    \
     case PP:                                                                                          \
         if (geo)                                                                                      \
-            hipLaunchKernelGGL((k_kappa_grad<PP, true>), dim3((unsigned)blocks), dim3(256), 0, st, pd, u, \
-                               v, alphaM, alphaK, scale, grad, cm0, G0);                             \
+            hipLaunchKernelGGL((k_kappa_grad<PP, true, false>), dim3((unsigned)blocks), dim3(256), 0, st, pd, \
+                               u, v, alphaM, alphaK, scale, scale_dev, grad, cm0, G0, nullptr, nullptr); \
         else                                                                                          \
-            hipLaunchKernelGGL((k_kappa_grad<PP, false>), dim3((unsigned)blocks), dim3(256), 0, st, pd, \
-                               u, v, alphaM, alphaK, scale, grad, nullptr, nullptr);                 \
+            hipLaunchKernelGGL((k_kappa_grad<PP, false, false>), dim3((unsigned)blocks), dim3(256), 0, st, pd, \
+                               u, v, alphaM, alphaK, scale, scale_dev, grad, nullptr, nullptr, nullptr,   \
+                               nullptr);                                                              \
         break;
         IGAF_A(1)
         IGAF_A(2)
@@ -301,6 +335,31 @@ int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, doub
     default:
         return -4;
     }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_bilinear(const PatchDev& pd, const double* kappa, const double* u, const double* v, double alphaM,
+                    double alphaK, double* L, double* part, hipStream_t st)
+{
+    const int64_t runs = (int64_t)((pd.d[0].K + 31) / 32) * pd.d[1].K * pd.d[2].K;
+    int64_t blocks = (runs + 3) / 4;
+    if (blocks > kLossParts / 4) blocks = kLossParts / 4;
+    switch (pd.p) {
+#define IGAF_L(PP)                                                                                    \
+    case PP:                                                                                          \
+        hipLaunchKernelGGL((k_kappa_grad<PP, false, true>), dim3((unsigned)blocks), dim3(256), 0, st, pd, u, \
+                           v, alphaM, alphaK, 1.0, nullptr, nullptr, nullptr, nullptr, kappa, part);  \
+        break;
+        IGAF_L(1)
+        IGAF_L(2)
+        IGAF_L(3)
+        IGAF_L(4)
+        IGAF_L(5)
+#undef IGAF_L
+    default:
+        return -4;
+    }
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, (int)(blocks * 4), 1.0, L);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

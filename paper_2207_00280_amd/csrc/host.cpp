@@ -150,6 +150,8 @@ struct igaf_plan {
     // Euler step: pinned slot and event for the residual read-back of CG
     double* rb_host = nullptr;
     hipEvent_t rb_ev = nullptr;
+    // igaf_bilinear_form: per-wavefront partial sums (kLossParts, in dmem)
+    double* dpart = nullptr;
 };
 
 namespace {
@@ -306,6 +308,8 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
         }
         icount += P->N[a] + 1;
     }
+    const int64_t part_off = dcount;
+    dcount += kLossParts;
     if (hipGetDevice(&P->device) != hipSuccess) {
         delete P;
         return fail(IGAF_EDEVICE, "hipGetDevice failed (no GPU?)");
@@ -324,6 +328,7 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
         return fail(IGAF_ENOMEM, "hipMalloc of prefix tables failed");
     }
     int64_t ioff = 0;
+    P->dpart = P->dmem + part_off;
     P->dev.p = P->p;
     // element kernels: two 256-lane workgroups per CU saturate the HBM store
     // path
@@ -659,13 +664,24 @@ igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm,
 }
 
 igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double* v,
-                            double alphaM, double alphaK, double scale, double* grad, void* stream)
+                            double alphaM, double alphaK, double scale, const double* scale_dev,
+                            double* grad, void* stream)
 {
     igaf_status st = check_hot(plan, IGAF_SUMFACT);
     if (st) return st;
     if (!u || !v || !grad) return fail(IGAF_EINVAL, "u, v or grad is NULL");
-    return launched(launch_kappa_grad(plan->dev, u, v, alphaM, alphaK, scale, grad,
+    return launched(launch_kappa_grad(plan->dev, u, v, alphaM, alphaK, scale, scale_dev, grad,
                                       (hipStream_t)stream), "kappa gradient");
+}
+
+igaf_status igaf_bilinear_form(const igaf_plan* plan, const double* kappa, const double* u, const double* v,
+                               double alphaM, double alphaK, double* L, void* stream)
+{
+    igaf_status st = check_hot(plan, IGAF_SUMFACT);
+    if (st) return st;
+    if (!kappa || !u || !v || !L) return fail(IGAF_EINVAL, "kappa, u, v or L is NULL");
+    return launched(launch_bilinear(plan->dev, kappa, u, v, alphaM, alphaK, L, plan->dpart, (hipStream_t)stream),
+                    "bilinear form");
 }
 
 int64_t igaf_apply_workspace(const igaf_plan* plan)
@@ -722,7 +738,7 @@ igaf_status igaf_kappa_grad_geo(const igaf_plan* plan, const double* cm0, const 
     igaf_status st = check_hot(plan, IGAF_SUMFACT);
     if (st) return st;
     if (!cm0 || !G0 || !u || !v || !grad) return fail(IGAF_EINVAL, "cm0, G0, u, v or grad is NULL");
-    return launched(launch_kappa_grad(plan->dev, u, v, alphaM, alphaK, scale, grad, (hipStream_t)stream,
+    return launched(launch_kappa_grad(plan->dev, u, v, alphaM, alphaK, scale, nullptr, grad, (hipStream_t)stream,
                                       cm0, G0),
                     "mapped-geometry kappa gradient");
 }

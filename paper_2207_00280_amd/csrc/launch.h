@@ -78,7 +78,14 @@ int run_euler_step(const PatchDev& pd, int64_t ndof, const double* kappa, const 
                    hipStream_t st, double* rb, hipEvent_t ev, const double* G = nullptr);
 
 int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, double alphaM,
-                      double alphaK, double scale, double* grad, hipStream_t st,
+                      double alphaK, double scale, const double* scale_dev, double* grad, hipStream_t st,
                       const double* cm0 = nullptr, const double* G0 = nullptr);
+
+// L[0] = alphaM u^T M(kappa) v + alphaK u^T K(kappa) v = sum_q kappa_q g_q by
+// the adjoint's interpolation: per-wavefront partial sums into part
+// (kLossParts doubles), then one workgroup sums them in a fixed order.
+constexpr int kLossParts = 4096;
+int launch_bilinear(const PatchDev& pd, const double* kappa, const double* u, const double* v, double alphaM,
+                    double alphaK, double* L, double* part, hipStream_t st);
 
 }  // namespace igaf

@@ -23,7 +23,8 @@ SYMBOLS = [
     "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_csr_pattern_host",
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes", "igaf_quad_points",
     "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
-    "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_apply_workspace",
+    "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_bilinear_form",
+    "igaf_apply_workspace",
     "igaf_apply", "igaf_apply_static",
     "igaf_apply_geo", "igaf_kappa_grad_geo", "igaf_euler_step_geo", "igaf_euler_workspace", "igaf_euler_step",
     "igaf_batch_create", "igaf_batch_destroy",
@@ -80,7 +81,8 @@ def lib():
     L.igaf_assemble.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     L.igaf_integrate_assemble.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
     L.igaf_kappa_grad.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
-                                  ctypes.c_double, _vp, _vp]
+                                  ctypes.c_double, _vp, _vp, _vp]
+    L.igaf_bilinear_form.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]
     L.igaf_apply_workspace.argtypes = [_vp]
     L.igaf_apply_workspace.restype = ctypes.c_int64
     L.igaf_apply.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]
@@ -470,15 +472,32 @@ class Plan:
                                          float(alphaK), float(scale), _ptr(grad), _stream(stream)))
         return grad
 
-    def kappa_grad(self, u, v, alphaM=1.0, alphaK=1.0, scale=1.0, grad=None, stream=None):
+    def kappa_grad(self, u, v, alphaM=1.0, alphaK=1.0, scale=1.0, grad=None, scale_dev=None, stream=None):
+        """dL/dkappa [E, q^3] (igaf_kappa_grad), times scale and, if given, the
+        device scalar scale_dev (a one-element float64 CUDA tensor)."""
         _need_f64_cuda(u, "u", self.ndof)
         _need_f64_cuda(v, "v", self.ndof)
+        if scale_dev is not None:
+            _need_f64_cuda(scale_dev, "scale_dev", 1)
         if grad is None:
-            grad = self._alloc(self.nelem, self.nqp)
+            grad = self._alloc(self.nelem, self.nqp, stream=stream)
         _need_f64_cuda(grad, "grad", self.nelem * self.nqp)
         _check(lib().igaf_kappa_grad(self._h, _ptr(u), _ptr(v), float(alphaM), float(alphaK),
-                                     float(scale), _ptr(grad), _stream(stream)))
+                                     float(scale), _ptr(scale_dev), _ptr(grad), _stream(stream)))
         return grad
+
+    def bilinear_form(self, kappa, u, v, alphaM=1.0, alphaK=1.0, out=None, stream=None):
+        """L = alphaM u^T M(kappa) v + alphaK u^T K(kappa) v as a 0-dim CUDA
+        tensor (igaf_bilinear_form: matrix-free, fixed-order sums)."""
+        _need_f64_cuda(kappa, "kappa", self.nelem * self.nqp)
+        _need_f64_cuda(u, "u", self.ndof)
+        _need_f64_cuda(v, "v", self.ndof)
+        if out is None:
+            out = self._alloc((), stream=stream)
+        _need_f64_cuda(out, "out", 1)
+        _check(lib().igaf_bilinear_form(self._h, _ptr(kappa), _ptr(u), _ptr(v), float(alphaM), float(alphaK),
+                                        _ptr(out), _stream(stream)))
+        return out
 
 
 def _ptr_array(tensors):
@@ -551,23 +570,32 @@ def _autograd():
     class KappaBilinearLoss(torch.autograd.Function):
         """L(kappa) = alphaM u^T M(kappa) v + alphaK u^T K(kappa) v.
 
-        L is linear in kappa, so L = <kappa, dL/dkappa>; both the value and
-        the gradient come from the adjoint kernel (igaf_kappa_grad), which
-        recomputes basis products instead of storing element matrices."""
+        The value comes from igaf_bilinear_form and the gradient from the
+        adjoint kernel (igaf_kappa_grad), with the incoming gradient passed to
+        the library as a device scalar: no arithmetic in Python and no host
+        synchronisation, so forward and backward can be captured in a HIP
+        graph.  Neither recomputes nor stores element matrices.  Gradients
+        with respect to u and v are not provided (an error if they require
+        grad)."""
 
         @staticmethod
         def forward(ctx, kappa, u, v, plan, alphaM=1.0, alphaK=1.0):
-            g = plan.kappa_grad(u, v, alphaM, alphaK, 1.0)
+            if u.requires_grad or v.requires_grad:
+                raise ValueError("KappaBilinearLoss differentiates with respect to kappa only; "
+                                 "u and v must not require grad")
+            L = plan.bilinear_form(kappa.detach().reshape(-1), u, v, alphaM, alphaK)
             ctx.save_for_backward(u, v)
-            ctx.plan, ctx.alphaM, ctx.alphaK = plan, alphaM, alphaK
-            return (g.reshape(-1) * kappa.reshape(-1)).sum()
+            ctx.plan, ctx.alphaM, ctx.alphaK, ctx.kshape = plan, alphaM, alphaK, kappa.shape
+            return L
 
         @staticmethod
         def backward(ctx, grad_out):
             u, v = ctx.saved_tensors
-            # recompute (no element matrices, no stored gradient); grad_out folded into scale
-            g = ctx.plan.kappa_grad(u, v, ctx.alphaM, ctx.alphaK, float(grad_out))
-            return g, None, None, None, None, None
+            go = grad_out
+            if go.dtype != torch.float64 or not go.is_cuda or not go.is_contiguous():
+                go = go.to(dtype=torch.float64, device=u.device).contiguous()
+            g = ctx.plan.kappa_grad(u, v, ctx.alphaM, ctx.alphaK, 1.0, scale_dev=go.reshape(1))
+            return g.view(ctx.kshape), None, None, None, None, None
 
     return KappaBilinearLoss
 

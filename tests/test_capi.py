@@ -140,7 +140,8 @@ def test_null_arguments():
     assert L.igaf_plan_sizes(None, None, None, None, None, None) == ig.EINVAL
     assert L.igaf_element_matrices(None, 1, None, None, None, None) == ig.EINVAL
     assert L.igaf_integrate_assemble(None, 1, None, None, None, None, None, None) == ig.EINVAL
-    assert L.igaf_kappa_grad(None, None, None, 1.0, 1.0, 1.0, None, None) == ig.EINVAL
+    assert L.igaf_kappa_grad(None, None, None, 1.0, 1.0, 1.0, None, None, None) == ig.EINVAL
+    assert L.igaf_bilinear_form(None, None, None, None, 1.0, 1.0, None, None) == ig.EINVAL
     assert L.igaf_apply(None, None, None, 1.0, 1.0, None, None, None) == ig.EINVAL
     assert L.igaf_apply_workspace(None) == 0
     assert L.igaf_apply_static(None, None, None, 1.0, 1.0, None, None) == ig.EINVAL
