@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.gpu_util import relfro, to_dev, to_host
+from tests.gpu_util import relfro, rowmax_rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +82,7 @@ def test_w2_headline_fullscale(orc, ig):
     Mref = (f(M1, 0, ix, jx) * f(M1, 1, iy, jy) * f(M1, 2, iz, jz)
             + 0.5 * f(S1, 0, ix, jx) * f(S1, 1, iy, jy) * f(S1, 2, iz, jz))
     assert relfro(Mvh, Mref) <= 1e-12
+    assert rowmax_rel(Mvh, Mref, rp) <= 1e-12
     del Mref
     Kref = (f(A1, 0, ix, jx) * f(M1, 1, iy, jy) * f(M1, 2, iz, jz)
             + f(M1, 0, ix, jx) * f(A1, 1, iy, jy) * f(M1, 2, iz, jz)
@@ -90,6 +91,7 @@ def test_w2_headline_fullscale(orc, ig):
                      + f(S1, 0, ix, jx) * f(T1, 1, iy, jy) * f(S1, 2, iz, jz)
                      + f(S1, 0, ix, jx) * f(S1, 1, iy, jy) * f(T1, 2, iz, jz)))
     assert relfro(Kvh, Kref) <= 1e-12
+    assert rowmax_rel(Kvh, Kref, rp) <= 1e-12
     del Kref, ix, iy, iz, jx, jy, jz
     rng = np.random.default_rng(11)
     # seeded element sample (contiguous runs, first and last elements included)
