@@ -39,6 +39,7 @@ METRIC = "element matrices/s (mass+stiffness, 64^3 p=3, FP64) + % HBM/FP64 roofl
 HBM_PEAK = 8.0e12        # bytes/s, MI355X published
 FP64_PEAK = 78.6e12      # flop/s, MI355X published (vector = matrix)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_element_sumfact_64c_p3.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_fp64_and_rows.json")
 ELEMENT_SRC = os.path.join(ROOT, "paper_2207_00280_amd", "csrc", "element.hip")
 
 
@@ -74,6 +75,43 @@ def timed(fn, steps, warmup, stream):
 
 def element_src_hash():
     return hashlib.sha256(open(ELEMENT_SRC, "rb").read()).hexdigest()[:16]
+
+
+def classical_flops(p):
+    """FP64 flops the classical kernel executes per element: for each of the
+    S^3 distinct (M, K) value pairs and each of the q^3 points, 4 fused
+    multiply-adds and 4 multiplies (12 flops; the inner loop of k_element<P,0>,
+    matched by the rocprofv3 FMA_F64/MUL_F64 counts)."""
+    n = q = p + 1
+    S = n * (n + 1) // 2
+    return 12 * S ** 3 * q ** 3
+
+
+def counters_for_current_sources():
+    """Per-kernel rocprofv3 counter summaries (FP64 and instruction counts)
+    from the committed passes, for kernels whose source file is unchanged
+    since the counters were taken."""
+    try:
+        t = json.load(open(COUNTERS_FILE))
+    except (OSError, ValueError):
+        return None
+    out = {}
+    for name, e in t.get("kernels", {}).items():
+        path = os.path.join(ROOT, e["source"])
+        try:
+            cur = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+        except OSError:
+            continue
+        if cur != e["src_sha256_16"]:
+            continue
+        c = e["counters_per_launch"]
+        out[name] = {"workload": e["workload"], "fma_f64": c.get("SQ_INSTS_VALU_FMA_F64"),
+                     "mul_f64": c.get("SQ_INSTS_VALU_MUL_F64"), "add_f64": c.get("SQ_INSTS_VALU_ADD_F64"),
+                     "mfma": c.get("SQ_INSTS_MFMA"), "valu": c.get("SQ_INSTS_VALU"), "salu": c.get("SQ_INSTS_SALU"),
+                     "smem": c.get("SQ_INSTS_SMEM"), "lds": c.get("SQ_INSTS_LDS"),
+                     "lds_bank_conflict_cycles": c.get("SQ_LDS_BANK_CONFLICT"), "waves": c.get("SQ_WAVES"),
+                     "fp64_flops_upper": e["fp64_flops_upper"]}
+    return out
 
 
 def traffic_for_current_kernel():
@@ -401,12 +439,58 @@ def bench_w6(ig, torch, stream, steps):
 
 
 def run_kernel_mode(name, ig, torch, steps):
-    """Run one kernel `steps` times (no timing output) for profiler passes."""
+    """Run one kernel `steps` times (no timing output) for profiler passes:
+    copy (1 GiB device copy, the counter calibration), element, csr,
+    classical, headline (W2), w3p<p> (W3 streamed CSR at degree p), w4 (the
+    batched launches of W4), adjoint, apply, apply_mass (W5), geo (W6
+    element matrices)."""
     if name == "copy":
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
         b = torch.empty_like(a)
         for _ in range(steps):
             b.copy_(a)
+    elif name.startswith("w3p"):
+        p, K = int(name[3:]), W.W3["K"]
+        plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
+        kap = torch.from_numpy(W.kappa_lognormal(plan.nelem, plan.nqp, W.W3["seed"])).cuda()
+        Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+        Kv = torch.empty_like(Mv)
+        for _ in range(steps):
+            plan.integrate_assemble(kap, want_elem=False, Mval=Mv, Kval=Kv)
+    elif name == "w4":
+        shapes = W.batch_patches(**{k: W.W4[k] for k in ("npatch", "seed", "kmin", "kmax", "ps")})
+        B = ig.Batch([(d["p"], d["K"], [W.open_uniform_knots(k, d["p"]) for k in d["K"]]) for d in shapes])
+        kaps = [torch.from_numpy(k).cuda() for k in W.batch_kappas(shapes, seed=W.W4["seed"])]
+        Ms = [torch.empty(pl.nnz, dtype=torch.float64, device="cuda") for pl in B.plans]
+        Ks = [torch.empty(pl.nnz, dtype=torch.float64, device="cuda") for pl in B.plans]
+        for _ in range(steps):
+            B.integrate_assemble(kaps, Ms, Ks)
+    elif name in ("adjoint", "apply", "apply_mass"):
+        cfg = W.W5
+        p, K = cfg["p"], cfg["K"]
+        plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
+        kap = torch.from_numpy(W.kappa_lognormal(plan.nelem, plan.nqp, cfg["seed_kappa"])).cuda()
+        u = torch.from_numpy(W.normal_vector(plan.ndof, cfg["seed_u"])).cuda()
+        v = torch.from_numpy(W.normal_vector(plan.ndof, cfg["seed_v"])).cuda()
+        g = torch.empty_like(kap)
+        y = torch.empty_like(u)
+        wk = torch.empty(plan.apply_workspace(), dtype=torch.float64, device="cuda")
+        for _ in range(steps):
+            if name == "adjoint":
+                plan.kappa_grad(u, v, grad=g)
+            else:
+                plan.apply(kap, u, 1.0, 0.0 if name == "apply_mass" else 1.0, y=y, work=wk)
+    elif name == "geo":
+        cfg = W.W6
+        p, K = cfg["p"], cfg["K"]
+        plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
+        xs = [plan.quad_nodes(d)[0] for d in range(3)]
+        cm, G = W.mapped_geometry(xs[0], xs[1], xs[2], W.kappa_sine(*xs), amp=cfg["amp"])
+        cmd, Gd = torch.from_numpy(cm).cuda(), torch.from_numpy(G).cuda()
+        Me = torch.empty(plan.nelem, plan.elem_dim, plan.elem_dim, dtype=torch.float64, device="cuda")
+        Ke = torch.empty_like(Me)
+        for _ in range(steps):
+            plan.integrate_assemble_geo(cmd, Gd, Me=Me, Ke=Ke, want_csr=False)
     else:
         h = Headline(ig, torch)
         fn = {"element": h.element, "csr": h.csr, "headline": h.step,
@@ -518,8 +602,12 @@ def main():
             "csr_rows": {"ms": ms_csr, "bytes": csr_b, "GB/s": csr_b / (ms_csr * 1e-3) / 1e9,
                          "frac_hbm": csr_b / (ms_csr * 1e-3) / HBM_PEAK},
             "element_classical": {"ms": ms_cl, "elements_per_s": E / (ms_cl * 1e-3),
-                                  "flops_8n6q3": E * 8 * 4 ** 6 * 4 ** 3,
-                                  "frac_fp64_8n6q3": E * 8 * 4 ** 6 * 4 ** 3 / (ms_cl * 1e-3) / FP64_PEAK},
+                                  "flops_executed": E * classical_flops(3),
+                                  "TFLOP/s": E * classical_flops(3) / (ms_cl * 1e-3) / 1e12,
+                                  "frac_fp64": E * classical_flops(3) / (ms_cl * 1e-3) / FP64_PEAK,
+                                  "dense_equivalent_flops_8n6q3": E * 8 * 4 ** 6 * 4 ** 3,
+                                  "note": "flops_executed = 12 S^3 q^3 per element (distinct values only); the "
+                                          "dense-equivalent 8 n^6 q^3 count is context, not work done"},
             "csr_atomic": {"ms": ms_at, "GB/s": csr_b / (ms_at * 1e-3) / 1e9},
         }
         rp_t = torch.empty(plan.ndof + 1, dtype=torch.int64, device="cuda")
@@ -535,7 +623,7 @@ def main():
         out["kernels"]["element_sumfact"]["frac_measured_write"] = \
             out["kernels"]["element_sumfact"]["GB/s"] / mp["write_GB/s"]
         out["kernels"]["element_classical"]["frac_measured_dgemm"] = \
-            out["kernels"]["element_classical"]["flops_8n6q3"] / (ms_cl * 1e-3) / 1e12 / mp["fp64_dgemm_TFLOP/s"]
+            out["kernels"]["element_classical"]["TFLOP/s"] / mp["fp64_dgemm_TFLOP/s"]
         log("measured peaks: %s" % json.dumps(out["measured_peaks"]))
         steps_x = max(3, args.steps // 4)
         out["w3_streamed_128c"] = bench_w3(ig, torch, stream, steps_x)
@@ -545,6 +633,9 @@ def main():
     else:
         del h
         torch.cuda.empty_cache()
+    cnt = counters_for_current_sources()
+    if cnt:
+        out["counters"] = cnt
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
         log("cpu baseline: %s" % json.dumps(out["cpu_baseline"]))
