@@ -4,7 +4,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  It wraps ``oracle.c`` (plain FP64,
 classical quadrature of Algorithm 1, assembly by brute-force union of
 element pairs) through ctypes and holds the exact-rational module
-``exact.py``.  It shares no code with the HIP path.
+``exact.py`` and the weighted-quadrature oracle ``wq.py`` (numpy).  It
+shares no code with the HIP path.
 """
 import ctypes
 import os

@@ -672,3 +672,159 @@ def test_geometry_kappa_grad(orc):
         Gq[..., r, t] = Gq[..., t, r] = G0[:, c, :]
     ref = wq * (aM * cm0 * (XI @ c1) * (XI @ c2) + aK * np.einsum("a,...ab,b->...", c1, Gq, c2))
     np.testing.assert_allclose(gl, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------- weighted quadrature (f4)
+# oracle/wq.py is pinned by what the method fixes: the point set's definition,
+# exactness of every 1D rule for the trial products (against exact.py's
+# rational integrals, not the oracle's own Gauss sums), the minimum-norm
+# choice, exactness of the 3D matrices for kappa = 1 (exact Kronecker forms),
+# the tensor structure for any kappa (a sum of separable kappas gives the
+# sum of Kronecker products of 1D rule matrices, so by linearity every kappa
+# on the point grid is covered), and convergence to the Galerkin integrals
+# for a smooth kappa.
+
+
+def test_wq_points_definition():
+    from oracle import wq
+
+    for p, K in ((1, 1), (2, 5), (3, 6), (5, 3)):
+        t = W.open_uniform_knots(K, p)
+        x, first = wq.points_1d(t, p)
+        for e in range(K):
+            R = p + 1 if e in (0, K - 1) else 2
+            assert first[e + 1] - first[e] == R
+            a, h = e / K, 1.0 / K
+            want = [a + h * (r + 0.5) / R for r in range(R)]
+            np.testing.assert_allclose(x[first[e]:first[e + 1]], want, rtol=0, atol=1e-15)
+        assert np.all(np.diff(x) > 0)
+    with pytest.raises(ValueError):
+        wq.points_1d(W.repeated_knots([0.5], [2], 2), 2)
+
+
+@pytest.mark.parametrize("p,K,nonuni", [(1, 4, False), (2, 6, True), (3, 7, False), (3, 5, True),
+                                        (4, 5, False), (5, 6, True), (5, 1, False)])
+def test_wq_rules_exact_against_rational_integrals(orc, p, K, nonuni):
+    """sum_q w00[i][q] B_j(x_q) = int B_i B_j and sum_q w11[i][q] B_j'(x_q) =
+    int B_i' B_j' for every overlapping pair, against exact.py's rational
+    integrals (relative to the largest entry)."""
+    from oracle import wq
+
+    t = _nonuniform_knots(K, p, 70 + p) if nonuni else W.open_uniform_knots(K, p)
+    R = wq.Rule1D(t, p)
+    Mw, Aw = R.matrices()
+    M1, A1 = exact.matrices_1d([Fraction(float(v)) for v in t], p)
+    M1 = np.array(M1, dtype=object).astype(float)
+    A1 = np.array(A1, dtype=object).astype(float)
+    assert np.abs(Mw - M1).max() <= 1e-13 * np.abs(M1).max()
+    assert np.abs(Aw - A1).max() <= 1e-11 * np.abs(A1).max()
+    # entries beyond the band are structurally zero
+    for i in range(R.N):
+        for j in range(R.N):
+            if abs(i - j) > p:
+                assert Mw[i, j] == 0.0 and Aw[i, j] == 0.0
+
+
+def test_wq_weights_are_minimum_norm(orc):
+    """Each w00[i] solves its exactness system and lies in the row space of
+    the system's matrix (the minimum-norm solution); the same for w11."""
+    from oracle import wq
+
+    p, K = 3, 6
+    t = W.open_uniform_knots(K, p)
+    R = wq.Rule1D(t, p)
+    M1, A1 = exact.matrices_1d([Fraction(float(v)) for v in t], p)
+    M1 = np.array(M1, dtype=object).astype(float)
+    A1 = np.array(A1, dtype=object).astype(float)
+    for i in range(R.N):
+        lo, hi = R.lo[i], R.hi[i]
+        j0, j1 = max(0, i - p), min(R.N - 1, i + p) + 1
+        for w, T, G in ((R.w00[i], R.V, M1), (R.w11[i], R.D, A1)):
+            A = T[lo:hi, j0:j1].T
+            np.testing.assert_allclose(A @ w, G[i, j0:j1], rtol=0, atol=1e-13)
+            y, *_ = np.linalg.lstsq(A.T, w, rcond=None)     # w = A^T y exactly?
+            assert np.linalg.norm(A.T @ y - w) <= 1e-12 * np.linalg.norm(w)
+        assert lo < hi and np.all(R.x[lo:hi] > t[i]) and np.all(R.x[lo:hi] < t[i + p + 1])
+
+
+@pytest.mark.parametrize("p,K", [(1, (3, 2, 4)), (2, (3, 4, 2)), (3, (2, 3, 3))])
+def test_wq_3d_constant_kappa_exact(orc, p, K):
+    """kappa = 1: the weighted-quadrature matrices are the exact Galerkin
+    matrices, M = Mz (x) My (x) Mx and K = Mz My Ax + Mz Ay Mx + Az My Mx
+    (exact rationals); the pattern is the structural one."""
+    from oracle import wq
+
+    knots = [W.open_uniform_knots(k, p) for k in K]
+    npts = [len(wq.points_1d(t, p)[0]) for t in knots]
+    rp, col, Mv, Kv = wq.assemble(knots, p, np.ones((npts[2], npts[1], npts[0])))
+    N = [k + p for k in K]
+    rp_s, col_s = _structural_pattern(N, p)
+    assert np.array_equal(rp, rp_s) and np.array_equal(col, col_s)
+    ex = [exact.matrices_1d(exact.open_uniform_knots(k, p), p) for k in K]
+    Mref = _fkron(ex[2][0], ex[1][0], ex[0][0]).astype(float)
+    Kref = (_fkron(ex[2][0], ex[1][0], ex[0][1]) + _fkron(ex[2][0], ex[1][1], ex[0][0]) +
+            _fkron(ex[2][1], ex[1][0], ex[0][0])).astype(float)
+    n = N[0] * N[1] * N[2]
+    assert np.linalg.norm(_csr_to_dense(rp, col, Mv, n) - Mref) / np.linalg.norm(Mref) < 1e-13
+    assert np.linalg.norm(_csr_to_dense(rp, col, Kv, n) - Kref) / np.linalg.norm(Kref) < 1e-12
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_wq_3d_sum_of_separable_kappas(orc, p):
+    """kappa = sum_r f_r(x) g_r(y) h_r(z) (random positive factors on the
+    point grid, three terms, different per axis): the 3D matrices equal
+    sum_r of the Kronecker forms of the 1D rule matrices with weights f_r,
+    g_r, h_r.  The 1D matrices are formed by a separate 1D loop, so a wrong
+    index, axis or weight set in the 3D triple sum fails; by linearity in
+    kappa this covers every kappa on the grid."""
+    from oracle import wq
+
+    K = (3, 2, 4)
+    knots = [W.open_uniform_knots(K[0], p), _nonuniform_knots(2, p, 5), _nonuniform_knots(4, p, 9)]
+    R = wq.rules(knots, p)
+    rng = np.random.default_rng(7)
+    kap = np.zeros((R[2].npts(), R[1].npts(), R[0].npts()))
+    n = R[0].N * R[1].N * R[2].N
+    Mref = np.zeros((n, n))
+    Kref = np.zeros((n, n))
+    for r in range(3):
+        f = [rng.uniform(0.5, 2.0, R[d].npts()) for d in range(3)]
+        kap += np.einsum("k,j,i->kji", f[2], f[1], f[0])
+        m = [R[d].matrices(f[d]) for d in range(3)]
+        Mref += np.kron(m[2][0], np.kron(m[1][0], m[0][0]))
+        Kref += (np.kron(m[2][0], np.kron(m[1][0], m[0][1])) + np.kron(m[2][0], np.kron(m[1][1], m[0][0])) +
+                 np.kron(m[2][1], np.kron(m[1][0], m[0][0])))
+    rp, col, Mv, Kv = wq.assemble(knots, p, kap)
+    assert np.linalg.norm(_csr_to_dense(rp, col, Mv, n) - Mref) / np.linalg.norm(Mref) < 1e-13
+    assert np.linalg.norm(_csr_to_dense(rp, col, Kv, n) - Kref) / np.linalg.norm(Kref) < 1e-12
+    # outside the structural band the Kronecker forms are zero too
+    assert np.abs(Mref).sum() == pytest.approx(np.abs(Mv).sum(), rel=1e-12)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_wq_converges_to_galerkin(orc, p):
+    """For a smooth coefficient f(x) = exp(sin 3x) the 1D rule matrices
+    approach the Galerkin integrals (a 12-point Gauss rule per element) as
+    the mesh is refined: the relative Frobenius error at 64 elements is at
+    most a quarter of that at 8."""
+    from oracle import wq
+
+    errs = []
+    for K in (8, 64):
+        t = W.open_uniform_knots(K, p)
+        R = wq.Rule1D(t, p)
+        Mw, Aw = R.matrices(np.exp(np.sin(3 * R.x)))
+        xi, wi = np.polynomial.legendre.leggauss(12)
+        N = K + p
+        Mg = np.zeros((N, N))
+        Ag = np.zeros((N, N))
+        for e in range(K):
+            a, b = t[e + p], t[e + p + 1]
+            for k in range(12):
+                x = a + 0.5 * (xi[k] + 1) * (b - a)
+                B, dB = orc.basis_all(t, p, x)
+                c = 0.5 * wi[k] * (b - a) * np.exp(np.sin(3 * x))
+                Mg += c * np.outer(B, B)
+                Ag += c * np.outer(dB, dB)
+        errs.append((np.linalg.norm(Mw - Mg) / np.linalg.norm(Mg), np.linalg.norm(Aw - Ag) / np.linalg.norm(Ag)))
+    assert errs[1][0] <= errs[0][0] / 4 and errs[1][1] <= errs[0][1] / 4, errs
