@@ -30,16 +30,17 @@ Readings (the choices the method leaves open, fixed here):
   * knots: open, with simple interior knots (every element of positive
     length);
   * weights: the exactness conditions are fewer than the points in the
-    support; the minimum-norm solution is taken (numpy's pseudo-inverse;
-    the w11 system has one dependent condition, since the derivatives of
-    the overlapping functions sum to zero on the support, and is
-    consistent);
-  * integrals int B_i B_j, int B_i' B_j' by the (p+1)-point Gauss rule per
-    element (exact for these degree <= 2p products).
+    support; the minimum-norm solution is taken (computed exactly, see
+    Rule1D; the w11 system has one dependent condition, since the
+    derivatives of the overlapping functions sum to zero on the support,
+    and is consistent);
+  * the integrals int B_i B_j, int B_i' B_j' are exact.
 """
+from fractions import Fraction
+
 import numpy as np
 
-from . import basis_all, gauss_legendre
+from . import basis_all, exact, gauss_legendre
 
 
 def points_1d(t, p):
@@ -58,19 +59,37 @@ def points_1d(t, p):
     return np.array(xs), np.array(first)
 
 
-def _basis_at(t, p, xs):
-    """B_j(x_q) and B_j'(x_q) for all functions j: arrays [npts][N]."""
-    V, D = [], []
-    for x in xs:
-        b, db = basis_all(t, p, x)
-        V.append(b)
-        D.append(db)
-    return np.array(V), np.array(D)
+def _solve_exact(G, b):
+    """Solve G y = b (G square, nonsingular; Fractions) by Gaussian
+    elimination with exact arithmetic."""
+    n = len(b)
+    A = [list(G[r]) + [b[r]] for r in range(n)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if A[r][c] != 0)
+        A[c], A[piv] = A[piv], A[c]
+        for r in range(c + 1, n):
+            f = A[r][c] / A[c][c]
+            if f:
+                A[r] = [x - f * y for x, y in zip(A[r], A[c])]
+    y = [Fraction(0)] * n
+    for r in range(n - 1, -1, -1):
+        y[r] = (A[r][n] - sum(A[r][k] * y[k] for k in range(r + 1, n))) / A[r][r]
+    return y
+
+
+def _min_norm_exact(A, b):
+    """The minimum-norm solution w = A^T (A A^T)^-1 b of the full-row-rank
+    system A w = b, in exact rational arithmetic."""
+    m = len(A)
+    G = [[sum(x * y for x, y in zip(A[r], A[c])) for c in range(m)] for r in range(m)]
+    y = _solve_exact(G, b)
+    return [sum(A[r][q] * y[r] for r in range(m)) for q in range(len(A[0]))]
 
 
 def _gram_1d(t, p):
-    """int B_i B_j and int B_i' B_j' (dense [N][N]) by the (p+1)-point Gauss
-    rule on every element."""
+    """int B_i B_j and int B_i' B_j' (dense [N][N], floating point) by the
+    (p+1)-point Gauss rule on every element, with the oracle's literal
+    Cox-de Boor values (an independent check of the exact integrals)."""
     t = np.asarray(t, dtype=np.float64)
     K = len(t) - 2 * p - 1
     N = K + p
@@ -93,7 +112,14 @@ class Rule1D:
 
     x: points; first: first point of each element; lo[i], hi[i]: the points
     inside supp(B_i) are x[lo[i]:hi[i]]; w00[i], w11[i]: the weights on
-    them; V, D: B_j(x_q), B_j'(x_q) for all points and functions."""
+    them; V, D: B_j(x_q), B_j'(x_q) for all points and functions.
+
+    The knots (doubles, hence rationals) and the points are taken exactly;
+    the basis polynomials and the integrals int B_i B_j, int B_i' B_j' come
+    from exact.py, and every minimum-norm solve is done in rational
+    arithmetic: the weights are the exact minimum-norm weights, rounded once
+    to FP64 (the systems are ill-conditioned at high p, cond ~ 1e5 at p = 5,
+    so a floating-point solve would carry errors of ~1e-12)."""
 
     def __init__(self, t, p):
         self.t = np.asarray(t, dtype=np.float64)
@@ -102,18 +128,43 @@ class Rule1D:
         N = K + p
         self.K, self.N = K, N
         self.x, self.first = points_1d(self.t, p)
-        self.V, self.D = _basis_at(self.t, p, self.x)
-        Mg, Ag = _gram_1d(self.t, p)
+        tf = [Fraction(float(v)) for v in self.t]
+        spans, Bp = exact.basis_on_spans(tf, p)
+        Mx, Ax = exact.matrices_1d(tf, p)
+        # exact points: element e's r-th point a + h (2r + 1) / (2 R)
+        xf, ef = [], []
+        for e in range(K):
+            a, b = tf[e + p], tf[e + p + 1]
+            R = int(self.first[e + 1] - self.first[e])
+            xf += [a + (b - a) * Fraction(2 * r + 1, 2 * R) for r in range(R)]
+            ef += [e + p] * R   # the knot span holding the point
+        sidx = {}
+        for k, (lo, hi) in enumerate(spans):
+            sidx.setdefault((lo, hi), k)
+        Vf = [[Fraction(0)] * N for _ in xf]
+        Df = [[Fraction(0)] * N for _ in xf]
+        for q, (x, s) in enumerate(zip(xf, ef)):
+            k = sidx[(tf[s], tf[s + 1])]
+            for j in range(max(0, s - p), min(N - 1, s) + 1):
+                if Bp[j][k]:
+                    Vf[q][j] = exact.peval(Bp[j][k], x)
+                    Df[q][j] = exact.peval(exact.pderiv(Bp[j][k]), x)
+        self.V = np.array([[float(v) for v in row] for row in Vf])
+        self.D = np.array([[float(v) for v in row] for row in Df])
         self.lo, self.hi, self.w00, self.w11 = [], [], [], []
         for i in range(N):
             lo, hi = self.first[max(0, i - p)], self.first[min(K - 1, i) + 1]
             j0, j1 = max(0, i - p), min(N - 1, i + p) + 1
-            Av = self.V[lo:hi, j0:j1].T      # [neighbour j][point q]
-            Ad = self.D[lo:hi, j0:j1].T
+            Av = [[Vf[q][j] for q in range(lo, hi)] for j in range(j0, j1)]
+            Ad = [[Df[q][j] for q in range(lo, hi)] for j in range(j0, j1)]
             self.lo.append(lo)
             self.hi.append(hi)
-            self.w00.append(np.linalg.pinv(Av) @ Mg[i, j0:j1])
-            self.w11.append(np.linalg.pinv(Ad) @ Ag[i, j0:j1])
+            self.w00.append(np.array([float(v) for v in _min_norm_exact(Av, [Mx[i][j] for j in range(j0, j1)])]))
+            # the derivatives of the overlapping functions sum to zero on the
+            # support, so one condition is dependent: drop the last one (the
+            # solution set, and so its minimum-norm element, is unchanged)
+            self.w11.append(np.array([float(v) for v in
+                                      _min_norm_exact(Ad[:-1], [Ax[i][j] for j in range(j0, j1 - 1)])]))
 
     def npts(self):
         return len(self.x)

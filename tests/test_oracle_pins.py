@@ -716,8 +716,13 @@ def test_wq_rules_exact_against_rational_integrals(orc, p, K, nonuni):
     M1, A1 = exact.matrices_1d([Fraction(float(v)) for v in t], p)
     M1 = np.array(M1, dtype=object).astype(float)
     A1 = np.array(A1, dtype=object).astype(float)
-    assert np.abs(Mw - M1).max() <= 1e-13 * np.abs(M1).max()
-    assert np.abs(Aw - A1).max() <= 1e-11 * np.abs(A1).max()
+    assert np.abs(Mw - M1).max() <= 1e-14 * np.abs(M1).max()
+    assert np.abs(Aw - A1).max() <= 1e-13 * np.abs(A1).max()
+    # and against the oracle's floating-point Gauss sums of its literal
+    # Cox-de Boor values (independent of exact.py)
+    Mg, Ag = wq._gram_1d(t, p)
+    assert np.abs(Mw - Mg).max() <= 1e-13 * np.abs(Mg).max()
+    assert np.abs(Aw - Ag).max() <= 1e-12 * np.abs(Ag).max()
     # entries beyond the band are structurally zero
     for i in range(R.N):
         for j in range(R.N):
