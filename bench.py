@@ -438,6 +438,49 @@ def bench_w6(ig, torch, stream, steps):
     return out
 
 
+def wq_fmas_per_row(p, pw):
+    """Fused multiply-adds of one CSR row of the weighted-quadrature kernel
+    with pw points per direction in the row's box: stage x 2 O pw^3,
+    stage y 3 O^2 pw^2, stage z 3 O^3 pw (O = 2p + 1)."""
+    O = 2 * p + 1
+    return 2 * O * pw ** 3 + 3 * O * O * pw ** 2 + 3 * O ** 3 * pw
+
+
+def bench_w7_wq(ig, torch, stream, steps):
+    """Weighted quadrature on the headline mesh (64^3, p = 3): the CSR values
+    of M and K from kappa = 1 + 0.5 sin sin sin at the weighted-quadrature
+    points, against the sum-factorised Gauss path's CSR-only call on the same
+    mesh (the same outputs, different quadrature)."""
+    p, K = W.W2["p"], W.W2["K"]
+    plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
+    t0 = time.perf_counter()
+    plan.wq_prepare()
+    t_prep = time.perf_counter() - t0
+    xs = [plan.wq_points(d) for d in range(3)]
+    s = [np.sin(2 * np.pi * x) for x in xs]
+    kap = torch.from_numpy(1.0 + 0.5 * np.einsum("k,j,i->kji", s[2], s[1], s[0])).cuda()
+    Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+    Kv = torch.empty_like(Mv)
+    ms = float(np.mean(timed(lambda: plan.wq_assemble(kap, Mval=Mv, Kval=Kv), steps, 2, stream)))
+    xg = [plan.quad_nodes(d)[0] for d in range(3)]
+    kg = torch.from_numpy(W.kappa_sine(*xg)).cuda()
+    ms_g = float(np.mean(timed(lambda: plan.integrate_assemble(kg, want_elem=False, Mval=Mv, Kval=Kv),
+                               steps, 2, stream)))
+    npts = [len(x) for x in xs]
+    b = 8.0 * npts[0] * npts[1] * npts[2] + 2 * plan.nnz * 8
+    f = 2.0 * plan.ndof * wq_fmas_per_row(p, 2 * (p + 1))   # interior rows: 2(p+1) points per direction
+    roof = max(b / HBM_PEAK, f / FP64_PEAK)
+    out = {"points": npts, "prepare_s": t_prep, "ms": ms, "rows_per_s": plan.ndof / (ms * 1e-3),
+           "elements_per_s": plan.nelem / (ms * 1e-3), "bytes": b, "flops": f, "roofline_ms": roof * 1e3,
+           "frac": roof / (ms * 1e-3), "bound": "fp64" if f / FP64_PEAK > b / HBM_PEAK else "hbm",
+           "gauss_sumfact_csr_ms": ms_g}
+    log("W7 weighted quadrature 64^3 p=3: CSR M+K %.3f ms (%.0f%% of roofline; Gauss sum-factorised CSR %.3f ms), "
+        "rules built in %.2f s" % (ms, 100 * out["frac"], ms_g, t_prep))
+    del kap, kg, Mv, Kv, plan
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_kernel_mode(name, ig, torch, steps):
     """Run one kernel `steps` times (no timing output) for profiler passes:
     copy (1 GiB device copy, the counter calibration), element, csr,
@@ -509,7 +552,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=262144,
                     help="elements of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--mode", default="full",
-                    help="full | headline | w3 | w4 | w5 | w6 | kernel:{element,csr,classical,headline,copy}")
+                    help="full | headline | w3 | w4 | w5 | w6 | w7 | kernel:{element,csr,classical,headline,copy}")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -526,9 +569,9 @@ def main():
     if args.mode.startswith("kernel:"):
         run_kernel_mode(args.mode.split(":", 1)[1], ig, torch, args.steps)
         return
-    if args.mode in ("w3", "w4", "w5", "w6"):
+    if args.mode in ("w3", "w4", "w5", "w6", "w7"):
         # one secondary workload alone (its JSON object on stdout)
-        fn = {"w3": bench_w3, "w4": bench_w4, "w5": bench_w5, "w6": bench_w6}[args.mode]
+        fn = {"w3": bench_w3, "w4": bench_w4, "w5": bench_w5, "w6": bench_w6, "w7": bench_w7_wq}[args.mode]
         print(json.dumps({args.mode: fn(ig, torch, torch.cuda.current_stream(), args.steps)}), flush=True)
         return
     stream = torch.cuda.current_stream()
@@ -630,6 +673,7 @@ def main():
         out["w4_batched_256"] = bench_w4(ig, torch, stream, steps_x)
         out["w5_adjoint_apply_96c"] = bench_w5(ig, torch, stream, steps_x)
         out["w6_mapped_geometry_64c"] = bench_w6(ig, torch, stream, steps_x)
+        out["w7_weighted_quadrature_64c"] = bench_w7_wq(ig, torch, stream, steps_x)
     else:
         del h
         torch.cuda.empty_cache()

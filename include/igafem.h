@@ -353,6 +353,43 @@ igaf_status igaf_euler_step_geo(const igaf_plan* plan, const double* cm, const d
                                 double dt, double tol, int32_t maxit, int32_t precond, double* mu_next,
                                 double* work, int32_t* iters, double* relres, void* stream);
 
+/* ---------------------------------------------------------------- weighted quadrature
+ * The variant of sum factorisation the paper names as reaching O(p^6)
+ * (Sec. 1, "Sum factorization"): weighted quadrature, after F. Calabro,
+ * G. Sangalli, M. Tani, "Fast formation of isogeometric Galerkin matrices by
+ * weighted quadrature", CMAME 316 (2017).  The test function moves into the
+ * weights: per direction every basis function B_i has its own rule over
+ * fixed points inside its support (two per element at its quarter points,
+ * p+1 points in the first and the last element, at a + h (r+1/2)/(p+1)),
+ * with the minimum-norm weights exact for its products with every trial
+ * function (sum_q w00_iq B_j(x_q) = int B_i B_j, sum_q w11_iq B_j'(x_q) =
+ * int B_i' B_j').  With kappa given on the tensor grid of those points,
+ *   M_IJ = sum_q w00[i1][q1] w00[i2][q2] w00[i3][q3] kappa(q) B_j1(q1) B_j2(q2) B_j3(q3)
+ *   K_IJ = sum_q kappa(q) sum_d (w11 B' in direction d, w00 B in the other two)
+ * (exact Galerkin matrices for kappa = 1).  Open knot vectors with elements
+ * of positive length; nquad = degree+1 (the plan's Gauss rule forms the
+ * exact 1D integrals). */
+
+/* Build the rules of every direction (synchronous; host work O(N p^3) and
+ * a device allocation the plan owns, released with it).  IGAF_EUNSUPPORTED
+ * for a knot vector with a repeated interior knot.  Calling it again is a
+ * no-op. */
+igaf_status igaf_wq_prepare(igaf_plan* plan);
+
+/* The points of direction dir (0, 1, 2) after igaf_wq_prepare: *npts
+ * receives their number and x_host (HOST, may be NULL) the coordinates in
+ * increasing order. */
+igaf_status igaf_wq_points(const igaf_plan* plan, int32_t dir, int64_t* npts, double* x_host);
+
+/* CSR values of M and K by weighted quadrature.  kappa: DEVICE
+ * [npts_z][npts_y][npts_x] (x fastest) at the points of igaf_wq_points;
+ * Mval, Kval: DEVICE [nnz], OVERWRITTEN (structural pattern of
+ * igaf_csr_pattern), either may be NULL (not both).  One workgroup per CSR
+ * row sums its values over the row's point box; deterministic.  Asynchronous
+ * on `stream`; IGAF_EINVAL before igaf_wq_prepare. */
+igaf_status igaf_wq_assemble(const igaf_plan* plan, const double* kappa, double* Mval, double* Kval,
+                             void* stream);
+
 /* ---------------------------------------------------------------- batches
  * Many independent patches (the paper's first concurrency level: parts of
  * the mesh computed concurrently) integrated and assembled to CSR (streamed

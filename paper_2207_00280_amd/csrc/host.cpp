@@ -2,6 +2,7 @@
 // tables), dispatch of the kernels.  See include/igafem.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -152,6 +153,13 @@ struct igaf_plan {
     hipEvent_t rb_ev = nullptr;
     // igaf_bilinear_form: per-wavefront partial sums (kLossParts, in dmem)
     double* dpart = nullptr;
+    // weighted quadrature (igaf_wq_prepare): host knots, the points of every
+    // direction and the rules in device memory
+    std::vector<double> knots_h[3];
+    std::vector<double> wq_x[3];
+    void* wq_mem = nullptr;
+    WqDev wq{};
+    bool wq_ready = false;
 };
 
 namespace {
@@ -349,6 +357,7 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
         std::vector<double> xi(Q), wr(Q);
         gauss_rule(Q, xi.data(), wr.data());
         const double* t = desc->knots[a];
+        P->knots_h[a].assign(t, t + nk);
         P->xnode[a].resize((size_t)K * Q);
         P->wnode[a].resize((size_t)K * Q);
         for (int e = 0; e < K; ++e) {
@@ -409,6 +418,7 @@ void igaf_plan_destroy(igaf_plan* plan)
     (void)hipFree(plan->dmem);
     (void)hipFree(plan->dpre);
     if (plan->geo_ws) (void)hipFree(plan->geo_ws);
+    if (plan->wq_mem) (void)hipFree(plan->wq_mem);
     if (plan->rb_ev) (void)hipEventDestroy(plan->rb_ev);
     if (plan->rb_host) (void)hipHostFree(plan->rb_host);
     delete plan;
@@ -741,6 +751,99 @@ igaf_status igaf_kappa_grad_geo(const igaf_plan* plan, const double* cm0, const 
     return launched(launch_kappa_grad(plan->dev, u, v, alphaM, alphaK, scale, nullptr, grad, (hipStream_t)stream,
                                       cm0, G0),
                     "mapped-geometry kappa gradient");
+}
+
+igaf_status igaf_wq_prepare(igaf_plan* plan)
+{
+    igaf_status st = check_hot(plan, IGAF_SUMFACT);
+    if (st) return st;
+    if (plan->wq_ready) return IGAF_OK;
+    WqHost H[3];
+    for (int d = 0; d < 3; ++d) {
+        const int rc = wq_build_dir(plan->p, plan->K[d], plan->knots_h[d].data(), plan->xnode[d].data(),
+                                    plan->wnode[d].data(), H[d]);
+        if (rc == -1)
+            return fail(IGAF_EUNSUPPORTED, "weighted quadrature needs elements of positive length (direction %d)", d);
+        if (rc) return fail(IGAF_EUNSUPPORTED, "weighted quadrature: a rule's system is singular (direction %d)", d);
+    }
+    const int PW = std::max(H[0].PW, std::max(H[1].PW, H[2].PW));
+    // one buffer: per direction w00 | w11 (N x PW) | Bv | dB (npts x n) doubles, then lo | cnt | eq ints
+    const int n = plan->p + 1;
+    int64_t nd = 0, ni = 0;
+    for (int d = 0; d < 3; ++d) {
+        nd += 2LL * H[d].N * PW + 2LL * H[d].npts * n;
+        ni += 2LL * H[d].N + H[d].npts;
+    }
+    std::vector<double> hd((size_t)nd, 0.0);
+    std::vector<int> hi((size_t)ni, 0);
+    void* mem = nullptr;
+    if (hipMalloc(&mem, sizeof(double) * nd + sizeof(int) * ni) != hipSuccess)
+        return fail(IGAF_ENOMEM, "weighted quadrature tables: device allocation failed");
+    double* dd = static_cast<double*>(mem);
+    int* di = reinterpret_cast<int*>(dd + nd);
+    WqDev w{};
+    w.PW = PW;
+    int64_t od = 0, oi = 0;
+    for (int d = 0; d < 3; ++d) {
+        const WqHost& h = H[d];
+        for (int g = 0; g < h.N; ++g)
+            for (int q = 0; q < h.PW; ++q) {
+                hd[od + (size_t)g * PW + q] = h.w00[(size_t)g * h.PW + q];
+                hd[od + (size_t)h.N * PW + (size_t)g * PW + q] = h.w11[(size_t)g * h.PW + q];
+            }
+        w.d[d].w00 = dd + od;
+        w.d[d].w11 = dd + od + (int64_t)h.N * PW;
+        od += 2LL * h.N * PW;
+        std::copy(h.Bv.begin(), h.Bv.end(), hd.begin() + od);
+        w.d[d].Bv = dd + od;
+        od += (int64_t)h.npts * n;
+        std::copy(h.dB.begin(), h.dB.end(), hd.begin() + od);
+        w.d[d].dB = dd + od;
+        od += (int64_t)h.npts * n;
+        std::copy(h.lo.begin(), h.lo.end(), hi.begin() + oi);
+        w.d[d].lo = di + oi;
+        oi += h.N;
+        std::copy(h.cnt.begin(), h.cnt.end(), hi.begin() + oi);
+        w.d[d].cnt = di + oi;
+        oi += h.N;
+        std::copy(h.eq.begin(), h.eq.end(), hi.begin() + oi);
+        w.d[d].eq = di + oi;
+        oi += h.npts;
+        w.d[d].N = h.N;
+        w.d[d].npts = h.npts;
+    }
+    if (hipMemcpy(dd, hd.data(), sizeof(double) * nd, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(di, hi.data(), sizeof(int) * ni, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(mem);
+        return fail(IGAF_EDEVICE, "weighted quadrature tables: upload failed");
+    }
+    plan->wq_mem = mem;
+    plan->wq = w;
+    for (int d = 0; d < 3; ++d) plan->wq_x[d] = H[d].x;
+    plan->wq_ready = true;
+    return IGAF_OK;
+}
+
+igaf_status igaf_wq_points(const igaf_plan* plan, int32_t dir, int64_t* npts, double* x_host)
+{
+    if (!plan) return fail(IGAF_EINVAL, "plan is NULL");
+    if (!plan->wq_ready) return fail(IGAF_EINVAL, "call igaf_wq_prepare first");
+    if (dir < 0 || dir > 2) return fail(IGAF_EINVAL, "dir %d not in 0..2", dir);
+    if (npts) *npts = (int64_t)plan->wq_x[dir].size();
+    if (x_host) std::memcpy(x_host, plan->wq_x[dir].data(), sizeof(double) * plan->wq_x[dir].size());
+    return IGAF_OK;
+}
+
+igaf_status igaf_wq_assemble(const igaf_plan* plan, const double* kappa, double* Mval, double* Kval,
+                             void* stream)
+{
+    igaf_status st = check_hot(plan, IGAF_SUMFACT);
+    if (st) return st;
+    if (!plan->wq_ready) return fail(IGAF_EINVAL, "call igaf_wq_prepare first");
+    if (!kappa) return fail(IGAF_EINVAL, "kappa is NULL");
+    if (!Mval && !Kval) return fail(IGAF_EINVAL, "Mval and Kval are both NULL");
+    return launched(launch_wq(plan->wq, plan->dev, kappa, Mval, Kval, (hipStream_t)stream),
+                    "weighted-quadrature rows");
 }
 
 int64_t igaf_euler_workspace(const igaf_plan* plan)

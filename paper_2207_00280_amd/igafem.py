@@ -30,7 +30,7 @@ SYMBOLS = [
     "igaf_batch_create", "igaf_batch_destroy",
     "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
     "igaf_batch_integrate_assemble_separate", "igaf_batch_autotune", "igaf_batch_split",
-    "igaf_batch_set_split",
+    "igaf_batch_set_split", "igaf_wq_prepare", "igaf_wq_points", "igaf_wq_assemble",
 ]
 
 
@@ -111,6 +111,9 @@ def lib():
     L.igaf_batch_autotune.argtypes = [_vp, ptrs, ptrs, ptrs, ctypes.c_int32, _vp]
     L.igaf_batch_split.argtypes = [_vp, _i32p, _i32p, ctypes.POINTER(ctypes.c_double)]
     L.igaf_batch_set_split.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+    L.igaf_wq_prepare.argtypes = [_vp]
+    L.igaf_wq_points.argtypes = [_vp, ctypes.c_int32, _i64p, _dp]
+    L.igaf_wq_assemble.argtypes = [_vp, _vp, _vp, _vp, _vp]
     for name in SYMBOLS:
         f = getattr(L, name)
         if f.restype is ctypes.c_int:   # default restype -> status
@@ -498,6 +501,37 @@ class Plan:
         _check(lib().igaf_bilinear_form(self._h, _ptr(kappa), _ptr(u), _ptr(v), float(alphaM), float(alphaK),
                                         _ptr(out), _stream(stream)))
         return out
+
+
+    # ---- weighted quadrature
+    def wq_prepare(self):
+        """Build the weighted-quadrature rules (igaf_wq_prepare)."""
+        _check(lib().igaf_wq_prepare(self._h))
+
+    def wq_points(self, d):
+        """The weighted-quadrature points of direction d (numpy array)."""
+        n = ctypes.c_int64()
+        _check(lib().igaf_wq_points(self._h, int(d), ctypes.byref(n), None))
+        x = np.zeros(n.value)
+        _check(lib().igaf_wq_points(self._h, int(d), None, x.ctypes.data_as(_dp)))
+        return x
+
+    def wq_assemble(self, kappa, want_m=True, want_k=True, Mval=None, Kval=None, stream=None):
+        """CSR values of M and K by weighted quadrature (igaf_wq_assemble);
+        kappa: CUDA float64 on the point grid [npts_z, npts_y, npts_x]."""
+        npts = [len(self.wq_points(d)) for d in range(3)]
+        _need_f64_cuda(kappa, "kappa", npts[0] * npts[1] * npts[2])
+        if want_m and Mval is None:
+            Mval = self._alloc(self.nnz, stream=stream)
+        if want_k and Kval is None:
+            Kval = self._alloc(self.nnz, stream=stream)
+        Mval = Mval if want_m else None
+        Kval = Kval if want_k else None
+        for t, nm in ((Mval, "Mval"), (Kval, "Kval")):
+            if t is not None:
+                _need_f64_cuda(t, nm, self.nnz)
+        _check(lib().igaf_wq_assemble(self._h, _ptr(kappa), _ptr(Mval), _ptr(Kval), _stream(stream)))
+        return Mval, Kval
 
 
 def _ptr_array(tensors):
