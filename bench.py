@@ -289,6 +289,7 @@ def bench_w4(ig, torch, stream, steps):
         B.integrate_assemble(kaps, Ms, Ks, stream=s)
     ms_g2 = float(np.mean(timed(g2.replay, steps, 2, torch.cuda.current_stream())))
     info = B.info()
+    info["degrees"] = {str(p): B.degree_config(p) for p in range(1, 6) if B.degree_config(p)["nitems"] > 0}
     out = {"patches": len(shapes), "elements": E, "nnz": nnz, "bytes": b, "flops": f,
            "roofline_ms": troof * 1e3,
            "batched": {"ms": ms_b, "elements_per_s": E / (ms_b * 1e-3), "frac": troof / (ms_b * 1e-3),

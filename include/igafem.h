@@ -393,14 +393,18 @@ igaf_status igaf_wq_assemble(const igaf_plan* plan, const double* kappa, double*
 /* ---------------------------------------------------------------- batches
  * Many independent patches (the paper's first concurrency level: parts of
  * the mesh computed concurrently) integrated and assembled to CSR (streamed
- * mode, M and K) from one work list by one kernel launch per degree present
- * (each degree's tile has its own block size and LDS): one workgroup per
- * (patch, tile of row pencils, x segment) item, items grouped by degree and
- * sorted longest first within a degree. */
+ * mode, M and K) by one kernel launch per degree present (each degree's tile
+ * has its own block size and LDS): one workgroup per (patch, tile of row
+ * pencils, x segment) item of that degree's work list, sorted longest first.
+ * Per degree the launch has a configuration: the tile shape (0: the shape of
+ * the single-patch kernel, 1: a smaller one), the x segments per tile (1, 2,
+ * 4, 8) and the items per XCD chunk (4, 16, 64); every combination has its
+ * own immutable work list, built at creation. */
 
 /* Build per-patch plans, the device patch table and the work lists of every
- * split (synchronous; one segment per tile and 16 items per XCD chunk until
- * igaf_batch_autotune or igaf_batch_set_split picks another split).  descs: HOST array of npatch
+ * configuration (synchronous; every degree starts with tile shape 0, one
+ * segment per tile and 16 items per XCD chunk until igaf_batch_autotune or
+ * igaf_batch_set_split / igaf_batch_set_degree_config choose others).  descs: HOST array of npatch
  * descriptions. */
 igaf_status igaf_batch_create(const igaf_patch_desc* descs, int32_t npatch, igaf_batch** out);
 
@@ -412,8 +416,8 @@ const igaf_plan* igaf_batch_plan(const igaf_batch* batch, int32_t i);
 
 /* The launch shape: family (kind of work item; 0 = a tile of row pencils,
  * the only kind), grid (workgroups launched over all degrees, each degree's
- * item count rounded up to whole XCD chunks), number of work items.  Any
- * output may be NULL. */
+ * item count rounded up to whole XCD chunks), number of work items, with
+ * every degree's current configuration.  Any output may be NULL. */
 igaf_status igaf_batch_info(const igaf_batch* batch, int32_t* family, int32_t* grid,
                             int32_t* nitems);
 
@@ -426,8 +430,8 @@ igaf_status igaf_batch_info(const igaf_batch* batch, int32_t* family, int32_t* g
  * the batch owns; when they differ from the previous call the host first
  * waits for `stream`.  The call may be captured in a HIP graph once it has
  * run eagerly with the same pointers (changing them during capture returns
- * IGAF_EINVAL).  A replay keeps the work split it was captured with (each
- * split has its own immutable work list) but copies the pointer tables the
+ * IGAF_EINVAL).  A replay keeps the configurations it was captured with
+ * (each has its own immutable work list) but copies the pointer tables the
  * batch holds at replay time, i.e. those of the latest call: after an eager
  * call with other pointers, replays read and write those arrays.
  * Overlapping calls on one batch from different streams race. */
@@ -443,28 +447,36 @@ igaf_status igaf_batch_integrate_assemble_separate(igaf_batch* batch,
                                                    void* stream);
 
 /* Autotuner of the batched launch (synchronous; not under stream capture).
- * The launch's work split has two knobs: the x segments each tile of row
- * pencils is cut into (1, 2, 4 or 8, never below 2(p+1) rows per segment; a
- * segment that does not start at the patch boundary sweeps p warm-up
- * elements first), which shortens the longest items at the cost of the
- * warm-ups, and the number of consecutive items handed to one XCD (4, 16 or
- * 64), which trades L2 sharing between neighbouring tiles against balance.
- * Every combination is timed on the caller's arrays (one warm-up launch,
- * then `reps` launches, 1..100, HIP events on `stream`, the median kept);
- * the fastest is used by every later igaf_batch_integrate_assemble.  Mval,
- * Kval are overwritten, with the same values every time: each CSR value is
- * summed in one thread in a fixed order whatever the split. */
+ * For every degree present, one at a time (the degrees' launches are
+ * independent), every configuration is timed on the caller's arrays: tile
+ * shape (0 or 1), x segments per tile (1, 2, 4 or 8, never below 2(p+1) rows
+ * per segment; a segment that does not start at the patch boundary sweeps p
+ * warm-up elements first: shorter items against more warm-up) and items per
+ * XCD chunk (4, 16 or 64: L2 sharing between neighbouring tiles against
+ * balance); one warm-up launch, then `reps` launches (1..100, HIP events on
+ * `stream`), the median kept; the fastest configuration of each degree is
+ * used by every later igaf_batch_integrate_assemble.  Mval, Kval are
+ * overwritten, with the same values every time: each CSR value is summed in
+ * one thread in a fixed order whatever the tile shape or split. */
 igaf_status igaf_batch_autotune(igaf_batch* batch, const double* const* kappa, double* const* Mval,
                                 double* const* Kval, int32_t reps, void* stream);
 
-/* Set the work split by hand: split in {1, 2, 4, 8}, chunk in {4, 16, 64},
- * else IGAF_EINVAL; e.g. to reuse an earlier tuning.  Host-only (the work
- * lists of every split are uploaded at creation); later calls use it. */
+/* Set every degree to tile shape 0 with this split in {1, 2, 4, 8} and chunk
+ * in {4, 16, 64} (else IGAF_EINVAL).  Host-only; later calls use it. */
 igaf_status igaf_batch_set_split(igaf_batch* batch, int32_t split, int32_t chunk);
 
-/* The work split in use: segments per tile (at most), items per XCD chunk,
- * and the median launch time in ms when the autotuner chose it (0 before).
- * Any output may be NULL. */
+/* Set one degree's configuration (tile 0 or 1, split, chunk as above), e.g.
+ * to reuse an earlier tuning.  Host-only. */
+igaf_status igaf_batch_set_degree_config(igaf_batch* batch, int32_t degree, int32_t tile, int32_t split,
+                                         int32_t chunk);
+
+/* One degree's configuration, the autotuner's median launch time for it (0
+ * when not tuned) and its number of work items.  Any output may be NULL. */
+igaf_status igaf_batch_degree_config(const igaf_batch* batch, int32_t degree, int32_t* tile, int32_t* split,
+                                     int32_t* chunk, double* tuned_ms, int32_t* nitems);
+
+/* The split and chunk of the highest degree present and the sum of the
+ * degrees' tuned launch times (0 before tuning).  Any output may be NULL. */
 igaf_status igaf_batch_split(const igaf_batch* batch, int32_t* split, int32_t* chunk, double* tuned_ms);
 
 #ifdef __cplusplus

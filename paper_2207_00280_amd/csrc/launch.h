@@ -31,13 +31,16 @@ int launch_rows(const PatchDev& pd, const double* kappa, double* Mval, double* K
 
 // Batched CSR rows of the degree-p patches: one workgroup per (patch, tile,
 // x segment, segment length) item of `items` (all of degree p), which the
-// host sorts longest first, `chunk` consecutive items per XCD;
-// rows_batch_grid is the launch's workgroup count, rows_tile_info the tiles
-// of a patch and the relative cost of one element step of a tile.
-int launch_rows_batch(int p, const BatchPatch* patches, const int4* items, int nitems, int chunk,
+// host sorts longest first, `chunk` consecutive items per XCD; `variant`
+// selects the tile shape (0: the standalone kernel's, 1: a smaller one,
+// kTileVariants in all).  rows_batch_grid is the launch's workgroup count,
+// rows_tile_info the tiles of a patch and the relative cost of one element
+// step of a tile of that variant.
+constexpr int kTileVariants = 2;
+int launch_rows_batch(int p, int variant, const BatchPatch* patches, const int4* items, int nitems, int chunk,
                       hipStream_t st);
 int rows_batch_grid(int nitems, int chunk);
-int rows_tile_info(int p, int Ny, int Nz, int* ntile, double* per_elem);
+int rows_tile_info(int p, int variant, int Ny, int Nz, int* ntile, double* per_elem);
 
 // CSR values gathered from stored element matrices: overwrites Mval / Kval
 // for the rows [g0, g1) (all rows by default); element e's matrices are read

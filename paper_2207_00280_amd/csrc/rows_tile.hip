@@ -124,6 +124,16 @@ template <> struct TileCfg<3> { using T = Tile<3, 2, 2, 4, false, true>; };
 template <> struct TileCfg<4> { using T = Tile<4, 2, 2, 2, true, true>; };
 template <> struct TileCfg<5> { using T = Tile<5, 3, 1, 2, false, true>; };
 
+// A second shape per degree for the batched launches, smaller (fewer
+// pencils: less LDS, more workgroups per CU, less work lost at the borders
+// of small patches); the batch autotuner chooses between the two per degree.
+template <int P> struct TileAlt;
+template <> struct TileAlt<1> { using T = Tile<1, 2, 2, 4, true, false>; };
+template <> struct TileAlt<2> { using T = Tile<2, 2, 2, 4, true, true>; };
+template <> struct TileAlt<3> { using T = Tile<3, 2, 1, 4, false, true>; };
+template <> struct TileAlt<4> { using T = Tile<4, 2, 1, 2, true, true>; };
+template <> struct TileAlt<5> { using T = Tile<5, 2, 1, 2, false, true>; };
+
 // Per-workgroup constants of one tile.
 struct TileCtx {
     const double* kappa;
@@ -679,19 +689,24 @@ static int launch_items_t(const BatchPatch* patches, const int4* items, int nite
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_rows_batch(int p, const BatchPatch* patches, const int4* items, int nitems, int chunk,
+int launch_rows_batch(int p, int variant, const BatchPatch* patches, const int4* items, int nitems, int chunk,
                       hipStream_t st)
 {
     if (nitems <= 0) return 0;
     if (chunk < 1) return -4;
+#define IGAF_RB(PP)                                                                                          \
+    case PP:                                                                                                 \
+        return variant ? launch_items_t<TileAlt<PP>::T>(patches, items, nitems, chunk, st)                   \
+                       : launch_items_t<TileCfg<PP>::T>(patches, items, nitems, chunk, st);
     switch (p) {
-    case 1: return launch_items_t<TileCfg<1>::T>(patches, items, nitems, chunk, st);
-    case 2: return launch_items_t<TileCfg<2>::T>(patches, items, nitems, chunk, st);
-    case 3: return launch_items_t<TileCfg<3>::T>(patches, items, nitems, chunk, st);
-    case 4: return launch_items_t<TileCfg<4>::T>(patches, items, nitems, chunk, st);
-    case 5: return launch_items_t<TileCfg<5>::T>(patches, items, nitems, chunk, st);
+        IGAF_RB(1)
+        IGAF_RB(2)
+        IGAF_RB(3)
+        IGAF_RB(4)
+        IGAF_RB(5)
     default: return -4;
     }
+#undef IGAF_RB
 }
 
 int rows_batch_grid(int nitems, int chunk)
@@ -711,16 +726,22 @@ static void tile_info_t(int Ny, int Nz, int* ntile, double* per_elem)
     *per_elem = T::NWZ * 2.0 * terms + T::NWY * 3.0 * terms + T::WX * 3.0 * terms;
 }
 
-int rows_tile_info(int p, int Ny, int Nz, int* ntile, double* per_elem)
+int rows_tile_info(int p, int variant, int Ny, int Nz, int* ntile, double* per_elem)
 {
+#define IGAF_TI(PP)                                                                                          \
+    case PP:                                                                                                 \
+        if (variant) tile_info_t<TileAlt<PP>::T>(Ny, Nz, ntile, per_elem);                                  \
+        else tile_info_t<TileCfg<PP>::T>(Ny, Nz, ntile, per_elem);                                          \
+        return 0;
     switch (p) {
-    case 1: tile_info_t<TileCfg<1>::T>(Ny, Nz, ntile, per_elem); return 0;
-    case 2: tile_info_t<TileCfg<2>::T>(Ny, Nz, ntile, per_elem); return 0;
-    case 3: tile_info_t<TileCfg<3>::T>(Ny, Nz, ntile, per_elem); return 0;
-    case 4: tile_info_t<TileCfg<4>::T>(Ny, Nz, ntile, per_elem); return 0;
-    case 5: tile_info_t<TileCfg<5>::T>(Ny, Nz, ntile, per_elem); return 0;
+        IGAF_TI(1)
+        IGAF_TI(2)
+        IGAF_TI(3)
+        IGAF_TI(4)
+        IGAF_TI(5)
     default: return -4;
     }
+#undef IGAF_TI
 }
 
 }  // namespace igaf

@@ -30,7 +30,7 @@ SYMBOLS = [
     "igaf_batch_create", "igaf_batch_destroy",
     "igaf_batch_plan", "igaf_batch_info", "igaf_batch_integrate_assemble",
     "igaf_batch_integrate_assemble_separate", "igaf_batch_autotune", "igaf_batch_split",
-    "igaf_batch_set_split", "igaf_wq_prepare", "igaf_wq_points", "igaf_wq_assemble",
+    "igaf_batch_set_split", "igaf_batch_set_degree_config", "igaf_batch_degree_config", "igaf_wq_prepare", "igaf_wq_points", "igaf_wq_assemble",
 ]
 
 
@@ -111,6 +111,9 @@ def lib():
     L.igaf_batch_autotune.argtypes = [_vp, ptrs, ptrs, ptrs, ctypes.c_int32, _vp]
     L.igaf_batch_split.argtypes = [_vp, _i32p, _i32p, ctypes.POINTER(ctypes.c_double)]
     L.igaf_batch_set_split.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+    L.igaf_batch_set_degree_config.argtypes = [_vp] + [ctypes.c_int32] * 4
+    L.igaf_batch_degree_config.argtypes = [_vp, ctypes.c_int32, _i32p, _i32p, _i32p,
+                                           ctypes.POINTER(ctypes.c_double), _i32p]
     L.igaf_wq_prepare.argtypes = [_vp]
     L.igaf_wq_points.argtypes = [_vp, ctypes.c_int32, _i64p, _dp]
     L.igaf_wq_assemble.argtypes = [_vp, _vp, _vp, _vp, _vp]
@@ -582,6 +585,19 @@ class Batch:
 
     def set_split(self, split, chunk):
         _check(lib().igaf_batch_set_split(self._h, int(split), int(chunk)))
+
+    def set_degree_config(self, degree, tile, split, chunk):
+        _check(lib().igaf_batch_set_degree_config(self._h, int(degree), int(tile), int(split), int(chunk)))
+
+    def degree_config(self, degree):
+        """One degree's launch configuration: tile shape, split, chunk, the
+        autotuner's median ms (0 if not tuned) and the number of items."""
+        v = [ctypes.c_int32() for _ in range(3)]
+        t = ctypes.c_double()
+        n = ctypes.c_int32()
+        _check(lib().igaf_batch_degree_config(self._h, int(degree), *[ctypes.byref(x) for x in v],
+                                              ctypes.byref(t), ctypes.byref(n)))
+        return dict(tile=v[0].value, split=v[1].value, chunk=v[2].value, ms=t.value, nitems=n.value)
 
     def autotune(self, kappas, Mvals, Kvals, reps=3, stream=None):
         """Time every work split on these arrays and keep the fastest

@@ -59,6 +59,16 @@ def test_batch_small_vs_oracle(orc, ig):
         assert csr_close(to_host(Ks[i]), Ko, rp), i
     info = B.info()
     assert info["family"] == 0 and info["grid"] >= info["nitems"] > 0
+    # the second tile shape of every degree vs the oracle too
+    for p in range(1, 6):
+        B.set_degree_config(p, 1, 1, 16)
+    Ma = [torch.full_like(m, np.nan) for m in Ms]
+    Ka = [torch.full_like(k, np.nan) for k in Ks]
+    B.integrate_assemble(kaps, Ma, Ka)
+    torch.cuda.synchronize()
+    for i, (rp, col, Mo, Ko) in enumerate(refs):
+        assert csr_close(to_host(Ma[i]), Mo, rp) and csr_close(to_host(Ka[i]), Ko, rp), i
+    B.set_split(1, 16)
     # mass only
     Ms2 = [torch.zeros_like(m) for m in Ms]
     B.integrate_assemble(kaps, Ms2, None)
@@ -116,13 +126,13 @@ def test_batch_graph_replay(ig):
 
 
 def test_batch_autotune(ig):
-    """The autotuner times every work split (segments per tile 1, 2, 4, 8;
-    items per XCD chunk 4, 16, 64) and keeps the fastest.  Patches long
-    enough in x to be cut into segments (K_x up to 40, p = 1..5): the values
-    after tuning equal the untuned launch bit for bit (each CSR value is
-    summed by one thread in a fixed order whatever the split), and match the
-    per-patch launches; a forced split of 8 segments also gives the same
-    bits."""
+    """The autotuner times, per degree, every configuration (tile shape 0 or
+    1, segments per tile 1, 2, 4, 8, items per XCD chunk 4, 16, 64) and keeps
+    the fastest.  Patches long enough in x to be cut into segments (K_x up to
+    40, p = 1..5): the values after tuning equal the untuned launch bit for
+    bit (each CSR value is summed by one thread in a fixed order whatever the
+    tile or split), and match the per-patch launches; forced splits and the
+    second tile shape of every degree also give the same bits."""
     import torch
 
     rng = np.random.default_rng(17)
@@ -155,6 +165,9 @@ def test_batch_autotune(ig):
     torch.cuda.synchronize()
     for a, b in zip(Ms + Ks, Ms2 + Ks2):
         assert float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) <= 1e-12
+    for p in range(1, 6):
+        c = B.degree_config(p)
+        assert c["tile"] in (0, 1) and c["split"] in (1, 2, 4, 8) and c["chunk"] in (4, 16, 64)
     for split, chunk in ((8, 4), (2, 64)):
         B.set_split(split, chunk)
         assert B.split()["split"] == split and B.info()["nitems"] > n_untuned
@@ -164,6 +177,18 @@ def test_batch_autotune(ig):
         torch.cuda.synchronize()
         for a, b in zip(Ms + Ks, ref):
             assert torch.equal(a, b), (split, chunk)
+    # the second tile shape of every degree, forced: the same bits
+    for p in range(1, 6):
+        B.set_degree_config(p, 1, 2, 16)
+        assert B.degree_config(p)["tile"] == 1
+    for t in Ms + Ks:
+        t.fill_(np.nan)
+    B.integrate_assemble(kaps, Ms, Ks)
+    torch.cuda.synchronize()
+    for a, b in zip(Ms + Ks, ref):
+        assert torch.equal(a, b)
+    with pytest.raises(ig.IgafError):
+        B.set_degree_config(3, 2, 1, 16)
     with pytest.raises(ig.IgafError):
         B.autotune(kaps, Ms, Ks, reps=0)
     with pytest.raises(ig.IgafError):
