@@ -439,12 +439,14 @@ def bench_w6(ig, torch, stream, steps):
     return out
 
 
-def wq_fmas_per_row(p, pw):
-    """Fused multiply-adds of one CSR row of the weighted-quadrature kernel
-    with pw points per direction in the row's box: stage x 2 O pw^3,
-    stage y 3 O^2 pw^2, stage z 3 O^3 pw (O = 2p + 1)."""
+def wq_fmas_per_row(p, w, R=8):
+    """Fused multiply-adds per CSR row of the weighted-quadrature kernel for
+    interior rows (w = 2(p+1) points per direction in a row's box): stages z
+    and y once per chunk of R rows over its 2(R+p) x points, each point
+    O w (2w + 3O), then stage x per row 3 O^3 w (O = 2p + 1)."""
     O = 2 * p + 1
-    return 2 * O * pw ** 3 + 3 * O * O * pw ** 2 + 3 * O ** 3 * pw
+    nx = 2 * (R + p)
+    return nx * O * w * (2 * w + 3 * O) / R + 3 * O ** 3 * w
 
 
 def bench_w7_wq(ig, torch, stream, steps):

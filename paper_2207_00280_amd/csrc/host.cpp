@@ -157,6 +157,7 @@ struct igaf_plan {
     // direction and the rules in device memory
     std::vector<double> knots_h[3];
     std::vector<double> wq_x[3];
+    std::vector<int> wq_lo0, wq_cnt0;
     void* wq_mem = nullptr;
     WqDev wq{};
     bool wq_ready = false;
@@ -818,6 +819,10 @@ igaf_status igaf_wq_prepare(igaf_plan* plan)
         return fail(IGAF_EDEVICE, "weighted quadrature tables: upload failed");
     }
     plan->wq_mem = mem;
+    plan->wq_lo0 = H[0].lo;
+    plan->wq_cnt0 = H[0].cnt;
+    w.h_lo0 = plan->wq_lo0.data();
+    w.h_cnt0 = plan->wq_cnt0.data();
     plan->wq = w;
     for (int d = 0; d < 3; ++d) plan->wq_x[d] = H[d].x;
     plan->wq_ready = true;

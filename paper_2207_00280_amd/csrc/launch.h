@@ -124,6 +124,8 @@ struct WqDir {
 struct WqDev {
     WqDir d[3];
     int PW;
+    const int* h_lo0;    // HOST copies of direction x's lo and cnt (launch sizing)
+    const int* h_cnt0;
 };
 // CSR values (overwritten; either output may be null) by weighted
 // quadrature, kappa [npts_z][npts_y][npts_x]; -4 if the LDS of a row exceeds

@@ -21,16 +21,11 @@
 // transposed exactness matrix in long double (min-norm solution; the
 // systems reach condition numbers of ~1e5 at p = 5).
 //
-// Kernel (k_wq_rows): one workgroup per CSR row, grid-stride over rows; the
-// row's sums run by sum factorisation over its point box in LDS, x -> y -> z:
-//   per direction d and column offset o: the weighted test values times the
-//     trial values, T[d][n|d][o][q] = w00|w11[i_d][q] * B_j|B_j'(x_q);
-//   stage x: E[n|d][o1][q3][q2]  = sum_q1 T[x][n|d][o1][q1] kappa(q1, q2, q3);
-//   stage y: F0[o1][o2][q3]      = sum_q2 T[y][n][o2][q2] En,
-//            F1[o1][o2][q3]      = sum_q2 (T[y][d][o2][q2] En + T[y][n][o2][q2] Ed);
-//   stage z: M[o1][o2][o3]       = sum_q3 T[z][n][o3][q3] F0,
-//            K[o1][o2][o3]       = sum_q3 (T[z][n][o3][q3] F1 + T[z][d][o3][q3] F0);
-// then the row is staged in LDS at its CSR positions and written contiguously.
+// Kernel (k_wq_pencil): one workgroup per chunk of R consecutive rows along
+// x of one pencil (i2, i3); the rows share the contractions over z and y,
+// taken once for all the x points their supports cover, and each row then
+// contracts x with its own weights (see the kernel).
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -206,144 +201,141 @@ int wq_build_dir(int p, int K, const double* t, const double* xg, const double* 
 
 template <int P>
 struct WqShape {
-    static constexpr int O = 2 * P + 1, n = P + 1, O3 = O * O * O;
+    static constexpr int O = 2 * P + 1, n = P + 1;
 };
 
-// LDS doubles of the row kernel for a largest point count PW per direction
+// LDS doubles of the pencil kernel: T1 [2][R][O][PW] (the rows' x tables),
+// T23 [2 dirs][2][O][PW], C [2][O][O][NX]
 template <int P>
-static int64_t wq_lds_doubles(int PW)
+static int64_t wq_lds_doubles(int R, int PW, int NX)
 {
-    using S = WqShape<P>;
-    const int64_t T = 6LL * S::O * PW, E = 2LL * S::O * PW * PW, F = 2LL * S::O * S::O * PW;
-    const int64_t RW = 2LL * (S::O3 + 1);
-    return T + (E > RW ? E : RW) + F;
+    constexpr int O = WqShape<P>::O;
+    return 2LL * R * O * PW + 4LL * O * PW + 2LL * O * O * NX;
 }
 
+// One workgroup per (chunk of R rows along x, i2, i3): the rows (i1, i2,
+// i3), i1 in [r0, r0 + R), share stages z and y over the x points their
+// supports cover, [X0, X1), taken by one thread per (x, o3), the stage-z sums
+// in registers:
+//   Dn|Dd[q2]     = sum_q3 T3[n|d][o3][q3] kappa(X0 + x, lo2 + q2, lo3 + q3)
+//   C0[o2][o3][x] = sum_q2 T2[n][o2][q2] Dn[q2]
+//   C1[o2][o3][x] = sum_q2 (T2[d][o2][q2] Dn[q2] + T2[n][o2][q2] Dd[q2])
+// and stage x gives each row's values from its own x tables:
+//   M = sum_q1 T1[n][o1][q1] C0[.][lo1 - X0 + q1],  K = sum_q1 (T1[d] C0 + T1[n] C1)
+// with T[d][n|d][o][q] = w00|w11[i_d][q] B_j|B_j'(x_q), j = i_d + o - p.
+// A thread of stage x owns (row, o2, o3) and writes the row's O values of
+// that (o2, o3), contiguous in the CSR row (columns jx fastest).
 template <int P>
-__global__ __launch_bounds__(256) void k_wq_rows(WqDev w, RowMap rm, const double* __restrict__ kappa,
-                                                 double* __restrict__ Mv, double* __restrict__ Kv, int64_t ndof)
+__global__ __launch_bounds__(256) void k_wq_pencil(WqDev w, RowMap rm, const double* __restrict__ kappa,
+                                                   double* __restrict__ Mv, double* __restrict__ Kv, int R,
+                                                   int NXM)
 {
     using S = WqShape<P>;
-    constexpr int O = S::O, n = S::n, O3 = S::O3;
+    constexpr int O = S::O, n = S::n;
     extern __shared__ double sm[];
     const int PW = w.PW, tid = threadIdx.x;
-    const int64_t sE = 2LL * O * PW * PW, sRW = 2LL * (O3 + 1);
-    double* const T = sm;                                  // [3][2][O][PW]
-    double* const E = T + 6 * O * PW;                      // [2][O][PW (q3)][PW (q2)]
-    double* const RW = E;                                  // row staging [2][O3 + 1], after stage y
-    double* const F = E + (sE > sRW ? sE : sRW);           // [2][O][O][PW]
+    double* const T1 = sm;                          // [2][R][O][PW]
+    double* const T23 = T1 + 2 * R * O * PW;        // [dir 0 = y, 1 = z][2][O][PW]
+    double* const C = T23 + 4 * O * PW;             // [2][O][O][NXM]
     const int N1 = w.d[0].N, N2 = w.d[1].N;
     const int np1 = w.d[0].npts, np2 = w.d[1].npts;
-    for (int64_t row = blockIdx.x; row < ndof; row += gridDim.x) {
-        const int i1 = (int)(row % N1), i2 = (int)((row / N1) % N2), i3 = (int)(row / ((int64_t)N1 * N2));
-        const int ii[3] = {i1, i2, i3};
-        int lo[3], c[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = w.d[d].lo[ii[d]];
-            c[d] = w.d[d].cnt[ii[d]];
-        }
-        // weighted test values times trial values, per direction and offset
-        for (int idx = tid; idx < 3 * O * PW; idx += 256) {
-            const int d = idx / (O * PW), o = (idx / PW) % O, q = idx % PW;
-            const int j = ii[d] + o - P;
-            double vn = 0.0, vd = 0.0;
-            if (q < c[d] && j >= 0 && j < w.d[d].N) {
-                const int pt = lo[d] + q, a = j - w.d[d].eq[pt];
-                if (a >= 0 && a < n) {
-                    vn = w.d[d].w00[(int64_t)ii[d] * PW + q] * w.d[d].Bv[(int64_t)pt * n + a];
-                    vd = w.d[d].w11[(int64_t)ii[d] * PW + q] * w.d[d].dB[(int64_t)pt * n + a];
-                }
+    const int nch = (N1 + R - 1) / R;
+    const int ch = blockIdx.x % nch;
+    const int i2 = (blockIdx.x / nch) % N2, i3 = blockIdx.x / (nch * N2);
+    const int r0 = ch * R, nr = min(R, N1 - r0);
+    const int X0 = w.d[0].lo[r0];
+    const int NX = w.d[0].lo[r0 + nr - 1] + w.d[0].cnt[r0 + nr - 1] - X0;
+    const int lo2 = w.d[1].lo[i2], c2 = w.d[1].cnt[i2];
+    const int lo3 = w.d[2].lo[i3], c3 = w.d[2].cnt[i3];
+    // weighted test values times trial values: the y and z tables of the
+    // pencil, the x tables of every row of the chunk
+    for (int idx = tid; idx < (2 + nr) * O * PW; idx += 256) {
+        const int t = idx / (O * PW), o = (idx / PW) % O, q = idx % PW;
+        const int d = t < 2 ? t + 1 : 0;
+        const int ii = t == 0 ? i2 : (t == 1 ? i3 : r0 + t - 2);
+        const int j = ii + o - P;
+        double vn = 0.0, vd = 0.0;
+        if (q < w.d[d].cnt[ii] && j >= 0 && j < w.d[d].N) {
+            const int pt = w.d[d].lo[ii] + q, a = j - w.d[d].eq[pt];
+            if (a >= 0 && a < n) {
+                vn = w.d[d].w00[(int64_t)ii * PW + q] * w.d[d].Bv[(int64_t)pt * n + a];
+                vd = w.d[d].w11[(int64_t)ii * PW + q] * w.d[d].dB[(int64_t)pt * n + a];
             }
-            T[(d * 2 + 0) * O * PW + o * PW + q] = vn;
-            T[(d * 2 + 1) * O * PW + o * PW + q] = vd;
         }
-        __syncthreads();
-        // stage x: item (q2, q3)
-        for (int it = tid; it < c[1] * c[2]; it += 256) {
-            const int q2 = it % c[1], q3 = it / c[1];
-            const double* kr = kappa + ((int64_t)(lo[2] + q3) * np2 + (lo[1] + q2)) * np1 + lo[0];
-            double en[O], ed[O];
+        if (t < 2) {
+            T23[(t * 2 + 0) * O * PW + o * PW + q] = vn;
+            T23[(t * 2 + 1) * O * PW + o * PW + q] = vd;
+        } else {
+            T1[(0 * R + t - 2) * O * PW + o * PW + q] = vn;
+            T1[(1 * R + t - 2) * O * PW + o * PW + q] = vd;
+        }
+    }
+    __syncthreads();
+    // stages z and y: item (x, o3), consecutive x in consecutive lanes
+    const int64_t zs = (int64_t)np2 * np1;
+    for (int it = tid; it < NX * O; it += 256) {
+        const int x = it % NX, o3 = it / NX;
+        const double* kp = kappa + ((int64_t)lo3 * np2 + lo2) * np1 + X0 + x;
+        const double* t3n = T23 + (1 * 2 + 0) * O * PW + o3 * PW;
+        const double* t3d = T23 + (1 * 2 + 1) * O * PW + o3 * PW;
+        double c0[O], c1[O];
 #pragma unroll
-            for (int o = 0; o < O; ++o) en[o] = ed[o] = 0.0;
-            for (int q1 = 0; q1 < c[0]; ++q1) {
-                const double k = kr[q1];
-#pragma unroll
-                for (int o = 0; o < O; ++o) {
-                    en[o] += T[(0 * 2 + 0) * O * PW + o * PW + q1] * k;
-                    ed[o] += T[(0 * 2 + 1) * O * PW + o * PW + q1] * k;
-                }
+        for (int o = 0; o < O; ++o) c0[o] = c1[o] = 0.0;
+        for (int q2 = 0; q2 < c2; ++q2) {
+            double dn = 0.0, dd = 0.0;
+            for (int q3 = 0; q3 < c3; ++q3) {
+                const double k = kp[q2 * np1 + q3 * zs];
+                dn += t3n[q3] * k;
+                dd += t3d[q3] * k;
             }
 #pragma unroll
             for (int o = 0; o < O; ++o) {
-                E[(0 * O + o) * PW * PW + q3 * PW + q2] = en[o];
-                E[(1 * O + o) * PW * PW + q3 * PW + q2] = ed[o];
+                const double tn = T23[(0 * 2 + 0) * O * PW + o * PW + q2];
+                const double td = T23[(0 * 2 + 1) * O * PW + o * PW + q2];
+                c0[o] += tn * dn;
+                c1[o] += td * dn + tn * dd;
             }
         }
-        __syncthreads();
-        // stage y: item (o1, q3)
-        for (int it = tid; it < O * c[2]; it += 256) {
-            const int o1 = it % O, q3 = it / O;
-            const double* en = E + (0 * O + o1) * PW * PW + q3 * PW;
-            const double* ed = E + (1 * O + o1) * PW * PW + q3 * PW;
-            double f0[O], f1[O];
 #pragma unroll
-            for (int o = 0; o < O; ++o) f0[o] = f1[o] = 0.0;
-            for (int q2 = 0; q2 < c[1]; ++q2) {
-                const double a = en[q2], b = ed[q2];
+        for (int o = 0; o < O; ++o) {
+            C[((0 * O + o) * O + o3) * NXM + x] = c0[o];
+            C[((1 * O + o) * O + o3) * NXM + x] = c1[o];
+        }
+    }
+    __syncthreads();
+    // stage x: item (row, o2, o3); the row's O values of (o2, o3) go out
+    const int bl2 = band_lo(i2, P), bl3 = band_lo(i3, P);
+    const int Ly = band_len(i2, P, rm.N[1]);
+    for (int it = tid; it < nr * O * O; it += 256) {
+        const int o2 = it % O, o3 = (it / O) % O, r = it / (O * O);
+        const int i1 = r0 + r, j2 = i2 + o2 - P, j3 = i3 + o3 - P;
+        if (j2 < 0 || j2 >= rm.N[1] || j3 < 0 || j3 >= rm.N[2]) continue;
+        const int xo = w.d[0].lo[i1] - X0, c1n = w.d[0].cnt[i1];
+        const double* tn = T1 + (0 * R + r) * O * PW;
+        const double* td = T1 + (1 * R + r) * O * PW;
+        const double* a = C + ((0 * O + o2) * O + o3) * NXM + xo;
+        const double* b = C + ((1 * O + o2) * O + o3) * NXM + xo;
+        double m[O], k[O];
 #pragma unroll
-                for (int o = 0; o < O; ++o) {
-                    const double tn = T[(1 * 2 + 0) * O * PW + o * PW + q2];
-                    const double td = T[(1 * 2 + 1) * O * PW + o * PW + q2];
-                    f0[o] += tn * a;
-                    f1[o] += td * a + tn * b;
-                }
-            }
+        for (int o = 0; o < O; ++o) m[o] = k[o] = 0.0;
+        for (int q1 = 0; q1 < c1n; ++q1) {
+            const double av = a[q1], bv = b[q1];
 #pragma unroll
             for (int o = 0; o < O; ++o) {
-                F[(0 * O + o1) * O * PW + o * PW + q3] = f0[o];
-                F[(1 * O + o1) * O * PW + o * PW + q3] = f1[o];
+                m[o] += tn[o * PW + q1] * av;
+                k[o] += td[o * PW + q1] * av + tn[o * PW + q1] * bv;
             }
         }
-        __syncthreads();
-        // stage z: item (o1, o2); the values go to their row positions
-        const int bl1 = band_lo(i1, P), bl2 = band_lo(i2, P), bl3 = band_lo(i3, P);
-        const int Lx = band_len(i1, P, rm.N[0]), Ly = band_len(i2, P, rm.N[1]), Lz = band_len(i3, P, rm.N[2]);
-        for (int it = tid; it < O * O; it += 256) {
-            const int o1 = it % O, o2 = it / O;
-            const double* f0 = F + (0 * O + o1) * O * PW + o2 * PW;
-            const double* f1 = F + (1 * O + o1) * O * PW + o2 * PW;
-            double m[O], k[O];
+        const int bl1 = band_lo(i1, P), Lx = band_len(i1, P, rm.N[0]);
+        const int64_t base = rm.row_start(i1, i2, i3) + ((int64_t)(j3 - bl3) * Ly + (j2 - bl2)) * Lx - bl1;
 #pragma unroll
-            for (int o = 0; o < O; ++o) m[o] = k[o] = 0.0;
-            for (int q3 = 0; q3 < c[2]; ++q3) {
-                const double a = f0[q3], b = f1[q3];
-#pragma unroll
-                for (int o = 0; o < O; ++o) {
-                    const double tn = T[(2 * 2 + 0) * O * PW + o * PW + q3];
-                    const double td = T[(2 * 2 + 1) * O * PW + o * PW + q3];
-                    m[o] += tn * a;
-                    k[o] += tn * b + td * a;
-                }
-            }
-            const int j1 = i1 + o1 - P, j2 = i2 + o2 - P;
-            const bool ok12 = j1 >= 0 && j1 < rm.N[0] && j2 >= 0 && j2 < rm.N[1];
-#pragma unroll
-            for (int o = 0; o < O; ++o) {
-                const int j3 = i3 + o - P;
-                const int pos = ok12 && j3 >= 0 && j3 < rm.N[2] ? ((j3 - bl3) * Ly + (j2 - bl2)) * Lx + (j1 - bl1) : O3;
-                RW[pos] = m[o];
-                RW[O3 + 1 + pos] = k[o];
+        for (int o = 0; o < O; ++o) {
+            const int j1 = i1 + o - P;
+            if (j1 >= 0 && j1 < rm.N[0]) {
+                if (Mv) Mv[base + j1] = m[o];
+                if (Kv) Kv[base + j1] = k[o];
             }
         }
-        __syncthreads();
-        const int64_t rs = rm.row_start(i1, i2, i3);
-        const int L = Lx * Ly * Lz;
-        for (int i = tid; i < L; i += 256) {
-            if (Mv) Mv[rs + i] = RW[i];
-            if (Kv) Kv[rs + i] = RW[O3 + 1 + i];
-        }
-        __syncthreads();   // T, E, F and the staged row are rewritten by the next row
     }
 }
 
@@ -351,15 +343,26 @@ template <int P>
 static int launch_wq_t(const WqDev& w, const PatchDev& pd, const double* kappa, double* Mv, double* Kv,
                        hipStream_t st)
 {
-    const int64_t lds = wq_lds_doubles<P>(w.PW) * (int64_t)sizeof(double);
-    if (lds > 160 * 1024) return -4;
-    if (hipFuncSetAttribute((const void*)k_wq_rows<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-        hipSuccess)
-        return -3;
-    int64_t blocks = pd.ndof < 16384 ? pd.ndof : 16384;
-    hipLaunchKernelGGL(k_wq_rows<P>, dim3((unsigned)blocks), dim3(256), (unsigned)lds, st, w, make_rowmap(pd), kappa,
-                       Mv, Kv, pd.ndof);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+    // rows per chunk: the most (8, 4, 2, 1) whose LDS fits a CU; NXM = the
+    // most x points a chunk's rows cover
+    const int N1 = w.d[0].N;
+    for (int R = 8; R >= 1; R /= 2) {
+        int NXM = 0;
+        for (int r0 = 0; r0 < N1; r0 += R) {
+            const int rl = std::min(N1, r0 + R) - 1;
+            NXM = std::max(NXM, w.h_lo0[rl] + w.h_cnt0[rl] - w.h_lo0[r0]);
+        }
+        const int64_t lds = wq_lds_doubles<P>(R, w.PW, NXM) * (int64_t)sizeof(double);
+        if (lds > 160 * 1024) continue;
+        if (hipFuncSetAttribute((const void*)k_wq_pencil<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess)
+            return -3;
+        const int64_t blocks = (int64_t)((N1 + R - 1) / R) * w.d[1].N * w.d[2].N;
+        hipLaunchKernelGGL(k_wq_pencil<P>, dim3((unsigned)blocks), dim3(256), (unsigned)lds, st, w, make_rowmap(pd),
+                           kappa, Mv, Kv, R, NXM);
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+    }
+    return -4;
 }
 
 int launch_wq(const WqDev& w, const PatchDev& pd, const double* kappa, double* Mv, double* Kv, hipStream_t st)
