@@ -221,12 +221,14 @@ igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const
  *      igaf_csr_pattern).  At least one output.  A CSR output whose element
  *      matrices are requested too is summed from them as in igaf_assemble;
  *      one without is summed the same way slab by slab of element layers
- *      through a workspace the plan allocates at the first such call (at
- *      most 2 GiB, freed with the plan; neighbouring slabs share p layers,
- *      integrated twice).  Both are deterministic and give the same bits.
- *      If that first call runs under stream capture, or the workspace
- *      cannot hold p+1 layers, the values are added with FP64 atomics
- *      instead (the last bits may then vary between calls).
+ *      through a workspace the plan allocates in igaf_geo_prepare, or else
+ *      at the first such call (at most 2 GiB, freed with the plan;
+ *      neighbouring slabs share p layers, integrated twice).  Both are
+ *      deterministic and give the same bits.  Under stream capture the
+ *      workspace must exist already (IGAF_EINVAL otherwise, before any
+ *      launch).  Only when the workspace cannot hold p+1 element layers (or
+ *      its allocation fails) are the values added with FP64 atomics instead
+ *      (the last bits may then vary between calls).
  * Sum factorisation (Algorithm 2) with ordered per-direction pairs (the
  * cross terms of G are not symmetric in a pair); nquad = degree+1 in every
  * direction, else IGAF_EUNSUPPORTED.  cm = kappa, G = kappa I (the identity
@@ -235,6 +237,13 @@ igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const
 igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm, const double* G,
                                         double* Me, double* Ke, double* Mval, double* Kval,
                                         void* stream);
+
+/* Allocate the plan's slab workspace of igaf_integrate_assemble_geo's
+ * CSR-only path now (synchronous; a no-op when it exists or when the mesh's
+ * element layers exceed its 2 GiB cap, which take the atomic path), so that
+ * later calls allocate nothing and may be captured.  IGAF_ENOMEM if the
+ * allocation fails. */
+igaf_status igaf_geo_prepare(igaf_plan* plan);
 
 /* Adjoint of L(kappa) = alphaM u^T M(kappa) v + alphaK u^T K(kappa) v with
  * respect to kappa at every quadrature point (L is linear in kappa through

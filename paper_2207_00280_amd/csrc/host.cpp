@@ -597,6 +597,35 @@ igaf_status igaf_plan_timing(igaf_plan* plan, int32_t kernel, double* avg_ms, in
 // values with atomics.
 static constexpr int64_t kGeoWorkspaceBytes = int64_t(2) << 30;
 
+// Element layers of the slab workspace that fit its cap (at most K_z), or 0
+// if fewer than the p+1 layers a slab needs (those meshes use atomics).
+static int geo_layers_for(const igaf_plan* P)
+{
+    const int64_t n6 = (int64_t)P->n * P->n * P->n * P->n * P->n * P->n;
+    const int64_t layer = (int64_t)P->K[0] * P->K[1];
+    int64_t layers = kGeoWorkspaceBytes / (layer * 2 * n6 * (int64_t)sizeof(double));
+    layers = std::min<int64_t>(layers, P->K[2]);
+    return layers < std::min(P->K[2], P->p + 1) ? 0 : (int)layers;
+}
+
+// Allocate the slab workspace (0, or -2 if the allocation failed).
+static int geo_alloc(igaf_plan* P, int layers)
+{
+    const int64_t n6 = (int64_t)P->n * P->n * P->n * P->n * P->n * P->n;
+    const int64_t layer = (int64_t)P->K[0] * P->K[1];
+    if (hipMalloc(&P->geo_ws, sizeof(double) * 2 * n6 * layer * layers) != hipSuccess) {
+        P->geo_ws = nullptr;
+        (void)hipGetLastError();
+        return -2;
+    }
+    P->geo_ws_layers = layers;
+    return 0;
+}
+
+// CSR values without stored element matrices, slab by slab of element
+// layers: 0 done, 1 use atomics (the layers exceed the workspace cap, or its
+// allocation failed), 2 refused (no workspace yet and the stream is being
+// captured: an allocation cannot be captured), -3 launch failure.
 static int geo_csr_slabs(igaf_plan* P, const double* cm, const double* G, double* Mval, double* Kval,
                          hipStream_t s)
 {
@@ -604,17 +633,11 @@ static int geo_csr_slabs(igaf_plan* P, const double* cm, const double* G, double
     const int64_t n6 = (int64_t)P->n * P->n * P->n * P->n * P->n * P->n;
     const int64_t layer = (int64_t)P->K[0] * P->K[1];   // elements per z layer
     if (!P->geo_ws) {
+        const int layers = geo_layers_for(P);
+        if (!layers) return 1;
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 1;
-        int64_t layers = kGeoWorkspaceBytes / (layer * 2 * n6 * (int64_t)sizeof(double));
-        layers = std::min<int64_t>(layers, P->K[2]);
-        if (layers < std::min(P->K[2], p + 1)) return 1;
-        if (hipMalloc(&P->geo_ws, sizeof(double) * 2 * n6 * layer * layers) != hipSuccess) {
-            P->geo_ws = nullptr;
-            (void)hipGetLastError();
-            return 1;
-        }
-        P->geo_ws_layers = (int)layers;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 2;
+        if (geo_alloc(P, layers)) return 1;
     }
     const int L = P->geo_ws_layers;
     const int T = L >= P->K[2] ? P->N[2] : L - p;   // row layers per slab
@@ -665,6 +688,9 @@ igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm,
     const int rc = geo_csr_slabs(P, cm, G, sm, sk, s);
     if (rc < 0) return launched(rc, "mapped-geometry slab assembly");
     if (rc == 0) return IGAF_OK;
+    if (rc == 2)
+        return fail(IGAF_EINVAL, "CSR-only values on a mapped geometry under stream capture need the slab "
+                                 "workspace: call igaf_geo_prepare (or the same call eagerly) first");
     st = launched(launch_fill_zero(sm, sm ? plan->nnz : 0, s), "zero");
     if (!st) st = launched(launch_fill_zero(sk, sk ? plan->nnz : 0, s), "zero");
     if (!st)
@@ -672,6 +698,17 @@ igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm,
                                          sk, s),
                       "mapped-geometry integration + atomic assembly");
     return st;
+}
+
+igaf_status igaf_geo_prepare(igaf_plan* plan)
+{
+    igaf_status st = check_hot(plan, IGAF_SUMFACT);
+    if (st) return st;
+    if (plan->geo_ws) return IGAF_OK;
+    const int layers = geo_layers_for(plan);
+    if (!layers) return IGAF_OK;   // these meshes use atomics, which need no workspace
+    if (geo_alloc(plan, layers)) return fail(IGAF_ENOMEM, "mapped-geometry slab workspace: allocation failed");
+    return IGAF_OK;
 }
 
 igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double* v,

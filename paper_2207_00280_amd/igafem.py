@@ -23,7 +23,7 @@ SYMBOLS = [
     "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_csr_pattern_host",
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes", "igaf_quad_points",
     "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
-    "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_kappa_grad", "igaf_bilinear_form",
+    "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_geo_prepare", "igaf_kappa_grad", "igaf_bilinear_form",
     "igaf_apply_workspace",
     "igaf_apply", "igaf_apply_static",
     "igaf_apply_geo", "igaf_kappa_grad_geo", "igaf_euler_step_geo", "igaf_euler_workspace", "igaf_euler_step",
@@ -88,6 +88,7 @@ def lib():
     L.igaf_apply.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]
     L.igaf_apply_static.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp]
     L.igaf_integrate_assemble_geo.argtypes = [_vp] * 8
+    L.igaf_geo_prepare.argtypes = [_vp]
     L.igaf_apply_geo.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _vp]
     L.igaf_kappa_grad_geo.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, _vp, _vp]
@@ -388,6 +389,11 @@ class Plan:
         if work.numel() < nw:
             raise ValueError("work has %d elements, needs %d" % (work.numel(), nw))
         return work
+
+    def geo_prepare(self):
+        """Allocate the slab workspace of the mapped-geometry CSR-only path now
+        (igaf_geo_prepare), so that later calls can be captured."""
+        _check(lib().igaf_geo_prepare(self._h))
 
     def apply(self, kappa, u, alphaM=1.0, alphaK=1.0, y=None, work=None, stream=None):
         """y = alphaM M(kappa) u + alphaK K(kappa) u, matrix-free (igaf_apply)."""

@@ -170,9 +170,11 @@ def test_geometry_fullscale(orc, ig):
 
 
 def test_geometry_csr_under_capture(ig):
-    """A CSR-only call captured in a HIP graph before the plan has its slab
-    workspace adds the values with FP64 atomics instead: replays (with eager
-    work between them) match the eager slab path within rounding."""
+    """A CSR-only call under HIP graph capture before the plan has its slab
+    workspace is refused before any launch (an allocation cannot be
+    captured); after igaf_geo_prepare it captures the deterministic slab
+    path: every replay (eager work between them) equals the eager result of
+    another plan bit for bit."""
     import torch
 
     p, K = 2, (6, 5, 7)
@@ -184,18 +186,25 @@ def test_geometry_csr_under_capture(ig):
     Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
     Kv = torch.empty_like(Mv)
     s = torch.cuda.Stream()
+    g0 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g0, stream=s):
+        with pytest.raises(ig.IgafError) as ei:
+            plan.integrate_assemble_geo(cmd, Gd, want_elem=False, Mval=Mv, Kval=Kv, stream=s)
+        _ = torch.zeros(1, device="cuda")
+    assert ei.value.status == ig.EINVAL and "igaf_geo_prepare" in str(ei.value)
+    plan.geo_prepare()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         plan.integrate_assemble_geo(cmd, Gd, want_elem=False, Mval=Mv, Kval=Kv, stream=s)
     plan2 = ig.Plan(p, K, knots)
     _, _, Mr, Kr = plan2.integrate_assemble_geo(cmd, Gd, want_elem=False)
-    for r in range(2):
+    for r in range(3):
         Mv.fill_(np.nan)
         Kv.fill_(np.nan)
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        assert relfro(to_host(Mv), to_host(Mr)) <= TOL and relfro(to_host(Kv), to_host(Kr)) <= TOL, r
+        assert torch.equal(Mv, Mr) and torch.equal(Kv, Kr), r
         _ = torch.ones(1000, device="cuda").sum().item()
 
 
