@@ -432,7 +432,7 @@ def bench_w6(ig, torch, stream, steps):
            "csr_only_ms": ms_csr,
            "apply_ms": ms_ap, "adjoint_ms": ms_ad}
     log("W6 mapped geometry: element matrices %.3f ms (%.0f%% of HBM roofline), + CSR gathered %.3f ms, "
-        "CSR alone (slabs) %.3f ms, apply %.3f ms, adjoint %.3f ms"
+        "CSR alone %.3f ms, apply %.3f ms, adjoint %.3f ms"
         % (ms_el, 100 * out["element_matrices"]["frac"], ms_all, ms_csr, ms_ap, ms_ad))
     del cmd, Gd, plan
     torch.cuda.empty_cache()

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libigafem.so")
-SOURCES = ["host.cpp", "batch.cpp", "tables.hip", "element.hip", "rows_tile.hip", "adjoint.hip", "apply.hip", "euler.hip", "geometry.hip", "assemble.hip", "wq.hip"]
+SOURCES = ["host.cpp", "batch.cpp", "tables.hip", "element.hip", "rows_tile.hip", "rows_geo.hip", "adjoint.hip", "apply.hip", "euler.hip", "geometry.hip", "assemble.hip", "wq.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -5,6 +5,8 @@
 //   Wdd[e][s][k] = w_k (h_e/2) N'_a(x_k) N'_b(x_k)
 //   Nv[e][a][k]  = N_{e+a}(x_k),  dN[e][a][k] = N'_{e+a}(x_k)
 //   wq[e][k]     = w_k h_e/2
+//   Wg[e][c][a][k] = w N_a, w N'_a, N_a, N'_a (c = 0..3): the ordered-pair
+//                  factors of a mapped geometry, test side weighted
 //   Lm[i][.]     = banded Cholesky factor and diagonal of the 1D mass matrix
 //   pre[i]       = sum_{i' < i} L(i'),  L(i) = min(N-1, i+p) - max(0, i-p) + 1
 // with x_k the Gauss nodes mapped to element e.  Pair products depend only on
@@ -29,6 +31,7 @@ struct DirTables {
     const double* Nv;
     const double* dN;
     const double* wq;
+    const double* Wg;     // [K][4][p+1][Q]
     const double* Lm;     // [N][p+2]: 1/L_ii, L_{i,i-1..i-p}, M_ii of the 1D mass (kappa = 1)
     const int64_t* pre;   // [N+1]
     int K, N, Q;

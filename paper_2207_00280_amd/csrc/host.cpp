@@ -303,15 +303,15 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
     }
     sizes_of(desc, &P->ndof, &P->E, &P->nqp, nullptr, &P->nnz);
 
-    // device layout: per direction [knots | xi | wr | Wnn | Wdd | Nv | dN | wq | Lm]
+    // device layout: per direction [knots | xi | wr | Wnn | Wdd | Nv | dN | wq | Lm | Wg]
     int64_t dcount = 0, icount = 0;
-    int64_t off[3][9];
+    int64_t off[3][10];
     for (int a = 0; a < 3; ++a) {
         int K = P->K[a], Q = P->q[a], nk = K + 2 * P->p + 1;
-        int64_t sz[9] = {nk, Q, Q, (int64_t)K * P->S * Q, (int64_t)K * P->S * Q,
-                         (int64_t)K * P->n * Q, (int64_t)K * P->n * Q, (int64_t)K * Q,
-                         (int64_t)P->N[a] * (P->p + 2)};
-        for (int j = 0; j < 9; ++j) {
+        int64_t sz[10] = {nk, Q, Q, (int64_t)K * P->S * Q, (int64_t)K * P->S * Q,
+                          (int64_t)K * P->n * Q, (int64_t)K * P->n * Q, (int64_t)K * Q,
+                          (int64_t)P->N[a] * (P->p + 2), (int64_t)K * 4 * P->n * Q};
+        for (int j = 0; j < 10; ++j) {
             off[a][j] = dcount;
             dcount += (sz[j] + 31) & ~int64_t(31);   // 256-byte aligned pieces
         }
@@ -388,6 +388,7 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
         D.dN = base + off[a][6];
         D.wq = base + off[a][7];
         D.Lm = base + off[a][8];
+        D.Wg = base + off[a][9];
         D.pre = P->dpre + ioff;
         D.K = K;
         D.N = N;
@@ -395,7 +396,7 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
         ioff += N + 1;
         if (launch_basis_tables(P->p, base + off[a][0], K, base + off[a][1], base + off[a][2], Q,
                                 base + off[a][3], base + off[a][4], base + off[a][5],
-                                base + off[a][6], base + off[a][7], nullptr) != 0)
+                                base + off[a][6], base + off[a][7], base + off[a][9], nullptr) != 0)
             rc = fail(IGAF_EDEVICE, "basis-table launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
     if (rc == IGAF_OK && hipStreamSynchronize(nullptr) != hipSuccess)
@@ -587,8 +588,12 @@ igaf_status igaf_plan_timing(igaf_plan* plan, int32_t kernel, double* avg_ms, in
     return IGAF_OK;
 }
 
+// Degrees whose mapped-geometry CSR values have an owner-computed rows
+// kernel (its stage-z buffers of nine products fit the LDS of a CU up to p = 4).
+static bool geo_rows_supported(const igaf_plan* P) { return P->p <= 4; }
+
 // Mapped-geometry CSR values whose element matrices the caller does not
-// store: slab by slab of z row layers, the element matrices of the element
+// store, for the other degrees: slab by slab of z row layers, the element matrices of the element
 // layers those rows touch go to the plan's workspace (at most
 // kGeoWorkspaceBytes, allocated at the first call), and the rows are
 // gathered from it; the p element layers shared by neighbouring slabs are
@@ -680,11 +685,12 @@ igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm,
             st = launched(launch_gather(plan->dev, gm ? Me : nullptr, gk ? Ke : nullptr, gm, gk, s), "assemble");
         if (st) return st;
     }
-    // the CSR values without stored element matrices: slabs through the
-    // plan's workspace, else FP64 atomics
+    // the CSR values without stored element matrices: owner-computed rows
+    // (p <= 4), else slabs through the plan's workspace, else FP64 atomics
     double* sm = Mval && !Me ? Mval : nullptr;
     double* sk = Kval && !Ke ? Kval : nullptr;
     if (!sm && !sk) return IGAF_OK;
+    if (geo_rows_supported(plan)) return launched(launch_rows_geo(plan->dev, cm, G, sm, sk, s), "mapped-geometry rows");
     const int rc = geo_csr_slabs(P, cm, G, sm, sk, s);
     if (rc < 0) return launched(rc, "mapped-geometry slab assembly");
     if (rc == 0) return IGAF_OK;
@@ -704,7 +710,7 @@ igaf_status igaf_geo_prepare(igaf_plan* plan)
 {
     igaf_status st = check_hot(plan, IGAF_SUMFACT);
     if (st) return st;
-    if (plan->geo_ws) return IGAF_OK;
+    if (plan->geo_ws || geo_rows_supported(plan)) return IGAF_OK;   // the rows kernel needs no workspace
     const int layers = geo_layers_for(plan);
     if (!layers) return IGAF_OK;   // these meshes use atomics, which need no workspace
     if (geo_alloc(plan, layers)) return fail(IGAF_ENOMEM, "mapped-geometry slab workspace: allocation failed");

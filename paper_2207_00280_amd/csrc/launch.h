@@ -12,7 +12,7 @@
 namespace igaf {
 
 int launch_basis_tables(int p, const double* t, int K, const double* xi, const double* wr, int Q,
-                        double* Wnn, double* Wdd, double* Nv, double* dN, double* wq,
+                        double* Wnn, double* Wdd, double* Nv, double* dN, double* wq, double* Wg,
                         hipStream_t st);
 
 int launch_csr_pattern(const PatchDev& pd, int64_t* row_ptr, int32_t* col, hipStream_t st);
@@ -28,6 +28,12 @@ int launch_element(const PatchDev& pd, int method, const double* kappa, double* 
 // row pencils: overwrites Mval / Kval.
 int launch_rows(const PatchDev& pd, const double* kappa, double* Mval, double* Kval,
                 hipStream_t st);
+
+// The same on a mapped geometry (point fields cm [E][q^3], G [E][6][q^3]; a
+// NULL output needs no field): overwrites Mval / Kval.  -4 for degrees whose
+// tile does not fit the LDS of a CU (p = 5).
+int launch_rows_geo(const PatchDev& pd, const double* cm, const double* G, double* Mval, double* Kval,
+                    hipStream_t st);
 
 // Batched CSR rows of the degree-p patches: one workgroup per (patch, tile,
 // x segment, segment length) item of `items` (all of degree p), which the

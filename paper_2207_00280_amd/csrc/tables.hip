@@ -21,7 +21,7 @@ template <int P>
 __global__ void k_basis_tables(const double* __restrict__ t, int K, const double* __restrict__ xi,
                                const double* __restrict__ wr, int Q, double* __restrict__ Wnn,
                                double* __restrict__ Wdd, double* __restrict__ Nv,
-                               double* __restrict__ dN, double* __restrict__ wq)
+                               double* __restrict__ dN, double* __restrict__ wq, double* __restrict__ Wg)
 {
     constexpr int n = P + 1;
     constexpr int S = n * (n + 1) / 2;
@@ -39,6 +39,7 @@ __global__ void k_basis_tables(const double* __restrict__ t, int K, const double
             dN[((int64_t)e * n + a) * Q + k] = 0.0;
         }
         wq[(int64_t)e * Q + k] = 0.0;
+        for (int i = 0; i < 4 * n; ++i) Wg[((int64_t)e * 4 * n + i) * Q + k] = 0.0;
         for (int sp = 0; sp < S; ++sp) {
             Wnn[((int64_t)e * S + sp) * Q + k] = 0.0;
             Wdd[((int64_t)e * S + sp) * Q + k] = 0.0;
@@ -73,6 +74,12 @@ __global__ void k_basis_tables(const double* __restrict__ t, int K, const double
         dN[((int64_t)e * n + a) * Q + k] = D[a];
     }
     wq[(int64_t)e * Q + k] = w;
+    for (int a = 0; a <= P; ++a) {
+        Wg[(((int64_t)e * 4 + 0) * n + a) * Q + k] = w * N[a];
+        Wg[(((int64_t)e * 4 + 1) * n + a) * Q + k] = w * D[a];
+        Wg[(((int64_t)e * 4 + 2) * n + a) * Q + k] = N[a];
+        Wg[(((int64_t)e * 4 + 3) * n + a) * Q + k] = D[a];
+    }
     for (int b = 0; b <= P; ++b)
         for (int a = 0; a <= b; ++a) {
             int sp = pair_index(a, b);
@@ -82,7 +89,7 @@ __global__ void k_basis_tables(const double* __restrict__ t, int K, const double
 }
 
 int launch_basis_tables(int p, const double* t, int K, const double* xi, const double* wr, int Q,
-                        double* Wnn, double* Wdd, double* Nv, double* dN, double* wq,
+                        double* Wnn, double* Wdd, double* Nv, double* dN, double* wq, double* Wg,
                         hipStream_t st)
 {
     int threads = 64;
@@ -91,7 +98,7 @@ int launch_basis_tables(int p, const double* t, int K, const double* xi, const d
 #define IGAF_CASE(PP)                                                                        \
     case PP:                                                                                 \
         hipLaunchKernelGGL(k_basis_tables<PP>, dim3(blocks), dim3(threads), 0, st, t, K, xi, \
-                           wr, Q, Wnn, Wdd, Nv, dN, wq);                                     \
+                           wr, Q, Wnn, Wdd, Nv, dN, wq, Wg);                                 \
         break;
         IGAF_CASE(1)
         IGAF_CASE(2)

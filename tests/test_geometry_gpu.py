@@ -4,10 +4,11 @@ On x = F(xi) the per-point factor of eq. (10) becomes cm = kappa det J for the
 mass and the tensor G = kappa det J J^-1 J^-T for the stiffness; the caller's
 side (workloads.mapped_geometry) evaluates them at the points.  The HIP path
 (sum factorisation with ordered per-direction pairs; CSR values gathered from
-the stored element matrices, or added with FP64 atomics when none are stored)
-is compared with the oracle's classical quadrature of the same integrands,
-which the CPU suite pins by scaled knots, exact affine Kronecker forms and
-linear patch tests.
+the stored element matrices, or, when none are stored, computed by
+owner-computed rows for p <= 4 and gathered slab by slab for p = 5) is
+compared with the oracle's classical quadrature of the same integrands, which
+the CPU suite pins by scaled knots, exact affine Kronecker forms and linear
+patch tests.
 """
 import math
 
@@ -15,7 +16,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.gpu_util import csr_close, nonuniform_knots, relfro, to_dev, to_host
+from tests.gpu_util import csr_close, nonuniform_knots, relfro, rowmax_rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -82,11 +83,47 @@ def test_geometry_vs_oracle(orc, ig, p, K, kind, geo):
     # with the element matrices stored the CSR values are gathered: bitwise repeatable
     _, _, Mv_b, Kv_b = plan.integrate_assemble_geo(cmd, Gd)
     assert np.array_equal(to_host(Mv_b), to_host(Mv)) and np.array_equal(to_host(Kv_b), to_host(Kv))
-    # one matrix at a time; element matrices only; CSR only (atomics)
+    # one matrix at a time; element matrices only; CSR only (rows kernel, or
+    # slabs at p = 5): both, each alone, repeated bit for bit
     Me2, Ke2, _, _ = plan.integrate_assemble_geo(cmd, None, want_k=False, want_csr=False)
     assert Ke2 is None and relfro(to_host(Me2), Me_o) <= TOL
     _, _, Mv3, Kv3 = plan.integrate_assemble_geo(None, Gd, want_m=False, want_elem=False)
     assert Mv3 is None and csr_close(to_host(Kv3), Kv_o, rp_o, TOL)
+    _, _, Mv4, _ = plan.integrate_assemble_geo(cmd, None, want_k=False, want_elem=False)
+    assert csr_close(to_host(Mv4), Mv_o, rp_o, TOL)
+    _, _, Mv5, Kv5 = plan.integrate_assemble_geo(cmd, Gd, want_elem=False)
+    assert csr_close(to_host(Mv5), Mv_o, rp_o, TOL) and csr_close(to_host(Kv5), Kv_o, rp_o, TOL)
+    _, _, Mv6, Kv6 = plan.integrate_assemble_geo(cmd, Gd, want_elem=False)
+    assert np.array_equal(to_host(Mv6), to_host(Mv5)) and np.array_equal(to_host(Kv6), to_host(Kv5))
+    assert np.array_equal(to_host(Kv3), to_host(Kv5)) and np.array_equal(to_host(Mv4), to_host(Mv5))
+
+
+ROWS_CASES = [
+    # several tiles in y and z, several x segments, ragged tile edges
+    (1, (37, 9, 6), "nonuniform", dict(amp=0.1)),
+    (2, (29, 7, 5), "nonuniform", dict(A=A_SHEAR, amp=0.05)),
+    (3, (26, 5, 5), "nonuniform", dict(A=A_SHEAR, amp=0.1)),
+    (3, (21, 1, 2), "uniform", dict(amp=0.1)),
+    (4, (20, 3, 2), "nonuniform", dict(amp=0.08)),
+]
+
+
+@pytest.mark.parametrize("p,K,kind,geo", ROWS_CASES)
+def test_geometry_rows_kernel_vs_oracle(orc, ig, p, K, kind, geo):
+    """The owner-computed CSR rows of a mapped geometry on meshes that span
+    several tiles and x segments: every CSR value of M and K vs the oracle
+    (global and per-row relative error), repeated calls bit for bit."""
+    knots, K = _knots(p, K, kind, 310 + p)
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    plan = ig.Plan(p, K, knots)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=320 + p)
+    cm, G = _coeffs(orc, P, kap, **geo)
+    rp_o, col_o, Mv_o, Kv_o = orc.assemble(P, cm, G=G)
+    cmd, Gd = to_dev(cm), to_dev(G)
+    _, _, Mv, Kv = plan.integrate_assemble_geo(cmd, Gd, want_elem=False)
+    assert csr_close(to_host(Mv), Mv_o, rp_o, TOL) and csr_close(to_host(Kv), Kv_o, rp_o, TOL)
+    _, _, Mv2, Kv2 = plan.integrate_assemble_geo(cmd, Gd, want_elem=False)
+    assert np.array_equal(to_host(Mv2), to_host(Mv)) and np.array_equal(to_host(Kv2), to_host(Kv))
 
 
 def test_identity_geometry_matches_plain_path(ig):
@@ -134,20 +171,22 @@ def test_geometry_fullscale(orc, ig):
         assert relfro(Me_s[i], mo[0]) <= TOL and relfro(Ke_s[i], ko[0]) <= TOL, e
     del Me, Ke
     torch.cuda.empty_cache()
-    # CSR alone: slabs of element layers through the plan's workspace (several
-    # slabs at this size), the same gather: the same bits
+    # CSR alone: the owner-computed rows kernel; the same values as the
+    # gather from the element matrices to rounding, row by row
     _, _, Mv2, Kv2 = plan.integrate_assemble_geo(cmd, Gd, want_elem=False)
-    assert torch.equal(Mv2, Mv) and torch.equal(Kv2, Kv)
-    del Mv2, Kv2
     rp = to_host(plan.csr_pattern()[0])
-    Mv_h, Kv_h = to_host(Mv), to_host(Kv)
+    Mv_h, Kv_h, Mv2_h, Kv2_h = to_host(Mv), to_host(Kv), to_host(Mv2), to_host(Kv2)
+    del Mv2, Kv2
+    assert rowmax_rel(Mv2_h, Mv_h, rp) <= TOL and rowmax_rel(Kv2_h, Kv_h, rp) <= TOL
     N = P.N
     corners = [0, N[0] - 1, plan.ndof - 1, plan.ndof - N[0]]
     dofs = np.concatenate([corners, rng.choice(plan.ndof, 28, replace=False)])
     for d, (c, m, k) in zip(dofs, orc.rows(P, cm, dofs, G=G)):
         seg = slice(rp[d], rp[d + 1])
-        assert np.abs(Mv_h[seg] - m).max() <= TOL * np.abs(m).sum()
-        assert np.abs(Kv_h[seg] - k).max() <= TOL * np.abs(k).sum()
+        for mv, kv in ((Mv_h, Kv_h), (Mv2_h, Kv2_h)):
+            assert np.abs(mv[seg] - m).max() <= TOL * np.abs(m).sum()
+            assert np.abs(kv[seg] - k).max() <= TOL * np.abs(k).sum()
+    del Mv2_h, Kv2_h
     # parametric linear functions through the assembled stiffness
     import scipy.sparse as sp
 
@@ -169,15 +208,16 @@ def test_geometry_fullscale(orc, ig):
     assert np.max(np.abs(k1)) <= 64 * np.finfo(float).eps * np.max(rowabs)
 
 
-def test_geometry_csr_under_capture(ig):
-    """A CSR-only call under HIP graph capture before the plan has its slab
-    workspace is refused before any launch (an allocation cannot be
-    captured); after igaf_geo_prepare it captures the deterministic slab
-    path: every replay (eager work between them) equals the eager result of
-    another plan bit for bit."""
+@pytest.mark.parametrize("p,K", [(2, (6, 5, 7)), (5, (3, 2, 4))])
+def test_geometry_csr_under_capture(ig, p, K):
+    """A CSR-only call under HIP graph capture: for p <= 4 the rows kernel
+    needs no workspace and captures at once; for p = 5 it is refused before
+    any launch until the plan has its slab workspace (an allocation cannot be
+    captured), and after igaf_geo_prepare the slab path captures.  Every
+    replay (eager work between them) equals the eager result of another plan
+    bit for bit."""
     import torch
 
-    p, K = 2, (6, 5, 7)
     knots = [nonuniform_knots(k, p, 230 + d) for d, k in enumerate(K)]
     plan = ig.Plan(p, K, knots)
     xs = [plan.quad_nodes(d)[0] for d in range(3)]
@@ -186,12 +226,13 @@ def test_geometry_csr_under_capture(ig):
     Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
     Kv = torch.empty_like(Mv)
     s = torch.cuda.Stream()
-    g0 = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g0, stream=s):
-        with pytest.raises(ig.IgafError) as ei:
-            plan.integrate_assemble_geo(cmd, Gd, want_elem=False, Mval=Mv, Kval=Kv, stream=s)
-        _ = torch.zeros(1, device="cuda")
-    assert ei.value.status == ig.EINVAL and "igaf_geo_prepare" in str(ei.value)
+    if p == 5:
+        g0 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g0, stream=s):
+            with pytest.raises(ig.IgafError) as ei:
+                plan.integrate_assemble_geo(cmd, Gd, want_elem=False, Mval=Mv, Kval=Kv, stream=s)
+            _ = torch.zeros(1, device="cuda")
+        assert ei.value.status == ig.EINVAL and "igaf_geo_prepare" in str(ei.value)
     plan.geo_prepare()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
