@@ -389,8 +389,8 @@ def bench_w6(ig, torch, stream, steps):
     """W6: the headline mesh on a curved map (mapped_geometry, amp 0.1): the
     element matrices from a per-point mass coefficient and stiffness tensor
     (7 q^3 doubles in, 2 n^6 out per element; HBM-bound), then with the CSR
-    values gathered from them, the CSR values alone (element-layer slabs
-    through the plan's workspace, gathered), and the
+    values gathered from them, the CSR values alone (owner-computed rows,
+    no element matrices), and the
     matrix-free apply and adjoint on the same geometry."""
     cfg = W.W6
     p, K = cfg["p"], cfg["K"]
@@ -489,7 +489,7 @@ def run_kernel_mode(name, ig, torch, steps):
     copy (1 GiB device copy, the counter calibration), element, csr,
     classical, headline (W2), w3p<p> (W3 streamed CSR at degree p), w4 (the
     batched launches of W4), adjoint, apply, apply_mass (W5), geo (W6
-    element matrices)."""
+    element matrices), geo_csr (W6 CSR values alone, owner-computed rows)."""
     if name == "copy":
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
         b = torch.empty_like(a)
@@ -526,17 +526,23 @@ def run_kernel_mode(name, ig, torch, steps):
                 plan.kappa_grad(u, v, grad=g)
             else:
                 plan.apply(kap, u, 1.0, 0.0 if name == "apply_mass" else 1.0, y=y, work=wk)
-    elif name == "geo":
+    elif name in ("geo", "geo_csr"):
         cfg = W.W6
         p, K = cfg["p"], cfg["K"]
         plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
         xs = [plan.quad_nodes(d)[0] for d in range(3)]
         cm, G = W.mapped_geometry(xs[0], xs[1], xs[2], W.kappa_sine(*xs), amp=cfg["amp"])
         cmd, Gd = torch.from_numpy(cm).cuda(), torch.from_numpy(G).cuda()
-        Me = torch.empty(plan.nelem, plan.elem_dim, plan.elem_dim, dtype=torch.float64, device="cuda")
-        Ke = torch.empty_like(Me)
-        for _ in range(steps):
-            plan.integrate_assemble_geo(cmd, Gd, Me=Me, Ke=Ke, want_csr=False)
+        if name == "geo_csr":
+            Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+            Kv = torch.empty_like(Mv)
+            for _ in range(steps):
+                plan.integrate_assemble_geo(cmd, Gd, want_elem=False, Mval=Mv, Kval=Kv)
+        else:
+            Me = torch.empty(plan.nelem, plan.elem_dim, plan.elem_dim, dtype=torch.float64, device="cuda")
+            Ke = torch.empty_like(Me)
+            for _ in range(steps):
+                plan.integrate_assemble_geo(cmd, Gd, Me=Me, Ke=Ke, want_csr=False)
     else:
         h = Headline(ig, torch)
         fn = {"element": h.element, "csr": h.csr, "headline": h.step,

@@ -62,6 +62,7 @@ struct GeoTile {
     static constexpr int NYI = TZ * O * Q, WYP = (NYI + 63) / 64; // stage y items per (y row, group)
     static constexpr int NYU = TY * 3 * WYP;                      // stage y units
     static constexpr int NWZY = NZW_;                        // z/y wavefronts
+    static constexpr bool ZPF = NZU <= NWZY;                 // one z unit per wavefront: prefetch
     static constexpr int NXI = NPEN * O * O, WXG = (NXI + 63) / 64;   // stage x: per slot group
     static constexpr int WX = G * WXG;
     static constexpr int NSL = (P + 1 + G - 1) / G;          // row slots per x thread
@@ -90,8 +91,8 @@ struct GeoTile {
 template <int P> struct GeoCfg;
 template <> struct GeoCfg<1> { using T = GeoTile<1, 4, 4, 6, 1, 2>; };
 template <> struct GeoCfg<2> { using T = GeoTile<2, 2, 2, 6, 1, 2>; };
-template <> struct GeoCfg<3> { using T = GeoTile<3, 1, 2, 6, 2, 2>; };
-template <> struct GeoCfg<4> { using T = GeoTile<4, 1, 1, 6, 3, 2>; };
+template <> struct GeoCfg<3> { using T = GeoTile<3, 1, 2, 6, 1, 2>; };
+template <> struct GeoCfg<4> { using T = GeoTile<4, 1, 1, 6, 1, 2>; };
 
 struct GeoCtx {
     TileCtx c;
@@ -108,22 +109,47 @@ template <> struct ZPass<0> { static constexpr int f[3] = {0, 1, 2}, tk[3] = {0,
 template <> struct ZPass<1> { static constexpr int f[3] = {3, 4, 5}, tk[3] = {1, 0, 0}, rk[3] = {3, 2, 3}; };
 template <> struct ZPass<2> { static constexpr int f[3] = {5, 6, 6}, tk[3] = {1, 0, 1}, rk[3] = {2, 3, 2}; };
 
-// ---- stage z, pass PASS of z row zr for element ex: thread on point item (ly, ky, kx)
+// ---- stage z, pass PASS of z row zr: thread on point item (ly, ky, kx).
+// gz_load fetches the pass's three fields of element ex for the p+1 z
+// elements of the row (z elements outside the patch are read at a clamped
+// index and never used; a field the call does not need is read from the
+// other one and its products are never stored); gz_unit contracts them.
 template <class T, int PASS>
-__device__ __forceinline__ void gz_unit(const GeoCtx& g, int zr, int item, int ex, double* D)
+__device__ __forceinline__ void gz_load(const GeoCtx& g, int zr, int item, int ex,
+                                        double (&pf)[3][T::P + 1][T::Q])
 {
-    constexpr int P = T::P, Q = T::Q, O = T::O, Q2 = T::Q2, Q3 = T::Q3;
+    constexpr int P = T::P, Q = T::Q, Q2 = T::Q2, Q3 = T::Q3;
     using PS = ZPass<PASS>;
     const TileCtx& c = g.c;
-    const bool act = item < T::NZI;
-    const int it = act ? item : T::NZI - 1;
+    const int it = item < T::NZI ? item : T::NZI - 1;
     const int ly = it / Q2, pq = it % Q2;   // pq = ky Q + kx
     const int ey = clampi_t(c.iy0 - P + ly, c.Ky - 1);   // y elements outside are never read
     const int iz = c.iz0 + zr;
-    const double* src[3];
+    const int64_t exy = (int64_t)ex + (int64_t)c.Kx * ey;   // element index without its z part
+    const int64_t layer = (int64_t)c.Kx * c.Ky;
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-        src[j] = PS::f[j] == 0 ? g.cm : (g.G ? g.G + (PS::f[j] - 1) * Q3 : nullptr);
+    for (int j = 0; j < 3; ++j) {
+        const bool gf = PS::f[j] > 0 && g.G;                      // a G component, present
+        const double* src = PS::f[j] == 0 ? (g.cm ? g.cm : g.G) : (g.G ? g.G + (PS::f[j] - 1) * Q3 : g.cm);
+        const int64_t es = gf ? 6 * Q3 : Q3;
+#pragma unroll
+        for (int e = 0; e <= P; ++e) {
+            const int ezc = clampi_t(iz - P + e, c.Kz - 1);
+            const double* sp = src + (exy + layer * ezc) * es + pq;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) pf[j][e][k] = sp[Q2 * k];
+        }
+    }
+}
+
+template <class T, int PASS>
+__device__ __forceinline__ void gz_unit(const GeoCtx& g, int zr, int item, const double (&pf)[3][T::P + 1][T::Q],
+                                        double* D)
+{
+    constexpr int P = T::P, Q = T::Q, O = T::O, Q2 = T::Q2;
+    using PS = ZPass<PASS>;
+    const TileCtx& c = g.c;
+    const int iz = c.iz0 + zr;
     double acc[3][O];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
@@ -133,18 +159,12 @@ __device__ __forceinline__ void gz_unit(const GeoCtx& g, int zr, int item, int e
     for (int e = 0; e <= P; ++e) {
         const int ez = iz - P + e;
         if (ez < 0 || ez >= c.Kz) continue;   // wave-uniform
-        const int64_t el = (int64_t)ex + (int64_t)c.Kx * (ey + (int64_t)c.Ky * ez);
         const ctab tb = g.Wz + (int64_t)ez * T::TBE;   // test index P - e, trial bb
         double gv[3][Q];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int64_t es = PS::f[j] == 0 ? Q3 : 6 * Q3;
+        for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                const double v = src[j] ? src[j][el * es + pq + Q2 * k] : 0.0;
-                gv[j][k] = v * tb[PS::tk[j] * Q2 + (P - e) * Q + k];
-            }
-        }
+            for (int k = 0; k < Q; ++k) gv[j][k] = pf[j][e][k] * tb[PS::tk[j] * Q2 + (P - e) * Q + k];
 #pragma unroll
         for (int bb = 0; bb <= P; ++bb)
 #pragma unroll
@@ -152,13 +172,34 @@ __device__ __forceinline__ void gz_unit(const GeoCtx& g, int zr, int item, int e
 #pragma unroll
                 for (int k = 0; k < Q; ++k) acc[j][e + bb] += tb[PS::rk[j] * Q2 + bb * Q + k] * gv[j][k];
     }
-    if (act) {
+    if (item < T::NZI) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            double* dp = D + zr * T::DZR + (3 * PASS + j) * T::DD + it;
+            double* dp = D + zr * T::DZR + (3 * PASS + j) * T::DD + item;
 #pragma unroll
             for (int o = 0; o < O; ++o) dp[o * T::DOZ] = acc[j][o];
         }
+    }
+}
+
+// one stage-z unit u (several per wavefront when the units outnumber the
+// z/y wavefronts): load and contract at once
+template <class T>
+__device__ __forceinline__ void gz_unit_direct(const GeoCtx& g, int u, int lane, int ex, double* D)
+{
+    const int zr = u / (3 * T::WZP), pass = (u / T::WZP) % 3;
+    const int item = (u % T::WZP) * 64 + lane;
+    if (g.c.iz0 + zr >= g.c.Nz) return;   // rows outside: D never read
+    double pf[3][T::P + 1][T::Q];
+    if (pass == 0) {
+        gz_load<T, 0>(g, zr, item, ex, pf);
+        gz_unit<T, 0>(g, zr, item, pf, D);
+    } else if (pass == 1) {
+        gz_load<T, 1>(g, zr, item, ex, pf);
+        gz_unit<T, 1>(g, zr, item, pf, D);
+    } else {
+        gz_load<T, 2>(g, zr, item, ex, pf);
+        gz_unit<T, 2>(g, zr, item, pf, D);
     }
 }
 
@@ -209,7 +250,10 @@ __device__ __forceinline__ void gy_unit(const GeoCtx& g, int yr, int item, const
 #pragma unroll
             for (int bb = 0; bb <= P; ++bb)
 #pragma unroll
-                for (int k = 0; k < Q; ++k) c0[e + bb] += Nb[bb * Q + k] * hN[k] + Db[bb * Q + k] * hD[k];
+                for (int k = 0; k < Q; ++k) {
+                    c0[e + bb] += Nb[bb * Q + k] * hN[k];
+                    c0[e + bb] += Db[bb * Q + k] * hD[k];
+                }
         } else {
             double b4[Q], c5[Q], d6[Q];
 #pragma unroll
@@ -223,7 +267,8 @@ __device__ __forceinline__ void gy_unit(const GeoCtx& g, int yr, int item, const
             for (int bb = 0; bb <= P; ++bb)
 #pragma unroll
                 for (int k = 0; k < Q; ++k) {
-                    c0[e + bb] += Db[bb * Q + k] * b4[k] + Nb[bb * Q + k] * c5[k];
+                    c0[e + bb] += Db[bb * Q + k] * b4[k];
+                    c0[e + bb] += Nb[bb * Q + k] * c5[k];
                     c1[e + bb] += Nb[bb * Q + k] * d6[k];
                 }
         }
@@ -280,7 +325,8 @@ __device__ __forceinline__ void gx_step(const GeoCtx& g, const XThread<T>& xt, d
 #pragma unroll
                 for (int k = 0; k < Q; ++k) {
                     am[j][ox] += tb[2 * Q2 + b * Q + k] * m[k];
-                    ak[j][ox] += tb[2 * Q2 + b * Q + k] * u[k] + tb[3 * Q2 + b * Q + k] * v[k];
+                    ak[j][ox] += tb[2 * Q2 + b * Q + k] * u[k];
+                    ak[j][ox] += tb[3 * Q2 + b * Q + k] * v[k];
                 }
             }
         }
@@ -342,6 +388,64 @@ __device__ __forceinline__ void gx_loop(const GeoCtx& g, int xi, int ts, int xs,
     }
 }
 
+// the z/y wavefronts over iterations t = xs .. X1: stage z and stage y of
+// element t (t < xe), the row t-1 stored by the wavefronts without y units.
+// PASS 0..2: the wavefront's one stage-z unit (prefetched fields), 3: none,
+// -1: its units taken one by one without prefetch.
+template <class T, int PASS>
+__device__ __forceinline__ void gzy_loop(const GeoCtx& g, int w, int lane, int xs, int xe, int X0, int X1,
+                                         double* D, double* C, double* STG)
+{
+    const TileCtx& c = g.c;
+    int64_t pbase = 0;
+    int plen = 0;
+    if (w >= T::HW0) pencil_rows<T>(c, lane, pbase, plen);
+    const int ts = 64 * (T::WX + w - T::HW0) + lane;
+    constexpr int PP = PASS >= 0 && PASS < 3 ? PASS : 0;
+    const int zr = w / (3 * T::WZP), item = (w % T::WZP) * 64 + lane;
+    const bool zlive = PASS >= 0 && PASS < 3 && c.iz0 + zr < c.Nz;
+    double pf[3][T::P + 1][T::Q];
+    if constexpr (PASS >= 0 && PASS < 3) {
+        if (zlive && xs < xe) gz_load<T, PP>(g, zr, item, xs, pf);
+    }
+    for (int t = xs; t <= X1; ++t) {
+        const bool el = t < xe;
+        if (el) {
+            if constexpr (PASS >= 0 && PASS < 3) {
+                if (zlive) {
+                    gz_unit<T, PP>(g, zr, item, pf, D);
+                    if (t + 1 < xe) gz_load<T, PP>(g, zr, item, t + 1, pf);
+                }
+            } else if constexpr (PASS < 0) {
+                for (int u = w; u < T::NZU; u += T::NWZY) gz_unit_direct<T>(g, u, lane, t, D);
+            }
+        }
+        __syncthreads();
+        if (el) {
+            for (int u = w; u < T::NYU; u += T::NWZY) {
+                const int yr = u / (3 * T::WYP), gr = (u / T::WYP) % 3;
+                const int yi = (u % T::WYP) * 64 + lane;
+                if (gr == 0) gy_unit<T, 0>(g, yr, yi, D, C);
+                else if (gr == 1) gy_unit<T, 1>(g, yr, yi, D, C);
+                else gy_unit<T, 2>(g, yr, yi, D, C);
+            }
+        }
+        if (w >= T::HW0 && t - 1 >= X0) store_row<T>(c, STG, t - 1, ts, pbase, plen);
+        __syncthreads();
+    }
+}
+
+// the x loop of slot group gg (wave-uniform), instantiated per group
+template <class T, int GG>
+__device__ __forceinline__ void gx_group(int gg, const GeoCtx& g, int xi, int ts, int xs, int xe, int X0, int X1,
+                                         const double* C, double* STG)
+{
+    if constexpr (GG < T::G) {
+        if (gg == GG) gx_loop<T, GG>(g, xi, ts, xs, xe, X0, X1, C, STG);
+        else gx_group<T, GG + 1>(gg, g, xi, ts, xs, xe, X0, X1, C, STG);
+    }
+}
+
 template <class T>
 __device__ __forceinline__ void geo_tile_run(const PatchDev& pd, const RowMap& rm, const double* __restrict__ cm,
                                              const double* __restrict__ G, double* __restrict__ Mv,
@@ -380,49 +484,21 @@ __device__ __forceinline__ void geo_tile_run(const PatchDev& pd, const RowMap& r
     const int w = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
 
     if (w < T::NWZY) {
-        int64_t pbase = 0;
-        int plen = 0;
-        if (w >= T::HW0) pencil_rows<T>(c, lane, pbase, plen);
-        const int ts = 64 * (T::WX + w - T::HW0) + lane;
-        for (int t = xs; t <= X1; ++t) {
-            const bool el = t < xe;
-            if (el) {
-                for (int u = w; u < T::NZU; u += T::NWZY) {
-                    const int zr = u / (3 * T::WZP), pass = (u / T::WZP) % 3;
-                    const int item = (u % T::WZP) * 64 + lane;
-                    if (c.iz0 + zr >= c.Nz) continue;   // rows outside: D never read
-                    if (pass == 0) gz_unit<T, 0>(g, zr, item, t, D);
-                    else if (pass == 1) gz_unit<T, 1>(g, zr, item, t, D);
-                    else gz_unit<T, 2>(g, zr, item, t, D);
-                }
-            }
-            __syncthreads();
-            if (el) {
-                for (int u = w; u < T::NYU; u += T::NWZY) {
-                    const int yr = u / (3 * T::WYP), gr = (u / T::WYP) % 3;
-                    const int item = (u % T::WYP) * 64 + lane;
-                    if (gr == 0) gy_unit<T, 0>(g, yr, item, D, C);
-                    else if (gr == 1) gy_unit<T, 1>(g, yr, item, D, C);
-                    else gy_unit<T, 2>(g, yr, item, D, C);
-                }
-            }
-            if (w >= T::HW0 && t - 1 >= X0) store_row<T>(c, STG, t - 1, ts, pbase, plen);
-            __syncthreads();
+        if constexpr (T::ZPF) {
+            // one stage-z unit per wavefront: its pass is fixed, the next
+            // element's fields are fetched while the current one is contracted
+            const int pass = w < T::NZU ? (w / T::WZP) % 3 : 3;
+            if (pass == 0) gzy_loop<T, 0>(g, w, lane, xs, xe, X0, X1, D, C, STG);
+            else if (pass == 1) gzy_loop<T, 1>(g, w, lane, xs, xe, X0, X1, D, C, STG);
+            else if (pass == 2) gzy_loop<T, 2>(g, w, lane, xs, xe, X0, X1, D, C, STG);
+            else gzy_loop<T, 3>(g, w, lane, xs, xe, X0, X1, D, C, STG);
+        } else {
+            gzy_loop<T, -1>(g, w, lane, xs, xe, X0, X1, D, C, STG);
         }
     } else {
         const int wx = w - T::XW0;
         const int gg = wx / T::WXG, xi = (wx % T::WXG) * 64 + lane, ts = wx * 64 + lane;
-        if constexpr (T::G == 1) {
-            gx_loop<T, 0>(g, xi, ts, xs, xe, X0, X1, C, STG);
-        } else if constexpr (T::G == 2) {
-            if (gg == 0) gx_loop<T, 0>(g, xi, ts, xs, xe, X0, X1, C, STG);
-            else gx_loop<T, 1>(g, xi, ts, xs, xe, X0, X1, C, STG);
-        } else {
-            static_assert(T::G <= 3, "slot groups");
-            if (gg == 0) gx_loop<T, 0>(g, xi, ts, xs, xe, X0, X1, C, STG);
-            else if (gg == 1) gx_loop<T, 1>(g, xi, ts, xs, xe, X0, X1, C, STG);
-            else gx_loop<T, 2>(g, xi, ts, xs, xe, X0, X1, C, STG);
-        }
+        gx_group<T, 0>(gg, g, xi, ts, xs, xe, X0, X1, C, STG);
     }
 }
 
