@@ -27,10 +27,13 @@
 // [iz0, iz0+TZ)) and sweeps the x elements of one x segment in order.  Its
 // wavefronts have two roles, pipelined one element apart (two barriers per
 // element):
-//   z/y wavefronts  element t: stage z, in units of one z row, one pass of
-//                   three products and up to 64 points (ly, ky, kx) of the
-//                   TY+p y elements of the window; then stage y, in units of
-//                   one y row, one output group and up to 64 (zr, oz, kx);
+//   z/y wavefronts  element t: stage z, in units of one pass of three
+//                   products and up to 64 points (ly, ky, kx) of the TY+p y
+//                   elements of the window, for all TZ z rows of the tile
+//                   (their z windows overlap: TZ+p z elements are loaded,
+//                   the next element's while the current one is contracted);
+//                   then stage y, in units of one y row, one output group
+//                   and up to 64 (zr, oz, kx);
 //   x wavefronts    element t-1: every (pencil, oy, oz) adds element t-1's
 //                   contributions to the p+1 rows it touches.  Row ix is kept
 //                   in slot ix mod (p+1) of the thread's accumulators; the
@@ -40,8 +43,8 @@
 //                   its CSR positions and stored as one contiguous segment per
 //                   pencil, and its slot restarts at zero.  The slots are
 //                   split over G groups of x wavefronts (register budget).
-// Every unit is uniform over its wavefront (one z row, one y row, one pass or
-// group), so every 1D table value (w N, w N', N, N' per element, the plan's
+// Every unit is uniform over its wavefront (one pass, one y row and group),
+// so every 1D table value (w N, w N', N, N' per element, the plan's
 // Wg tables) is a scalar operand.
 #include "common.h"
 #include "launch.h"
@@ -57,8 +60,9 @@ struct GeoTile {
     static constexpr int Q = P + 1, O = 2 * P + 1, Q2 = Q * Q, Q3 = Q2 * Q;
     static constexpr int NLY = TY + P;                       // y elements in the window
     static constexpr int NPEN = TY * TZ;                     // pencils per tile
-    static constexpr int NZI = NLY * Q2, WZP = (NZI + 63) / 64;   // stage z items per (z row, pass)
-    static constexpr int NZU = TZ * 3 * WZP;                      // stage z units
+    static constexpr int NLZ = TZ + P;                       // z elements of the tile's rows
+    static constexpr int NZI = NLY * Q2, WZP = (NZI + 63) / 64;   // stage z items per pass
+    static constexpr int NZU = 3 * WZP;                           // stage z units (all z rows each)
     static constexpr int NYI = TZ * O * Q, WYP = (NYI + 63) / 64; // stage y items per (y row, group)
     static constexpr int NYU = TY * 3 * WYP;                      // stage y units
     static constexpr int NWZY = NZW_;                        // z/y wavefronts
@@ -91,7 +95,7 @@ struct GeoTile {
 template <int P> struct GeoCfg;
 template <> struct GeoCfg<1> { using T = GeoTile<1, 4, 4, 6, 1, 2>; };
 template <> struct GeoCfg<2> { using T = GeoTile<2, 2, 2, 6, 1, 2>; };
-template <> struct GeoCfg<3> { using T = GeoTile<3, 1, 2, 6, 1, 2>; };
+template <> struct GeoCfg<3> { using T = GeoTile<3, 1, 2, 3, 2, 2>; };
 template <> struct GeoCfg<4> { using T = GeoTile<4, 1, 1, 6, 1, 2>; };
 
 struct GeoCtx {
@@ -109,14 +113,14 @@ template <> struct ZPass<0> { static constexpr int f[3] = {0, 1, 2}, tk[3] = {0,
 template <> struct ZPass<1> { static constexpr int f[3] = {3, 4, 5}, tk[3] = {1, 0, 0}, rk[3] = {3, 2, 3}; };
 template <> struct ZPass<2> { static constexpr int f[3] = {5, 6, 6}, tk[3] = {1, 0, 1}, rk[3] = {2, 3, 2}; };
 
-// ---- stage z, pass PASS of z row zr: thread on point item (ly, ky, kx).
-// gz_load fetches the pass's three fields of element ex for the p+1 z
-// elements of the row (z elements outside the patch are read at a clamped
-// index and never used; a field the call does not need is read from the
-// other one and its products are never stored); gz_unit contracts them.
+// ---- stage z, pass PASS for all TZ z rows of the tile: thread on point
+// item (ly, ky, kx).  The rows' z windows overlap: the TZ+p z elements
+// iz0-p .. iz0+TZ-1 are loaded once.  gz_load fetches the pass's three
+// fields of element ex on them (z elements outside the patch are read at a
+// clamped index and never used; a field the call does not need is read from
+// the other one and its products are never stored); gz_unit contracts them.
 template <class T, int PASS>
-__device__ __forceinline__ void gz_load(const GeoCtx& g, int zr, int item, int ex,
-                                        double (&pf)[3][T::P + 1][T::Q])
+__device__ __forceinline__ void gz_load(const GeoCtx& g, int item, int ex, double (&pf)[3][T::NLZ][T::Q])
 {
     constexpr int P = T::P, Q = T::Q, Q2 = T::Q2, Q3 = T::Q3;
     using PS = ZPass<PASS>;
@@ -124,7 +128,6 @@ __device__ __forceinline__ void gz_load(const GeoCtx& g, int zr, int item, int e
     const int it = item < T::NZI ? item : T::NZI - 1;
     const int ly = it / Q2, pq = it % Q2;   // pq = ky Q + kx
     const int ey = clampi_t(c.iy0 - P + ly, c.Ky - 1);   // y elements outside are never read
-    const int iz = c.iz0 + zr;
     const int64_t exy = (int64_t)ex + (int64_t)c.Kx * ey;   // element index without its z part
     const int64_t layer = (int64_t)c.Kx * c.Ky;
 #pragma unroll
@@ -133,51 +136,54 @@ __device__ __forceinline__ void gz_load(const GeoCtx& g, int zr, int item, int e
         const double* src = PS::f[j] == 0 ? (g.cm ? g.cm : g.G) : (g.G ? g.G + (PS::f[j] - 1) * Q3 : g.cm);
         const int64_t es = gf ? 6 * Q3 : Q3;
 #pragma unroll
-        for (int e = 0; e <= P; ++e) {
-            const int ezc = clampi_t(iz - P + e, c.Kz - 1);
+        for (int m = 0; m < T::NLZ; ++m) {
+            const int ezc = clampi_t(c.iz0 - P + m, c.Kz - 1);
             const double* sp = src + (exy + layer * ezc) * es + pq;
 #pragma unroll
-            for (int k = 0; k < Q; ++k) pf[j][e][k] = sp[Q2 * k];
+            for (int k = 0; k < Q; ++k) pf[j][m][k] = sp[Q2 * k];
         }
     }
 }
 
 template <class T, int PASS>
-__device__ __forceinline__ void gz_unit(const GeoCtx& g, int zr, int item, const double (&pf)[3][T::P + 1][T::Q],
-                                        double* D)
+__device__ __forceinline__ void gz_unit(const GeoCtx& g, int item, const double (&pf)[3][T::NLZ][T::Q], double* D)
 {
     constexpr int P = T::P, Q = T::Q, O = T::O, Q2 = T::Q2;
     using PS = ZPass<PASS>;
     const TileCtx& c = g.c;
-    const int iz = c.iz0 + zr;
-    double acc[3][O];
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int o = 0; o < O; ++o) acc[j][o] = 0.0;
-#pragma unroll
-    for (int e = 0; e <= P; ++e) {
-        const int ez = iz - P + e;
-        if (ez < 0 || ez >= c.Kz) continue;   // wave-uniform
-        const ctab tb = g.Wz + (int64_t)ez * T::TBE;   // test index P - e, trial bb
-        double gv[3][Q];
+    for (int zr = 0; zr < T::TZ; ++zr) {
+        const int iz = c.iz0 + zr;
+        if (iz >= c.Nz) break;   // rows outside: D never read (wave-uniform)
+        double acc[3][O];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int k = 0; k < Q; ++k) gv[j][k] = pf[j][e][k] * tb[PS::tk[j] * Q2 + (P - e) * Q + k];
+            for (int o = 0; o < O; ++o) acc[j][o] = 0.0;
 #pragma unroll
-        for (int bb = 0; bb <= P; ++bb)
+        for (int e = 0; e <= P; ++e) {
+            const int ez = iz - P + e;
+            if (ez < 0 || ez >= c.Kz) continue;   // wave-uniform
+            const ctab tb = g.Wz + (int64_t)ez * T::TBE;   // test index P - e, trial bb
+            double gv[3][Q];
 #pragma unroll
             for (int j = 0; j < 3; ++j)
 #pragma unroll
-                for (int k = 0; k < Q; ++k) acc[j][e + bb] += tb[PS::rk[j] * Q2 + bb * Q + k] * gv[j][k];
-    }
-    if (item < T::NZI) {
+                for (int k = 0; k < Q; ++k) gv[j][k] = pf[j][zr + e][k] * tb[PS::tk[j] * Q2 + (P - e) * Q + k];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            double* dp = D + zr * T::DZR + (3 * PASS + j) * T::DD + item;
+            for (int bb = 0; bb <= P; ++bb)
 #pragma unroll
-            for (int o = 0; o < O; ++o) dp[o * T::DOZ] = acc[j][o];
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) acc[j][e + bb] += tb[PS::rk[j] * Q2 + bb * Q + k] * gv[j][k];
+        }
+        if (item < T::NZI) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                double* dp = D + zr * T::DZR + (3 * PASS + j) * T::DD + item;
+#pragma unroll
+                for (int o = 0; o < O; ++o) dp[o * T::DOZ] = acc[j][o];
+            }
         }
     }
 }
@@ -187,19 +193,18 @@ __device__ __forceinline__ void gz_unit(const GeoCtx& g, int zr, int item, const
 template <class T>
 __device__ __forceinline__ void gz_unit_direct(const GeoCtx& g, int u, int lane, int ex, double* D)
 {
-    const int zr = u / (3 * T::WZP), pass = (u / T::WZP) % 3;
+    const int pass = u / T::WZP;
     const int item = (u % T::WZP) * 64 + lane;
-    if (g.c.iz0 + zr >= g.c.Nz) return;   // rows outside: D never read
-    double pf[3][T::P + 1][T::Q];
+    double pf[3][T::NLZ][T::Q];
     if (pass == 0) {
-        gz_load<T, 0>(g, zr, item, ex, pf);
-        gz_unit<T, 0>(g, zr, item, pf, D);
+        gz_load<T, 0>(g, item, ex, pf);
+        gz_unit<T, 0>(g, item, pf, D);
     } else if (pass == 1) {
-        gz_load<T, 1>(g, zr, item, ex, pf);
-        gz_unit<T, 1>(g, zr, item, pf, D);
+        gz_load<T, 1>(g, item, ex, pf);
+        gz_unit<T, 1>(g, item, pf, D);
     } else {
-        gz_load<T, 2>(g, zr, item, ex, pf);
-        gz_unit<T, 2>(g, zr, item, pf, D);
+        gz_load<T, 2>(g, item, ex, pf);
+        gz_unit<T, 2>(g, item, pf, D);
     }
 }
 
@@ -402,20 +407,17 @@ __device__ __forceinline__ void gzy_loop(const GeoCtx& g, int w, int lane, int x
     if (w >= T::HW0) pencil_rows<T>(c, lane, pbase, plen);
     const int ts = 64 * (T::WX + w - T::HW0) + lane;
     constexpr int PP = PASS >= 0 && PASS < 3 ? PASS : 0;
-    const int zr = w / (3 * T::WZP), item = (w % T::WZP) * 64 + lane;
-    const bool zlive = PASS >= 0 && PASS < 3 && c.iz0 + zr < c.Nz;
-    double pf[3][T::P + 1][T::Q];
+    const int item = (w % T::WZP) * 64 + lane;
+    double pf[3][T::NLZ][T::Q];
     if constexpr (PASS >= 0 && PASS < 3) {
-        if (zlive && xs < xe) gz_load<T, PP>(g, zr, item, xs, pf);
+        if (xs < xe) gz_load<T, PP>(g, item, xs, pf);
     }
     for (int t = xs; t <= X1; ++t) {
         const bool el = t < xe;
         if (el) {
             if constexpr (PASS >= 0 && PASS < 3) {
-                if (zlive) {
-                    gz_unit<T, PP>(g, zr, item, pf, D);
-                    if (t + 1 < xe) gz_load<T, PP>(g, zr, item, t + 1, pf);
-                }
+                gz_unit<T, PP>(g, item, pf, D);
+                if (t + 1 < xe) gz_load<T, PP>(g, item, t + 1, pf);
             } else if constexpr (PASS < 0) {
                 for (int u = w; u < T::NZU; u += T::NWZY) gz_unit_direct<T>(g, u, lane, t, D);
             }
@@ -487,7 +489,7 @@ __device__ __forceinline__ void geo_tile_run(const PatchDev& pd, const RowMap& r
         if constexpr (T::ZPF) {
             // one stage-z unit per wavefront: its pass is fixed, the next
             // element's fields are fetched while the current one is contracted
-            const int pass = w < T::NZU ? (w / T::WZP) % 3 : 3;
+            const int pass = w < T::NZU ? w / T::WZP : 3;
             if (pass == 0) gzy_loop<T, 0>(g, w, lane, xs, xe, X0, X1, D, C, STG);
             else if (pass == 1) gzy_loop<T, 1>(g, w, lane, xs, xe, X0, X1, D, C, STG);
             else if (pass == 2) gzy_loop<T, 2>(g, w, lane, xs, xe, X0, X1, D, C, STG);
