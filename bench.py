@@ -73,8 +73,22 @@ def timed(fn, steps, warmup, stream):
     return [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
 
 
+def src_hash(path):
+    """Hash of a kernel source and the local headers it includes (one level
+    deep, in include order): a profile taken on the kernel stays attached to
+    it only while none of them changes."""
+    import re
+
+    h = hashlib.sha256()
+    text = open(path, "rb").read()
+    h.update(text)
+    for inc in re.findall(rb'#include "([^"]+)"', text):
+        h.update(open(os.path.join(os.path.dirname(path), inc.decode()), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def element_src_hash():
-    return hashlib.sha256(open(ELEMENT_SRC, "rb").read()).hexdigest()[:16]
+    return src_hash(ELEMENT_SRC)
 
 
 def classical_flops(p):
@@ -89,8 +103,8 @@ def classical_flops(p):
 
 def counters_for_current_sources():
     """Per-kernel rocprofv3 counter summaries (FP64 and instruction counts)
-    from the committed passes, for kernels whose source file is unchanged
-    since the counters were taken."""
+    from the committed passes, for kernels whose source (with its local
+    headers) is unchanged since the counters were taken."""
     try:
         t = json.load(open(COUNTERS_FILE))
     except (OSError, ValueError):
@@ -99,7 +113,7 @@ def counters_for_current_sources():
     for name, e in t.get("kernels", {}).items():
         path = os.path.join(ROOT, e["source"])
         try:
-            cur = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+            cur = src_hash(path)
         except OSError:
             continue
         if cur != e["src_sha256_16"]:
