@@ -91,11 +91,13 @@ struct GeoTile {
 
 // Tile shapes per degree: TZ rows fill the lanes of stage y, TY pencils share
 // stage z; G slot groups bound the x wavefronts' accumulators ((p+1)/G slots
-// of 2(2p+1) values).
+// of 2(2p+1) values).  At p = 3 a one-pencil tile (48 KB of LDS, four
+// wavefronts) lets two workgroups share a CU, which measured faster than the
+// larger tiles with one workgroup per CU.
 template <int P> struct GeoCfg;
 template <> struct GeoCfg<1> { using T = GeoTile<1, 4, 4, 6, 1, 2>; };
 template <> struct GeoCfg<2> { using T = GeoTile<2, 2, 2, 6, 1, 2>; };
-template <> struct GeoCfg<3> { using T = GeoTile<3, 1, 2, 3, 2, 2>; };
+template <> struct GeoCfg<3> { using T = GeoTile<3, 1, 1, 3, 1, 2>; };
 template <> struct GeoCfg<4> { using T = GeoTile<4, 1, 1, 6, 1, 2>; };
 
 struct GeoCtx {
