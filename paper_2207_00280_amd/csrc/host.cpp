@@ -589,8 +589,8 @@ igaf_status igaf_plan_timing(igaf_plan* plan, int32_t kernel, double* avg_ms, in
 }
 
 // Degrees whose mapped-geometry CSR values have an owner-computed rows
-// kernel (its stage-z buffers of nine products fit the LDS of a CU up to p = 4).
-static bool geo_rows_supported(const igaf_plan* P) { return P->p <= 4; }
+// kernel (all of them: p = 5 takes its stage-z products in three rounds).
+static bool geo_rows_supported(const igaf_plan* P) { return P->p <= 5; }
 
 // Mapped-geometry CSR values whose element matrices the caller does not
 // store, for the other degrees: slab by slab of z row layers, the element matrices of the element

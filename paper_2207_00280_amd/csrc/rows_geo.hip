@@ -54,19 +54,22 @@
 
 namespace igaf {
 
-template <int P_, int TY_, int TZ_, int NZW_, int G_, int WPE_>
+template <int P_, int TY_, int TZ_, int NZW_, int G_, int WPE_, int ROUNDS_ = 1>
 struct GeoTile {
     static constexpr int P = P_, TY = TY_, TZ = TZ_, G = G_, WPE = WPE_;
+    // 1: all nine stage-z products of an element in LDS at once; 3: one pass
+    // (three products) at a time, stage y accumulating over the three rounds
+    static constexpr int ROUNDS = ROUNDS_;
     static constexpr int Q = P + 1, O = 2 * P + 1, Q2 = Q * Q, Q3 = Q2 * Q;
     static constexpr int NLY = TY + P;                       // y elements in the window
     static constexpr int NPEN = TY * TZ;                     // pencils per tile
     static constexpr int NLZ = TZ + P;                       // z elements of the tile's rows
     static constexpr int NZI = NLY * Q2, WZP = (NZI + 63) / 64;   // stage z items per pass
-    static constexpr int NZU = 3 * WZP;                           // stage z units (all z rows each)
+    static constexpr int NZU = (ROUNDS == 1 ? 3 : 1) * WZP;       // stage z units per round
     static constexpr int NYI = TZ * O * Q, WYP = (NYI + 63) / 64; // stage y items per (y row, group)
     static constexpr int NYU = TY * 3 * WYP;                      // stage y units
     static constexpr int NWZY = NZW_;                        // z/y wavefronts
-    static constexpr bool ZPF = NZU <= NWZY;                 // one z unit per wavefront: prefetch
+    static constexpr bool ZPF = ROUNDS == 1 && NZU <= NWZY;  // one z unit per wavefront: prefetch
     static constexpr int NXI = NPEN * O * O, WXG = (NXI + 63) / 64;   // stage x: per slot group
     static constexpr int WX = G * WXG;
     static constexpr int NSL = (P + 1 + G - 1) / G;          // row slots per x thread
@@ -76,9 +79,9 @@ struct GeoTile {
     static constexpr int SROW = O * O * O + 1;
     static constexpr int SIT = (O * O * O + NTS - 1) / NTS;
     static constexpr int SGP = NPEN;
-    // LDS (doubles): D[zr][9][O][DOZ] (DOZ >= NZI: [ly][ky][kx]);
+    // LDS (doubles): D[zr][9 or 3][O][DOZ] (DOZ >= NZI: [ly][ky][kx]);
     // C[5][NPEN][CP] (CP >= Q O O: [kx][oy][oz]); staged rows [NPEN][2][SROW]
-    static constexpr int DOZ = pad16(NZI, Q), DD = O * DOZ, DZR = 9 * DD, DSZ = TZ * DZR;
+    static constexpr int DOZ = pad16(NZI, Q), DD = O * DOZ, DZR = (ROUNDS == 1 ? 9 : 3) * DD, DSZ = TZ * DZR;
     static constexpr int CP = pad16(Q * O * O, O * O), CC = NPEN * CP, CSZ = 5 * CC;
     static constexpr int SSZ = NPEN * 2 * SROW;
     static constexpr int TBE = 4 * Q2;                       // one element's Wg table
@@ -86,6 +89,7 @@ struct GeoTile {
     static constexpr int LDS = OFF_S + SSZ;
     static_assert(NW <= 16, "workgroup too large");
     static_assert(NZU <= 4 * NWZY && NYU <= 4 * NWZY, "units per wavefront");
+    static_assert(ROUNDS == 1 || (ROUNDS == 3 && NZU <= NWZY && NYU <= 2 * NWZY), "units per wavefront (rounds)");
     static_assert(LDS * 8 <= 160 * 1024, "LDS");
 };
 
@@ -99,6 +103,9 @@ template <> struct GeoCfg<1> { using T = GeoTile<1, 4, 4, 6, 1, 2>; };
 template <> struct GeoCfg<2> { using T = GeoTile<2, 2, 2, 6, 1, 2>; };
 template <> struct GeoCfg<3> { using T = GeoTile<3, 1, 1, 3, 1, 2>; };
 template <> struct GeoCfg<4> { using T = GeoTile<4, 1, 1, 6, 1, 2>; };
+// p = 5: the nine products of one element would need 182 KB of LDS; three
+// rounds of three (111 KB)
+template <> struct GeoCfg<5> { using T = GeoTile<5, 1, 1, 4, 2, 2, 3>; };
 
 struct GeoCtx {
     TileCtx c;
@@ -182,7 +189,7 @@ __device__ __forceinline__ void gz_unit(const GeoCtx& g, int item, const double 
         if (item < T::NZI) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                double* dp = D + zr * T::DZR + (3 * PASS + j) * T::DD + item;
+                double* dp = D + zr * T::DZR + (T::ROUNDS == 1 ? 3 * PASS + j : j) * T::DD + item;
 #pragma unroll
                 for (int o = 0; o < O; ++o) dp[o * T::DOZ] = acc[j][o];
             }
@@ -207,6 +214,66 @@ __device__ __forceinline__ void gz_unit_direct(const GeoCtx& g, int u, int lane,
     } else {
         gz_load<T, 2>(g, item, ex, pf);
         gz_unit<T, 2>(g, item, pf, D);
+    }
+}
+
+// stage z of pass PASS for the rounds schedule: the fields of one z element
+// at a time are loaded and contracted (no prefetch: the register budget of
+// the degree the rounds are for)
+template <class T, int PASS>
+__device__ __forceinline__ void gz_stream(const GeoCtx& g, int item, int ex, double* D)
+{
+    constexpr int P = T::P, Q = T::Q, O = T::O, Q2 = T::Q2, Q3 = T::Q3;
+    using PS = ZPass<PASS>;
+    const TileCtx& c = g.c;
+    const int it = item < T::NZI ? item : T::NZI - 1;
+    const int ly = it / Q2, pq = it % Q2;
+    const int ey = clampi_t(c.iy0 - P + ly, c.Ky - 1);
+    const int64_t exy = (int64_t)ex + (int64_t)c.Kx * ey;
+    const int64_t layer = (int64_t)c.Kx * c.Ky;
+    const double* src[3];
+    int64_t es[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        src[j] = PS::f[j] == 0 ? (g.cm ? g.cm : g.G) : (g.G ? g.G + (PS::f[j] - 1) * Q3 : g.cm);
+        es[j] = PS::f[j] > 0 && g.G ? 6 * Q3 : Q3;
+    }
+#pragma unroll
+    for (int zr = 0; zr < T::TZ; ++zr) {
+        const int iz = c.iz0 + zr;
+        if (iz >= c.Nz) break;   // wave-uniform
+        double acc[3][O];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int o = 0; o < O; ++o) acc[j][o] = 0.0;
+#pragma unroll
+        for (int e = 0; e <= P; ++e) {
+            const int ez = iz - P + e;
+            if (ez < 0 || ez >= c.Kz) continue;   // wave-uniform
+            const ctab tb = g.Wz + (int64_t)ez * T::TBE;
+            double gv[3][Q];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double* sp = src[j] + (exy + layer * ez) * es[j] + pq;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) gv[j][k] = sp[Q2 * k] * tb[PS::tk[j] * Q2 + (P - e) * Q + k];
+            }
+#pragma unroll
+            for (int bb = 0; bb <= P; ++bb)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int k = 0; k < Q; ++k) acc[j][e + bb] += tb[PS::rk[j] * Q2 + bb * Q + k] * gv[j][k];
+        }
+        if (item < T::NZI) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                double* dp = D + zr * T::DZR + j * T::DD + item;
+#pragma unroll
+                for (int o = 0; o < O; ++o) dp[o * T::DOZ] = acc[j][o];
+            }
+        }
     }
 }
 
@@ -289,6 +356,99 @@ __device__ __forceinline__ void gy_unit(const GeoCtx& g, int yr, int item, const
         if constexpr (GR != 1) {
 #pragma unroll
             for (int o = 0; o < O; ++o) cp[o1 * T::CC + o * O] = c1[o];
+        }
+    }
+}
+
+// ---- stage y for the rounds schedule: round R adds the terms of output
+// group GR whose stage-z products are pass R's (D slot j = product 3R + j);
+// the accumulators c0, c1 stay in the thread's registers from round 0 (which
+// clears them) to round 2 (which writes C)
+//   round 0 (D0 D1 D2):  CM += nn D0, Cdd += nn D1, Cnn += dd D2
+//   round 1 (D3 D4 D5):  Cnn += nn D3, Cdn += nd D4 + nn D5, Cnd += dn D4
+//   round 2 (D6 D7 D8):  Cnn += dn D7 + nd D8, Cnd += nn D6
+template <class T, int GR, int R>
+__device__ __forceinline__ void gy_round(const GeoCtx& g, int yr, int item, const double* D, double* C,
+                                         double (&c0)[T::O], double (&c1)[T::O])
+{
+    constexpr int P = T::P, Q = T::Q, O = T::O, Q2 = T::Q2;
+    const TileCtx& c = g.c;
+    const int iy = c.iy0 + yr;
+    if (iy >= c.Ny) return;   // wave-uniform
+    const bool act = item < T::NYI;
+    const int it = act ? item : T::NYI - 1;
+    const int zr = it / (O * Q), oz = (it / Q) % O, kx = it % Q;
+    if constexpr (R == 0) {
+#pragma unroll
+        for (int o = 0; o < O; ++o) c0[o] = c1[o] = 0.0;
+    }
+    constexpr bool any = GR == 0 ? R == 0 : (GR == 1 ? true : R >= 1);
+    if constexpr (any) {
+#pragma unroll
+        for (int e = 0; e <= P; ++e) {
+            const int ey = iy - P + e;
+            if (ey < 0 || ey >= c.Ky) continue;   // wave-uniform
+            const ctab tb = g.Wy + (int64_t)ey * T::TBE;
+            const ctab wN = tb + (P - e) * Q, wD = tb + Q2 + (P - e) * Q;
+            const ctab Nb = tb + 2 * Q2, Db = tb + 3 * Q2;
+            const double* dp = D + zr * T::DZR + oz * T::DOZ + (yr + e) * Q2 + kx;
+            // fa (trial N), fb (trial N') fold into c0; fc (trial N) into c1
+            double fa[Q], fb[Q], fc[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const double d0 = dp[0 * T::DD + k * Q], d1 = dp[1 * T::DD + k * Q], d2 = dp[2 * T::DD + k * Q];
+                if constexpr (GR == 0) {        // R == 0: CM += nn D0, Cdd += nn D1
+                    fa[k] = wN[k] * d0;
+                    fb[k] = 0.0;
+                    fc[k] = wN[k] * d1;
+                } else if constexpr (GR == 1) {
+                    if constexpr (R == 0) {     // Cnn += dd D2
+                        fa[k] = 0.0;
+                        fb[k] = wD[k] * d2;
+                    } else if constexpr (R == 1) {   // Cnn += nn D3
+                        fa[k] = wN[k] * d0;
+                        fb[k] = 0.0;
+                    } else {                    // Cnn += dn D7 + nd D8
+                        fa[k] = wD[k] * d1;
+                        fb[k] = wN[k] * d2;
+                    }
+                    fc[k] = 0.0;
+                } else {
+                    if constexpr (R == 1) {     // Cdn += nd D4 + nn D5, Cnd += dn D4
+                        fa[k] = wN[k] * d2;
+                        fb[k] = wN[k] * d1;
+                        fc[k] = wD[k] * d1;
+                    } else {                    // Cnd += nn D6
+                        fa[k] = 0.0;
+                        fb[k] = 0.0;
+                        fc[k] = wN[k] * d0;
+                    }
+                }
+            }
+            constexpr bool ua = !(GR == 1 && R == 0) && !(GR == 2 && R == 2);
+            constexpr bool ub = (GR == 1 && R != 1) || (GR == 2 && R == 1);
+            constexpr bool uc = GR == 0 || GR == 2;
+#pragma unroll
+            for (int bb = 0; bb <= P; ++bb)
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    if constexpr (ua) c0[e + bb] += Nb[bb * Q + k] * fa[k];
+                    if constexpr (ub) c0[e + bb] += Db[bb * Q + k] * fb[k];
+                    if constexpr (uc) c1[e + bb] += Nb[bb * Q + k] * fc[k];
+                }
+        }
+    }
+    if constexpr (R == 2 || T::ROUNDS == 1) {
+        if (act) {
+            constexpr int o0 = GR == 0 ? 0 : (GR == 1 ? 1 : 3);
+            constexpr int o1 = GR == 0 ? 2 : 4;
+            double* cp = C + (yr * T::TZ + zr) * T::CP + kx * O * O + oz;
+#pragma unroll
+            for (int o = 0; o < O; ++o) cp[o0 * T::CC + o * O] = c0[o];
+            if constexpr (GR != 1) {
+#pragma unroll
+                for (int o = 0; o < O; ++o) cp[o1 * T::CC + o * O] = c1[o];
+            }
         }
     }
 }
@@ -384,6 +544,11 @@ __device__ __forceinline__ void gx_loop(const GeoCtx& g, int xi, int ts, int xs,
         __syncthreads();
         if (live && r >= X0) store_row<T>(g.c, STG, r, ts, pbase, plen);
         __syncthreads();
+#pragma unroll
+        for (int k = 1; k < T::ROUNDS; ++k) {   // the z/y wavefronts' later rounds
+            __syncthreads();
+            __syncthreads();
+        }
     };
     for (int r0 = r00; r0 <= X1 - 1; r0 += P + 1) {
         row(std::integral_constant<int, 0>{}, r0);
@@ -439,6 +604,51 @@ __device__ __forceinline__ void gzy_loop(const GeoCtx& g, int w, int lane, int x
     }
 }
 
+// the z/y wavefronts under the rounds schedule: per iteration t, three
+// rounds of (stage z of pass R | barrier | stage y, round R | barrier); the
+// wavefront's stage-y units (at most two) keep their accumulators across the
+// rounds; the row t-1 is stored in round 0 by the wavefronts without y units
+template <class T>
+__device__ __forceinline__ void gzy_loop_rounds(const GeoCtx& g, int w, int lane, int xs, int xe, int X0, int X1,
+                                                double* D, double* C, double* STG)
+{
+    constexpr int O = T::O;
+    const TileCtx& c = g.c;
+    int64_t pbase = 0;
+    int plen = 0;
+    if (w >= T::HW0) pencil_rows<T>(c, lane, pbase, plen);
+    const int ts = 64 * (T::WX + w - T::HW0) + lane;
+    const int zitem = (w % T::WZP) * 64 + lane;
+    double a0[2][O], a1[2][O];
+    auto yround = [&](auto rr) {
+        constexpr int R = decltype(rr)::value;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int u = w + k * T::NWZY;
+            if (u >= T::NYU) break;   // wave-uniform
+            const int yr = u / (3 * T::WYP), gr = (u / T::WYP) % 3;
+            const int yi = (u % T::WYP) * 64 + lane;
+            if (gr == 0) gy_round<T, 0, R>(g, yr, yi, D, C, a0[k], a1[k]);
+            else if (gr == 1) gy_round<T, 1, R>(g, yr, yi, D, C, a0[k], a1[k]);
+            else gy_round<T, 2, R>(g, yr, yi, D, C, a0[k], a1[k]);
+        }
+    };
+    auto round = [&](auto rr, int t, bool el) {
+        constexpr int R = decltype(rr)::value;
+        if (el && w < T::NZU) gz_stream<T, R>(g, zitem, t, D);
+        __syncthreads();
+        if (el) yround(rr);
+        if (R == 0 && w >= T::HW0 && t - 1 >= X0) store_row<T>(c, STG, t - 1, ts, pbase, plen);
+        __syncthreads();
+    };
+    for (int t = xs; t <= X1; ++t) {
+        const bool el = t < xe;
+        round(std::integral_constant<int, 0>{}, t, el);
+        round(std::integral_constant<int, 1>{}, t, el);
+        round(std::integral_constant<int, 2>{}, t, el);
+    }
+}
+
 // the x loop of slot group gg (wave-uniform), instantiated per group
 template <class T, int GG>
 __device__ __forceinline__ void gx_group(int gg, const GeoCtx& g, int xi, int ts, int xs, int xe, int X0, int X1,
@@ -488,7 +698,9 @@ __device__ __forceinline__ void geo_tile_run(const PatchDev& pd, const RowMap& r
     const int w = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
 
     if (w < T::NWZY) {
-        if constexpr (T::ZPF) {
+        if constexpr (T::ROUNDS == 3) {
+            gzy_loop_rounds<T>(g, w, lane, xs, xe, X0, X1, D, C, STG);
+        } else if constexpr (T::ZPF) {
             // one stage-z unit per wavefront: its pass is fixed, the next
             // element's fields are fetched while the current one is contracted
             const int pass = w < T::NZU ? w / T::WZP : 3;
@@ -557,7 +769,8 @@ int launch_rows_geo(const PatchDev& pd, const double* cm, const double* G, doubl
     case 2: return launch_rows_geo_t<GeoCfg<2>::T>(pd, cm, G, Mv, Kv, st);
     case 3: return launch_rows_geo_t<GeoCfg<3>::T>(pd, cm, G, Mv, Kv, st);
     case 4: return launch_rows_geo_t<GeoCfg<4>::T>(pd, cm, G, Mv, Kv, st);
-    default: return -4;   // p = 5: the stage-z buffers exceed the LDS of a CU
+    case 5: return launch_rows_geo_t<GeoCfg<5>::T>(pd, cm, G, Mv, Kv, st);
+    default: return -4;
     }
 }
 

@@ -5,7 +5,7 @@ mass and the tensor G = kappa det J J^-1 J^-T for the stiffness; the caller's
 side (workloads.mapped_geometry) evaluates them at the points.  The HIP path
 (sum factorisation with ordered per-direction pairs; CSR values gathered from
 the stored element matrices, or, when none are stored, computed by
-owner-computed rows for p <= 4 and gathered slab by slab for p = 5) is
+owner-computed rows) is
 compared with the oracle's classical quadrature of the same integrands, which
 the CPU suite pins by scaled knots, exact affine Kronecker forms and linear
 patch tests.
@@ -105,14 +105,19 @@ ROWS_CASES = [
     (3, (26, 5, 5), "nonuniform", dict(A=A_SHEAR, amp=0.1)),
     (3, (21, 1, 2), "uniform", dict(amp=0.1)),
     (4, (20, 3, 2), "nonuniform", dict(amp=0.08)),
+    (5, (16, 2, 2), "nonuniform", dict(A=A_SHEAR, amp=0.05)),
+    (5, (13, 1, 3), "uniform", dict(amp=0.1)),
+    (3, (1, 1, 1), "uniform", dict(amp=0.1)),
+    (5, (1, 1, 1), "uniform", dict(amp=0.1)),
 ]
 
 
 @pytest.mark.parametrize("p,K,kind,geo", ROWS_CASES)
 def test_geometry_rows_kernel_vs_oracle(orc, ig, p, K, kind, geo):
     """The owner-computed CSR rows of a mapped geometry on meshes that span
-    several tiles and x segments: every CSR value of M and K vs the oracle
-    (global and per-row relative error), repeated calls bit for bit."""
+    several tiles and x segments, and single elements: every CSR value of M
+    and K vs the oracle (global and per-row relative error), repeated calls
+    bit for bit."""
     knots, K = _knots(p, K, kind, 310 + p)
     P = orc.Patch(p, K, [p + 1] * 3, knots)
     plan = ig.Plan(p, K, knots)
@@ -210,10 +215,8 @@ def test_geometry_fullscale(orc, ig):
 
 @pytest.mark.parametrize("p,K", [(2, (6, 5, 7)), (5, (3, 2, 4))])
 def test_geometry_csr_under_capture(ig, p, K):
-    """A CSR-only call under HIP graph capture: for p <= 4 the rows kernel
-    needs no workspace and captures at once; for p = 5 it is refused before
-    any launch until the plan has its slab workspace (an allocation cannot be
-    captured), and after igaf_geo_prepare the slab path captures.  Every
+    """A CSR-only call under HIP graph capture: the rows kernel needs no
+    workspace and captures at once (igaf_geo_prepare is a no-op); every
     replay (eager work between them) equals the eager result of another plan
     bit for bit."""
     import torch
@@ -226,14 +229,6 @@ def test_geometry_csr_under_capture(ig, p, K):
     Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
     Kv = torch.empty_like(Mv)
     s = torch.cuda.Stream()
-    if p == 5:
-        g0 = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g0, stream=s):
-            with pytest.raises(ig.IgafError) as ei:
-                plan.integrate_assemble_geo(cmd, Gd, want_elem=False, Mval=Mv, Kval=Kv, stream=s)
-            _ = torch.zeros(1, device="cuda")
-        assert ei.value.status == ig.EINVAL and "igaf_geo_prepare" in str(ei.value)
-    plan.geo_prepare()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         plan.integrate_assemble_geo(cmd, Gd, want_elem=False, Mval=Mv, Kval=Kv, stream=s)
