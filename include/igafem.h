@@ -220,19 +220,11 @@ igaf_status igaf_integrate_assemble(const igaf_plan* plan, int32_t method, const
  *      OVERWRITTEN with the assembled CSR values (structural pattern of
  *      igaf_csr_pattern).  At least one output.  A CSR output whose element
  *      matrices are requested too is summed from them as in igaf_assemble.
- *      One without is computed, for degree <= 4, by owner-computed rows:
- *      every value summed by one thread over the Gauss points of the
- *      elements its row and column share, contracted z -> y -> x (no
- *      workspace, no atomics, same bits on every call, capturable).  For
- *      degree 5 it is summed as in igaf_assemble slab by slab of element
- *      layers through a workspace the plan allocates in igaf_geo_prepare,
- *      or else at the first such call (at most 2 GiB, freed with the plan;
- *      neighbouring slabs share p layers, integrated twice), also
- *      deterministic; under stream capture that workspace must exist
- *      already (IGAF_EINVAL otherwise, before any launch), and only when it
- *      cannot hold p+1 element layers (or its allocation fails) are the
- *      values added with FP64 atomics instead (the last bits may then vary
- *      between calls).  The three ways agree to rounding, not bit for bit.
+ *      One without is computed by owner-computed rows: every value summed
+ *      by one thread over the Gauss points of the elements its row and
+ *      column share, contracted z -> y -> x (no workspace, no atomics, the
+ *      same bits on every call, capturable).  The two ways agree to
+ *      rounding, not bit for bit.
  * Sum factorisation (Algorithm 2) with ordered per-direction pairs (the
  * cross terms of G are not symmetric in a pair); nquad = degree+1 in every
  * direction, else IGAF_EUNSUPPORTED.  cm = kappa, G = kappa I (the identity
@@ -242,12 +234,11 @@ igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm,
                                         double* Me, double* Ke, double* Mval, double* Kval,
                                         void* stream);
 
-/* Allocate the plan's slab workspace of igaf_integrate_assemble_geo's
- * degree-5 CSR-only path now (synchronous; a no-op for degree <= 4, whose
- * rows kernel needs none, when it exists, or when the mesh's element layers
- * exceed its 2 GiB cap, which take the atomic path), so that later calls
- * allocate nothing and may be captured.  IGAF_ENOMEM if the allocation
- * fails. */
+/* Nothing to prepare: igaf_integrate_assemble_geo allocates nothing on any
+ * path (its CSR-only values come from the owner-computed rows kernel).  Kept
+ * so that callers that prepared a plan before capturing it still work; it
+ * only checks the plan (IGAF_EINVAL for NULL, IGAF_EUNSUPPORTED for a
+ * quadrature order other than degree+1). */
 igaf_status igaf_geo_prepare(igaf_plan* plan);
 
 /* Adjoint of L(kappa) = alphaM u^T M(kappa) v + alphaK u^T K(kappa) v with

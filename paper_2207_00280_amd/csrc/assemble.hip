@@ -25,10 +25,8 @@ namespace igaf {
 template <int P>
 __global__ __launch_bounds__(256) void k_gather(PatchDev pd, RowMap rm, const double* __restrict__ Me,
                                                 const double* __restrict__ Ke, double* __restrict__ Mv,
-                                                double* __restrict__ Kv, int64_t g0, int64_t g1,
-                                                int64_t eoff)
+                                                double* __restrict__ Kv)
 {
-    // rows [g0, g1); element e's matrices are slot e - eoff of Me, Ke
     constexpr int n = P + 1, n3 = n * n * n, O = 2 * P + 1, O3 = O * O * O;
     constexpr int LPR = n3 < 64 ? n3 : 64;                   // lanes per row
     constexpr int RW = 64 / LPR;                             // rows per wavefront
@@ -39,8 +37,8 @@ __global__ __launch_bounds__(256) void k_gather(PatchDev pd, RowMap rm, const do
     const int rw = (tid / 64) * RW + lane / LPR, jl = lane % LPR;
     for (int i = tid; i < 2 * RB * O3; i += 256) (&acc[0][0][0])[i] = 0.0;
     __syncthreads();
-    const int64_t g = g0 + (int64_t)blockIdx.x * RB + rw;
-    if (lane / LPR >= RW || g >= g1) return;
+    const int64_t g = (int64_t)blockIdx.x * RB + rw;
+    if (lane / LPR >= RW || g >= pd.ndof) return;
     const int Nx = pd.d[0].N, Ny = pd.d[1].N, Nz = pd.d[2].N;
     const int Kx = pd.d[0].K, Ky = pd.d[1].K, Kz = pd.d[2].K;
     const int ix = (int)(g % Nx), iy = (int)((g / Nx) % Ny), iz = (int)(g / ((int64_t)Nx * Ny));
@@ -54,7 +52,7 @@ __global__ __launch_bounds__(256) void k_gather(PatchDev pd, RowMap rm, const do
             for (int ex = elx; ex <= ehx; ++ex) {
                 const int64_t e = ex + (int64_t)Kx * (ey + (int64_t)Ky * ez);
                 const int I = (ix - ex) + n * ((iy - ey) + n * (iz - ez));
-                const int64_t row = (e - eoff) * (int64_t)n3 * n3 + (int64_t)I * n3;
+                const int64_t row = e * (int64_t)n3 * n3 + (int64_t)I * n3;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const int J = c * LPR + jl;
@@ -75,18 +73,17 @@ __global__ __launch_bounds__(256) void k_gather(PatchDev pd, RowMap rm, const do
 }
 
 int launch_gather(const PatchDev& pd, const double* Me, const double* Ke, double* Mv, double* Kv,
-                  hipStream_t st, int64_t g0, int64_t g1, int64_t eoff)
+                  hipStream_t st)
 {
     RowMap rm = make_rowmap(pd);
-    if (g1 < 0) g1 = pd.ndof;
-    if (g1 <= g0) return 0;
+    if (pd.ndof <= 0) return 0;
     switch (pd.p) {
 #define IGAF_G(PP)                                                                                  \
     case PP: {                                                                                      \
         constexpr int n3 = (PP + 1) * (PP + 1) * (PP + 1), RB = 4 * (64 / (n3 < 64 ? n3 : 64));    \
-        const int64_t blocks = (g1 - g0 + RB - 1) / RB;                                             \
+        const int64_t blocks = (pd.ndof + RB - 1) / RB;                                             \
         hipLaunchKernelGGL(k_gather<PP>, dim3((unsigned)blocks), dim3(256), 0, st, pd, rm, Me, Ke, Mv, \
-                           Kv, g0, g1, eoff);                                                       \
+                           Kv);                                                                     \
         break;                                                                                      \
     }
         IGAF_G(1)

@@ -31,8 +31,7 @@
 //
 // One 256-thread workgroup per element (grid-stride), the stages in LDS; the
 // next element's point coefficients are fetched into registers while the
-// current one is computed.  CSR outputs requested without element matrices
-// are added here with FP64 atomics at their structural positions.
+// current one is computed.
 #include "common.h"
 #include "launch.h"
 
@@ -58,17 +57,12 @@ struct GeoShape {
 // its thread on a fixed set of trial indices, folds the trial values into its
 // inputs once, and then loops over the test index, whose weighted values are
 // the same for every lane (LDS broadcast reads).
-template <int P, bool ATOMIC>
-__global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap rm,
-                                                             const double* __restrict__ cm,
+template <int P>
+__global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, const double* __restrict__ cm,
                                                              const double* __restrict__ G,
                                                              double* __restrict__ Me,
-                                                             double* __restrict__ Ke,
-                                                             double* __restrict__ Mv,
-                                                             double* __restrict__ Kv, int64_t e0,
-                                                             int64_t e1)
+                                                             double* __restrict__ Ke)
 {
-    // elements [e0, e1); element e's matrices go to slot e - e0 of Me, Ke
     using Sh = GeoShape<P>;
     constexpr int n = Sh::n, Q = Sh::Q, n3 = Sh::n3, Q3 = Sh::Q3, T = kGeoThreads;
     __shared__ double fld[Sh::NF][Q3];
@@ -79,7 +73,8 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
 
     const int tid = threadIdx.x;
     const int Kx = pd.d[0].K, Ky = pd.d[1].K;
-    const bool want_m = Me || Mv, want_k = Ke || Kv;
+    const bool want_m = Me, want_k = Ke;
+    const int64_t E = pd.E;
 
     double pf[Sh::NPF];
     auto fetch = [&](int64_t e) {
@@ -95,9 +90,9 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
             pf[r] = v;
         }
     };
-    if (e0 + blockIdx.x < e1) fetch(e0 + blockIdx.x);
+    if (blockIdx.x < E) fetch(blockIdx.x);
 
-    for (int64_t e = e0 + blockIdx.x; e < e1; e += gridDim.x) {
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const int ex = (int)(e % Kx);
         const int ey = (int)((e / Kx) % Ky);
         const int ez = (int)(e / ((int64_t)Kx * Ky));
@@ -116,7 +111,7 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
             wsc[d][1][r] = w * dN;
         }
         __syncthreads();
-        if (e + gridDim.x < e1) fetch(e + gridDim.x);
+        if (e + gridDim.x < E) fetch(e + gridDim.x);
 
         for (int a3 = 0; a3 < n; ++a3) {
             // stage z: thread on (b3, kx, ky)
@@ -186,7 +181,7 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
             __syncthreads();
             // stage x + store: thread on (a2, J), loop over the test index a1;
             // lanes run along a row, so every store is a contiguous run
-            const int64_t base = (e - e0) * Sh::n6 + (int64_t)a3 * Sh::n5;
+            const int64_t base = e * Sh::n6 + (int64_t)a3 * Sh::n5;
             for (int i = tid; i < Sh::n4; i += T) {
                 const int a2 = i / n3, J = i % n3;
                 const int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
@@ -213,11 +208,6 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
                     const int64_t at = base + (int64_t)(a2 * n + a1) * n3 + J;
                     if (Me) Me[at] = m;
                     if (Ke) Ke[at] = k;
-                    if (ATOMIC) {
-                        const int64_t pos = rm.pos(ex + a1, ey + a2, ez + a3, ex + b1, ey + b2, ez + b3);
-                        if (Mv) unsafeAtomicAdd(Mv + pos, m);
-                        if (Kv) unsafeAtomicAdd(Kv + pos, k);
-                    }
                 }
             }
             __syncthreads();
@@ -225,37 +215,27 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, RowMap
     }
 }
 
-template <int P, bool ATOMIC>
+template <int P>
 static int launch_geo_t(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
-                        double* Mv, double* Kv, int64_t e0, int64_t e1, hipStream_t st)
+                        hipStream_t st)
 {
-    const int slots = device_slots((const void*)k_element_geo<P, ATOMIC>, kGeoThreads);
+    const int slots = device_slots((const void*)k_element_geo<P>, kGeoThreads);
     if (!slots) return -3;
-    if (e1 <= e0) return 0;
-    const int64_t blocks = e1 - e0 < slots ? e1 - e0 : slots;
-    hipLaunchKernelGGL((k_element_geo<P, ATOMIC>), dim3((unsigned)blocks), dim3(kGeoThreads), 0, st, pd,
-                       make_rowmap(pd), cm, G, Me, Ke, Mv, Kv, e0, e1);
+    if (pd.E <= 0) return 0;
+    const int64_t blocks = pd.E < slots ? pd.E : slots;
+    hipLaunchKernelGGL(k_element_geo<P>, dim3((unsigned)blocks), dim3(kGeoThreads), 0, st, pd, cm, G, Me, Ke);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_element_geo(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
-                       double* Mv, double* Kv, hipStream_t st, int64_t e0, int64_t e1)
+int launch_element_geo(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke, hipStream_t st)
 {
-    const bool atomic = Mv || Kv;
-    if (e1 < 0) e1 = pd.E;
     switch (pd.p) {
-#define IGAF_GEO(PP)                                                                          \
-    case PP:                                                                                  \
-        return atomic ? launch_geo_t<PP, true>(pd, cm, G, Me, Ke, Mv, Kv, e0, e1, st)         \
-                      : launch_geo_t<PP, false>(pd, cm, G, Me, Ke, Mv, Kv, e0, e1, st);
-        IGAF_GEO(1)
-        IGAF_GEO(2)
-        IGAF_GEO(3)
-        IGAF_GEO(4)
-        IGAF_GEO(5)
-#undef IGAF_GEO
-    default:
-        return -4;
+    case 1: return launch_geo_t<1>(pd, cm, G, Me, Ke, st);
+    case 2: return launch_geo_t<2>(pd, cm, G, Me, Ke, st);
+    case 3: return launch_geo_t<3>(pd, cm, G, Me, Ke, st);
+    case 4: return launch_geo_t<4>(pd, cm, G, Me, Ke, st);
+    case 5: return launch_geo_t<5>(pd, cm, G, Me, Ke, st);
+    default: return -4;
     }
 }
 

@@ -144,10 +144,6 @@ struct igaf_plan {
     // opt-in kernel interval log of igaf_integrate_assemble (timing events)
     bool timing = false;
     std::vector<hipEvent_t> tev[2];   // [element | csr]: start, end, start, end, ...
-    // mapped-geometry CSR without stored element matrices: element matrices
-    // of a slab of element layers (allocated at the first such call)
-    double* geo_ws = nullptr;
-    int geo_ws_layers = 0;
     // Euler step: pinned slot and event for the residual read-back of CG
     double* rb_host = nullptr;
     hipEvent_t rb_ev = nullptr;
@@ -419,7 +415,6 @@ void igaf_plan_destroy(igaf_plan* plan)
     timing_clear(plan);
     (void)hipFree(plan->dmem);
     (void)hipFree(plan->dpre);
-    if (plan->geo_ws) (void)hipFree(plan->geo_ws);
     if (plan->wq_mem) (void)hipFree(plan->wq_mem);
     if (plan->rb_ev) (void)hipEventDestroy(plan->rb_ev);
     if (plan->rb_host) (void)hipHostFree(plan->rb_host);
@@ -588,80 +583,6 @@ igaf_status igaf_plan_timing(igaf_plan* plan, int32_t kernel, double* avg_ms, in
     return IGAF_OK;
 }
 
-// Degrees whose mapped-geometry CSR values have an owner-computed rows
-// kernel (all of them: p = 5 takes its stage-z products in three rounds).
-static bool geo_rows_supported(const igaf_plan* P) { return P->p <= 5; }
-
-// Mapped-geometry CSR values whose element matrices the caller does not
-// store, for the other degrees: slab by slab of z row layers, the element matrices of the element
-// layers those rows touch go to the plan's workspace (at most
-// kGeoWorkspaceBytes, allocated at the first call), and the rows are
-// gathered from it; the p element layers shared by neighbouring slabs are
-// integrated twice.  Returns 1 when no workspace can be had (too thin, or a
-// stream capture is running at the first call): the caller then adds the
-// values with atomics.
-static constexpr int64_t kGeoWorkspaceBytes = int64_t(2) << 30;
-
-// Element layers of the slab workspace that fit its cap (at most K_z), or 0
-// if fewer than the p+1 layers a slab needs (those meshes use atomics).
-static int geo_layers_for(const igaf_plan* P)
-{
-    const int64_t n6 = (int64_t)P->n * P->n * P->n * P->n * P->n * P->n;
-    const int64_t layer = (int64_t)P->K[0] * P->K[1];
-    int64_t layers = kGeoWorkspaceBytes / (layer * 2 * n6 * (int64_t)sizeof(double));
-    layers = std::min<int64_t>(layers, P->K[2]);
-    return layers < std::min(P->K[2], P->p + 1) ? 0 : (int)layers;
-}
-
-// Allocate the slab workspace (0, or -2 if the allocation failed).
-static int geo_alloc(igaf_plan* P, int layers)
-{
-    const int64_t n6 = (int64_t)P->n * P->n * P->n * P->n * P->n * P->n;
-    const int64_t layer = (int64_t)P->K[0] * P->K[1];
-    if (hipMalloc(&P->geo_ws, sizeof(double) * 2 * n6 * layer * layers) != hipSuccess) {
-        P->geo_ws = nullptr;
-        (void)hipGetLastError();
-        return -2;
-    }
-    P->geo_ws_layers = layers;
-    return 0;
-}
-
-// CSR values without stored element matrices, slab by slab of element
-// layers: 0 done, 1 use atomics (the layers exceed the workspace cap, or its
-// allocation failed), 2 refused (no workspace yet and the stream is being
-// captured: an allocation cannot be captured), -3 launch failure.
-static int geo_csr_slabs(igaf_plan* P, const double* cm, const double* G, double* Mval, double* Kval,
-                         hipStream_t s)
-{
-    const int p = P->p;
-    const int64_t n6 = (int64_t)P->n * P->n * P->n * P->n * P->n * P->n;
-    const int64_t layer = (int64_t)P->K[0] * P->K[1];   // elements per z layer
-    if (!P->geo_ws) {
-        const int layers = geo_layers_for(P);
-        if (!layers) return 1;
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 2;
-        if (geo_alloc(P, layers)) return 1;
-    }
-    const int L = P->geo_ws_layers;
-    const int T = L >= P->K[2] ? P->N[2] : L - p;   // row layers per slab
-    double* Mw = P->geo_ws;
-    double* Kw = Mw + n6 * layer * L;
-    const int64_t rowlayer = (int64_t)P->N[0] * P->N[1];
-    for (int z0 = 0; z0 < P->N[2]; z0 += T) {
-        const int z1 = std::min(P->N[2], z0 + T);
-        const int L0 = std::max(0, z0 - p), L1 = std::min(P->K[2], z1);   // element layers of the rows
-        const int64_t e0 = (int64_t)L0 * layer, e1 = (int64_t)L1 * layer;
-        if (launch_element_geo(P->dev, Mval ? cm : nullptr, Kval ? G : nullptr, Mval ? Mw : nullptr,
-                               Kval ? Kw : nullptr, nullptr, nullptr, s, e0, e1) ||
-            launch_gather(P->dev, Mval ? Mw : nullptr, Kval ? Kw : nullptr, Mval, Kval, s, z0 * rowlayer,
-                          z1 * rowlayer, e0))
-            return -3;
-    }
-    return 0;
-}
-
 igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm, const double* G,
                                         double* Me, double* Ke, double* Mval, double* Kval,
                                         void* stream)
@@ -672,12 +593,10 @@ igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm,
     if ((Me || Mval) && !cm) return fail(IGAF_EINVAL, "cm is NULL but a mass output is requested");
     if ((Ke || Kval) && !G) return fail(IGAF_EINVAL, "G is NULL but a stiffness output is requested");
     hipStream_t s = (hipStream_t)stream;
-    igaf_plan* P = const_cast<igaf_plan*>(plan);
     // dense element matrices into the caller's arrays, and the CSR values
     // that have theirs gathered from them (deterministic, no atomics)
     if (Me || Ke) {
-        st = launched(launch_element_geo(plan->dev, Me ? cm : nullptr, Ke ? G : nullptr, Me, Ke, nullptr,
-                                         nullptr, s),
+        st = launched(launch_element_geo(plan->dev, Me ? cm : nullptr, Ke ? G : nullptr, Me, Ke, s),
                       "mapped-geometry integration");
         double* gm = Mval && Me ? Mval : nullptr;
         double* gk = Kval && Ke ? Kval : nullptr;
@@ -686,35 +605,17 @@ igaf_status igaf_integrate_assemble_geo(const igaf_plan* plan, const double* cm,
         if (st) return st;
     }
     // the CSR values without stored element matrices: owner-computed rows
-    // (p <= 4), else slabs through the plan's workspace, else FP64 atomics
+    // (no workspace, no atomics)
     double* sm = Mval && !Me ? Mval : nullptr;
     double* sk = Kval && !Ke ? Kval : nullptr;
     if (!sm && !sk) return IGAF_OK;
-    if (geo_rows_supported(plan)) return launched(launch_rows_geo(plan->dev, cm, G, sm, sk, s), "mapped-geometry rows");
-    const int rc = geo_csr_slabs(P, cm, G, sm, sk, s);
-    if (rc < 0) return launched(rc, "mapped-geometry slab assembly");
-    if (rc == 0) return IGAF_OK;
-    if (rc == 2)
-        return fail(IGAF_EINVAL, "CSR-only values on a mapped geometry under stream capture need the slab "
-                                 "workspace: call igaf_geo_prepare (or the same call eagerly) first");
-    st = launched(launch_fill_zero(sm, sm ? plan->nnz : 0, s), "zero");
-    if (!st) st = launched(launch_fill_zero(sk, sk ? plan->nnz : 0, s), "zero");
-    if (!st)
-        st = launched(launch_element_geo(plan->dev, sm ? cm : nullptr, sk ? G : nullptr, nullptr, nullptr, sm,
-                                         sk, s),
-                      "mapped-geometry integration + atomic assembly");
-    return st;
+    return launched(launch_rows_geo(plan->dev, cm, G, sm, sk, s), "mapped-geometry rows");
 }
 
 igaf_status igaf_geo_prepare(igaf_plan* plan)
 {
-    igaf_status st = check_hot(plan, IGAF_SUMFACT);
-    if (st) return st;
-    if (plan->geo_ws || geo_rows_supported(plan)) return IGAF_OK;   // the rows kernel needs no workspace
-    const int layers = geo_layers_for(plan);
-    if (!layers) return IGAF_OK;   // these meshes use atomics, which need no workspace
-    if (geo_alloc(plan, layers)) return fail(IGAF_ENOMEM, "mapped-geometry slab workspace: allocation failed");
-    return IGAF_OK;
+    // the mapped-geometry paths allocate nothing: only the checks remain
+    return check_hot(plan, IGAF_SUMFACT);
 }
 
 igaf_status igaf_kappa_grad(const igaf_plan* plan, const double* u, const double* v,

@@ -48,11 +48,9 @@ int launch_rows_batch(int p, int variant, const BatchPatch* patches, const int4*
 int rows_batch_grid(int nitems, int chunk);
 int rows_tile_info(int p, int variant, int Ny, int Nz, int* ntile, double* per_elem);
 
-// CSR values gathered from stored element matrices: overwrites Mval / Kval
-// for the rows [g0, g1) (all rows by default); element e's matrices are read
-// from slot e - eoff.
+// CSR values gathered from stored element matrices: overwrites Mval / Kval.
 int launch_gather(const PatchDev& pd, const double* Me, const double* Ke, double* Mval,
-                  double* Kval, hipStream_t st, int64_t g0 = 0, int64_t g1 = -1, int64_t eoff = 0);
+                  double* Kval, hipStream_t st);
 
 int launch_fill_zero(double* a, int64_t n, hipStream_t st);
 
@@ -61,11 +59,9 @@ int launch_fill_zero(double* a, int64_t n, hipStream_t st);
 // Cached per (device, kernel); returns 0 if the device cannot be queried.
 int device_slots(const void* kernel, int threads);
 
-// element matrices (and/or atomically assembled CSR values) on a mapped
-// geometry: cm [E][q^3], G [E][6][q^3]; elements [e0, e1) (all by default),
-// element e's matrices written to slot e - e0
+// element matrices on a mapped geometry: cm [E][q^3], G [E][6][q^3]
 int launch_element_geo(const PatchDev& pd, const double* cm, const double* G, double* Me, double* Ke,
-                       double* Mv, double* Kv, hipStream_t st, int64_t e0 = 0, int64_t e1 = -1);
+                       hipStream_t st);
 // y = alphaM M(kappa) u + alphaK K(kappa) u (overwritten; no atomics: each
 // x-run of elements writes its DOF values to its slot of W, then one thread
 // per DOF sums the slots in a fixed order); with G, kappa is the mass

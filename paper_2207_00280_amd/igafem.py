@@ -391,8 +391,8 @@ class Plan:
         return work
 
     def geo_prepare(self):
-        """Allocate the slab workspace of the mapped-geometry CSR-only path now
-        (igaf_geo_prepare), so that later calls can be captured."""
+        """igaf_geo_prepare: checks the plan; the mapped-geometry calls allocate
+        nothing, so there is nothing to prepare before a capture."""
         _check(lib().igaf_geo_prepare(self._h))
 
     def apply(self, kappa, u, alphaM=1.0, alphaK=1.0, y=None, work=None, stream=None):

@@ -83,8 +83,8 @@ def test_geometry_vs_oracle(orc, ig, p, K, kind, geo):
     # with the element matrices stored the CSR values are gathered: bitwise repeatable
     _, _, Mv_b, Kv_b = plan.integrate_assemble_geo(cmd, Gd)
     assert np.array_equal(to_host(Mv_b), to_host(Mv)) and np.array_equal(to_host(Kv_b), to_host(Kv))
-    # one matrix at a time; element matrices only; CSR only (rows kernel, or
-    # slabs at p = 5): both, each alone, repeated bit for bit
+    # one matrix at a time; element matrices only; CSR only (rows kernel):
+    # both, each alone, repeated bit for bit
     Me2, Ke2, _, _ = plan.integrate_assemble_geo(cmd, None, want_k=False, want_csr=False)
     assert Ke2 is None and relfro(to_host(Me2), Me_o) <= TOL
     _, _, Mv3, Kv3 = plan.integrate_assemble_geo(None, Gd, want_m=False, want_elem=False)
