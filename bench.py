@@ -93,12 +93,13 @@ def element_src_hash():
 
 def classical_flops(p):
     """FP64 flops the classical kernel executes per element: for each of the
-    S^3 distinct (M, K) value pairs and each of the q^3 points, 4 fused
-    multiply-adds and 4 multiplies (12 flops; the inner loop of k_element<P,0>,
-    matched by the rocprofv3 FMA_F64/MUL_F64 counts)."""
+    S^3 distinct (M, K) value pairs, 3 fused multiply-adds and 2 multiplies
+    at each of the q^3 points and 1 fused multiply-add and 2 multiplies per
+    (ky, kz) point pair for the y-z factors (8 q^3 + 4 q^2 flops; the inner
+    loop of k_element<P,0>, matched by the rocprofv3 FMA_F64/MUL_F64 counts)."""
     n = q = p + 1
     S = n * (n + 1) // 2
-    return 12 * S ** 3 * q ** 3
+    return S ** 3 * (8 * q ** 3 + 4 * q ** 2)
 
 
 def counters_for_current_sources():
@@ -672,8 +673,8 @@ def main():
                                   "TFLOP/s": E * classical_flops(3) / (ms_cl * 1e-3) / 1e12,
                                   "frac_fp64": E * classical_flops(3) / (ms_cl * 1e-3) / FP64_PEAK,
                                   "dense_equivalent_flops_8n6q3": E * 8 * 4 ** 6 * 4 ** 3,
-                                  "note": "flops_executed = 12 S^3 q^3 per element (distinct values only); the "
-                                          "dense-equivalent 8 n^6 q^3 count is context, not work done"},
+                                  "note": "flops_executed = S^3 (8 q^3 + 4 q^2) per element (distinct values only); "
+                                          "the dense-equivalent 8 n^6 q^3 count is context, not work done"},
             "csr_atomic": {"ms": ms_at, "GB/s": csr_b / (ms_at * 1e-3) / 1e9},
         }
         rp_t = torch.empty(plan.ndof + 1, dtype=torch.int64, device="cuda")

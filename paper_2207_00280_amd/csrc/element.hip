@@ -76,17 +76,23 @@ __global__ __launch_bounds__(kElemThreads) void k_element(PatchDev pd, RowMap rm
                 k += wd * ca + wn * cb;
             }
         } else {
+            // the integrand at each point, with the factors of the y and z
+            // directions formed once per (ky, kz): c nx (ny nz) for M and
+            // c (dx (ny nz) + nx (dy nz + ny dz)) for K
             for (int kz = 0; kz < Q; ++kz) {
                 double nz = tw[2][0][zp * Q + kz], dz = tw[2][1][zp * Q + kz];
 #pragma unroll
                 for (int ky = 0; ky < Q; ++ky) {
                     double ny = tw[1][0][yp * Q + ky], dy = tw[1][1][yp * Q + ky];
+                    const double nyz = ny * nz, dyz = dy * nz + ny * dz;
 #pragma unroll
                     for (int kx = 0; kx < Q; ++kx) {
                         double c = kap[kx + Q * (ky + Q * kz)];
                         double nx = tw[0][0][xp * Q + kx], dx = tw[0][1][xp * Q + kx];
-                        m += c * nx * ny * nz;
-                        k += c * (dx * ny * nz + nx * dy * nz + nx * ny * dz);
+                        const double cn = c * nyz;
+                        m += cn * nx;
+                        k += cn * dx;
+                        k += (c * dyz) * nx;
                     }
                 }
             }
