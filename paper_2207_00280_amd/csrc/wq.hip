@@ -293,7 +293,8 @@ __global__ __launch_bounds__(256) void k_wq_pencil(WqDev w, RowMap rm, const dou
                 const double tn = T23[(0 * 2 + 0) * O * PW + o * PW + q2];
                 const double td = T23[(0 * 2 + 1) * O * PW + o * PW + q2];
                 c0[o] += tn * dn;
-                c1[o] += td * dn + tn * dd;
+                c1[o] += td * dn;
+                c1[o] += tn * dd;
             }
         }
 #pragma unroll
@@ -323,7 +324,8 @@ __global__ __launch_bounds__(256) void k_wq_pencil(WqDev w, RowMap rm, const dou
 #pragma unroll
             for (int o = 0; o < O; ++o) {
                 m[o] += tn[o * PW + q1] * av;
-                k[o] += td[o * PW + q1] * av + tn[o * PW + q1] * bv;
+                k[o] += td[o * PW + q1] * av;
+                k[o] += tn[o * PW + q1] * bv;
             }
         }
         const int bl1 = band_lo(i1, P), Lx = band_len(i1, P, rm.N[0]);
