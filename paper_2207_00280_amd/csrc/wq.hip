@@ -205,12 +205,13 @@ struct WqShape {
 };
 
 // LDS doubles of the pencil kernel: T1 [2][R][O][PW] (the rows' x tables),
-// T23 [2 dirs][2][O][PW], C [2][O][O][NX]
+// T23 [2 dirs][2][O][PW], C [2][O][O][NX], KB [PW][PW][NX] (kappa of the
+// chunk's point box)
 template <int P>
 static int64_t wq_lds_doubles(int R, int PW, int NX)
 {
     constexpr int O = WqShape<P>::O;
-    return 2LL * R * O * PW + 4LL * O * PW + 2LL * O * O * NX;
+    return 2LL * R * O * PW + 4LL * O * PW + 2LL * O * O * NX + (int64_t)PW * PW * NX;
 }
 
 // One workgroup per (chunk of R rows along x, i2, i3): the rows (i1, i2,
@@ -237,6 +238,7 @@ __global__ __launch_bounds__(256) void k_wq_pencil(WqDev w, RowMap rm, const dou
     double* const T1 = sm;                          // [2][R][O][PW]
     double* const T23 = T1 + 2 * R * O * PW;        // [dir 0 = y, 1 = z][2][O][PW]
     double* const C = T23 + 4 * O * PW;             // [2][O][O][NXM]
+    double* const KB = C + 2 * O * O * NXM;         // [q3][q2][x], strides PW, NXM
     const int N1 = w.d[0].N, N2 = w.d[1].N;
     const int np1 = w.d[0].npts, np2 = w.d[1].npts;
     const int nch = (N1 + R - 1) / R;
@@ -270,12 +272,18 @@ __global__ __launch_bounds__(256) void k_wq_pencil(WqDev w, RowMap rm, const dou
             T1[(1 * R + t - 2) * O * PW + o * PW + q] = vd;
         }
     }
+    // kappa of the chunk's point box, read once (consecutive x in
+    // consecutive lanes): every stage-z thread of an x shares it
+    const int64_t zs = (int64_t)np2 * np1;
+    for (int idx = tid; idx < c3 * c2 * NX; idx += 256) {
+        const int x = idx % NX, q2 = (idx / NX) % c2, q3 = idx / (NX * c2);
+        KB[(q3 * PW + q2) * NXM + x] = kappa[((int64_t)lo3 + q3) * zs + (int64_t)(lo2 + q2) * np1 + X0 + x];
+    }
     __syncthreads();
     // stages z and y: item (x, o3), consecutive x in consecutive lanes
-    const int64_t zs = (int64_t)np2 * np1;
     for (int it = tid; it < NX * O; it += 256) {
         const int x = it % NX, o3 = it / NX;
-        const double* kp = kappa + ((int64_t)lo3 * np2 + lo2) * np1 + X0 + x;
+        const double* kp = KB + x;
         const double* t3n = T23 + (1 * 2 + 0) * O * PW + o3 * PW;
         const double* t3d = T23 + (1 * 2 + 1) * O * PW + o3 * PW;
         double c0[O], c1[O];
@@ -284,7 +292,7 @@ __global__ __launch_bounds__(256) void k_wq_pencil(WqDev w, RowMap rm, const dou
         for (int q2 = 0; q2 < c2; ++q2) {
             double dn = 0.0, dd = 0.0;
             for (int q3 = 0; q3 < c3; ++q3) {
-                const double k = kp[q2 * np1 + q3 * zs];
+                const double k = kp[(q3 * PW + q2) * NXM];
                 dn += t3n[q3] * k;
                 dd += t3d[q3] * k;
             }
