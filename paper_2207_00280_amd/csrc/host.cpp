@@ -16,6 +16,7 @@
 #include "batch.h"
 #include "common.h"
 #include "launch.h"
+#include "wq.h"
 
 using namespace igaf;
 
@@ -712,11 +713,12 @@ igaf_status igaf_wq_prepare(igaf_plan* plan)
         if (rc) return fail(IGAF_EUNSUPPORTED, "weighted quadrature: a rule's system is singular (direction %d)", d);
     }
     const int PW = std::max(H[0].PW, std::max(H[1].PW, H[2].PW));
-    // one buffer: per direction w00 | w11 (N x PW) | Bv | dB (npts x n) doubles, then lo | cnt | eq ints
-    const int n = plan->p + 1;
+    // one buffer: per direction w00 | w11 (N x PW) | Bv | dB (npts x n) |
+    // TN | TD (N x O x PW) doubles, then lo | cnt | eq ints
+    const int n = plan->p + 1, O = 2 * plan->p + 1;
     int64_t nd = 0, ni = 0;
     for (int d = 0; d < 3; ++d) {
-        nd += 2LL * H[d].N * PW + 2LL * H[d].npts * n;
+        nd += 2LL * H[d].N * PW + 2LL * H[d].npts * n + 2LL * H[d].N * O * PW;
         ni += 2LL * H[d].N + H[d].npts;
     }
     std::vector<double> hd((size_t)nd, 0.0);
@@ -745,6 +747,25 @@ igaf_status igaf_wq_prepare(igaf_plan* plan)
         std::copy(h.dB.begin(), h.dB.end(), hd.begin() + od);
         w.d[d].dB = dd + od;
         od += (int64_t)h.npts * n;
+        // TN, TD: the weighted test value times the trial value of the column
+        // j = g + o - p at each point of g's support (zero outside the patch
+        // and where x_q is outside supp(B_j))
+        const int64_t otn = od, otd = od + (int64_t)h.N * O * PW;
+        for (int g = 0; g < h.N; ++g)
+            for (int o = 0; o < O; ++o) {
+                const int j = g + o - plan->p;
+                if (j < 0 || j >= h.N) continue;
+                for (int q = 0; q < h.cnt[g]; ++q) {
+                    const int pt = h.lo[g] + q, a = j - h.eq[pt];
+                    if (a < 0 || a >= n) continue;
+                    const size_t at = ((size_t)g * O + o) * PW + q;
+                    hd[otn + at] = h.w00[(size_t)g * h.PW + q] * h.Bv[(size_t)pt * n + a];
+                    hd[otd + at] = h.w11[(size_t)g * h.PW + q] * h.dB[(size_t)pt * n + a];
+                }
+            }
+        w.d[d].TN = dd + otn;
+        w.d[d].TD = dd + otd;
+        od += 2LL * h.N * O * PW;
         std::copy(h.lo.begin(), h.lo.end(), hi.begin() + oi);
         w.d[d].lo = di + oi;
         oi += h.N;

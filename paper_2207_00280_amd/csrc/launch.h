@@ -5,8 +5,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <vector>
-
 #include "common.h"
 
 namespace igaf {
@@ -94,44 +92,5 @@ int launch_kappa_grad(const PatchDev& pd, const double* u, const double* v, doub
 constexpr int kLossParts = 4096;
 int launch_bilinear(const PatchDev& pd, const double* kappa, const double* u, const double* v, double alphaM,
                     double alphaK, double* L, double* part, hipStream_t st);
-
-// ---- weighted quadrature
-constexpr int kWqMaxP = 5;
-
-// The rules of one direction on the host: points x (npts) with their
-// element eq; per function g the points inside its support are
-// [lo[g], lo[g] + cnt[g]) and its weights w00/w11[g * PW + q]; the trial
-// values Bv/dB[q * (p+1) + a] of the functions eq[q] + a at every point.
-struct WqHost {
-    std::vector<double> x, w00, w11, Bv, dB;
-    std::vector<int> eq, lo, cnt;
-    int N = 0, npts = 0, PW = 0;
-};
-// Build them from the knots t and the plan's Gauss nodes/weights xg, wg
-// ([K][p+1], for the exact integrals).  0, -1 (an element of zero length) or
-// -2 (a rule's system is singular).
-int wq_build_dir(int p, int K, const double* t, const double* xg, const double* wg, WqHost& out);
-
-// The same tables in device memory (w00, w11 padded to the common width PW)
-struct WqDir {
-    const double* w00;
-    const double* w11;
-    const double* Bv;
-    const double* dB;
-    const int* lo;
-    const int* cnt;
-    const int* eq;
-    int N, npts;
-};
-struct WqDev {
-    WqDir d[3];
-    int PW;
-    const int* h_lo0;    // HOST copies of direction x's lo and cnt (launch sizing)
-    const int* h_cnt0;
-};
-// CSR values (overwritten; either output may be null) by weighted
-// quadrature, kappa [npts_z][npts_y][npts_x]; -4 if the LDS of a row exceeds
-// the CU's.
-int launch_wq(const WqDev& w, const PatchDev& pd, const double* kappa, double* Mv, double* Kv, hipStream_t st);
 
 }  // namespace igaf

@@ -31,6 +31,7 @@
 
 #include "common.h"
 #include "launch.h"
+#include "wq.h"
 
 namespace igaf {
 
@@ -232,7 +233,7 @@ __global__ __launch_bounds__(256) void k_wq_pencil(WqDev w, RowMap rm, const dou
                                                    int NXM)
 {
     using S = WqShape<P>;
-    constexpr int O = S::O, n = S::n;
+    constexpr int O = S::O;
     extern __shared__ double sm[];
     const int PW = w.PW, tid = threadIdx.x;
     double* const T1 = sm;                          // [2][R][O][PW]
@@ -249,21 +250,14 @@ __global__ __launch_bounds__(256) void k_wq_pencil(WqDev w, RowMap rm, const dou
     const int NX = w.d[0].lo[r0 + nr - 1] + w.d[0].cnt[r0 + nr - 1] - X0;
     const int lo2 = w.d[1].lo[i2], c2 = w.d[1].cnt[i2];
     const int lo3 = w.d[2].lo[i3], c3 = w.d[2].cnt[i3];
-    // weighted test values times trial values: the y and z tables of the
-    // pencil, the x tables of every row of the chunk
+    // weighted test values times trial values (the plan's TN, TD): the y and
+    // z tables of the pencil, the x tables of every row of the chunk
     for (int idx = tid; idx < (2 + nr) * O * PW; idx += 256) {
-        const int t = idx / (O * PW), o = (idx / PW) % O, q = idx % PW;
+        const int t = idx / (O * PW), r = idx % (O * PW);
         const int d = t < 2 ? t + 1 : 0;
         const int ii = t == 0 ? i2 : (t == 1 ? i3 : r0 + t - 2);
-        const int j = ii + o - P;
-        double vn = 0.0, vd = 0.0;
-        if (q < w.d[d].cnt[ii] && j >= 0 && j < w.d[d].N) {
-            const int pt = w.d[d].lo[ii] + q, a = j - w.d[d].eq[pt];
-            if (a >= 0 && a < n) {
-                vn = w.d[d].w00[(int64_t)ii * PW + q] * w.d[d].Bv[(int64_t)pt * n + a];
-                vd = w.d[d].w11[(int64_t)ii * PW + q] * w.d[d].dB[(int64_t)pt * n + a];
-            }
-        }
+        const int o = r / PW, q = r % PW;
+        const double vn = w.d[d].TN[(int64_t)ii * O * PW + r], vd = w.d[d].TD[(int64_t)ii * O * PW + r];
         if (t < 2) {
             T23[(t * 2 + 0) * O * PW + o * PW + q] = vn;
             T23[(t * 2 + 1) * O * PW + o * PW + q] = vd;
