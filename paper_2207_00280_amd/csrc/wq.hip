@@ -205,14 +205,13 @@ struct WqShape {
     static constexpr int O = 2 * P + 1, n = P + 1;
 };
 
-// LDS doubles of the pencil kernel: T1 [2][R][O][PW] (the rows' x tables),
-// T23 [2 dirs][2][O][PW], C [2][O][O][NX], KB [PW][PW][NX] (kappa of the
-// chunk's point box)
+// LDS doubles of the pencil kernel: T23 [2 dirs][2][O][PW], C [2][O][O][NX],
+// KB [PW][PW][NX] (kappa of the chunk's point box)
 template <int P>
-static int64_t wq_lds_doubles(int R, int PW, int NX)
+static int64_t wq_lds_doubles(int PW, int NX)
 {
     constexpr int O = WqShape<P>::O;
-    return 2LL * R * O * PW + 4LL * O * PW + 2LL * O * O * NX + (int64_t)PW * PW * NX;
+    return 4LL * O * PW + 2LL * O * O * NX + (int64_t)PW * PW * NX;
 }
 
 // One workgroup per (chunk of R rows along x, i2, i3): the rows (i1, i2,
@@ -236,8 +235,7 @@ __global__ __launch_bounds__(256) void k_wq_pencil(WqDev w, RowMap rm, const dou
     constexpr int O = S::O;
     extern __shared__ double sm[];
     const int PW = w.PW, tid = threadIdx.x;
-    double* const T1 = sm;                          // [2][R][O][PW]
-    double* const T23 = T1 + 2 * R * O * PW;        // [dir 0 = y, 1 = z][2][O][PW]
+    double* const T23 = sm;                         // [dir 0 = y, 1 = z][2][O][PW]
     double* const C = T23 + 4 * O * PW;             // [2][O][O][NXM]
     double* const KB = C + 2 * O * O * NXM;         // [q3][q2][x], strides PW, NXM
     const int N1 = w.d[0].N, N2 = w.d[1].N;
@@ -251,20 +249,12 @@ __global__ __launch_bounds__(256) void k_wq_pencil(WqDev w, RowMap rm, const dou
     const int lo2 = w.d[1].lo[i2], c2 = w.d[1].cnt[i2];
     const int lo3 = w.d[2].lo[i3], c3 = w.d[2].cnt[i3];
     // weighted test values times trial values (the plan's TN, TD): the y and
-    // z tables of the pencil, the x tables of every row of the chunk
-    for (int idx = tid; idx < (2 + nr) * O * PW; idx += 256) {
+    // z tables of the pencil (stage x reads its rows' own as scalars)
+    for (int idx = tid; idx < 2 * O * PW; idx += 256) {
         const int t = idx / (O * PW), r = idx % (O * PW);
-        const int d = t < 2 ? t + 1 : 0;
-        const int ii = t == 0 ? i2 : (t == 1 ? i3 : r0 + t - 2);
-        const int o = r / PW, q = r % PW;
-        const double vn = w.d[d].TN[(int64_t)ii * O * PW + r], vd = w.d[d].TD[(int64_t)ii * O * PW + r];
-        if (t < 2) {
-            T23[(t * 2 + 0) * O * PW + o * PW + q] = vn;
-            T23[(t * 2 + 1) * O * PW + o * PW + q] = vd;
-        } else {
-            T1[(0 * R + t - 2) * O * PW + o * PW + q] = vn;
-            T1[(1 * R + t - 2) * O * PW + o * PW + q] = vd;
-        }
+        const int ii = t == 0 ? i2 : i3;
+        T23[(t * 2 + 0) * O * PW + r] = w.d[t + 1].TN[(int64_t)ii * O * PW + r];
+        T23[(t * 2 + 1) * O * PW + r] = w.d[t + 1].TD[(int64_t)ii * O * PW + r];
     }
     // kappa of the chunk's point box, read once (consecutive x in
     // consecutive lanes): every stage-z thread of an x shares it
@@ -306,16 +296,23 @@ __global__ __launch_bounds__(256) void k_wq_pencil(WqDev w, RowMap rm, const dou
         }
     }
     __syncthreads();
-    // stage x: item (row, o2, o3); the row's O values of (o2, o3) go out
+    // stage x: each wavefront takes one row at a time, lanes on (o2, o3)
+    // (ceil(O^2 / 64) wavefront passes per row), so that the row's own
+    // tables TN, TD are the same in every lane (scalar operands); the row's
+    // O values of (o2, o3) go out
+    constexpr int WPR = (O * O + 63) / 64;
     const int bl2 = band_lo(i2, P), bl3 = band_lo(i3, P);
     const int Ly = band_len(i2, P, rm.N[1]);
-    for (int it = tid; it < nr * O * O; it += 256) {
-        const int o2 = it % O, o3 = (it / O) % O, r = it / (O * O);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
+    for (int sl = wv; sl < nr * WPR; sl += 4) {
+        const int r = sl / WPR, it = (sl % WPR) * 64 + lane;
+        if (it >= O * O) continue;
+        const int o2 = it % O, o3 = it / O;
         const int i1 = r0 + r, j2 = i2 + o2 - P, j3 = i3 + o3 - P;
         if (j2 < 0 || j2 >= rm.N[1] || j3 < 0 || j3 >= rm.N[2]) continue;
         const int xo = w.d[0].lo[i1] - X0, c1n = w.d[0].cnt[i1];
-        const double* tn = T1 + (0 * R + r) * O * PW;
-        const double* td = T1 + (1 * R + r) * O * PW;
+        const ctab tn = as_ctab(w.d[0].TN) + (int64_t)i1 * O * PW;
+        const ctab td = as_ctab(w.d[0].TD) + (int64_t)i1 * O * PW;
         const double* a = C + ((0 * O + o2) * O + o3) * NXM + xo;
         const double* b = C + ((1 * O + o2) * O + o3) * NXM + xo;
         double m[O], k[O];
@@ -356,7 +353,7 @@ static int launch_wq_t(const WqDev& w, const PatchDev& pd, const double* kappa, 
             const int rl = std::min(N1, r0 + R) - 1;
             NXM = std::max(NXM, w.h_lo0[rl] + w.h_cnt0[rl] - w.h_lo0[r0]);
         }
-        const int64_t lds = wq_lds_doubles<P>(R, w.PW, NXM) * (int64_t)sizeof(double);
+        const int64_t lds = wq_lds_doubles<P>(w.PW, NXM) * (int64_t)sizeof(double);
         if (lds > 160 * 1024) continue;
         if (hipFuncSetAttribute((const void*)k_wq_pencil<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
             hipSuccess)
