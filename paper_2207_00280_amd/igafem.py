@@ -5,6 +5,7 @@ kernels of the library; torch provides device memory and streams.  Importing
 this module loads the library and raises if it has not been built; the
 integration calls raise if no GPU is present.  There is no CPU fallback.
 """
+import contextlib
 import ctypes
 import os
 
@@ -277,8 +278,12 @@ class Plan:
     def csr_pattern(self, row_ptr=None, col=None, stream=None):
         """The structural CSR pattern into (new, or the given) device arrays."""
         torch = _torch()
-        rp = torch.empty(self.ndof + 1, dtype=torch.int64, device="cuda") if row_ptr is None else row_ptr
-        col = torch.empty(self.nnz, dtype=torch.int32, device="cuda") if col is None else col
+        with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
+            if row_ptr is None:
+                row_ptr = torch.empty(self.ndof + 1, dtype=torch.int64, device="cuda")
+            if col is None:
+                col = torch.empty(self.nnz, dtype=torch.int32, device="cuda")
+        rp = row_ptr
         _check(lib().igaf_csr_pattern(self._h, _ptr(rp), _ptr(col), _stream(stream)))
         return rp, col
 
@@ -297,9 +302,9 @@ class Plan:
         _need_f64_cuda(kappa, "kappa", self.nelem * self.nqp)
         n3 = self.elem_dim
         if want_m and Me is None:
-            Me = self._alloc(self.nelem, n3, n3)
+            Me = self._alloc(self.nelem, n3, n3, stream=stream)
         if want_k and Ke is None:
-            Ke = self._alloc(self.nelem, n3, n3)
+            Ke = self._alloc(self.nelem, n3, n3, stream=stream)
         Me = Me if want_m else None
         Ke = Ke if want_k else None
         for t, nm in ((Me, "Me"), (Ke, "Ke")):
@@ -311,9 +316,9 @@ class Plan:
 
     def assemble(self, Me, Ke, Mval=None, Kval=None, stream=None):
         if Me is not None and Mval is None:
-            Mval = self._alloc(self.nnz)
+            Mval = self._alloc(self.nnz, stream=stream)
         if Ke is not None and Kval is None:
-            Kval = self._alloc(self.nnz)
+            Kval = self._alloc(self.nnz, stream=stream)
         _check(lib().igaf_assemble(self._h, _ptr(Me), _ptr(Ke), _ptr(Mval), _ptr(Kval),
                                    _stream(stream)))
         return Mval, Kval
@@ -324,14 +329,14 @@ class Plan:
         n3 = self.elem_dim
         if want_elem:
             if want_m and Me is None:
-                Me = self._alloc(self.nelem, n3, n3)
+                Me = self._alloc(self.nelem, n3, n3, stream=stream)
             if want_k and Ke is None:
-                Ke = self._alloc(self.nelem, n3, n3)
+                Ke = self._alloc(self.nelem, n3, n3, stream=stream)
         if want_csr:
             if want_m and Mval is None:
-                Mval = self._alloc(self.nnz)
+                Mval = self._alloc(self.nnz, stream=stream)
             if want_k and Kval is None:
-                Kval = self._alloc(self.nnz)
+                Kval = self._alloc(self.nnz, stream=stream)
         Me = Me if (want_elem and want_m) else None
         Ke = Ke if (want_elem and want_k) else None
         Mval = Mval if (want_csr and want_m) else None
@@ -356,14 +361,14 @@ class Plan:
         n3 = self.elem_dim
         if want_elem:
             if want_m and Me is None:
-                Me = self._alloc(self.nelem, n3, n3)
+                Me = self._alloc(self.nelem, n3, n3, stream=stream)
             if want_k and Ke is None:
-                Ke = self._alloc(self.nelem, n3, n3)
+                Ke = self._alloc(self.nelem, n3, n3, stream=stream)
         if want_csr:
             if want_m and Mval is None:
-                Mval = self._alloc(self.nnz)
+                Mval = self._alloc(self.nnz, stream=stream)
             if want_k and Kval is None:
-                Kval = self._alloc(self.nnz)
+                Kval = self._alloc(self.nnz, stream=stream)
         Me = Me if (want_elem and want_m) else None
         Ke = Ke if (want_elem and want_k) else None
         Mval = Mval if (want_csr and want_m) else None
@@ -478,7 +483,7 @@ class Plan:
         _need_f64_cuda(u, "u", self.ndof)
         _need_f64_cuda(v, "v", self.ndof)
         if grad is None:
-            grad = self._alloc(self.nelem, self.nqp)
+            grad = self._alloc(self.nelem, self.nqp, stream=stream)
         _need_f64_cuda(grad, "grad", self.nelem * self.nqp)
         _check(lib().igaf_kappa_grad_geo(self._h, _ptr(cm0), _ptr(G0), _ptr(u), _ptr(v), float(alphaM),
                                          float(alphaK), float(scale), _ptr(grad), _stream(stream)))
