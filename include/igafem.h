@@ -122,6 +122,17 @@ igaf_status igaf_desc_check(const igaf_patch_desc* desc);
 igaf_status igaf_desc_sizes(const igaf_patch_desc* desc, int64_t* ndof, int64_t* nelem,
                             int64_t* nqp, int64_t* elem_dim, int64_t* nnz);
 
+/* The run of elements of direction `dir` (0..2) whose basis tables the plan
+ * shares (Sec. 2.3: the values on an element depend only on the 2p knots
+ * around its span, relative to the span): the longest run [*first, *end) of
+ * consecutive elements whose knot differences t[e+j] - t[e+p], j = 1..2p,
+ * agree with those of element *first up to 8 eps times the largest knot
+ * involved.  A plan gives every element of the run the tables computed for
+ * element *first, bit for bit (uniform spacing: all elements but the p - 1
+ * nearest each end).  *first = *end = 0 when no two neighbours agree.
+ * Returns IGAF_EINVAL for a bad description, dir or NULL output. */
+igaf_status igaf_desc_shared_run(const igaf_patch_desc* desc, int dir, int* first, int* end);
+
 /* The structural CSR pattern computed on the host into HOST arrays
  * row_ptr_host[ndof+1], col_idx_host[nnz]. */
 igaf_status igaf_csr_pattern_host(const igaf_patch_desc* desc, int64_t* row_ptr_host,

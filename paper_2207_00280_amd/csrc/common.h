@@ -11,6 +11,14 @@
 //   pre[i]       = sum_{i' < i} L(i'),  L(i) = min(N-1, i+p) - max(0, i-p) + 1
 // with x_k the Gauss nodes mapped to element e.  Pair products depend only on
 // the unordered pair {a, b}, so S = (p+1)(p+2)/2 of them are stored.
+//
+// The values on an element depend only on its local knot window taken
+// relative to the element (Sec. 2.3: the recursion reads the 2p knots around
+// the span).  The elements [r0, r1) of a direction, a run whose windows agree
+// up to the rounding of the knots (uniform spacing), all hold the tables
+// computed for element r0, bit for bit; kernels that address the tables per
+// element may read r0's copy for the whole run, which keeps the tables a
+// workgroup touches in a few cache lines.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,7 +43,11 @@ struct DirTables {
     const double* Lm;     // [N][p+2]: 1/L_ii, L_{i,i-1..i-p}, M_ii of the 1D mass (kappa = 1)
     const int64_t* pre;   // [N+1]
     int K, N, Q;
+    int r0, r1;           // elements [r0, r1) hold the tables of element r0 (r0 = r1: none)
 };
+
+// the element whose copy of the tables element e may read
+__host__ __device__ inline int tab_elem(int e, int r0, int r1) { return e >= r0 && e < r1 ? r0 : e; }
 
 struct PatchDev {
     DirTables d[3];

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <string>
 #include <vector>
@@ -130,6 +131,41 @@ void sizes_of(const igaf_patch_desc* d, int64_t* ndof, int64_t* nelem, int64_t* 
     if (nnz) *nnz = T;
 }
 
+// The longest run [r0, r1) of consecutive elements of one direction whose
+// local knot windows agree: the values on span s = e+p depend on the 2p knots
+// t_{e+1} .. t_{e+2p} only through their differences to the span's left end
+// t_{e+p} (the recursion of Sec. 2.3), so element e may take the tables of r0
+// when every difference t_{e+j} - t_{e+p} equals r0's up to the rounding of
+// the knots (8 eps times the largest knot involved).  Uniform spacing gives
+// one run over all elements away from the repeated end knots; r0 = r1 = 0
+// when no two neighbours agree.
+void shared_run(const double* t, int K, int p, int* r0, int* r1)
+{
+    const double eps = std::numeric_limits<double>::epsilon();
+    auto same = [&](int e, int r) {
+        for (int j = 1; j <= 2 * p; ++j) {
+            const double de = t[e + j] - t[e + p], dr = t[r + j] - t[r + p];
+            const double sc = std::max(std::max(std::fabs(t[e + j]), std::fabs(t[e + p])),
+                                       std::max(std::fabs(t[r + j]), std::fabs(t[r + p])));
+            if (!(std::fabs(de - dr) <= 8.0 * eps * sc)) return false;
+        }
+        return true;
+    };
+    int best0 = 0, best1 = 0;
+    for (int s = 0; s < K;) {
+        int e = s + 1;
+        while (e < K && same(e, s)) ++e;
+        if (e - s > best1 - best0) {
+            best0 = s;
+            best1 = e;
+        }
+        s = e;
+    }
+    if (best1 - best0 < 2) best0 = best1 = 0;
+    *r0 = best0;
+    *r1 = best1;
+}
+
 }  // namespace
 
 struct igaf_plan {
@@ -209,6 +245,16 @@ igaf_status igaf_desc_sizes(const igaf_patch_desc* desc, int64_t* ndof, int64_t*
     igaf_status st = check_desc(desc);
     if (st) return st;
     sizes_of(desc, ndof, nelem, nqp, elem_dim, nnz);
+    return IGAF_OK;
+}
+
+igaf_status igaf_desc_shared_run(const igaf_patch_desc* desc, int dir, int* first, int* end)
+{
+    igaf_status st = check_desc(desc);
+    if (st) return st;
+    if (dir < 0 || dir > 2) return fail(IGAF_EINVAL, "dir %d outside [0, 2]", dir);
+    if (!first || !end) return fail(IGAF_EINVAL, "first / end is NULL");
+    shared_run(desc->knots[dir], desc->nelem[dir], desc->degree, first, end);
     return IGAF_OK;
 }
 
@@ -390,10 +436,11 @@ igaf_status igaf_plan_create(const igaf_patch_desc* desc, igaf_plan** out)
         D.K = K;
         D.N = N;
         D.Q = Q;
+        shared_run(t, K, P->p, &D.r0, &D.r1);
         ioff += N + 1;
         if (launch_basis_tables(P->p, base + off[a][0], K, base + off[a][1], base + off[a][2], Q,
                                 base + off[a][3], base + off[a][4], base + off[a][5],
-                                base + off[a][6], base + off[a][7], base + off[a][9], nullptr) != 0)
+                                base + off[a][6], base + off[a][7], base + off[a][9], D.r0, D.r1, nullptr) != 0)
             rc = fail(IGAF_EDEVICE, "basis-table launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
     if (rc == IGAF_OK && hipStreamSynchronize(nullptr) != hipSuccess)

@@ -11,7 +11,7 @@ namespace igaf {
 
 int launch_basis_tables(int p, const double* t, int K, const double* xi, const double* wr, int Q,
                         double* Wnn, double* Wdd, double* Nv, double* dN, double* wq, double* Wg,
-                        hipStream_t st);
+                        int r0, int r1, hipStream_t st);
 
 int launch_csr_pattern(const PatchDev& pd, int64_t* row_ptr, int32_t* col, hipStream_t st);
 

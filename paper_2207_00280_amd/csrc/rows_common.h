@@ -39,7 +39,18 @@ struct TileCtx {
     int64_t T0, T1;   // structural entries of one direction's 1D pattern
     int Kx, Ky, Kz, Nx, Ny, Nz;
     int iy0, iz0;
+    int rx0, rx1, ry0, ry1, rz0, rz1;   // per direction: elements [r0, r1) read the tables of r0
 };
+
+__device__ inline void tile_runs(TileCtx& c, const PatchDev& pd)
+{
+    c.rx0 = pd.d[0].r0;
+    c.rx1 = pd.d[0].r1;
+    c.ry0 = pd.d[1].r0;
+    c.ry1 = pd.d[1].r1;
+    c.rz0 = pd.d[2].r0;
+    c.rz1 = pd.d[2].r1;
+}
 
 // ---- stage x: thread xi = (stage-x wavefront)*64 + lane owns combo (pen, oy, oz)
 template <class T>

@@ -173,7 +173,7 @@ __device__ __forceinline__ void gz_unit(const GeoCtx& g, int item, const double 
         for (int e = 0; e <= P; ++e) {
             const int ez = iz - P + e;
             if (ez < 0 || ez >= c.Kz) continue;   // wave-uniform
-            const ctab tb = g.Wz + (int64_t)ez * T::TBE;   // test index P - e, trial bb
+            const ctab tb = g.Wz + (int64_t)tab_elem(ez, c.rz0, c.rz1) * T::TBE;   // test index P - e, trial bb
             double gv[3][Q];
 #pragma unroll
             for (int j = 0; j < 3; ++j)
@@ -251,7 +251,7 @@ __device__ __forceinline__ void gz_stream(const GeoCtx& g, int item, int ex, dou
         for (int e = 0; e <= P; ++e) {
             const int ez = iz - P + e;
             if (ez < 0 || ez >= c.Kz) continue;   // wave-uniform
-            const ctab tb = g.Wz + (int64_t)ez * T::TBE;
+            const ctab tb = g.Wz + (int64_t)tab_elem(ez, c.rz0, c.rz1) * T::TBE;
             double gv[3][Q];
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
@@ -296,7 +296,7 @@ __device__ __forceinline__ void gy_unit(const GeoCtx& g, int yr, int item, const
     for (int e = 0; e <= P; ++e) {
         const int ey = iy - P + e;
         if (ey < 0 || ey >= c.Ky) continue;   // wave-uniform
-        const ctab tb = g.Wy + (int64_t)ey * T::TBE;
+        const ctab tb = g.Wy + (int64_t)tab_elem(ey, c.ry0, c.ry1) * T::TBE;
         const ctab wN = tb + (P - e) * Q, wD = tb + Q2 + (P - e) * Q;
         const ctab Nb = tb + 2 * Q2, Db = tb + 3 * Q2;
         const double* dp = D + zr * T::DZR + oz * T::DOZ + (yr + e) * Q2 + kx;
@@ -388,7 +388,7 @@ __device__ __forceinline__ void gy_round(const GeoCtx& g, int yr, int item, cons
         for (int e = 0; e <= P; ++e) {
             const int ey = iy - P + e;
             if (ey < 0 || ey >= c.Ky) continue;   // wave-uniform
-            const ctab tb = g.Wy + (int64_t)ey * T::TBE;
+            const ctab tb = g.Wy + (int64_t)tab_elem(ey, c.ry0, c.ry1) * T::TBE;
             const ctab wN = tb + (P - e) * Q, wD = tb + Q2 + (P - e) * Q;
             const ctab Nb = tb + 2 * Q2, Db = tb + 3 * Q2;
             const double* dp = D + zr * T::DZR + oz * T::DOZ + (yr + e) * Q2 + kx;
@@ -462,7 +462,7 @@ __device__ __forceinline__ void gx_step(const GeoCtx& g, const XThread<T>& xt, d
 {
     constexpr int P = T::P, Q = T::Q, O = T::O, Q2 = T::Q2, G = T::G;
     if (elem) {
-        const ctab tb = g.Wx + (int64_t)r * T::TBE;
+        const ctab tb = g.Wx + (int64_t)tab_elem(r, g.c.rx0, g.c.rx1) * T::TBE;
         double cM[Q], cN[Q], cD[Q], cDN[Q], cND[Q];
         const double* cp = C + xt.pen * T::CP + xt.oy * O + xt.oz;
 #pragma unroll
@@ -682,6 +682,7 @@ __device__ __forceinline__ void geo_tile_run(const PatchDev& pd, const RowMap& r
     c.Nz = pd.d[2].N;
     c.iy0 = (tile % nty) * T::TY;
     c.iz0 = (tile / nty) * T::TZ;
+    tile_runs(c, pd);
     g.cm = Mv ? cm : nullptr;
     g.G = Kv ? G : nullptr;
     g.Wx = as_ctab(pd.d[0].Wg);

@@ -174,7 +174,8 @@ __device__ __forceinline__ void z_stage(const TileCtx& c, const ZThread<T>& zt, 
 #pragma unroll
             for (int k = 0; k < Q; ++k) kz[k] = kp[Q2 * k];
         }
-        const ctab wnE = wnz + (int64_t)ez * (S * Q), wdE = wdz + (int64_t)ez * (S * Q);
+        const int et = tab_elem(ez, c.rz0, c.rz1);
+        const ctab wnE = wnz + (int64_t)et * (S * Q), wdE = wdz + (int64_t)et * (S * Q);
 #pragma unroll
         for (int bb = 0; bb <= P; ++bb) {
             const int sp = pair_index(P - e, bb);
@@ -225,7 +226,8 @@ __device__ __forceinline__ void y_stage(const TileCtx& c, int w, int lane, const
             a[k] = dp[k * Q];
             b[k] = dp[T::DT + k * Q];
         }
-        const ctab wnE = wny + (int64_t)ey * (S * Q), wdE = wdy + (int64_t)ey * (S * Q);
+        const int et = tab_elem(ey, c.ry0, c.ry1);
+        const ctab wnE = wny + (int64_t)et * (S * Q), wdE = wdy + (int64_t)et * (S * Q);
 #pragma unroll
         for (int bb = 0; bb <= P; ++bb) {
             const int sp = pair_index(P - e, bb);
@@ -292,7 +294,8 @@ __device__ __forceinline__ void x_row(const TileCtx& c, const XThread<T>& xt,
     for (int o = 0; o < O; ++o) m[o] = k[o] = 0.0;
 #pragma unroll
     for (int e = 0; e <= P; ++e) {
-        const int exc = clampi_t(ix - P + e, c.Kx - 1);   // the ring holds zeros outside
+        // the ring holds zeros outside the patch
+        const int exc = tab_elem(clampi_t(ix - P + e, c.Kx - 1), c.rx0, c.rx1);
         const ctab wnE = c.Wnx + (int64_t)exc * (S * Q), wdE = c.Wdx + (int64_t)exc * (S * Q);
 #pragma unroll
         for (int bb = 0; bb <= P; ++bb) {
@@ -346,6 +349,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
     c.Nz = pd.d[2].N;
     c.iy0 = (tile % nty) * T::TY;
     c.iz0 = (tile / nty) * T::TZ;
+    tile_runs(c, pd);
     const int X0 = seg * seglen, X1 = min(c.Nx, X0 + seglen);   // rows emitted
     const int xs = max(0, X0 - P);                               // first element swept
 

@@ -16,19 +16,21 @@ namespace igaf {
 // uses the standard B-spline derivative formula (the same book, eq. 2.9) with
 // the degree p-1 values of the same triangle.  A span of zero length (a
 // repeated interior knot) has zero Gauss weights: all of its tables are zero,
-// so the element adds nothing anywhere.
+// so the element adds nothing anywhere.  The elements of the run [r0, r1)
+// (equal local knot windows) are all given the tables of element r0.
 template <int P>
 __global__ void k_basis_tables(const double* __restrict__ t, int K, const double* __restrict__ xi,
                                const double* __restrict__ wr, int Q, double* __restrict__ Wnn,
                                double* __restrict__ Wdd, double* __restrict__ Nv,
-                               double* __restrict__ dN, double* __restrict__ wq, double* __restrict__ Wg)
+                               double* __restrict__ dN, double* __restrict__ wq, double* __restrict__ Wg,
+                               int r0, int r1)
 {
     constexpr int n = P + 1;
     constexpr int S = n * (n + 1) / 2;
     int gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= K * Q) return;
     int e = gid / Q, k = gid % Q;
-    int s = e + P;
+    int s = tab_elem(e, r0, r1) + P;   // the span whose values element e takes
     double x0 = t[s], x1 = t[s + 1], h = x1 - x0;
     double x = x0 + 0.5 * (xi[k] + 1.0) * h;
     double w = 0.5 * wr[k] * h;
@@ -90,7 +92,7 @@ __global__ void k_basis_tables(const double* __restrict__ t, int K, const double
 
 int launch_basis_tables(int p, const double* t, int K, const double* xi, const double* wr, int Q,
                         double* Wnn, double* Wdd, double* Nv, double* dN, double* wq, double* Wg,
-                        hipStream_t st)
+                        int r0, int r1, hipStream_t st)
 {
     int threads = 64;
     int blocks = (K * Q + threads - 1) / threads;
@@ -98,7 +100,7 @@ int launch_basis_tables(int p, const double* t, int K, const double* xi, const d
 #define IGAF_CASE(PP)                                                                        \
     case PP:                                                                                 \
         hipLaunchKernelGGL(k_basis_tables<PP>, dim3(blocks), dim3(threads), 0, st, t, K, xi, \
-                           wr, Q, Wnn, Wdd, Nv, dN, wq, Wg);                                 \
+                           wr, Q, Wnn, Wdd, Nv, dN, wq, Wg, r0, r1);                         \
         break;
         IGAF_CASE(1)
         IGAF_CASE(2)

@@ -21,7 +21,8 @@ ASM_ROWS, ASM_ATOMIC = 0, 1
 MAX_DEGREE = 5
 
 SYMBOLS = [
-    "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_csr_pattern_host",
+    "igaf_version", "igaf_last_error", "igaf_desc_check", "igaf_desc_sizes", "igaf_desc_shared_run",
+    "igaf_csr_pattern_host",
     "igaf_plan_create", "igaf_plan_destroy", "igaf_plan_sizes", "igaf_quad_nodes", "igaf_quad_points",
     "igaf_plan_set_assembly", "igaf_plan_set_timing", "igaf_plan_timing", "igaf_csr_pattern", "igaf_element_matrices", "igaf_assemble",
     "igaf_integrate_assemble", "igaf_integrate_assemble_geo", "igaf_geo_prepare", "igaf_kappa_grad", "igaf_bilinear_form",
@@ -67,6 +68,7 @@ def lib():
     st = ctypes.c_int32
     L.igaf_desc_check.argtypes = [ctypes.POINTER(PatchDesc)]
     L.igaf_desc_sizes.argtypes = [ctypes.POINTER(PatchDesc)] + [_i64p] * 5
+    L.igaf_desc_shared_run.argtypes = [ctypes.POINTER(PatchDesc), ctypes.c_int32, _i32p, _i32p]
     L.igaf_csr_pattern_host.argtypes = [ctypes.POINTER(PatchDesc), _i64p, _i32p]
     L.igaf_plan_create.argtypes = [ctypes.POINTER(PatchDesc), ctypes.POINTER(_vp)]
     L.igaf_plan_destroy.argtypes = [_vp]
@@ -163,6 +165,14 @@ def desc_check(desc):
     """Returns (status, message)."""
     s = lib().igaf_desc_check(ctypes.byref(desc))
     return s, (lib().igaf_last_error().decode() if s else "")
+
+
+def desc_shared_run(desc, d):
+    """(first, end): the elements [first, end) of direction d that share the
+    basis tables of element `first` (equal local knot windows)."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().igaf_desc_shared_run(ctypes.byref(desc), int(d), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def csr_pattern_host(desc):

@@ -163,3 +163,66 @@ def test_plan_create_rejects_before_device():
     d = _bad(p=0, knots=[W.open_uniform_knots(3, 0)] * 3)
     assert L.igaf_plan_create(ctypes.byref(d), ctypes.byref(h)) == ig.EINVAL
     assert h.value is None
+
+
+def _local_values(orc, t, p, e):
+    """Values and derivatives of the p+1 functions of element e at its Gauss
+    nodes (oracle Cox-de Boor), derivatives scaled by the element length."""
+    xi, _ = orc.gauss_legendre(p + 1)
+    lo, hi = t[e + p], t[e + p + 1]
+    out = []
+    for x in lo + 0.5 * (xi + 1.0) * (hi - lo):
+        B, dB = orc.basis_all(t, p, x)
+        out.append(np.concatenate([B[e:e + p + 1], dB[e:e + p + 1] * (hi - lo)]))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("p,K", [(1, 9), (2, 12), (3, 37), (5, 48), (3, 5), (4, 7)])
+def test_shared_table_run(orc, p, K):
+    """Uniform spacing: the run is every element but the p - 1 nearest each
+    end (their windows hold the repeated end knots), it is the longest run of
+    elements whose knot differences agree with its first element's, and the
+    oracle's basis values on every element of the run equal those on its
+    first element (the tables the plan shares); the elements just outside
+    differ."""
+    t = W.open_uniform_knots(K, p)
+    d = ig.make_desc(p, (K, 4, 4), [t, W.open_uniform_knots(4, p), W.open_uniform_knots(4, p)])
+    r0, r1 = ig.desc_shared_run(d, 0)
+    lo, hi = p - 1, K - p + 1
+    if hi - lo >= 2:
+        assert (r0, r1) == (lo, hi)
+    else:
+        assert (r0, r1) == (0, 0)
+        return
+    ref = _local_values(orc, t, p, r0)
+    for e in range(r0, r1):
+        assert np.abs(_local_values(orc, t, p, e) - ref).max() <= 1e-12 * np.abs(ref).max()
+    for e in (r0 - 1, r1):
+        if 0 <= e < K:
+            assert np.abs(_local_values(orc, t, p, e) - ref).max() > 1e-3
+
+
+def test_shared_table_run_nonuniform():
+    """Graded knots share nothing; one interior knot moved splits the uniform
+    run, and the longer side is kept (brute force over all starting points)."""
+    p, K = 3, 20
+    g = np.concatenate([[0.0] * p, (np.arange(K + 1) / K) ** 2, [1.0] * p])
+    d = ig.make_desc(p, (K, 4, 4), [g, W.open_uniform_knots(4, p), W.open_uniform_knots(4, p)])
+    assert ig.desc_shared_run(d, 0) == (0, 0)
+    t = W.open_uniform_knots(K, p)
+    t[p + 6] += 0.3 / K   # knot p+6 lies in the windows t_{e+1} .. t_{e+2p} of e = 3 .. 8
+    d = ig.make_desc(p, (K, 4, 4), [t, W.open_uniform_knots(4, p), W.open_uniform_knots(4, p)])
+    r0, r1 = ig.desc_shared_run(d, 0)
+
+    def same(e, r):
+        for j in range(1, 2 * p + 1):
+            sc = max(abs(t[e + j]), abs(t[e + p]), abs(t[r + j]), abs(t[r + p]))
+            if abs((t[e + j] - t[e + p]) - (t[r + j] - t[r + p])) > 8 * np.finfo(float).eps * sc:
+                return False
+        return True
+
+    best = max((e - s, s) for s in range(K) for e in range(s + 1, K + 1)
+               if all(same(i, s) for i in range(s, e)))
+    assert r1 - r0 == best[0] and (r0, r1) == (9, K - p + 1)
+    for e in range(r0, r1):
+        assert same(e, r0)
