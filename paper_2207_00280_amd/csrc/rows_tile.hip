@@ -52,12 +52,18 @@ __device__ inline int opaque_zero_t()
 
 }  // namespace
 
-template <int P_, int TY_, int TZ_, int WPE_, bool PREF_, bool PIPE_>
+template <int P_, int TY_, int TZ_, int WPE_, bool PREF_, bool PIPE_, int XS_ = 0>
 struct Tile {
     static constexpr int P = P_, TY = TY_, TZ = TZ_;
     static constexpr int WPE = WPE_;                    // wavefronts per SIMD aimed at
     static constexpr bool PREF = PREF_;                 // sequential: kappa of the next element in registers
     static constexpr bool PIPE = PIPE_;                 // pipelined schedule
+    // pipelined, stage-x wavefronts storing alone: XS > 0 sums the row's first
+    // XS ring elements before the iteration's first barrier and the rest
+    // after it, with two staged-row buffers, so that a row goes out in the
+    // first phase of the next iteration (the stores and the stage-x sums
+    // then fill both phases instead of the second only)
+    static constexpr int XS = XS_;
     static constexpr int Q = P + 1, O = 2 * P + 1, S = (P + 1) * (P + 2) / 2;
     static constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
     static constexpr int NLY = TY + P;                  // y elements in the window
@@ -88,35 +94,40 @@ struct Tile {
     static constexpr int SROW = O * O * O + 1;
     static constexpr int SSZ = NPEN * 2 * SROW;
     static constexpr int SIT = (O * O * O + NTS - 1) / NTS;   // store passes per row
-    static constexpr int SGP = PIPE ? NPEN : 1;         // pencils whose LDS reads go out together
+    static constexpr int SGP = PIPE && !XS ? NPEN : 1;  // pencils whose LDS reads go out together
     // LDS (doubles).  Sequential: [D | staged rows] [C]; the rows reuse D,
     // dead after stage y.  Pipelined: [D] [C] [staged rows]; one C suffices:
     // stage y writes it after the barrier that follows the stage-x reads.
     static constexpr int OFF_C = PIPE ? DSZ : cmax(DSZ, SSZ);
     static constexpr int OFF_S = PIPE ? DSZ + CSZ : 0;
-    static constexpr int LDS = PIPE ? DSZ + CSZ + SSZ : cmax(DSZ, SSZ) + CSZ;
+    static constexpr int NSTG = XS ? 2 : 1;             // staged-row buffers
+    static constexpr int LDS = PIPE ? DSZ + CSZ + NSTG * SSZ : cmax(DSZ, SSZ) + CSZ;
     static_assert(NW <= 16, "workgroup too large");
+    static_assert(XS == 0 || (PIPE && HW0 == NWZY && XS <= P), "split stage x: pipelined, x wavefronts store");
 };
 
 // Tile shapes per degree (measured on MI355X): TY pencils share stage z; TZ
 // rows fill the lanes of stage y; the register budget (WPE wavefronts per
-// SIMD) and the LDS size let two to four workgroups share a CU.
+// SIMD) and the LDS size let one to four workgroups share a CU.  At p = 5 the
+// stage-x wavefronts carry the critical path (their sums and the row stores
+// one after the other), hence the split stage x there.
 template <int P> struct TileCfg;
 template <> struct TileCfg<1> { using T = Tile<1, 4, 4, 4, true, false>; };
 template <> struct TileCfg<2> { using T = Tile<2, 4, 2, 4, true, true>; };
 template <> struct TileCfg<3> { using T = Tile<3, 2, 2, 4, false, true>; };
 template <> struct TileCfg<4> { using T = Tile<4, 2, 2, 2, true, true>; };
-template <> struct TileCfg<5> { using T = Tile<5, 3, 1, 2, false, true>; };
+template <> struct TileCfg<5> { using T = Tile<5, 2, 1, 2, false, true, 3>; };
 
-// A second shape per degree for the batched launches, smaller (fewer
-// pencils: less LDS, more workgroups per CU, less work lost at the borders
-// of small patches); the batch autotuner chooses between the two per degree.
+// A second shape per degree for the batched launches, the batch autotuner
+// choosing between the two per degree: for p <= 4 a smaller one (fewer
+// pencils: less LDS, more workgroups per CU, less work lost at the borders of
+// small patches), for p = 5 three pencils sharing stage z without the split.
 template <int P> struct TileAlt;
 template <> struct TileAlt<1> { using T = Tile<1, 2, 2, 4, true, false>; };
 template <> struct TileAlt<2> { using T = Tile<2, 2, 2, 4, true, true>; };
 template <> struct TileAlt<3> { using T = Tile<3, 2, 1, 4, false, true>; };
 template <> struct TileAlt<4> { using T = Tile<4, 2, 1, 2, true, true>; };
-template <> struct TileAlt<5> { using T = Tile<5, 2, 1, 2, false, true>; };
+template <> struct TileAlt<5> { using T = Tile<5, 3, 1, 2, false, true>; };
 
 // ---- stage z: thread of wavefront w (< NWZ) holds item (kx, ky, ly) of z row zr
 template <class T>
@@ -280,20 +291,15 @@ __device__ __forceinline__ void x_shift(const XThread<T>& xt, double (&ring)[T::
     }
 }
 
-// row ix: every ox of the thread's (oy, oz), staged at its row position
-template <class T>
-__device__ __forceinline__ void x_row(const TileCtx& c, const XThread<T>& xt,
-                                      const double (&ring)[T::P + 1][T::Q][2], int ix, double* STG)
+// row ix, ring elements E0 <= e < E1: every ox of the thread's (oy, oz)
+// summed into m, k
+template <class T, int E0, int E1>
+__device__ __forceinline__ void x_row_sum(const TileCtx& c, const double (&ring)[T::P + 1][T::Q][2], int ix,
+                                          double (&m)[T::O], double (&k)[T::O])
 {
-    constexpr int P = T::P, Q = T::Q, O = T::O, S = T::S;
-    const int Lx = band_len(ix, P, c.Nx);
-    const int sub = xt.sub * Lx + (ix - P - band_lo(ix, P));   // + ox
-    double* stM = STG + xt.pen * 2 * T::SROW;
-    double m[O], k[O];
+    constexpr int P = T::P, Q = T::Q, S = T::S;
 #pragma unroll
-    for (int o = 0; o < O; ++o) m[o] = k[o] = 0.0;
-#pragma unroll
-    for (int e = 0; e <= P; ++e) {
+    for (int e = E0; e < E1; ++e) {
         // the ring holds zeros outside the patch
         const int exc = tab_elem(clampi_t(ix - P + e, c.Kx - 1), c.rx0, c.rx1);
         const ctab wnE = c.Wnx + (int64_t)exc * (S * Q), wdE = c.Wdx + (int64_t)exc * (S * Q);
@@ -309,6 +315,17 @@ __device__ __forceinline__ void x_row(const TileCtx& c, const XThread<T>& xt,
             }
         }
     }
+}
+
+// row ix summed: staged at the row positions of the thread's (oy, oz)
+template <class T>
+__device__ __forceinline__ void x_row_put(const TileCtx& c, const XThread<T>& xt, int ix,
+                                          const double (&m)[T::O], const double (&k)[T::O], double* STG)
+{
+    constexpr int P = T::P, O = T::O;
+    const int Lx = band_len(ix, P, c.Nx);
+    const int sub = xt.sub * Lx + (ix - P - band_lo(ix, P));   // + ox
+    double* stM = STG + xt.pen * 2 * T::SROW;
     // branch-free stores (a branch per column would pull the column's
     // arithmetic, and all its table loads, apart)
 #pragma unroll
@@ -318,6 +335,17 @@ __device__ __forceinline__ void x_row(const TileCtx& c, const XThread<T>& xt,
         stM[pos] = m[ox];
         stM[T::SROW + pos] = k[ox];
     }
+}
+
+template <class T>
+__device__ __forceinline__ void x_row(const TileCtx& c, const XThread<T>& xt,
+                                      const double (&ring)[T::P + 1][T::Q][2], int ix, double* STG)
+{
+    double m[T::O], k[T::O];
+#pragma unroll
+    for (int o = 0; o < T::O; ++o) m[o] = k[o] = 0.0;
+    x_row_sum<T, 0, T::P + 1>(c, ring, ix, m, k);
+    x_row_put<T>(c, xt, ix, m, k, STG);
 }
 
 // One tile (pencils iy0.., iz0..) over the rows [seg*seglen, (seg+1)*seglen)
@@ -402,8 +430,10 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
     } else {
         // pipelined: iteration t computes element t on the stage-z/y
         // wavefronts and finishes row t-1 on the stage-x wavefronts; both
-        // roles pass the same two barriers per iteration
+        // roles pass the same two barriers per iteration (split stage x: one
+        // more iteration, which stores the last row)
         const int xe = min(c.Kx, X1);   // elements swept: [xs, xe)
+        const int tend = X1 + (T::XS ? 1 : 0);
         if (w < T::NWZY) {
             const ZThread<T> zt(c, w, lane);
             double kw[P + 1][Q];
@@ -412,7 +442,7 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
             int plen = 0;
             if (w >= T::HW0) pencil_rows<T>(c, lane, pbase, plen);
             const int ts = 64 * (T::WX + w - T::HW0) + lane;
-            for (int t = xs; t <= X1; ++t) {
+            for (int t = xs; t <= tend; ++t) {
                 const bool el = t < xe;
                 const int z0 = 0;   // no ring here: table bases may stay in registers
                 if (el && w < T::NWZ) {
@@ -438,16 +468,39 @@ __device__ __forceinline__ void tile_run(const PatchDev& pd, const RowMap& rm,
             for (int e = 0; e <= P; ++e)
 #pragma unroll
                 for (int k = 0; k < Q; ++k) ring[e][k][0] = ring[e][k][1] = 0.0;
-            for (int t = xs; t <= X1; ++t) {
-                const int r = t - 1;   // row finished in this iteration
-                const bool live = r >= xs, emit = r >= X0;
-                if (live) {
-                    x_shift<T>(xt, ring, r < xe ? C0 : nullptr);
-                    if (emit) x_row<T>(c, xt, ring, r, STG);
+            if constexpr (T::XS == 0) {
+                for (int t = xs; t <= X1; ++t) {
+                    const int r = t - 1;   // row finished in this iteration
+                    const bool live = r >= xs, emit = r >= X0;
+                    if (live) {
+                        x_shift<T>(xt, ring, r < xe ? C0 : nullptr);
+                        if (emit) x_row<T>(c, xt, ring, r, STG);
+                    }
+                    __syncthreads();
+                    if (emit) store_row<T>(c, STG, r, wx * 64 + lane, pbase, plen);
+                    __syncthreads();
                 }
-                __syncthreads();
-                if (emit) store_row<T>(c, STG, r, wx * 64 + lane, pbase, plen);
-                __syncthreads();
+            } else {
+                // row r = t-1 summed over both phases of iteration t into
+                // buffer r & 1, stored in the first phase of iteration t+1
+                for (int t = xs; t <= tend; ++t) {
+                    const int r = t - 1;
+                    const bool live = r >= xs && r < X1, emit = live && r >= X0;
+                    if (live) x_shift<T>(xt, ring, r < xe ? C0 : nullptr);
+                    if (r - 1 >= X0)
+                        store_row<T>(c, STG + ((r - 1) & 1) * T::SSZ, r - 1, wx * 64 + lane, pbase, plen);
+                    __builtin_amdgcn_sched_barrier(0);
+                    double m[T::O], k[T::O];
+#pragma unroll
+                    for (int o = 0; o < T::O; ++o) m[o] = k[o] = 0.0;
+                    if (emit) x_row_sum<T, 0, T::XS>(c, ring, r, m, k);
+                    __syncthreads();
+                    if (emit) {
+                        x_row_sum<T, T::XS, P + 1>(c, ring, r, m, k);
+                        x_row_put<T>(c, xt, r, m, k, STG + (r & 1) * T::SSZ);
+                    }
+                    __syncthreads();
+                }
             }
         }
     }
