@@ -413,7 +413,8 @@ igaf_status igaf_wq_assemble(const igaf_plan* plan, const double* kappa, double*
  * has its own block size and LDS): one workgroup per (patch, tile of row
  * pencils, x segment) item of that degree's work list, sorted longest first.
  * Per degree the launch has a configuration: the tile shape (0: the shape of
- * the single-patch kernel, 1: a smaller one), the x segments per tile (1, 2,
+ * the single-patch kernel, 1: a second one, smaller for p <= 4 and for p = 5
+ * three pencils without the split stage x), the x segments per tile (1, 2,
  * 4, 8) and the items per XCD chunk (4, 16, 64); every combination has its
  * own immutable work list, built at creation. */
 

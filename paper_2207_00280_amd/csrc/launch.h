@@ -36,8 +36,8 @@ int launch_rows_geo(const PatchDev& pd, const double* cm, const double* G, doubl
 // Batched CSR rows of the degree-p patches: one workgroup per (patch, tile,
 // x segment, segment length) item of `items` (all of degree p), which the
 // host sorts longest first, `chunk` consecutive items per XCD; `variant`
-// selects the tile shape (0: the standalone kernel's, 1: a smaller one,
-// kTileVariants in all).  rows_batch_grid is the launch's workgroup count,
+// selects the tile shape (0: the standalone kernel's, 1: the second shape of
+// the degree, kTileVariants in all).  rows_batch_grid is the launch's workgroup count,
 // rows_tile_info the tiles of a patch and the relative cost of one element
 // step of a tile of that variant.
 constexpr int kTileVariants = 2;
