@@ -36,6 +36,12 @@ CHILD = textwrap.dedent(r'''
             sz = ig.desc_sizes(d)
             rp, col = ig.csr_pattern_host(d)
             assert rp[-1] == sz["nnz"] and len(col) == sz["nnz"]
+            for a in range(3):
+                r0, r1 = ig.desc_shared_run(d, a)
+                assert 0 <= r0 <= r1 <= K[a]
+            i = ctypes.c_int32()
+            assert L.igaf_desc_shared_run(ctypes.byref(d), 3, ctypes.byref(i), ctypes.byref(i)) == ig.EINVAL
+            assert L.igaf_desc_shared_run(ctypes.byref(d), 0, None, ctypes.byref(i)) == ig.EINVAL
     # repeated interior knots (accepted) and malformed ones (refused)
     t = W.repeated_knots([0.5], [3], 3)
     d = ig.make_desc(3, (len(t) - 7, 2, 2), [t, W.open_uniform_knots(2, 3), W.open_uniform_knots(2, 3)])
@@ -69,6 +75,7 @@ CHILD = textwrap.dedent(r'''
     assert L.igaf_plan_create(None, None) == ig.EINVAL
     assert L.igaf_plan_sizes(None, None, None, None, None, None) == ig.EINVAL
     assert L.igaf_csr_pattern_host(None, None, None) == ig.EINVAL
+    assert L.igaf_desc_shared_run(None, 0, None, None) == ig.EINVAL
     assert L.igaf_element_matrices(None, 1, None, None, None, None) == ig.EINVAL
     assert L.igaf_integrate_assemble(None, 1, None, None, None, None, None, None) == ig.EINVAL
     assert L.igaf_kappa_grad(None, None, None, 1.0, 1.0, 1.0, None, None, None) == ig.EINVAL
