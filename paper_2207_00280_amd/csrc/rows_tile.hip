@@ -115,7 +115,7 @@ template <int P> struct TileCfg;
 template <> struct TileCfg<1> { using T = Tile<1, 4, 4, 4, true, false>; };
 template <> struct TileCfg<2> { using T = Tile<2, 4, 2, 4, true, true>; };
 template <> struct TileCfg<3> { using T = Tile<3, 5, 2, 2, false, true>; };
-template <> struct TileCfg<4> { using T = Tile<4, 2, 2, 2, true, true>; };
+template <> struct TileCfg<4> { using T = Tile<4, 5, 1, 2, true, true>; };
 template <> struct TileCfg<5> { using T = Tile<5, 2, 1, 2, false, true, 3>; };
 
 // A second shape per degree for the batched launches, the batch autotuner
