@@ -129,6 +129,26 @@ def test_csr_assembly(orc, ig, p, K, nonuni):
     assert csr_close(to_host(Mv4), Mv_o, rp_o, TOL) and csr_close(to_host(Kv4), Kv_o, rp_o, TOL)
 
 
+@pytest.mark.parametrize("p,K", [(3, (13, 7, 12)), (4, (9, 8, 8)), (5, (10, 10, 4)), (5, (4, 4, 10))])
+def test_csr_rows_shared_tables(orc, ig, p, K):
+    """Owner-computed CSR rows on meshes long enough (K >= 2p) for the
+    elements away from the ends of a direction to share one copy of the basis
+    tables, which the rows kernels then read for the whole run (x, y and z
+    runs covered; p = 3, 4: the ten- and five-pencil tiles over several tiles,
+    p = 5: the split stage x): every CSR value vs the oracle's assembly."""
+    knots = [W.open_uniform_knots(k, p) for k in K]
+    d = ig.make_desc(p, K, knots)
+    for a in range(3):
+        lo, hi = p - 1, K[a] - p + 1
+        assert ig.desc_shared_run(d, a) == ((lo, hi) if hi - lo >= 2 else (0, 0))
+    P = orc.Patch(p, K, [p + 1] * 3, knots)
+    kap = W.kappa_lognormal(P.nelem, P.nq, seed=300 + p)
+    plan = ig.Plan(p, K, knots)
+    rp_o, col_o, Mv_o, Kv_o = orc.assemble(P, kap)
+    _, _, Mv, Kv = plan.integrate_assemble(to_dev(kap), want_elem=False)
+    assert csr_close(to_host(Mv), Mv_o, rp_o, TOL) and csr_close(to_host(Kv), Kv_o, rp_o, TOL)
+
+
 def test_rows_deterministic(ig):
     """Owner-computed rows: bitwise identical results on repeated calls."""
     p, K = 3, (9, 7, 6)
