@@ -182,32 +182,76 @@ __global__ __launch_bounds__(kGeoThreads) void k_element_geo(PatchDev pd, const 
             // stage x + store: thread on (a2, J), loop over the test index a1;
             // lanes run along a row, so every store is a contiguous run
             const int64_t base = e * Sh::n6 + (int64_t)a3 * Sh::n5;
-            for (int i = tid; i < Sh::n4; i += T) {
-                const int a2 = i / n3, J = i % n3;
-                const int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
-                const int ci = ((a2 * n + b2) * n + b3) * Q;
-                double u[Q], v[Q], wm[Q];
-#pragma unroll
-                for (int kx = 0; kx < Q; ++kx) {
-                    const double Nb = raw[0][0][b1 * Q + kx], Db = raw[0][1][b1 * Q + kx];
-                    u[kx] = Nb * C[1][ci + kx];
-                    u[kx] += Db * C[4][ci + kx];
-                    v[kx] = Db * C[2][ci + kx];
-                    v[kx] += Nb * C[3][ci + kx];
-                    wm[kx] = Nb * C[0][ci + kx];
-                }
-                for (int a1 = 0; a1 < n; ++a1) {
-                    double m = 0.0, k = 0.0;
+            if constexpr (n % 2 == 0) {
+                // two neighbouring trial indices b1, b1+1 per thread: the C
+                // values are shared and every store writes 16 bytes
+                for (int i = tid; i < Sh::n4 / 2; i += T) {
+                    const int a2 = i / (n3 / 2), J = 2 * (i % (n3 / 2));
+                    const int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
+                    const int ci = ((a2 * n + b2) * n + b3) * Q;
+                    double u0[Q], v0[Q], w0[Q], u1[Q], v1[Q], w1[Q];
 #pragma unroll
                     for (int kx = 0; kx < Q; ++kx) {
-                        const double sN = wsc[0][0][a1 * Q + kx], sD = wsc[0][1][a1 * Q + kx];
-                        m += sN * wm[kx];
-                        k += sN * u[kx];
-                        k += sD * v[kx];
+                        const double c0 = C[0][ci + kx], c1 = C[1][ci + kx], c2 = C[2][ci + kx];
+                        const double c3 = C[3][ci + kx], c4 = C[4][ci + kx];
+                        const double N0 = raw[0][0][b1 * Q + kx], D0 = raw[0][1][b1 * Q + kx];
+                        const double N1 = raw[0][0][(b1 + 1) * Q + kx], D1 = raw[0][1][(b1 + 1) * Q + kx];
+                        u0[kx] = N0 * c1;
+                        u0[kx] += D0 * c4;
+                        v0[kx] = D0 * c2;
+                        v0[kx] += N0 * c3;
+                        w0[kx] = N0 * c0;
+                        u1[kx] = N1 * c1;
+                        u1[kx] += D1 * c4;
+                        v1[kx] = D1 * c2;
+                        v1[kx] += N1 * c3;
+                        w1[kx] = N1 * c0;
                     }
-                    const int64_t at = base + (int64_t)(a2 * n + a1) * n3 + J;
-                    if (Me) Me[at] = m;
-                    if (Ke) Ke[at] = k;
+                    for (int a1 = 0; a1 < n; ++a1) {
+                        double m0 = 0.0, k0 = 0.0, m1 = 0.0, k1 = 0.0;
+#pragma unroll
+                        for (int kx = 0; kx < Q; ++kx) {
+                            const double sN = wsc[0][0][a1 * Q + kx], sD = wsc[0][1][a1 * Q + kx];
+                            m0 += sN * w0[kx];
+                            k0 += sN * u0[kx];
+                            k0 += sD * v0[kx];
+                            m1 += sN * w1[kx];
+                            k1 += sN * u1[kx];
+                            k1 += sD * v1[kx];
+                        }
+                        const int64_t at = base + (int64_t)(a2 * n + a1) * n3 + J;
+                        if (Me) *reinterpret_cast<double2*>(Me + at) = make_double2(m0, m1);
+                        if (Ke) *reinterpret_cast<double2*>(Ke + at) = make_double2(k0, k1);
+                    }
+                }
+            } else {
+                for (int i = tid; i < Sh::n4; i += T) {
+                    const int a2 = i / n3, J = i % n3;
+                    const int b1 = J % n, b2 = (J / n) % n, b3 = J / (n * n);
+                    const int ci = ((a2 * n + b2) * n + b3) * Q;
+                    double u[Q], v[Q], wm[Q];
+#pragma unroll
+                    for (int kx = 0; kx < Q; ++kx) {
+                        const double Nb = raw[0][0][b1 * Q + kx], Db = raw[0][1][b1 * Q + kx];
+                        u[kx] = Nb * C[1][ci + kx];
+                        u[kx] += Db * C[4][ci + kx];
+                        v[kx] = Db * C[2][ci + kx];
+                        v[kx] += Nb * C[3][ci + kx];
+                        wm[kx] = Nb * C[0][ci + kx];
+                    }
+                    for (int a1 = 0; a1 < n; ++a1) {
+                        double m = 0.0, k = 0.0;
+#pragma unroll
+                        for (int kx = 0; kx < Q; ++kx) {
+                            const double sN = wsc[0][0][a1 * Q + kx], sD = wsc[0][1][a1 * Q + kx];
+                            m += sN * wm[kx];
+                            k += sN * u[kx];
+                            k += sD * v[kx];
+                        }
+                        const int64_t at = base + (int64_t)(a2 * n + a1) * n3 + J;
+                        if (Me) Me[at] = m;
+                        if (Ke) Ke[at] = k;
+                    }
                 }
             }
             __syncthreads();
