@@ -504,7 +504,8 @@ def run_kernel_mode(name, ig, torch, steps):
     copy (1 GiB device copy, the counter calibration), element, csr,
     classical, headline (W2), w3p<p> (W3 streamed CSR at degree p), w4 (the
     batched launches of W4), adjoint, apply, apply_mass (W5), geo (W6
-    element matrices), geo_csr (W6 CSR values alone, owner-computed rows)."""
+    element matrices), geo_csr (W6 CSR values alone, owner-computed rows),
+    wq (W7 weighted quadrature, CSR values)."""
     if name == "copy":
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
         b = torch.empty_like(a)
@@ -541,6 +542,17 @@ def run_kernel_mode(name, ig, torch, steps):
                 plan.kappa_grad(u, v, grad=g)
             else:
                 plan.apply(kap, u, 1.0, 0.0 if name == "apply_mass" else 1.0, y=y, work=wk)
+    elif name == "wq":
+        p, K = W.W2["p"], W.W2["K"]
+        plan = ig.Plan(p, K, [W.open_uniform_knots(k, p) for k in K])
+        plan.wq_prepare()
+        xs = [plan.wq_points(d) for d in range(3)]
+        s = [np.sin(2 * np.pi * x) for x in xs]
+        kap = torch.from_numpy(1.0 + 0.5 * np.einsum("k,j,i->kji", s[2], s[1], s[0])).cuda()
+        Mv = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+        Kv = torch.empty_like(Mv)
+        for _ in range(steps):
+            plan.wq_assemble(kap, Mval=Mv, Kval=Kv)
     elif name in ("geo", "geo_csr"):
         cfg = W.W6
         p, K = cfg["p"], cfg["K"]
@@ -576,7 +588,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=262144,
                     help="elements of the CPU-oracle sample (0 = skip)")
     ap.add_argument("--mode", default="full",
-                    help="full | headline | w3 | w4 | w5 | w6 | w7 | kernel:{element,csr,classical,headline,copy}")
+                    help="full | headline | w3 | w4 | w5 | w6 | w7 | kernel:{element,csr,classical,headline,copy,"
+                         "w3p<p>,w4,adjoint,apply,apply_mass,geo,geo_csr,wq}")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
